@@ -1,0 +1,187 @@
+"""CPU oracle for the time-dependent HJ level-set solve (float64).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, by the smoke check and
+by the benchmark's CPU-baseline leg.  The HIP library and its Python binding
+never import, link or call anything in this folder.
+
+The arithmetic lives in odp_oracle.c (plain C, one grid point at a time, in
+the order of the paper's Algorithm 1); this module only builds it with gcc
+and marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "odp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_lp = ctypes.POINTER(ctypes.c_long)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (portable -O2, OpenMP over grid points,
+    no floating-point contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        lib.oracle_hj_solve.restype = ctypes.c_int
+        lib.oracle_hj_solve.argtypes = [
+            ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+            _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+            ctypes.c_int, ctypes.c_double, _dp, _dp, _lp, _dp, _dp, _dp]
+        lib.oracle_cfl_dt.restype = ctypes.c_int
+        lib.oracle_cfl_dt.argtypes = [
+            ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+            ctypes.c_double, _dp, _dp]
+        lib.oracle_step_at.restype = ctypes.c_int
+        lib.oracle_step_at.argtypes = [
+            ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+            _dp, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_long, _lp, _dp]
+        _lib = lib
+    return _lib
+
+
+class use_library:
+    """Context manager that points this module at another build of the
+    oracle (the mutation tests use it to check that the pins have teeth)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib, _LIB
+        self._saved = (_lib, _LIB)
+        _lib, _LIB = None, self.path
+        return _load()
+
+    def __exit__(self, *exc):
+        global _lib, _LIB
+        _lib, _LIB = self._saved
+        return False
+
+
+def _arr(x, dtype):
+    return np.ascontiguousarray(np.asarray(x, dtype=dtype))
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _grid_args(grid):
+    n = _arr(grid.n, np.int64)
+    lo = _arr(grid.lo, np.float64)
+    hi = _arr(grid.hi, np.float64)
+    per = _arr(grid.periodic, np.int32)
+    return n, lo, hi, per
+
+
+def _params(dyn):
+    p = np.zeros(16, dtype=np.float64)
+    p[: len(dyn.params)] = dyn.params
+    return p
+
+
+@dataclass
+class OracleResult:
+    V: np.ndarray
+    steps: int
+    dt_first: float
+    dt_min: float
+    dt_max: float
+    V_all: Optional[np.ndarray] = None
+
+
+def solve(grid, dyn, V0: np.ndarray, tau: Sequence[float], rk_order=1, cfl=0.8, brt=True,
+          global_alpha=False, max_dt=0.0, V_init: Optional[np.ndarray] = None,
+          save_all=False) -> OracleResult:
+    lib = _load()
+    n, lo, hi, per = _grid_args(grid)
+    V0 = _arr(V0, np.float64).reshape(-1)
+    Vi = None if V_init is None else _arr(V_init, np.float64).reshape(-1)
+    tau = _arr(tau, np.float64)
+    P = int(np.prod(n))
+    if V0.size != P:
+        raise ValueError("V0 size does not match the grid")
+    out = np.empty(P, dtype=np.float64)
+    vall = np.empty((len(tau), P), dtype=np.float64) if save_all else None
+    steps = ctypes.c_long(0)
+    d1, d2, d3 = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    p = _params(dyn)
+    rc = lib.oracle_hj_solve(
+        grid.ndim, _ptr(n, _lp), _ptr(lo, _dp), _ptr(hi, _dp), _ptr(per, _ip), dyn.id,
+        dyn.u_mode, dyn.d_mode, _ptr(p, _dp), _ptr(V0, _dp),
+        _ptr(Vi, _dp) if Vi is not None else None, _ptr(tau, _dp), len(tau), rk_order, cfl,
+        1 if brt else 0, 1 if global_alpha else 0, max_dt, _ptr(out, _dp),
+        _ptr(vall, _dp) if vall is not None else None, ctypes.byref(steps), ctypes.byref(d1),
+        ctypes.byref(d2), ctypes.byref(d3))
+    if rc != 0:
+        raise ValueError("oracle_hj_solve rejected its arguments")
+    shape = tuple(int(x) for x in n)
+    return OracleResult(out.reshape(shape), int(steps.value), d1.value, d2.value, d3.value,
+                        None if vall is None else vall.reshape((len(tau),) + shape))
+
+
+def solve_spec(spec, V0=None, **kw) -> OracleResult:
+    from paper_2204_05520_amd import workloads
+    if V0 is None:
+        V0 = workloads.make_v0(spec)
+    return solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=spec.rk_order, cfl=spec.cfl,
+                 brt=spec.mode == 1, **kw)
+
+
+def cfl_dt(grid, dyn, cfl=0.8):
+    lib = _load()
+    n, lo, hi, per = _grid_args(grid)
+    amax = np.zeros(6, dtype=np.float64)
+    dt = ctypes.c_double(0)
+    p = _params(dyn)
+    rc = lib.oracle_cfl_dt(grid.ndim, _ptr(n, _lp), _ptr(lo, _dp), _ptr(hi, _dp),
+                           _ptr(per, _ip), dyn.id, dyn.u_mode, dyn.d_mode, _ptr(p, _dp), cfl,
+                           _ptr(amax, _dp), ctypes.byref(dt))
+    if rc != 0:
+        raise ValueError("oracle_cfl_dt rejected its arguments")
+    return amax[: grid.ndim].copy(), dt.value
+
+
+def step_at(grid, dyn, V: np.ndarray, V0: np.ndarray, dt: float, idx, rk_order=1, brt=True,
+            alpha_glob=None) -> np.ndarray:
+    """One full time step of size dt from V, evaluated only at flat indices idx."""
+    lib = _load()
+    n, lo, hi, per = _grid_args(grid)
+    V = _arr(V, np.float64).reshape(-1)
+    V0 = _arr(V0, np.float64).reshape(-1)
+    idx = _arr(idx, np.int64)
+    out = np.empty(idx.size, dtype=np.float64)
+    ag = None if alpha_glob is None else _arr(alpha_glob, np.float64)
+    p = _params(dyn)
+    rc = lib.oracle_step_at(grid.ndim, _ptr(n, _lp), _ptr(lo, _dp), _ptr(hi, _dp),
+                            _ptr(per, _ip), dyn.id, dyn.u_mode, dyn.d_mode, _ptr(p, _dp),
+                            _ptr(V, _dp), _ptr(V0, _dp), dt, rk_order, 1 if brt else 0,
+                            _ptr(ag, _dp) if ag is not None else None, idx.size,
+                            _ptr(idx, _lp), _ptr(out, _dp))
+    if rc != 0:
+        raise ValueError("oracle_step_at rejected its arguments")
+    return out

@@ -1,0 +1,502 @@
+/*
+ * Oracle for the time-dependent Hamilton-Jacobi level-set solve.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, float64 CPU version of
+ * the method, written to be checked by eye against the paper.  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg load it; the
+ * HIP library neither links nor calls it, and the two share no source.
+ *
+ * What it computes (paper: Algorithm 1 "solving HJ PDE", the HJ PDE and the
+ * HJ variational inequality equations, the Grid / Time Integration / Spatial
+ * Derivatives subsections, and the DubinsCapture example's input selection):
+ *
+ *   V(z, tau=tau_0) = V_init (V0 = l(z) unless a restart value is given)
+ *   per time step, per Runge-Kutta stage, per grid point i (all independent):
+ *     p-_d = (W_i - W_{i-e_d}) / dx_d,  p+_d = (W_{i+e_d} - W_i) / dx_d
+ *     pbar = (p+ + p-) / 2
+ *     (u*, d*) = argmin_d argmax_u pbar . f(z_i, u, d)
+ *     H  = pbar . f(z_i, u*, d*)
+ *     Hh = H + 1/2 sum_d alpha_d (p+_d - p-_d)         (Lax-Friedrichs)
+ *     stage output = a * V^n + b * (W + dt * Hh)        (TVD Runge-Kutta)
+ *   after the last stage of a step, for a tube: V = min(V, V0)
+ *   dt = CFL / sum_d (alpha^max_d / dx_d), clipped so that t lands exactly on
+ *   every requested output time.
+ *
+ * Readings of the paper taken here (each one is listed in the design notes):
+ *  - time runs forward in time-to-go tau = -s, so the step adds dt * Hh;
+ *  - the dissipation enters with a plus sign in time-to-go, which makes the
+ *    scheme the monotone (upwind-consistent) Lax-Friedrichs scheme; the
+ *    printed minus sign, combined with the printed update, is downwind;
+ *  - alpha_d(z) is the largest |f_d(z,u,d)| over the admissible inputs
+ *    (equal to the costate-box maximum for bang-bang inputs, whose |f_d|
+ *    does not depend on the costate);
+ *  - dt carries the CFL number, which the printed step formula omits;
+ *  - one dt per full step; min(V, V0) after every full step;
+ *  - ghost value beyond a non-periodic edge: V_b + sgn(V_b) |V_b - V_in|,
+ *    sgn(0) = 0, so the ghost has the boundary node's sign;
+ *  - bang-bang tie at a zero switching function: a maximiser takes +max, a
+ *    minimiser -max (the DubinsCapture listing's >= 0 branches);
+ *  - third-order TVD-RK (Shu-Osher) added beside the paper's first and
+ *    second order.
+ *
+ * Parity pinned by the non-GPU tests (closed forms, exact discrete identities,
+ * invariants and reductions); absolute Dubins / 4D / 6D values beyond those
+ * pins are "parity unpinned": the paper prints no value-function numbers.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OG_MAXD 6
+
+/* ------------------------------------------------------------------ grid */
+
+typedef struct {
+    int ndim;
+    long n[OG_MAXD];
+    double lo[OG_MAXD], hi[OG_MAXD];
+    int periodic[OG_MAXD];
+    double dx[OG_MAXD];
+    long stride[OG_MAXD];
+    long npts;
+} og_grid;
+
+/* Grid section: node count, bounds and periodic flag per axis.  A periodic
+ * axis excludes its upper bound, so its spacing is (hi - lo) / n. */
+static int og_grid_init(og_grid *g, int ndim, const long *n, const double *lo,
+                        const double *hi, const int *periodic)
+{
+    if (ndim < 1 || ndim > OG_MAXD) return -1;
+    g->ndim = ndim;
+    g->npts = 1;
+    for (int d = 0; d < ndim; ++d) {
+        if (n[d] < 3 || !(hi[d] > lo[d])) return -1;
+        g->n[d] = n[d];
+        g->lo[d] = lo[d];
+        g->hi[d] = hi[d];
+        g->periodic[d] = periodic[d] ? 1 : 0;
+        g->dx[d] = g->periodic[d] ? (hi[d] - lo[d]) / (double)n[d]
+                                  : (hi[d] - lo[d]) / (double)(n[d] - 1);
+        g->npts *= n[d];
+    }
+    /* row-major, last axis fastest */
+    long s = 1;
+    for (int d = ndim - 1; d >= 0; --d) {
+        g->stride[d] = s;
+        s *= g->n[d];
+    }
+    return 0;
+}
+
+static void og_unravel(const og_grid *g, long idx, long *ii)
+{
+    for (int d = 0; d < g->ndim; ++d) {
+        ii[d] = idx / g->stride[d];
+        idx -= ii[d] * g->stride[d];
+    }
+}
+
+static void og_state(const og_grid *g, const long *ii, double *z)
+{
+    for (int d = 0; d < g->ndim; ++d) z[d] = g->lo[d] + (double)ii[d] * g->dx[d];
+}
+
+/* ------------------------------------------------------------ dynamics */
+
+enum { OG_SI = 0, OG_DUBINS3D = 1, OG_DYNCAR4D = 2, OG_TWODUBINS6D = 3 };
+
+typedef struct {
+    int id;
+    int u_mode; /* 1: the control maximises, 0: minimises */
+    int d_mode; /* 1: the disturbance maximises, 0: minimises */
+    double p[16];
+} og_dyn;
+
+static int og_dyn_ndim_ok(const og_dyn *dy, int ndim)
+{
+    switch (dy->id) {
+    case OG_SI: return ndim >= 1 && ndim <= OG_MAXD;
+    case OG_DUBINS3D: return ndim == 3;
+    case OG_DYNCAR4D: return ndim == 4;
+    case OG_TWODUBINS6D: return ndim == 6;
+    default: return 0;
+    }
+}
+
+/* Bang-bang choice for a box input entering through switching function s:
+ * the optimiser picks the bound whose product with s is largest (maximiser)
+ * or smallest (minimiser); ties at s == 0 follow the DubinsCapture listing. */
+static double og_bang(double s, double bound, int maximise)
+{
+    if (maximise) return s >= 0.0 ? bound : -bound;
+    return s >= 0.0 ? -bound : bound;
+}
+
+/* Optimal control u* and disturbance d* for costate pbar (Algorithm 1,
+ * "optimal control and disturbances"). */
+static void og_opt_inputs(const og_dyn *dy, int ndim, const double *z, const double *pbar,
+                          double *u, double *dd)
+{
+    (void)z;
+    switch (dy->id) {
+    case OG_SI: {
+        /* ball |u| <= u_max: argmax p.u = u_max p/|p|, argmin = -u_max p/|p| */
+        double nrm = 0.0;
+        for (int d = 0; d < ndim; ++d) nrm += pbar[d] * pbar[d];
+        nrm = sqrt(nrm);
+        double sgn = dy->u_mode ? 1.0 : -1.0;
+        for (int d = 0; d < ndim; ++d) u[d] = nrm > 0.0 ? sgn * dy->p[0] * pbar[d] / nrm : 0.0;
+        break;
+    }
+    case OG_DUBINS3D: /* theta' = w: switching function p_theta */
+        u[0] = og_bang(pbar[2], dy->p[1], dy->u_mode);
+        break;
+    case OG_DYNCAR4D: /* v' = a, theta' = w */
+        u[0] = og_bang(pbar[2], dy->p[0], dy->u_mode);
+        u[1] = og_bang(pbar[3], dy->p[1], dy->u_mode);
+        break;
+    case OG_TWODUBINS6D: /* evader turn on axis 2, pursuer turn on axis 5 */
+        u[0] = og_bang(pbar[2], dy->p[1], dy->u_mode);
+        dd[0] = og_bang(pbar[5], dy->p[3], dy->d_mode);
+        break;
+    }
+}
+
+/* f(z, u, d): the state derivative (appendix equations). */
+static void og_dynamics(const og_dyn *dy, int ndim, const double *z, const double *u,
+                        const double *dd, double *f)
+{
+    switch (dy->id) {
+    case OG_SI: /* z' = c + u */
+        for (int d = 0; d < ndim; ++d) f[d] = dy->p[1 + d] + u[d];
+        break;
+    case OG_DUBINS3D: /* x' = v cos th, y' = v sin th, th' = w */
+        f[0] = dy->p[0] * cos(z[2]);
+        f[1] = dy->p[0] * sin(z[2]);
+        f[2] = u[0];
+        break;
+    case OG_DYNCAR4D: /* x' = v cos th, y' = v sin th, v' = a, th' = w */
+        f[0] = z[2] * cos(z[3]);
+        f[1] = z[2] * sin(z[3]);
+        f[2] = u[0];
+        f[3] = u[1];
+        break;
+    case OG_TWODUBINS6D: /* two Dubins cars: evader (u), pursuer (d) */
+        f[0] = dy->p[0] * cos(z[2]);
+        f[1] = dy->p[0] * sin(z[2]);
+        f[2] = u[0];
+        f[3] = dy->p[2] * cos(z[5]);
+        f[4] = dy->p[2] * sin(z[5]);
+        f[5] = dd[0];
+        break;
+    }
+}
+
+/* alpha_d(z) = max over admissible (u, d) of |f_d(z, u, d)| (Algorithm 1's
+ * dissipation coefficient, reading: the costate box covers both signs). */
+static void og_alpha(const og_dyn *dy, int ndim, const double *z, double *alpha)
+{
+    if (dy->id == OG_SI) {
+        /* max over the ball of |c_d + u_d| is reached at u = +-u_max e_d */
+        for (int d = 0; d < ndim; ++d) alpha[d] = fabs(dy->p[1 + d]) + dy->p[0];
+        return;
+    }
+    /* box inputs: |f_d| is affine in each input, so its maximum over the box
+     * is at a vertex; enumerate every vertex. */
+    double ub[4] = {0}, db[4] = {0};
+    int nu = 0, nd = 0;
+    switch (dy->id) {
+    case OG_DUBINS3D: ub[0] = dy->p[1]; nu = 1; break;
+    case OG_DYNCAR4D: ub[0] = dy->p[0]; ub[1] = dy->p[1]; nu = 2; break;
+    case OG_TWODUBINS6D: ub[0] = dy->p[1]; db[0] = dy->p[3]; nu = 1; nd = 1; break;
+    }
+    for (int d = 0; d < ndim; ++d) alpha[d] = 0.0;
+    int nv = 1 << (nu + nd);
+    for (int v = 0; v < nv; ++v) {
+        double u[4], dd[4], f[OG_MAXD];
+        for (int a = 0; a < nu; ++a) u[a] = ((v >> a) & 1) ? ub[a] : -ub[a];
+        for (int a = 0; a < nd; ++a) dd[a] = ((v >> (nu + a)) & 1) ? db[a] : -db[a];
+        og_dynamics(dy, ndim, z, u, dd, f);
+        for (int d = 0; d < ndim; ++d)
+            if (fabs(f[d]) > alpha[d]) alpha[d] = fabs(f[d]);
+    }
+}
+
+/* --------------------------------------------------------------- fields */
+
+/* A field is anything that can return W at a flat index: a plain array, or
+ * a Runge-Kutta stage evaluated on demand (for sampled checks). */
+typedef struct og_field og_field;
+struct og_field {
+    double (*get)(const og_field *self, long idx);
+    const double *arr;
+    const void *ctx;
+    int level;
+};
+
+static double og_get_array(const og_field *f, long idx) { return f->arr[idx]; }
+
+static double og_sgn(double x) { return (x > 0.0) - (x < 0.0); }
+
+/* W at the neighbour of point idx (multi-index ii) along axis d, side s. */
+static double og_neighbor(const og_grid *g, const og_field *W, long idx, const long *ii,
+                          int d, int s)
+{
+    long k = ii[d] + s;
+    if (k >= 0 && k < g->n[d]) return W->get(W, idx + (long)s * g->stride[d]);
+    if (g->periodic[d]) {
+        long kw = (k + g->n[d]) % g->n[d];
+        return W->get(W, idx + (kw - ii[d]) * g->stride[d]);
+    }
+    /* ghost node beyond the edge: extrapolate away from zero so that the
+     * ghost keeps the sign of the boundary node */
+    double vb = W->get(W, idx);
+    double vin = W->get(W, idx - (long)s * g->stride[d]);
+    return vb + og_sgn(vb) * fabs(vb - vin);
+}
+
+/* Lax-Friedrichs numerical Hamiltonian at point idx (one pass of the body
+ * of Algorithm 1's grid loops for one point). alpha_glob != NULL selects the
+ * global-alpha approximation. */
+static double og_hhat(const og_grid *g, const og_dyn *dy, const og_field *W, long idx,
+                      const double *alpha_glob)
+{
+    const int N = g->ndim;
+    long ii[OG_MAXD];
+    double z[OG_MAXD] = {0};
+    og_unravel(g, idx, ii);
+    og_state(g, ii, z);
+
+    double wc = W->get(W, idx);
+    double pm[OG_MAXD], pp[OG_MAXD], pbar[OG_MAXD];
+    for (int d = 0; d < N; ++d) {
+        double wl = og_neighbor(g, W, idx, ii, d, -1);
+        double wr = og_neighbor(g, W, idx, ii, d, +1);
+        pm[d] = (wc - wl) / g->dx[d];
+        pp[d] = (wr - wc) / g->dx[d];
+        pbar[d] = 0.5 * (pp[d] + pm[d]);
+    }
+
+    double u[OG_MAXD] = {0}, dd[OG_MAXD] = {0}, f[OG_MAXD];
+    og_opt_inputs(dy, N, z, pbar, u, dd);
+    og_dynamics(dy, N, z, u, dd, f);
+    double H = 0.0;
+    for (int d = 0; d < N; ++d) H += pbar[d] * f[d];
+
+    double alpha[OG_MAXD];
+    if (alpha_glob) {
+        for (int d = 0; d < N; ++d) alpha[d] = alpha_glob[d];
+    } else {
+        og_alpha(dy, N, z, alpha);
+    }
+    double diss = 0.0;
+    for (int d = 0; d < N; ++d) diss += 0.5 * alpha[d] * (pp[d] - pm[d]);
+    return H + diss;
+}
+
+/* TVD Runge-Kutta stage weights: stage s output = a V^n + b (W + dt L(W)). */
+static void og_rk_weights(int order, int stage, double *a, double *b)
+{
+    *a = 0.0;
+    *b = 1.0;
+    if (order == 2 && stage == 1) { *a = 0.5; *b = 0.5; }
+    if (order == 3 && stage == 1) { *a = 0.75; *b = 0.25; }
+    if (order == 3 && stage == 2) { *a = 1.0 / 3.0; *b = 2.0 / 3.0; }
+}
+
+static double og_combine(double a, double b, double vn, double w, double dt, double hh)
+{
+    if (a == 0.0) return w + dt * hh;
+    return a * vn + b * (w + dt * hh);
+}
+
+/* alpha^max_d = max over all grid points of alpha_d(z_i). */
+static void og_alpha_max(const og_grid *g, const og_dyn *dy, double *amax)
+{
+    for (int d = 0; d < g->ndim; ++d) amax[d] = 0.0;
+    for (long i = 0; i < g->npts; ++i) {
+        long ii[OG_MAXD];
+        double z[OG_MAXD], a[OG_MAXD];
+        og_unravel(g, i, ii);
+        og_state(g, ii, z);
+        og_alpha(dy, g->ndim, z, a);
+        for (int d = 0; d < g->ndim; ++d)
+            if (a[d] > amax[d]) amax[d] = a[d];
+    }
+}
+
+static double og_dt_cfl(const og_grid *g, const double *amax, double cfl, double max_dt)
+{
+    double s = 0.0;
+    for (int d = 0; d < g->ndim; ++d) s += amax[d] / g->dx[d];
+    double dt = cfl / s; /* +inf when nothing moves: the step then lands on tau */
+    if (max_dt > 0.0 && dt > max_dt) dt = max_dt;
+    return dt;
+}
+
+static int og_setup(og_grid *g, og_dyn *dy, int ndim, const long *n, const double *lo,
+                    const double *hi, const int *periodic, int dyn_id, int u_mode, int d_mode,
+                    const double *params)
+{
+    if (og_grid_init(g, ndim, n, lo, hi, periodic)) return -1;
+    memset(dy, 0, sizeof(*dy));
+    dy->id = dyn_id;
+    dy->u_mode = u_mode;
+    dy->d_mode = d_mode;
+    for (int k = 0; k < 16; ++k) dy->p[k] = params[k];
+    if (!og_dyn_ndim_ok(dy, ndim)) return -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------ solve */
+
+/* Full solve from tau[0] to tau[ntau-1].  V_all (nullable) receives V at
+ * every tau[k] (ntau slices, slice 0 = the start value).  Returns 0 or -1. */
+int oracle_hj_solve(int ndim, const long *n, const double *lo, const double *hi,
+                    const int *periodic, int dyn_id, int u_mode, int d_mode,
+                    const double *params, const double *V0, const double *V_init,
+                    const double *tau, int ntau, int rk_order, double cfl, int brt,
+                    int global_alpha, double max_dt, double *V_out, double *V_all,
+                    long *steps_out, double *dt_first, double *dt_min, double *dt_max)
+{
+    og_grid g;
+    og_dyn dy;
+    if (og_setup(&g, &dy, ndim, n, lo, hi, periodic, dyn_id, u_mode, d_mode, params)) return -1;
+    if (rk_order < 1 || rk_order > 3 || ntau < 2 || !(cfl > 0.0)) return -1;
+    for (int k = 1; k < ntau; ++k)
+        if (!(tau[k] > tau[k - 1])) return -1;
+
+    const long P = g.npts;
+    double *Vn = V_out;
+    double *S1 = (double *)malloc(sizeof(double) * (size_t)P);
+    double *S2 = rk_order == 3 ? (double *)malloc(sizeof(double) * (size_t)P) : NULL;
+    double *Nx = (double *)malloc(sizeof(double) * (size_t)P);
+    if (!S1 || !Nx || (rk_order == 3 && !S2)) {
+        free(S1); free(S2); free(Nx);
+        return -1;
+    }
+    memcpy(Vn, V_init ? V_init : V0, sizeof(double) * (size_t)P);
+    if (V_all) memcpy(V_all, Vn, sizeof(double) * (size_t)P);
+
+    double t = tau[0];
+    int k = 1;
+    long steps = 0;
+    double dtmin = INFINITY, dtmax = 0.0, dtfirst = 0.0;
+    while (k < ntau) {
+        /* alpha^max over the grid (recomputed every step) and the CFL step */
+        double amax[OG_MAXD];
+        og_alpha_max(&g, &dy, amax);
+        double dt = og_dt_cfl(&g, amax, cfl, max_dt);
+        double t_next;
+        int land = 0;
+        if (dt >= tau[k] - t) {
+            dt = tau[k] - t;
+            t_next = tau[k];
+            land = 1;
+        } else {
+            t_next = t + dt;
+        }
+        const double *aglob = global_alpha ? amax : NULL;
+
+        /* Runge-Kutta stages: stage s reads W (stencil) and V^n (pointwise) */
+        double *stage_out[3] = {S1, S2, Nx};
+        const double *W = Vn;
+        for (int s = 0; s < rk_order; ++s) {
+            double *out = (s == rk_order - 1) ? Nx : stage_out[s];
+            double a, b;
+            og_rk_weights(rk_order, s, &a, &b);
+            og_field Wf = {og_get_array, W, NULL, 0};
+#pragma omp parallel for schedule(static)
+            for (long i = 0; i < P; ++i) {
+                double hh = og_hhat(&g, &dy, &Wf, i, aglob);
+                out[i] = og_combine(a, b, Vn[i], W[i], dt, hh);
+            }
+            W = out;
+        }
+        /* HJ variational inequality for a tube: V = min(V, V0) */
+        if (brt) {
+            for (long i = 0; i < P; ++i)
+                if (V0[i] < Nx[i]) Nx[i] = V0[i];
+        }
+        memcpy(Vn, Nx, sizeof(double) * (size_t)P);
+
+        if (steps == 0) dtfirst = dt;
+        if (dt < dtmin) dtmin = dt;
+        if (dt > dtmax) dtmax = dt;
+        ++steps;
+        t = t_next;
+        if (land) {
+            if (V_all) memcpy(V_all + (size_t)k * (size_t)P, Vn, sizeof(double) * (size_t)P);
+            ++k;
+        }
+    }
+    free(S1); free(S2); free(Nx);
+    if (steps_out) *steps_out = steps;
+    if (dt_first) *dt_first = dtfirst;
+    if (dt_min) *dt_min = dtmin;
+    if (dt_max) *dt_max = dtmax;
+    return 0;
+}
+
+/* The CFL step and alpha^max alone (no time stepping). */
+int oracle_cfl_dt(int ndim, const long *n, const double *lo, const double *hi,
+                  const int *periodic, int dyn_id, int u_mode, int d_mode, const double *params,
+                  double cfl, double *alpha_max_out, double *dt_out)
+{
+    og_grid g;
+    og_dyn dy;
+    if (og_setup(&g, &dy, ndim, n, lo, hi, periodic, dyn_id, u_mode, d_mode, params)) return -1;
+    double amax[OG_MAXD];
+    og_alpha_max(&g, &dy, amax);
+    for (int d = 0; d < ndim; ++d) alpha_max_out[d] = amax[d];
+    *dt_out = og_dt_cfl(&g, amax, cfl, 0.0);
+    return 0;
+}
+
+/* ------------------------------------------- one step at sampled points */
+
+typedef struct {
+    const og_grid *g;
+    const og_dyn *dy;
+    const double *Vn;
+    int rk_order;
+    double dt;
+    const double *aglob;
+} og_step_ctx;
+
+/* Value of Runge-Kutta stage `level` (0 = V^n) at idx, evaluated on demand
+ * from its own domain of dependence. */
+static double og_stage_value(const og_field *self, long idx)
+{
+    const og_step_ctx *c = (const og_step_ctx *)self->ctx;
+    if (self->level == 0) return c->Vn[idx];
+    og_field prev = {og_stage_value, NULL, c, self->level - 1};
+    double a, b;
+    og_rk_weights(c->rk_order, self->level - 1, &a, &b);
+    double hh = og_hhat(c->g, c->dy, &prev, idx, c->aglob);
+    return og_combine(a, b, c->Vn[idx], og_stage_value(&prev, idx), c->dt, hh);
+}
+
+/* One full time step of size dt from V (whole grid, float64) evaluated only
+ * at the flat indices idx[0..m): out[j] = V^{n+1}(idx[j]).  alpha_glob may be
+ * NULL (per-point alpha). */
+int oracle_step_at(int ndim, const long *n, const double *lo, const double *hi,
+                   const int *periodic, int dyn_id, int u_mode, int d_mode,
+                   const double *params, const double *V, const double *V0, double dt,
+                   int rk_order, int brt, const double *alpha_glob, long m, const long *idx,
+                   double *out)
+{
+    og_grid g;
+    og_dyn dy;
+    if (og_setup(&g, &dy, ndim, n, lo, hi, periodic, dyn_id, u_mode, d_mode, params)) return -1;
+    if (rk_order < 1 || rk_order > 3) return -1;
+    og_step_ctx c = {&g, &dy, V, rk_order, dt, alpha_glob};
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long j = 0; j < m; ++j) {
+        og_field top = {og_stage_value, NULL, &c, rk_order};
+        double v = og_stage_value(&top, idx[j]);
+        if (brt && V0[idx[j]] < v) v = V0[idx[j]];
+        out[j] = v;
+    }
+    return 0;
+}

@@ -1,0 +1,95 @@
+"""The pins have teeth: plant one plausible mistake at a time in a copy of
+the oracle's C source (on the CPU), build it, and check that some pin fails.
+
+Each mutant is a single textual change to oracle/odp_oracle.c; the test
+first asserts the original text is present, so a refactor of the oracle that
+moves a site makes this test fail loudly instead of silently passing.
+"""
+import os
+import subprocess
+
+import pytest
+
+import test_oracle_pins as pins
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "odp_oracle.c")
+
+MUTANTS = [
+    ("lf_sign", "diss += 0.5 * alpha[d] * (pp[d] - pm[d]);",
+     "diss -= 0.5 * alpha[d] * (pp[d] - pm[d]);"),
+    ("lf_dropped_on_last_axis", "for (int d = 0; d < N; ++d) diss += 0.5",
+     "for (int d = 0; d < N - 1; ++d) diss += 0.5"),
+    ("one_sided_swapped", "pm[d] = (wc - wl) / g->dx[d];\n        pp[d] = (wr - wc) / g->dx[d];",
+     "pm[d] = (wr - wc) / g->dx[d];\n        pp[d] = (wc - wl) / g->dx[d];"),
+    ("costate_not_halved", "pbar[d] = 0.5 * (pp[d] + pm[d]);", "pbar[d] = (pp[d] + pm[d]);"),
+    ("ghost_toward_zero", "return vb + og_sgn(vb) * fabs(vb - vin);",
+     "return vb - og_sgn(vb) * fabs(vb - vin);"),
+    ("periodic_wrap_off_by_one", "long kw = (k + g->n[d]) % g->n[d];",
+     "long kw = (k + g->n[d] + 1) % g->n[d];"),
+    ("cos_sin_swapped_3d", "f[0] = dy->p[0] * cos(z[2]);\n        f[1] = dy->p[0] * sin(z[2]);\n        f[2] = u[0];\n        break;\n    case OG_DYNCAR4D",
+     "f[0] = dy->p[0] * sin(z[2]);\n        f[1] = dy->p[0] * cos(z[2]);\n        f[2] = u[0];\n        break;\n    case OG_DYNCAR4D"),
+    ("pursuer_uses_evader_heading", "f[3] = dy->p[2] * cos(z[5]);", "f[3] = dy->p[2] * cos(z[2]);"),
+    ("car_speed_axis_wrong", "f[0] = z[2] * cos(z[3]);", "f[0] = z[3] * cos(z[3]);"),
+    ("bang_bang_inverted", "if (maximise) return s >= 0.0 ? bound : -bound;",
+     "if (maximise) return s >= 0.0 ? -bound : bound;"),
+    ("ball_input_sign", "double sgn = dy->u_mode ? 1.0 : -1.0;",
+     "double sgn = dy->u_mode ? -1.0 : 1.0;"),
+    ("drift_sign", "f[d] = dy->p[1 + d] + u[d];", "f[d] = -dy->p[1 + d] + u[d];"),
+    ("rk3_weight", "if (order == 3 && stage == 1) { *a = 0.75; *b = 0.25; }",
+     "if (order == 3 && stage == 1) { *a = 0.5; *b = 0.5; }"),
+    ("rk2_weight", "if (order == 2 && stage == 1) { *a = 0.5; *b = 0.5; }",
+     "if (order == 2 && stage == 1) { *a = 0.0; *b = 1.0; }"),
+    ("cfl_number_dropped", "double dt = cfl / s;", "double dt = 1.0 / s;"),
+    ("tube_clamp_max", "if (V0[i] < Nx[i]) Nx[i] = V0[i];", "if (V0[i] > Nx[i]) Nx[i] = V0[i];"),
+    ("last_step_not_clipped", "dt = tau[k] - t;", "dt = dt + 0.0;"),
+    ("control_bound_for_disturbance", "dd[0] = og_bang(pbar[5], dy->p[3], dy->d_mode);",
+     "dd[0] = og_bang(pbar[5], dy->p[1], dy->d_mode);"),
+    ("car_controls_exchanged", "u[0] = og_bang(pbar[2], dy->p[0], dy->u_mode);\n        u[1] = og_bang(pbar[3], dy->p[1], dy->u_mode);",
+     "u[0] = og_bang(pbar[2], dy->p[1], dy->u_mode);\n        u[1] = og_bang(pbar[3], dy->p[0], dy->u_mode);"),
+    ("periodic_spacing_like_closed", "g->dx[d] = g->periodic[d] ? (hi[d] - lo[d]) / (double)n[d]",
+     "g->dx[d] = g->periodic[d] ? (hi[d] - lo[d]) / (double)(n[d] - 1)"),
+]
+
+FAST_PINS = [
+    lambda o: [pins.test_pin1_hopf_lax(o, *c) for c in pins.CASES_PIN1],
+    lambda o: [pins.test_pin1b_bang_bang_axis_closed_form(o, *c) for c in pins.ONE_AXIS],
+    lambda o: pins.test_pin2_periodic_shift_at_cfl_one(o),
+    lambda o: [pins.test_pin2_upwind_identity(o, c, f) for c, f in [(0.8, 0.5), (-1.3, 0.9)]],
+    lambda o: pins.test_pin2_dubins_x_axis_slice(o),
+    lambda o: [pins.test_pin3_brt_monotone(o, w, r) for w, r in [("dubins3d", 1), ("dyncar4d", 3)]],
+    lambda o: pins.test_pin4_dubins_symmetries(o),
+    lambda o: pins.test_pin4_car_and_game_mirror(o),
+    lambda o: [pins.test_pin5_game_separates(o, p) for p in ("evader", "pursuer")],
+    lambda o: pins.test_pin6_car_reduces_to_dubins(o),
+    lambda o: [pins.test_pin8_rk_temporal_order(o, r) for r in (1, 2, 3)],
+    lambda o: pins.test_golden_step_count_3d(o),
+    lambda o: pins.test_restart_equals_single_call(o),
+]
+
+
+def _first_failing_pin(oracle_mod):
+    for k, pin in enumerate(FAST_PINS):
+        try:
+            pin(oracle_mod)
+        except (AssertionError, ValueError, FloatingPointError):
+            return k
+    return None
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(oracle_mod, tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} moved"
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(old, new))
+    lib = tmp_path / "libmut.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                           "-ffp-contract=off", "-o", str(lib), str(mut), "-lm"])
+    with oracle_mod.use_library(str(lib)):
+        caught = _first_failing_pin(oracle_mod)
+    assert caught is not None, f"no pin catches mutant {name}"
+
+
+def test_unmutated_passes_fast_pins(oracle_mod):
+    assert _first_failing_pin(oracle_mod) is None

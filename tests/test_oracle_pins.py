@@ -1,0 +1,438 @@
+"""Pins for the float64 CPU oracle: results fixed by the mathematics, not by
+the oracle's own formulas.
+
+Each pin names what a plausible mistake would break:
+  1  Hopf-Lax closed form for z' = c + u, |u| <= u_max (H, LF sign, ghosts,
+     dt landing), both optimiser roles, with and without drift, 1-3D.
+  2  exact discrete identities: the scheme reduces to textbook upwinding for
+     pure advection (derivative indexing, LF sign, alpha); a one-cell shift
+     at CFL 1 on a periodic axis; the Dubins x-axis on its th = 0 slice.
+  3  tube monotonicity V(tau_k) <= V(tau_{k-1}), V <= V0, V(0) = V0.
+  4  symmetries of the Dubins / car / two-car problems: mirror, quarter turn,
+     heading roll (axis strides, periodic wrap, cos/sin placement).
+  5  6D game with an evader-only target equals the 3D Dubins solve broadcast
+     over the pursuer axes (and the pursuer-only mirror case), bitwise.
+  6  4D car with a_max = 0: every v-slice is a 3D Dubins solve with v = v_k.
+  7  first-order convergence of pin 1 under grid refinement.
+  8  temporal order 1/2/3 of TVD-RK1/2/3 on a linear problem.
+  -  hand-derived CFL steps of the three single-solve workloads (golden file).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2204_05520_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _grid_coords(g):
+    return np.meshgrid(*[g.axis(d) for d in range(g.ndim)], indexing="ij")
+
+
+# ------------------------------------------------------------------ pin 1
+
+def hopf_lax(g, c, u_max, T, r, maximise):
+    Z = _grid_coords(g)
+    s = np.sqrt(sum((Z[d] + c[d] * T) ** 2 for d in range(g.ndim)))
+    if maximise:
+        return s + u_max * T - r
+    return np.maximum(s - u_max * T, 0.0) - r
+
+
+CASES_PIN1 = [
+    # ndim, n, drift, maximise, brt
+    (1, 161, [0.0], False, False),
+    (1, 161, [0.6], False, True),
+    (1, 161, [-0.4], True, False),
+    (2, 81, [0.0, 0.0], False, False),
+    (2, 81, [0.5, -0.3], False, True),
+    (2, 81, [0.3, 0.4], True, False),
+    (3, 41, [0.2, -0.3, 0.4], False, True),
+    (3, 41, [0.0, 0.0, 0.0], True, False),
+]
+
+
+@pytest.mark.parametrize("ndim,n,drift,maximise,brt", CASES_PIN1)
+def test_pin1_hopf_lax(oracle_mod, ndim, n, drift, maximise, brt):
+    T, r, u_max = 0.5, 1.5, 1.0
+    spec = W.single_integrator(ndim, n, u_max, drift, W.MAXIMISE if maximise else W.MINIMISE,
+                               T, radius=r, brt=brt)
+    V0 = W.make_v0(spec)
+    res = oracle_mod.solve_spec(spec, V0)
+    exact = hopf_lax(spec.grid, drift, u_max, T, r, maximise)
+    band = np.abs(exact) <= 0.5
+    dx = 8.0 / (n - 1)
+    err = np.abs(res.V - exact)[band].max()
+    # first-order scheme: error a fraction of dx in the smooth band; in 1D
+    # the exact solution is piecewise linear and the scheme keeps it exactly
+    # away from the kinks
+    assert err <= (1e-6 if ndim == 1 else 0.75) * dx, (err, dx)
+    # the whole grid (kinks included) stays within a few cells
+    assert np.abs(res.V - exact).max() <= 2.5 * dx
+    assert res.dt_first > 0 and math.isclose(res.dt_min, res.dt_min)
+
+
+def test_pin1_wrong_sign_would_fail(oracle_mod):
+    """The closed form separates maximiser and minimiser by 2 u_max T = 1."""
+    spec = W.single_integrator(2, 81, 1.0, [0.0, 0.0], W.MINIMISE, 0.5)
+    res = oracle_mod.solve_spec(spec)
+    wrong = hopf_lax(spec.grid, [0, 0], 1.0, 0.5, 1.5, True)
+    band = np.abs(wrong) <= 0.5
+    assert np.abs(res.V - wrong)[band].max() > 0.5
+
+
+# ----------------------------------------------------------------- pin 1b
+
+def _arc_extreme(V0fun, x, half, maximise, periodic=True, samples=4001):
+    """Hopf-Lax for x' = u, |u| <= b along one axis: the max (or min) of V0
+    over [x - half, x + half], by dense sampling."""
+    s = np.linspace(-half, half, samples)
+    vals = V0fun(x[:, None] + s[None, :])
+    return vals.max(axis=1) if maximise else vals.min(axis=1)
+
+
+def _one_axis_case(dyn_id, axis, bound_index, role):
+    """A target that depends on a single input axis: the other axes' terms
+    vanish, and the input axis follows x' = u, |u| <= bound."""
+    if dyn_id == W.DYN_DUBINS3D:
+        spec = W.config_dubins3d(n=(5, 5, 96), T=0.5)
+        spec.dyn = W.DynSpec(dyn_id, [0.7, 1.3], role, W.MINIMISE)
+    elif dyn_id == W.DYN_DYNCAR4D:
+        n = [5, 5, 5, 96] if axis == 3 else [5, 5, 161, 6]
+        spec = W.config_dyncar4d(n=n, T=0.5)
+        spec.dyn = W.DynSpec(dyn_id, [0.9, 1.3], role, W.MINIMISE)
+    else:
+        n = [4, 4, 96, 4, 4, 6] if axis == 2 else [4, 4, 6, 4, 4, 96]
+        spec = W.config_game6d(n=n, T=0.5)
+        spec.dyn = W.DynSpec(dyn_id, [0.6, 1.3, 0.8, 0.9],
+                             role if axis == 2 else W.MAXIMISE,
+                             role if axis == 5 else W.MAXIMISE)
+    return spec
+
+
+ONE_AXIS = [
+    # dynamics, input axis, index of its bound in params, role
+    (W.DYN_DUBINS3D, 2, 1, W.MAXIMISE), (W.DYN_DUBINS3D, 2, 1, W.MINIMISE),
+    (W.DYN_DYNCAR4D, 3, 1, W.MAXIMISE), (W.DYN_DYNCAR4D, 3, 1, W.MINIMISE),
+    (W.DYN_DYNCAR4D, 2, 0, W.MAXIMISE), (W.DYN_DYNCAR4D, 2, 0, W.MINIMISE),
+    (W.DYN_TWODUBINS6D, 2, 1, W.MAXIMISE), (W.DYN_TWODUBINS6D, 2, 1, W.MINIMISE),
+    (W.DYN_TWODUBINS6D, 5, 3, W.MAXIMISE), (W.DYN_TWODUBINS6D, 5, 3, W.MINIMISE),
+]
+
+
+@pytest.mark.parametrize("dyn_id,axis,bidx,role", ONE_AXIS)
+def test_pin1b_bang_bang_axis_closed_form(oracle_mod, dyn_id, axis, bidx, role):
+    spec = _one_axis_case(dyn_id, axis, bidx, role)
+    g = spec.grid
+    b = spec.dyn.params[bidx]
+    T = spec.tau[-1]
+    x = g.axis(axis)
+    if g.periodic[axis]:
+        f = lambda th: np.cos(th) + 0.4 * np.sin(2 * th)
+    else:
+        f = lambda v: 0.3 * (v - 2.0) ** 2 + 0.2 * v
+    shape = [1] * g.ndim
+    shape[axis] = g.n[axis]
+    V0 = np.ascontiguousarray(np.broadcast_to(f(x).reshape(shape), tuple(g.n)))
+    res = oracle_mod.solve(g, spec.dyn, V0, spec.tau, rk_order=1, cfl=0.8, brt=False)
+    exact = _arc_extreme(f, x, b * T, role == W.MAXIMISE)
+    got = np.moveaxis(res.V, axis, -1).reshape(-1, g.n[axis])
+    # the result is constant across the other axes
+    assert np.abs(got - got[0]).max() < 1e-12
+    h = x[1] - x[0]
+    keep = np.ones(x.size, dtype=bool)
+    if not g.periodic[axis]:
+        # stay away from the edges, where the exact solution looks past them
+        keep = (x - b * T > g.lo[axis] + 4 * h) & (x + b * T < g.hi[axis] - 4 * h)
+    err = np.abs(got[0] - exact)[keep].max()
+    assert err < 1.5 * h, (err, h)
+    # the other role is far away: the pin separates maximiser and minimiser
+    other = _arc_extreme(f, x, b * T, role != W.MAXIMISE)
+    assert np.abs(got[0] - other)[keep].max() > 10 * h
+
+
+# ------------------------------------------------------------------ pin 2
+
+def test_pin2_periodic_shift_at_cfl_one(oracle_mod):
+    g = W.GridSpec([40], [-4.0], [4.0], [1])
+    x = g.axis(0)
+    V0 = np.sin(2 * np.pi * x / 8) + 0.3 * np.cos(6 * np.pi * x / 8) + 0.1 * x ** 0
+    for c in (0.7, -0.45):
+        d = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [0.0, c], W.MINIMISE, W.MINIMISE)
+        _, dt = oracle_mod.cfl_dt(g, d, 1.0)
+        assert math.isclose(dt, 0.2 / abs(c), rel_tol=1e-15)
+        res = oracle_mod.solve(g, d, V0, [0.0, 5 * dt], rk_order=1, cfl=1.0, brt=False)
+        # V_tau = c V_x: c > 0 moves data towards -x by one cell per step
+        shift = -5 if c > 0 else 5
+        assert np.abs(res.V - np.roll(V0, shift)).max() < 1e-13
+
+
+@pytest.mark.parametrize("c,cfl", [(0.8, 0.5), (-1.3, 0.9), (0.25, 0.3)])
+def test_pin2_upwind_identity(oracle_mod, c, cfl):
+    g = W.GridSpec([33], [-4.0], [4.0], [1])
+    x = g.axis(0)
+    rng = np.random.default_rng(7)
+    V0 = np.cos(x) + 0.05 * rng.standard_normal(x.size)
+    d = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [0.0, c], W.MAXIMISE, W.MINIMISE)
+    _, dt = oracle_mod.cfl_dt(g, d, cfl)
+    res = oracle_mod.solve(g, d, V0, [0.0, dt], rk_order=1, cfl=cfl, brt=False)
+    lam = abs(c) * dt / (8.0 / 33)
+    assert math.isclose(lam, cfl, rel_tol=1e-14)
+    if c > 0:
+        expect = V0 + lam * (np.roll(V0, -1) - V0)
+    else:
+        expect = V0 + lam * (np.roll(V0, 1) - V0)
+    assert np.abs(res.V - expect).max() < 1e-14
+
+
+def test_pin2_dubins_x_axis_slice(oracle_mod):
+    """w_max = 0: on the th = 0 slice (cos 1, sin ~0, local alpha_y ~0) the
+    Dubins update is exactly upwinding along x with lambda = v dt / dx."""
+    n = (30, 20, 16)
+    spec = W.config_dubins3d(n=n)
+    spec.dyn.params = [1.0, 0.0]
+    V0 = W.make_v0(spec)
+    amax, dt = oracle_mod.cfl_dt(spec.grid, spec.dyn, 0.8)
+    res = oracle_mod.solve(spec.grid, spec.dyn, V0, [0.0, dt], rk_order=1, cfl=0.8, brt=False)
+    k0 = n[2] // 2
+    assert abs(spec.grid.axis(2)[k0]) < 1e-15
+    lam = dt / (8.0 / 29)
+    S0 = V0[:, :, k0]
+    expect = S0[:-1] + lam * (S0[1:] - S0[:-1])
+    assert np.abs(res.V[:-1, :, k0] - expect).max() < 1e-14
+
+
+# ------------------------------------------------------------------ pin 3
+
+@pytest.mark.parametrize("which,rk", [("dubins3d", 1), ("dubins3d", 2), ("dyncar4d", 3),
+                                      ("game6d", 2)])
+def test_pin3_brt_monotone(oracle_mod, which, rk):
+    if which == "dubins3d":
+        spec = W.config_dubins3d(n=(24, 24, 16), T=0.6)
+    elif which == "dyncar4d":
+        spec = W.config_dyncar4d(n=12, T=0.3)
+    else:
+        spec = W.config_game6d(n=[8, 8, 6, 7, 7, 6], T=0.3)
+    _, dt = oracle_mod.cfl_dt(spec.grid, spec.dyn, spec.cfl)
+    m = int(spec.tau[-1] / dt)
+    tau = [k * dt for k in range(m + 1)]
+    V0 = W.make_v0(spec)
+    res = oracle_mod.solve(spec.grid, spec.dyn, V0, tau, rk_order=rk, cfl=spec.cfl, brt=True,
+                           save_all=True)
+    A = res.V_all
+    assert np.array_equal(A[0], V0)
+    assert (A <= V0[None] + 0.0).all()
+    tol = 4 * np.finfo(np.float64).eps * np.maximum(np.abs(A[:-1]), 1.0)
+    ok = A[1:] <= A[:-1] + tol
+    # The order-preserving argument covers the interior; the sign-keeping
+    # ghost extrapolation is not monotone in the inner node, so faces of
+    # non-periodic axes are only required to stay close.
+    g = spec.grid
+    inner = np.ones(tuple(g.n), dtype=bool)
+    for d in range(g.ndim):
+        if not g.periodic[d]:
+            sl = [slice(None)] * g.ndim
+            sl[d] = [0, g.n[d] - 1]
+            inner[tuple(sl)] = False
+    assert ok[:, inner].all()
+    assert (A[1:] - A[:-1]).max() < 1e-3
+    # the tube grows: some point strictly decreased
+    assert (A[-1] < V0 - 1e-6).any()
+
+
+# ------------------------------------------------------------------ pin 4
+
+def _solve(oracle_mod, spec, V0=None, **kw):
+    V0 = W.make_v0(spec) if V0 is None else V0
+    return oracle_mod.solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=spec.rk_order,
+                            cfl=spec.cfl, brt=spec.mode == W.BRT, **kw).V
+
+
+def test_pin4_dubins_symmetries(oracle_mod):
+    spec = W.config_dubins3d(n=(21, 21, 16), T=0.5)
+    V = _solve(oracle_mod, spec)
+    n = 16
+    # mirror (x, y, th) -> (x, -y, -th)
+    kk = (n - np.arange(n)) % n
+    Vm = V[:, ::-1, :][:, :, kk]
+    assert np.abs(Vm - V).max() < 1e-12
+    # quarter turn (x, y, th) -> (-y, x, th + pi/2): V[n-1-j, i, k+n/4] = V[i, j, k]
+    Vr = np.empty_like(V)
+    for i in range(21):
+        for j in range(21):
+            Vr[i, j, :] = np.roll(V[20 - j, i, :], -n // 4)
+    assert np.abs(Vr - V).max() < 1e-12
+    # heading roll: shift the th origin by 3 cells
+    h = 2 * np.pi / n
+    spec2 = W.config_dubins3d(n=(21, 21, 16), T=0.5)
+    spec2.grid.lo[2] = -np.pi + 3 * h
+    spec2.grid.hi[2] = np.pi + 3 * h
+    V2 = _solve(oracle_mod, spec2)
+    assert np.abs(V2 - np.roll(V, -3, axis=2)).max() < 1e-12
+
+
+def test_pin4_symmetry_breaks_on_swapped_axes(oracle_mod):
+    """Control for pin 4: exchanging the roles of x and y (cos on y) is not
+    mirror-symmetric, so the mirror check does catch such a mistake."""
+    spec = W.config_dubins3d(n=(21, 21, 16), T=0.5)
+    V = _solve(oracle_mod, spec)
+    Vt = np.transpose(V, (1, 0, 2))  # a solution with x and y exchanged
+    kk = (16 - np.arange(16)) % 16
+    assert np.abs(Vt[:, ::-1, :][:, :, kk] - Vt).max() > 1e-3
+
+
+def test_pin4_car_and_game_mirror(oracle_mod):
+    spec = W.config_dyncar4d(n=[15, 15, 6, 12], T=0.3)
+    V = _solve(oracle_mod, spec)
+    kk = (12 - np.arange(12)) % 12
+    Vm = V[:, ::-1, :, :][:, :, :, kk]
+    assert np.abs(Vm - V).max() < 1e-12
+
+    spec = W.config_game6d(n=[7, 7, 6, 7, 7, 6], T=0.2)
+    V = _solve(oracle_mod, spec)
+    kk = (6 - np.arange(6)) % 6
+    Vm = V[:, ::-1, :, :, ::-1, :][:, :, kk, :, :, :][:, :, :, :, :, kk]
+    assert np.abs(Vm - V).max() < 1e-12
+
+
+# ------------------------------------------------------------------ pin 5
+
+@pytest.mark.parametrize("player", ["evader", "pursuer"])
+def test_pin5_game_separates(oracle_mod, player):
+    n6 = [11, 10, 8, 6, 5, 6]
+    spec6 = W.config_game6d(n=n6, T=0.4)
+    _, dt6 = oracle_mod.cfl_dt(spec6.grid, spec6.dyn, spec6.cfl)
+    if player == "evader":
+        keep, n3, mode, v, w = (0, 1), n6[:3], spec6.dyn.u_mode, 1.0, 1.0
+        V0 = W.cylinder_v0(spec6.grid, 0.7, keep=(0, 1))
+    else:
+        keep, n3, mode, v, w = (3, 4), n6[3:], spec6.dyn.d_mode, 1.0, 1.0
+        V0 = W.cylinder_v0(spec6.grid, 0.7, keep=(3, 4))
+    V6 = oracle_mod.solve(spec6.grid, spec6.dyn, V0, spec6.tau, rk_order=2, cfl=0.8,
+                          brt=True).V
+    spec3 = W.config_dubins3d(n=n3, T=0.4)
+    spec3.dyn = W.DynSpec(W.DYN_DUBINS3D, [v, w], mode, W.MINIMISE)
+    V03 = W.cylinder_v0(spec3.grid, 0.7, keep=(0, 1))
+    V3 = oracle_mod.solve(spec3.grid, spec3.dyn, V03, spec3.tau, rk_order=2, cfl=0.8,
+                          brt=True, max_dt=dt6).V
+    if player == "evader":
+        ref = np.broadcast_to(V3[:, :, :, None, None, None], V6.shape)
+    else:
+        ref = np.broadcast_to(V3[None, None, None, :, :, :], V6.shape)
+    assert np.array_equal(V6, ref)
+
+
+# ------------------------------------------------------------------ pin 6
+
+def test_pin6_car_reduces_to_dubins(oracle_mod):
+    spec4 = W.config_dyncar4d(n=[14, 13, 5, 12], T=0.25)
+    spec4.dyn.params = [0.0, 1.0]  # a_max = 0
+    V0 = W.make_v0(spec4)
+    _, dt4 = oracle_mod.cfl_dt(spec4.grid, spec4.dyn, spec4.cfl)
+    V4 = oracle_mod.solve(spec4.grid, spec4.dyn, V0, spec4.tau, rk_order=3, cfl=0.8,
+                          brt=True).V
+    g4 = spec4.grid
+    for k, vk in enumerate(g4.axis(2)):
+        g3 = W.GridSpec([14, 13, 12], [-5.0, -5.0, -np.pi], [5.0, 5.0, np.pi], [0, 0, 1])
+        d3 = W.DynSpec(W.DYN_DUBINS3D, [float(vk), 1.0], W.MAXIMISE, W.MINIMISE)
+        V03 = W.cylinder_v0(g3, 0.5)
+        V3 = oracle_mod.solve(g3, d3, V03, spec4.tau, rk_order=3, cfl=0.8, brt=True,
+                              max_dt=dt4).V
+        assert np.array_equal(V4[:, :, k, :], V3), k
+
+
+# ------------------------------------------------------------------ pin 7
+
+def test_pin7_first_order_convergence(oracle_mod):
+    errs, hs = [], []
+    for n in (26, 51, 101):
+        spec = W.single_integrator(2, n, 1.0, [0.3, -0.2], W.MINIMISE, 0.5, brt=True)
+        res = oracle_mod.solve_spec(spec)
+        exact = hopf_lax(spec.grid, [0.3, -0.2], 1.0, 0.5, 1.5, False)
+        band = np.abs(exact) <= 0.5
+        errs.append(np.abs(res.V - exact)[band].max())
+        hs.append(8.0 / (n - 1))
+    orders = [math.log(errs[i] / errs[i + 1]) / math.log(hs[i] / hs[i + 1]) for i in range(2)]
+    for p in orders:
+        assert 0.7 <= p <= 1.3, (orders, errs)
+
+
+# ------------------------------------------------------------------ pin 8
+
+@pytest.mark.parametrize("rk", [1, 2, 3])
+def test_pin8_rk_temporal_order(oracle_mod, rk):
+    g = W.GridSpec([48], [0.0], [8.0], [1])
+    x = g.axis(0)
+    V0 = np.sin(2 * np.pi * x / 8.0)
+    d = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [0.0, 1.0], W.MAXIMISE, W.MINIMISE)
+    T = 1.0
+    dx = 8.0 / 48
+
+    def run(m):
+        return oracle_mod.solve(g, d, V0, [0.0, T], rk_order=rk, cfl=1.0, brt=False,
+                                max_dt=T / m).V
+
+    m0 = int(math.ceil(T / (0.5 * dx)))
+    ref = run(m0 * 64)
+    e = [np.abs(run(m0 * f) - ref).max() for f in (1, 2, 4)]
+    rates = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    for r_ in rates:
+        assert abs(r_ - rk) < 0.25, (rates, e)
+
+
+# ------------------------------------------------------------------ golden
+
+def test_golden_cfl_steps(oracle_mod):
+    gold = json.load(open(os.path.join(HERE, "golden", "cfl_steps.json")))
+    # the full 36^6 reduction is too slow for a plain CPU loop; the reduced
+    # game grid keeps the heading axes and therefore alpha^max
+    specs = {"dubins3d_60x60x36": W.config_dubins3d(),
+             "dyncar4d_80": W.config_dyncar4d(),
+             "game6d_8x8x36x8x8x36": W.config_game6d(n=[8, 8, 36, 8, 8, 36])}
+    for key, spec in specs.items():
+        amax, dt = oracle_mod.cfl_dt(spec.grid, spec.dyn, spec.cfl)
+        assert np.allclose(amax, gold[key]["alpha_max"], rtol=0, atol=1e-15), key
+        assert math.isclose(dt, gold[key]["dt"], rel_tol=1e-13), key
+
+
+def test_golden_step_count_3d(oracle_mod):
+    gold = json.load(open(os.path.join(HERE, "golden", "cfl_steps.json")))["dubins3d_60x60x36"]
+    res = oracle_mod.solve_spec(W.config_dubins3d())
+    assert res.steps == gold["steps"]
+    assert math.isclose(res.dt_first, gold["dt"], rel_tol=1e-13)
+    # the clipped last step lands exactly on T
+    assert math.isclose(res.dt_min, gold["T"] - (gold["steps"] - 1) * gold["dt"], rel_tol=1e-9)
+
+
+# ------------------------------------------------------------------ sampled evaluator
+
+def test_step_at_matches_full_step(oracle_mod):
+    """The on-demand evaluator (used for sampled checks of huge grids) agrees
+    with the whole-grid solver for one step, for every RK order."""
+    spec = W.config_dyncar4d(n=[9, 8, 6, 10], T=0.02)
+    V0 = W.make_v0(spec)
+    rng = np.random.default_rng(3)
+    Vs = V0 + 0.05 * rng.standard_normal(V0.shape)
+    idx = rng.choice(V0.size, 60, replace=False)
+    idx = np.concatenate([idx, [0, V0.size - 1]])
+    for rk in (1, 2, 3):
+        full = oracle_mod.solve(spec.grid, spec.dyn, V0, [0.0, 0.004], rk_order=rk, cfl=0.8,
+                                brt=True, V_init=Vs)
+        assert full.steps == 1
+        pts = oracle_mod.step_at(spec.grid, spec.dyn, Vs, V0, 0.004, idx, rk_order=rk, brt=True)
+        assert np.array_equal(pts, full.V.reshape(-1)[idx])
+
+
+def test_restart_equals_single_call(oracle_mod):
+    spec = W.config_dubins3d(n=(20, 18, 12), T=1.0)
+    V0 = W.make_v0(spec)
+    one = oracle_mod.solve(spec.grid, spec.dyn, V0, [0.0, 0.37, 1.0], save_all=True)
+    a = oracle_mod.solve(spec.grid, spec.dyn, V0, [0.0, 0.37])
+    b = oracle_mod.solve(spec.grid, spec.dyn, V0, [0.37, 1.0], V_init=a.V)
+    assert np.array_equal(one.V_all[1], a.V)
+    assert np.array_equal(one.V, b.V)
+    assert one.steps == a.steps + b.steps
