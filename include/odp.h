@@ -1,0 +1,224 @@
+/*
+ * odp.h -- C ABI of libodp.so, a gfx950 (MI355X) solver for the time-dependent
+ * Hamilton-Jacobi level-set equation (backward reachable sets and tubes).
+ *
+ * Method (paper "OptimizedDP", Algorithm 1 and the HJ PDE / HJ variational
+ * inequality equations of its Methods section): for every grid point and
+ * every time step, one-sided differences in each dimension, the optimal
+ * control and disturbance for the central costate, the Hamiltonian,
+ * Lax-Friedrichs dissipation, a CFL time step from a grid-wide maximum of
+ * the dissipation coefficients, a TVD Runge-Kutta update and, for a tube,
+ * V = min(V, V0).
+ *
+ * Conventions shared by every entry point:
+ *  - Grid arrays are contiguous, row-major, last axis fastest (the layout of
+ *    the paper's cache-aware loop-order section).  Element type is float
+ *    (precision 32) or double (precision 64).
+ *  - Pointers named *_dev are device (HBM) pointers on the current HIP
+ *    device; all other pointers are host pointers.  The caller owns every
+ *    buffer it passes; the library never frees caller memory and keeps no
+ *    pointer after a call returns (server calls copy what they keep).
+ *  - Time is time-to-go tau >= 0 (tau = -s for the paper's backward time s).
+ *    tau arrays are strictly increasing; tau[0] is the start time.
+ *  - Return codes: 0 OK, > 0 informational, < 0 error.  No C++ exception
+ *    crosses the ABI.  odp_last_error() gives a thread-local message for the
+ *    last failing call on the calling thread.
+ */
+#ifndef ODP_H
+#define ODP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ODP_OK = 0,
+    ODP_PENDING = 1,        /* serve: request not finished yet */
+    ODP_EINVAL = -1,        /* bad argument (shape, bounds, tau, cfl, id) */
+    ODP_ENOMEM = -2,        /* allocation failed / workspace too small /
+                               request larger than the server's budget */
+    ODP_EHIP = -3,          /* a HIP runtime call failed */
+    ODP_EUNSUPPORTED = -4,  /* valid but unsupported combination */
+    ODP_EAGAIN = -5,        /* serve queue full, retry later */
+    ODP_ENONFINITE = -6,    /* NaN or Inf appeared in the value function */
+    ODP_ECANCELED = -7      /* serve request was cancelled */
+};
+
+/* Static description of a return code (never NULL). */
+const char *odp_strerror(int code);
+/* Detail of the last error raised on this thread (empty string if none). */
+const char *odp_last_error(void);
+
+/* ------------------------------------------------------------------ grid */
+
+/* Cartesian grid (paper: Grid section).  ndim in [1, 6]; n[d] >= 3 nodes;
+ * lo[d] < hi[d]; periodic[d] != 0 makes axis d periodic, in which case hi[d]
+ * is excluded and the spacing is (hi - lo) / n, otherwise (hi - lo)/(n - 1).
+ * Non-periodic edges use ghost nodes extrapolated away from zero (the ghost
+ * keeps the sign of the boundary node).  The total point count must stay
+ * below 2^31 per hyperplane of axes 1..ndim-1 and below 2^40 overall.
+ * On success *out owns a host object freed by odp_grid_destroy. */
+typedef struct odp_grid odp_grid;
+int odp_grid_create(int ndim, const int64_t *n, const double *lo, const double *hi,
+                    const uint8_t *periodic, odp_grid **out);
+void odp_grid_destroy(odp_grid *grid);
+/* Number of grid points (product of n). */
+int64_t odp_grid_points(const odp_grid *grid);
+
+/* -------------------------------------------------------------- dynamics */
+
+/* Closed set of control-affine dynamics (paper: Dynamical Systems
+ * Specification section and appendix).  Parameter layout of p[]:
+ *  SINGLE_INTEGRATOR (any ndim, test problem): z' = c + u, |u|_2 <= u_max;
+ *      p[0] = u_max, p[1..ndim] = c.
+ *  DUBINS3D (x, y, th):  x' = v cos th, y' = v sin th, th' = w, |w| <= w_max;
+ *      p[0] = v, p[1] = w_max.  Control w.
+ *  DYNCAR4D (x, y, v, th): x' = v cos th, y' = v sin th, v' = a, th' = w;
+ *      p[0] = a_max, p[1] = w_max.  Controls a, w.
+ *  TWODUBINS6D (x_e, y_e, th_e, x_p, y_p, th_p): two Dubins cars; the
+ *      evader turns with the control u (|u| <= u_max), the pursuer with the
+ *      disturbance d (|d| <= d_max); p[0] = v_e, p[1] = u_max, p[2] = v_p,
+ *      p[3] = d_max.
+ * u_mode / d_mode: 1 = that player maximises the Hamiltonian, 0 = minimises
+ * (for a box input: maximiser picks +bound when its switching function is
+ * >= 0, minimiser picks -bound). */
+typedef enum {
+    ODP_DYN_SINGLE_INTEGRATOR = 0,
+    ODP_DYN_DUBINS3D = 1,
+    ODP_DYN_DYNCAR4D = 2,
+    ODP_DYN_TWODUBINS6D = 3
+} odp_dyn_id;
+
+typedef struct {
+    int32_t id;      /* odp_dyn_id */
+    int32_t u_mode;  /* 1 maximise, 0 minimise */
+    int32_t d_mode;  /* 1 maximise, 0 minimise */
+    int32_t pad_;
+    double p[16];
+} odp_dynamics;
+
+/* ----------------------------------------------------------------- solve */
+
+typedef enum { ODP_BRS = 0, ODP_BRT = 1 } odp_mode;
+
+typedef struct {
+    int32_t precision;   /* 32 or 64: element type of every grid array */
+    int32_t rk_order;    /* 1, 2 or 3 (TVD Runge-Kutta) */
+    double cfl;          /* in (0, 1] */
+    int32_t mode;        /* odp_mode: BRS (plain PDE) or BRT (min with V0 after
+                            every full step: the HJ variational inequality) */
+    int32_t dissipation; /* 0: per-point alpha_d(z_i); 1: global alpha^max_d
+                            (the paper's cheaper approximation) */
+    double max_dt;       /* 0: none; > 0 caps the CFL step (tests use it) */
+    int32_t save_all;    /* 1: also write V at every tau[k] into V_all_dev */
+    int32_t tile_chunk;  /* 0: library default; else planes marched per block */
+    void *stream;        /* hipStream_t for every launch (NULL: null stream) */
+} odp_solve_opts;
+
+typedef struct {
+    int64_t steps;       /* CFL steps taken */
+    double dt_min, dt_max, t_final;
+    double kernel_ms;    /* device time of the time-stepping loop */
+    double alg_bytes;    /* algorithmic HBM bytes of the loop */
+    double alg_gbps;     /* alg_bytes / kernel time */
+    double roofline_frac;/* alg_gbps / 8000 */
+    double alpha_max[6]; /* grid-wide maximum dissipation coefficients */
+    int32_t nonfinite;   /* 1 if a NaN / Inf was produced */
+    int32_t pad_;
+} odp_solve_stats;
+
+/* Device workspace bytes odp_hj_solve needs for this problem (the float64
+ * dt schedule is sized from the dynamics' speed bounds and the horizon).
+ * Returns 0 for invalid arguments. */
+size_t odp_hj_workspace_bytes(const odp_grid *grid, const odp_dynamics *dyn, const double *tau,
+                              int ntau, const odp_solve_opts *opts);
+
+/* Solve V from tau[0] to tau[ntau-1] (ntau >= 2) on opts->stream.
+ *  V0_dev:     l(z), the target's implicit function (read only; also the
+ *              clamp of a tube).
+ *  V_init_dev: value at tau[0]; NULL means V0 (restart: pass V(tau[0])).
+ *  workspace_dev: NULL (the library allocates stream-ordered and frees
+ *              after the call) or at least odp_hj_workspace_bytes bytes,
+ *              256-byte aligned, used exclusively by this call until the
+ *              stream reaches its end.
+ *  V_out_dev:  receives V(tau[ntau-1]); may not alias V0/V_init.
+ *  V_all_dev:  NULL unless opts->save_all; then ntau slices, slice 0 =
+ *              the start value, slice k = V(tau[k]).
+ *  stats:      NULL, or filled after an internal stream synchronisation.
+ * The CFL step is dt = cfl / sum_d alpha^max_d / dx_d, computed in float64 on
+ * the device and clipped so that time lands exactly on every tau[k].  The
+ * call blocks once, to learn the step count; the time stepping itself is
+ * stream-ordered.  With stats != NULL, ODP_ENONFINITE reports NaN/Inf. */
+int odp_hj_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_dev,
+                 const void *V_init_dev, const double *tau, int ntau,
+                 const odp_solve_opts *opts, void *workspace_dev, void *V_out_dev,
+                 void *V_all_dev, odp_solve_stats *stats);
+
+/* ----------------------------------------------------------------- batch */
+
+/* One solve of a batch: its own grid, dynamics, target and horizon. */
+typedef struct {
+    const odp_grid *grid;
+    odp_dynamics dyn;
+    const void *V0_dev;    /* device, element type = common->precision */
+    const double *tau;     /* host, strictly increasing, ntau >= 2 */
+    int32_t ntau;
+    int32_t pad_;
+    void *V_out_dev;       /* device, receives V(tau[ntau-1]) */
+} odp_solve_desc;
+
+/* Workspace for odp_hj_batch (device bytes). */
+size_t odp_hj_batch_workspace_bytes(int nsolves, const odp_solve_desc *descs,
+                                    const odp_solve_opts *common);
+
+/* Run nsolves independent solves in one persistent launch on
+ * common->stream: each workgroup takes whole solves from a device queue,
+ * longest first, and steps them with workgroup barriers only (no
+ * cross-workgroup waits).  common->save_all must be 0.  workspace_dev may be
+ * NULL (library allocates) or hold odp_hj_batch_workspace_bytes bytes.
+ * stats_per_solve: NULL or nsolves entries, filled after a synchronisation
+ * (kernel_ms is the whole launch).  Results equal the same solves run one by
+ * one through odp_hj_solve with the same options, bit for bit. */
+int odp_hj_batch(int nsolves, const odp_solve_desc *descs, const odp_solve_opts *common,
+                 void *workspace_dev, size_t workspace_bytes,
+                 odp_solve_stats *stats_per_solve);
+
+/* ----------------------------------------------------------------- serve */
+
+/* In-process continuous-batching server.  A scheduler thread admits queued
+ * requests while their device footprint fits hbm_budget_bytes and a slot is
+ * free, keeps their value functions resident, and advances every active
+ * solve by a few steps per tick in one batched launch, so requests that
+ * arrive while others run join at the next tick.  Results are the same as
+ * odp_hj_solve with the server's options, bit for bit. */
+typedef struct odp_server odp_server;
+
+int odp_server_create(size_t hbm_budget_bytes, int max_slots, const odp_solve_opts *opts,
+                      odp_server **out);
+/* Copy the request (grid shape, dynamics, tau, and V0 from HOST memory:
+ * desc->V0_dev is read as a host pointer here, desc->V_out_dev is ignored)
+ * and queue it.  The caller may free its buffers on return.
+ * ODP_ENOMEM if the request can never fit the budget, ODP_EAGAIN if the
+ * queue is full. */
+int odp_serve_submit(odp_server *srv, const odp_solve_desc *host_desc, uint64_t *ticket);
+/* ODP_PENDING while queued or running.  Once finished: copies V(tau_last)
+ * into V_out_host (bytes must equal the grid size times the element size),
+ * fills stats (may be NULL), releases the ticket and returns ODP_OK, or the
+ * request's error code (ODP_ECANCELED, ODP_ENONFINITE, ...). */
+int odp_serve_poll(odp_server *srv, uint64_t ticket, void *V_out_host, size_t bytes,
+                   odp_solve_stats *stats);
+/* Cancel a queued or running request; its poll then returns ODP_ECANCELED. */
+int odp_serve_cancel(odp_server *srv, uint64_t ticket);
+/* Number of requests queued, running and finished-but-unpolled. */
+int odp_server_counts(odp_server *srv, int *queued, int *running, int *done);
+/* Stop the scheduler (running requests are cancelled) and free everything. */
+void odp_server_destroy(odp_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ODP_H */

@@ -1,0 +1,319 @@
+"""Python binding of libodp.so: the gfx950 time-dependent HJ level-set solver.
+
+Argument marshalling only.  Every step of the solve runs in the library's HIP
+kernels; torch provides device memory and streams.  The entry points keep
+the C names of include/odp.h (odp_grid_create, odp_hj_solve, odp_hj_batch,
+odp_server_create, odp_serve_submit, odp_serve_poll, ...); `solve`,
+`batch` and `Server` are thin conveniences on top of them.
+
+If libodp.so has not been built the first call raises: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libodp.so")
+
+ODP_OK = 0
+ODP_PENDING = 1
+ODP_EINVAL = -1
+ODP_ENOMEM = -2
+ODP_EHIP = -3
+ODP_EUNSUPPORTED = -4
+ODP_EAGAIN = -5
+ODP_ENONFINITE = -6
+ODP_ECANCELED = -7
+
+ODP_BRS = 0
+ODP_BRT = 1
+
+SYMBOLS = [
+    "odp_strerror", "odp_last_error", "odp_grid_create", "odp_grid_destroy", "odp_grid_points",
+    "odp_hj_workspace_bytes", "odp_hj_solve", "odp_hj_batch_workspace_bytes", "odp_hj_batch",
+    "odp_server_create", "odp_serve_submit", "odp_serve_poll", "odp_serve_cancel",
+    "odp_server_counts", "odp_server_destroy",
+]
+
+
+class OdpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"odp error {code}: {msg}")
+        self.code = code
+
+
+class odp_dynamics(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int32), ("u_mode", ctypes.c_int32), ("d_mode", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("p", ctypes.c_double * 16)]
+
+
+class odp_solve_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("rk_order", ctypes.c_int32), ("cfl", ctypes.c_double),
+                ("mode", ctypes.c_int32), ("dissipation", ctypes.c_int32), ("max_dt", ctypes.c_double),
+                ("save_all", ctypes.c_int32), ("tile_chunk", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class odp_solve_stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double),
+                ("t_final", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double), ("alg_gbps", ctypes.c_double),
+                ("roofline_frac", ctypes.c_double), ("alpha_max", ctypes.c_double * 6),
+                ("nonfinite", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: (list(getattr(self, k)) if k == "alpha_max" else getattr(self, k))
+                for k, _ in self._fields_ if k != "pad_"}
+
+
+class odp_solve_desc(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_void_p), ("dyn", odp_dynamics), ("V0_dev", ctypes.c_void_p),
+                ("tau", ctypes.POINTER(ctypes.c_double)), ("ntau", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("V_out_dev", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libodp.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -c "
+                               "'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+        L.odp_strerror.restype = ctypes.c_char_p
+        L.odp_strerror.argtypes = [i32]
+        L.odp_last_error.restype = ctypes.c_char_p
+        L.odp_last_error.argtypes = []
+        L.odp_grid_create.restype = i32
+        L.odp_grid_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int64), dp, dp,
+                                      ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(vp)]
+        L.odp_grid_destroy.restype = None
+        L.odp_grid_destroy.argtypes = [vp]
+        L.odp_grid_points.restype = i64
+        L.odp_grid_points.argtypes = [vp]
+        L.odp_hj_workspace_bytes.restype = ctypes.c_size_t
+        L.odp_hj_workspace_bytes.argtypes = [vp, ctypes.POINTER(odp_dynamics), dp, i32,
+                                             ctypes.POINTER(odp_solve_opts)]
+        L.odp_hj_solve.restype = i32
+        L.odp_hj_solve.argtypes = [vp, ctypes.POINTER(odp_dynamics), vp, vp, dp, i32,
+                                   ctypes.POINTER(odp_solve_opts), vp, vp, vp,
+                                   ctypes.POINTER(odp_solve_stats)]
+        if hasattr(L, "odp_hj_batch"):
+            L.odp_hj_batch_workspace_bytes.restype = ctypes.c_size_t
+            L.odp_hj_batch_workspace_bytes.argtypes = [i32, ctypes.POINTER(odp_solve_desc),
+                                                       ctypes.POINTER(odp_solve_opts)]
+            L.odp_hj_batch.restype = i32
+            L.odp_hj_batch.argtypes = [i32, ctypes.POINTER(odp_solve_desc),
+                                       ctypes.POINTER(odp_solve_opts), vp, ctypes.c_size_t,
+                                       ctypes.POINTER(odp_solve_stats)]
+        if hasattr(L, "odp_server_create"):
+            L.odp_server_create.restype = i32
+            L.odp_server_create.argtypes = [ctypes.c_size_t, i32, ctypes.POINTER(odp_solve_opts),
+                                            ctypes.POINTER(vp)]
+            L.odp_serve_submit.restype = i32
+            L.odp_serve_submit.argtypes = [vp, ctypes.POINTER(odp_solve_desc),
+                                           ctypes.POINTER(ctypes.c_uint64)]
+            L.odp_serve_poll.restype = i32
+            L.odp_serve_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_size_t,
+                                         ctypes.POINTER(odp_solve_stats)]
+            L.odp_serve_cancel.restype = i32
+            L.odp_serve_cancel.argtypes = [vp, ctypes.c_uint64]
+            L.odp_server_counts.restype = i32
+            L.odp_server_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ctypes.c_int)]
+            L.odp_server_destroy.restype = None
+            L.odp_server_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise OdpError(rc, f"{lib().odp_strerror(rc).decode()}: {lib().odp_last_error().decode()}")
+    return rc
+
+
+def odp_strerror(code: int) -> str:
+    return lib().odp_strerror(code).decode()
+
+
+def odp_last_error() -> str:
+    return lib().odp_last_error().decode()
+
+
+# ----------------------------------------------------------------- grid
+
+class Grid:
+    """Owning wrapper of an odp_grid handle."""
+
+    def __init__(self, n: Sequence[int], lo: Sequence[float], hi: Sequence[float],
+                 periodic: Sequence[int]):
+        self.n = [int(x) for x in n]
+        self.handle = odp_grid_create(len(n), n, lo, hi, periodic)
+
+    @classmethod
+    def from_spec(cls, g):
+        return cls(g.n, g.lo, g.hi, g.periodic)
+
+    @property
+    def npts(self) -> int:
+        return int(lib().odp_grid_points(self.handle))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.odp_grid_destroy(h)
+            self.handle = None
+
+
+def odp_grid_create(ndim, n, lo, hi, periodic):
+    n_a = (ctypes.c_int64 * ndim)(*[int(x) for x in n])
+    lo_a = (ctypes.c_double * ndim)(*[float(x) for x in lo])
+    hi_a = (ctypes.c_double * ndim)(*[float(x) for x in hi])
+    pe_a = (ctypes.c_uint8 * ndim)(*[1 if x else 0 for x in periodic])
+    out = ctypes.c_void_p()
+    _check(lib().odp_grid_create(ndim, n_a, lo_a, hi_a, pe_a, ctypes.byref(out)))
+    return out.value
+
+
+def odp_grid_destroy(handle):
+    lib().odp_grid_destroy(handle)
+
+
+def make_dynamics(dyn) -> odp_dynamics:
+    d = odp_dynamics()
+    d.id = int(dyn.id)
+    d.u_mode = int(dyn.u_mode)
+    d.d_mode = int(dyn.d_mode)
+    for k, v in enumerate(dyn.params):
+        d.p[k] = float(v)
+    return d
+
+
+def make_opts(precision=32, rk_order=1, cfl=0.8, mode=ODP_BRT, dissipation=0, max_dt=0.0,
+              save_all=0, tile_chunk=0, stream=None) -> odp_solve_opts:
+    o = odp_solve_opts()
+    o.precision = precision
+    o.rk_order = rk_order
+    o.cfl = cfl
+    o.mode = mode
+    o.dissipation = dissipation
+    o.max_dt = max_dt
+    o.save_all = save_all
+    o.tile_chunk = tile_chunk
+    o.stream = stream
+    return o
+
+
+def _tau_array(tau):
+    arr = (ctypes.c_double * len(tau))(*[float(x) for x in tau])
+    return arr
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    return ctypes.c_void_p(int(stream.cuda_stream)) if hasattr(stream, "cuda_stream") else stream
+
+
+def odp_hj_workspace_bytes(grid: Grid, dyn, tau, opts: odp_solve_opts) -> int:
+    d = make_dynamics(dyn)
+    t = _tau_array(tau)
+    return int(lib().odp_hj_workspace_bytes(grid.handle, ctypes.byref(d), t, len(tau), ctypes.byref(opts)))
+
+
+def odp_hj_solve(grid: Grid, dyn, V0, V_init, tau, opts: odp_solve_opts, workspace, V_out,
+                 V_all=None, want_stats=True):
+    """Raw entry point: tensors (or None) are passed by data_ptr."""
+    d = make_dynamics(dyn)
+    t = _tau_array(tau)
+    st = odp_solve_stats()
+    ptr = lambda x: None if x is None else ctypes.c_void_p(x.data_ptr())
+    rc = lib().odp_hj_solve(grid.handle, ctypes.byref(d), ptr(V0), ptr(V_init), t, len(tau),
+                            ctypes.byref(opts), ptr(workspace), ptr(V_out), ptr(V_all),
+                            ctypes.byref(st) if want_stats else None)
+    _check(rc)
+    return st
+
+
+# ----------------------------------------------------------- conveniences
+
+@dataclass
+class SolveResult:
+    V: "object"            # torch tensor on the device
+    stats: dict
+    V_all: Optional[object] = None
+
+
+def _torch_dtype(precision):
+    import torch
+    return torch.float32 if precision == 32 else torch.float64
+
+
+def check_device_tensor(x, precision, npts, name):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if x.dtype != _torch_dtype(precision) or not x.is_contiguous() or x.numel() != npts:
+        raise ValueError(f"{name} must be contiguous {_torch_dtype(precision)} with {npts} elements")
+
+
+def solve(spec, V0, precision=32, V_init=None, tau=None, stream=None, save_all=False,
+          dissipation=0, max_dt=0.0, tile_chunk=0, workspace=None, rk_order=None, cfl=None,
+          mode=None) -> SolveResult:
+    """One solve of a workloads.SolveSpec with a device V0 tensor."""
+    import torch
+    grid = Grid.from_spec(spec.grid)
+    npts = grid.npts
+    check_device_tensor(V0, precision, npts, "V0")
+    if V_init is not None:
+        check_device_tensor(V_init, precision, npts, "V_init")
+    tau = list(spec.tau if tau is None else tau)
+    opts = make_opts(precision, spec.rk_order if rk_order is None else rk_order,
+                     spec.cfl if cfl is None else cfl, spec.mode if mode is None else mode,
+                     dissipation, max_dt, 1 if save_all else 0, tile_chunk, _stream_handle(stream))
+    out = torch.empty_like(V0)
+    vall = torch.empty((len(tau),) + tuple(V0.shape), dtype=V0.dtype, device=V0.device) if save_all else None
+    st = odp_hj_solve(grid, spec.dyn, V0, V_init, tau, opts, workspace, out, vall)
+    return SolveResult(out, st.as_dict(), vall)
+
+
+def batch(specs, V0s, precision=32, stream=None, tile_chunk=0, dissipation=0, max_dt=0.0,
+          workspace=None, want_stats=True):
+    """odp_hj_batch over a list of SolveSpecs (common RK order / CFL / mode)."""
+    import torch
+    n = len(specs)
+    grids = [Grid.from_spec(s.grid) for s in specs]
+    outs = [torch.empty_like(v) for v in V0s]
+    descs = (odp_solve_desc * n)()
+    taus = []
+    for i, s in enumerate(specs):
+        check_device_tensor(V0s[i], precision, grids[i].npts, f"V0[{i}]")
+        t = _tau_array(s.tau)
+        taus.append(t)
+        descs[i].grid = grids[i].handle
+        descs[i].dyn = make_dynamics(s.dyn)
+        descs[i].V0_dev = V0s[i].data_ptr()
+        descs[i].tau = ctypes.cast(t, ctypes.POINTER(ctypes.c_double))
+        descs[i].ntau = len(s.tau)
+        descs[i].V_out_dev = outs[i].data_ptr()
+    s0 = specs[0]
+    opts = make_opts(precision, s0.rk_order, s0.cfl, s0.mode, dissipation, max_dt, 0, tile_chunk,
+                     _stream_handle(stream))
+    stats = (odp_solve_stats * n)()
+    rc = lib().odp_hj_batch(n, descs, ctypes.byref(opts), None if workspace is None else
+                            ctypes.c_void_p(workspace.data_ptr()),
+                            0 if workspace is None else workspace.numel() * workspace.element_size(),
+                            stats if want_stats else None)
+    _check(rc)
+    return outs, [stats[i].as_dict() for i in range(n)] if want_stats else None

@@ -1,0 +1,518 @@
+// gfx950 kernels of libodp: the time-dependent HJ level-set step.
+//
+// Method (paper: Algorithm 1 and the HJ variational inequality): per grid
+// point, one-sided differences along every axis, optimal bang-bang inputs
+// for the central costate, the Hamiltonian, Lax-Friedrichs dissipation, a
+// TVD Runge-Kutta stage and, for a tube, min with V0.  The Hamiltonian and
+// the dissipation are folded per axis onto the raw differences:
+//   drift axis d (f_d independent of the inputs, alpha_d >= |f_d|):
+//     f pbar + alpha (p+ - p-)/2 = dr (f + alpha)/(2dx) + dl (f - alpha)/(2dx)
+//   input axis d (box input of bound b, role sigma = +1 max / -1 min):
+//     sigma b |pbar| + alpha (p+ - p-)/2 = sigma b |dr + dl|/(2dx)
+//                                         + alpha (dr - dl)/(2dx)
+// with dl = W_i - W_{i-e_d}, dr = W_{i+e_d} - W_i.  The per-axis
+// coefficients depend only on the in-plane coordinates of a point (heading,
+// speed), so each thread computes them once in float64 and then marches
+// along axis 0, keeping the axis-0 neighbours in registers.
+//
+// Every floating-point contraction is written out (fma); the library is
+// built with -ffp-contract=off so that all launch forms (single solve,
+// batch, server tick) give the same bits for the same point.
+#include <hip/hip_runtime.h>
+
+#include "odp_dev.h"
+
+namespace odp {
+
+// ------------------------------------------------------------- helpers
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f) {
+    return (__umulhi(n, f.m) + n) >> f.s;
+}
+
+// Blocks are dealt round robin to the 8 XCDs; renumber them so that each
+// XCD works on one contiguous range of tiles (neighbouring tiles then share
+// that XCD's L2).
+__device__ __forceinline__ uint32_t xcd_logical(uint32_t p, uint32_t nb) {
+    const uint32_t per = nb / kNumXcd, rem = nb % kNumXcd;
+    const uint32_t x = p % kNumXcd, k = p / kNumXcd;
+    return x * per + min(x, rem) + k;
+}
+
+template <typename T>
+__device__ __forceinline__ T ghost(T vb, T vin) {
+    // ghost node beyond a non-periodic edge: extrapolated away from zero
+    const T sg = T((vb > T(0)) - (vb < T(0)));
+    return vb + sg * fabs(vb - vin);
+}
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---------------------------------------------------------- dynamics
+
+// Axis kind per dynamics id: 0 drift, 1 box input.  Id 0 (single
+// integrator, ball input) is handled separately.
+__host__ __device__ constexpr int axis_kind(int dyn, int d) {
+    return dyn == 1 ? (d == 2 ? 1 : 0)
+         : dyn == 2 ? (d >= 2 ? 1 : 0)
+         : dyn == 3 ? ((d == 2 || d == 5) ? 1 : 0)
+         : 0;
+}
+
+__device__ __forceinline__ double tab_x(const SolveDesc &s, int d, int k) { return s.tabd[s.tab[d].off + k]; }
+__device__ __forceinline__ double tab_cos(const SolveDesc &s, int d, int k) { return s.tabd[s.tab[d].off + s.tab[d].n + k]; }
+__device__ __forceinline__ double tab_sin(const SolveDesc &s, int d, int k) { return s.tabd[s.tab[d].off + 2 * s.tab[d].n + k]; }
+
+// f_d for drift axes and the bound for input axes at multi-index ii.
+template <int DYN, int N>
+__device__ __forceinline__ void axis_terms(const SolveDesc &s, const int (&ii)[N], double (&f)[N]) {
+    if constexpr (DYN == 1) {          // x' = v cos th, y' = v sin th, th' = w
+        f[0] = s.p[0] * tab_cos(s, 2, ii[2]);
+        f[1] = s.p[0] * tab_sin(s, 2, ii[2]);
+        f[2] = s.p[1];
+    } else if constexpr (DYN == 2) {   // x' = v cos th, y' = v sin th, v' = a, th' = w
+        const double v = tab_x(s, 2, ii[2]);
+        f[0] = v * tab_cos(s, 3, ii[3]);
+        f[1] = v * tab_sin(s, 3, ii[3]);
+        f[2] = s.p[0];
+        f[3] = s.p[1];
+    } else if constexpr (DYN == 3) {   // evader (u on th_e), pursuer (d on th_p)
+        f[0] = s.p[0] * tab_cos(s, 2, ii[2]);
+        f[1] = s.p[0] * tab_sin(s, 2, ii[2]);
+        f[2] = s.p[1];
+        f[3] = s.p[2] * tab_cos(s, 5, ii[5]);
+        f[4] = s.p[2] * tab_sin(s, 5, ii[5]);
+        f[5] = s.p[3];
+    } else {                           // z' = c + u: drift c_d
+        for (int d = 0; d < N; ++d) f[d] = s.p[1 + d];
+    }
+}
+
+// alpha_d(z): the largest |f_d| over the admissible inputs.
+template <int DYN, int N>
+__device__ __forceinline__ void alpha_point(const SolveDesc &s, const int (&ii)[N], double (&a)[N]) {
+    double f[N];
+    axis_terms<DYN, N>(s, ii, f);
+    if constexpr (DYN == 0) {
+        for (int d = 0; d < N; ++d) a[d] = fabs(f[d]) + s.p[0];
+    } else {
+        for (int d = 0; d < N; ++d) a[d] = fabs(f[d]);  // input axes: the bound
+    }
+}
+
+// Per-point coefficients of the folded Hamiltonian + dissipation (float64,
+// rounded once to T).
+template <typename T, int DYN, int N>
+struct Coef {
+    T a[N], b[N];
+    T sig_umax;  // ball input only
+};
+
+template <typename T, int DYN, int N>
+__device__ __forceinline__ Coef<T, DYN, N> make_coef(const SolveDesc &s, const int (&ii)[N]) {
+    Coef<T, DYN, N> c;
+    double f[N], al[N];
+    axis_terms<DYN, N>(s, ii, f);
+    if (s.global_alpha) {
+        for (int d = 0; d < N; ++d) al[d] = s.amax[d];
+    } else {
+        alpha_point<DYN, N>(s, ii, al);
+    }
+    if constexpr (DYN == 0) {
+        for (int d = 0; d < N; ++d) {
+            c.a[d] = T(f[d] * s.inv2dx[d]);   // drift part of H, on (dr + dl)
+            c.b[d] = T(al[d] * s.inv2dx[d]);  // dissipation, on (dr - dl)
+        }
+        c.sig_umax = T((s.u_mode ? 1.0 : -1.0) * s.p[0]);
+    } else {
+        for (int d = 0; d < N; ++d) {
+            if (axis_kind(DYN, d) == 0) {
+                c.a[d] = T((f[d] + al[d]) * s.inv2dx[d]);
+                c.b[d] = T((f[d] - al[d]) * s.inv2dx[d]);
+            } else {
+                const int role = (DYN == 3 && d == 5) ? s.d_mode : s.u_mode;
+                c.a[d] = T((role ? 1.0 : -1.0) * f[d] * s.inv2dx[d]);
+                c.b[d] = T(al[d] * s.inv2dx[d]);
+            }
+        }
+        c.sig_umax = T(0);
+    }
+    return c;
+}
+
+// Folded Lax-Friedrichs Hamiltonian from the raw differences.
+template <typename T, int DYN, int N>
+__device__ __forceinline__ T hhat(const Coef<T, DYN, N> &c, const T (&dl)[N], const T (&dr)[N],
+                                  const SolveDesc &s) {
+    T L = T(0);
+    if constexpr (DYN == 0) {
+        T n2 = T(0);
+        for (int d = 0; d < N; ++d) {
+            const T sum = dr[d] + dl[d];
+            const T pb = sum * T(s.inv2dx[d]);
+            n2 = fma_t(pb, pb, n2);
+            L = fma_t(c.a[d], sum, L);
+            L = fma_t(c.b[d], dr[d] - dl[d], L);
+        }
+        L = fma_t(c.sig_umax, sqrt(n2), L);
+    } else {
+#pragma unroll
+        for (int d = 0; d < N; ++d) {
+            if (axis_kind(DYN, d) == 0) {
+                L = fma_t(c.a[d], dr[d], L);
+                L = fma_t(c.b[d], dl[d], L);
+            } else {
+                L = fma_t(c.a[d], fabs(dr[d] + dl[d]), L);
+                L = fma_t(c.b[d], dr[d] - dl[d], L);
+            }
+        }
+    }
+    return L;
+}
+
+// TVD Runge-Kutta stage weights: out = a V^n + b (W + dt L).
+__host__ __device__ inline void rk_weights(int order, int stage, double &a, double &b) {
+    a = 0.0;
+    b = 1.0;
+    if (order == 2 && stage == 1) { a = 0.5; b = 0.5; }
+    if (order == 3 && stage == 1) { a = 0.75; b = 0.25; }
+    if (order == 3 && stage == 2) { a = 1.0 / 3.0; b = 2.0 / 3.0; }
+}
+
+// Buffers of stage `stage` of step k: stencil input W, pointwise V^n, output.
+template <typename T>
+__device__ __forceinline__ void stage_buffers(const SolveDesc &s, int stage, int64_t k, const T *&W,
+                                              const T *&Vn, T *&out) {
+    T *A = (T *)s.A, *B = (T *)s.B, *C = (T *)s.C;
+    if (s.rk_order == 1) {
+        // ping-pong; parity chosen so that the last step writes A
+        const int64_t nst = *s.nsteps;
+        const bool in_a = ((k + nst) & 1) == 0;
+        W = in_a ? A : B;
+        out = in_a ? B : A;
+        Vn = W;
+    } else if (s.rk_order == 2) {
+        W = stage == 0 ? A : B;
+        Vn = A;
+        out = stage == 0 ? B : A;
+    } else {
+        W = stage == 0 ? A : (stage == 1 ? B : C);
+        Vn = A;
+        out = stage == 0 ? B : (stage == 1 ? C : A);
+    }
+}
+
+// ------------------------------------------------------------ kernels
+
+// Stage `stage` of step k (k = fixed_step, or the solve's own step counter
+// when step_from_desc != 0) for every listed solve.
+template <typename T, int DYN, int N>
+__global__ __launch_bounds__(kBlock) void stage_kernel(const SolveDesc *__restrict__ descs,
+                                                       const uint32_t *__restrict__ tile_solve,
+                                                       const uint32_t *__restrict__ tile_local,
+                                                       int stage, int step_from_desc,
+                                                       int64_t fixed_step) {
+    const uint32_t L = xcd_logical(blockIdx.x, gridDim.x);
+    const uint32_t si = tile_solve ? tile_solve[L] : 0u;
+    const uint32_t lt = tile_solve ? tile_local[L] : L;
+    const SolveDesc &s = descs[si];
+
+    const int64_t nsteps = *s.nsteps;
+    const int64_t k = step_from_desc ? *s.step : fixed_step;
+    if (k >= nsteps || stage >= s.rk_order) return;
+
+    const uint32_t cid = lt / s.nqb;
+    const uint32_t qb = lt - cid * s.nqb;
+    const uint32_t q = qb * kBlock + threadIdx.x;
+    const bool active = q < s.Q;
+    const uint32_t qq = active ? q : s.Q - 1;
+
+    // in-plane multi-index and neighbour offsets (fixed for the march)
+    int ii[N];
+    ii[0] = 0;
+    uint32_t rem = qq;
+#pragma unroll
+    for (int d = N - 1; d >= 1; --d) {
+        const uint32_t t = fdiv(rem, s.div[d]);
+        ii[d] = int(rem - t * uint32_t(s.n[d]));
+        rem = t;
+    }
+    int32_t offL[N], offR[N];
+    uint32_t gl = 0, gr = 0;
+#pragma unroll
+    for (int d = 1; d < N; ++d) {
+        const int32_t st = s.stride[d], nd = s.n[d];
+        const bool per = (s.periodic >> d) & 1u;
+        if (ii[d] > 0) offL[d] = -st;
+        else if (per) offL[d] = (nd - 1) * st;
+        else { offL[d] = 0; gl |= 1u << d; }
+        if (ii[d] < nd - 1) offR[d] = st;
+        else if (per) offR[d] = -(nd - 1) * st;
+        else { offR[d] = 0; gr |= 1u << d; }
+    }
+    const Coef<T, DYN, N> cf = make_coef<T, DYN, N>(s, ii);
+
+    const T *W, *Vn;
+    T *out;
+    stage_buffers<T>(s, stage, k, W, Vn, out);
+    const T *V0 = (const T *)s.V0;
+    double wa, wb;
+    rk_weights(s.rk_order, stage, wa, wb);
+    const T ra = T(wa), rb = T(wb);
+    const bool last = stage == s.rk_order - 1;
+    const bool clamp = last && s.brt;
+    const T dt = T(s.dt_sched[k]);
+
+    const int64_t s0 = s.s0;
+    const int n0 = s.n0;
+    const bool per0 = s.periodic & 1u;
+    const int i0b = int(cid) * s.chunk;
+    const int i0e = min(i0b + s.chunk, n0);
+
+    T wc = W[int64_t(i0b) * s0 + qq];
+    T wm = i0b > 0 ? W[int64_t(i0b - 1) * s0 + qq] : (per0 ? W[int64_t(n0 - 1) * s0 + qq] : wc);
+    int bad = 0;
+    for (int i0 = i0b; i0 < i0e; ++i0) {
+        const T *plane = W + int64_t(i0) * s0;
+        const T wp = i0 + 1 < n0 ? plane[s0 + qq] : (per0 ? W[qq] : wc);
+        T dl[N], dr[N];
+        {
+            T l0 = wm, r0 = wp;
+            if (!per0) {
+                if (i0 == 0) l0 = ghost(wc, wp);
+                if (i0 == n0 - 1) r0 = ghost(wc, wm);
+            }
+            dl[0] = wc - l0;
+            dr[0] = r0 - wc;
+        }
+#pragma unroll
+        for (int d = 1; d < N; ++d) {
+            T wl = plane[qq + offL[d]];
+            T wr = plane[qq + offR[d]];
+            if (gl & (1u << d)) wl = ghost(wc, wr);
+            if (gr & (1u << d)) wr = ghost(wc, wl);
+            dl[d] = wc - wl;
+            dr[d] = wr - wc;
+        }
+        const T Lh = hhat<T, DYN, N>(cf, dl, dr, s);
+        const int64_t o = int64_t(i0) * s0 + qq;
+        T v = fma_t(dt, Lh, wc);
+        if (wa != 0.0) v = fma_t(ra, Vn[o], rb * v);
+        if (clamp) {
+            const T z = V0[o];
+            if (z < v) v = z;
+        }
+        bad |= !isfinite(v);
+        if (active) out[o] = v;
+        wm = wc;
+        wc = wp;
+    }
+    if (bad && active) atomicOr(s.flags, 1);
+}
+
+// Zero alpha^max, the flags and the step counter of every listed solve.
+__global__ void init_kernel(const SolveDesc *__restrict__ descs, int nsolves) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsolves) return;
+    const SolveDesc &s = descs[i];
+    for (int d = 0; d < kMaxDim; ++d) s.amax[d] = 0.0;
+    *s.flags = 0;
+    *s.step = 0;
+    *s.nsteps = 0;
+}
+
+// alpha^max_d = max over every grid point of alpha_d(z): per-thread maxima,
+// wave64 butterfly, LDS across the waves, one atomic max per block and axis
+// (float64 bit patterns of non-negative numbers order like the numbers).
+template <int DYN, int N>
+__global__ __launch_bounds__(kBlock) void alpha_kernel(const SolveDesc *__restrict__ descs) {
+    const SolveDesc &s = descs[blockIdx.y];
+    double m[N];
+    for (int d = 0; d < N; ++d) m[d] = 0.0;
+    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < s.Q; q += gridDim.x * kBlock) {
+        int ii[N];
+        uint32_t rem = q;
+        for (int d = N - 1; d >= 1; --d) {
+            const uint32_t t = fdiv(rem, s.div[d]);
+            ii[d] = int(rem - t * uint32_t(s.n[d]));
+            rem = t;
+        }
+        for (int i0 = 0; i0 < s.n0; ++i0) {
+            ii[0] = i0;
+            double a[N];
+            alpha_point<DYN, N>(s, ii, a);
+            for (int d = 0; d < N; ++d) m[d] = fmax(m[d], a[d]);
+        }
+    }
+    __shared__ double red[kBlock / 64][kMaxDim];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int d = 0; d < N; ++d) {
+        double v = m[d];
+        for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+        if (lane == 0) red[wave][d] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        double v = red[0][threadIdx.x];
+        for (int w = 1; w < kBlock / 64; ++w) v = fmax(v, red[w][threadIdx.x]);
+        atomicMax((unsigned long long *)&s.amax[threadIdx.x], (unsigned long long)__double_as_longlong(v));
+    }
+}
+
+// The float64 CFL schedule of every listed solve (one thread per solve):
+// dt = cfl / sum_d alpha^max_d / dx_d, capped by max_dt, clipped so that the
+// time lands exactly on every tau[k].
+__global__ void sched_kernel(const SolveDesc *__restrict__ descs, int nsolves) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsolves) return;
+    const SolveDesc &s = descs[i];
+    double sum = 0.0;
+    for (int d = 0; d < s.ndim; ++d) sum += s.amax[d] / s.dx[d];
+    double dtc = s.cfl / sum;
+    if (s.max_dt > 0.0 && dtc > s.max_dt) dtc = s.max_dt;
+    double t = s.tau[0];
+    int k = 1;
+    int64_t n = 0;
+    while (k < s.ntau) {
+        if (n >= s.max_steps) { n = -1; break; }
+        double dt, tn;
+        int land = -1;
+        if (dtc >= s.tau[k] - t) {
+            dt = s.tau[k] - t;
+            tn = s.tau[k];
+            land = k;
+        } else {
+            dt = dtc;
+            tn = t + dt;
+        }
+        s.dt_sched[n] = dt;
+        s.land[n] = land;
+        ++n;
+        t = tn;
+        if (land >= 0) ++k;
+    }
+    *s.nsteps = n;
+}
+
+// Server ticks: advance the step counter of every unfinished solve.
+__global__ void advance_kernel(const SolveDesc *__restrict__ descs, int nsolves) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsolves) return;
+    const SolveDesc &s = descs[i];
+    if (*s.step < *s.nsteps) *s.step += 1;
+}
+
+// Copy V0 into the buffer the first step reads, for every listed solve.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void start_copy_kernel(const SolveDesc *__restrict__ descs,
+                                                            const uint32_t *__restrict__ tile_solve,
+                                                            const uint32_t *__restrict__ tile_local) {
+    const uint32_t L = xcd_logical(blockIdx.x, gridDim.x);
+    const uint32_t si = tile_solve ? tile_solve[L] : 0u;
+    const uint32_t lt = tile_solve ? tile_local[L] : L;
+    const SolveDesc &s = descs[si];
+    const uint32_t cid = lt / s.nqb;
+    const uint32_t q = (lt - cid * s.nqb) * kBlock + threadIdx.x;
+    if (q >= s.Q) return;
+    T *dst = (s.rk_order == 1 && ((*s.nsteps) & 1)) ? (T *)s.B : (T *)s.A;
+    const T *src = (const T *)s.V0;
+    const int i0b = int(cid) * s.chunk;
+    const int i0e = min(i0b + s.chunk, s.n0);
+    for (int i0 = i0b; i0 < i0e; ++i0) {
+        const int64_t o = int64_t(i0) * s.s0 + q;
+        dst[o] = src[o];
+    }
+}
+
+// --------------------------------------------------------- launchers
+
+template <typename T, int DYN, int N>
+static hipError_t launch_stage_t(const SolveDesc *d, const uint32_t *ts, const uint32_t *tl,
+                                 uint32_t nblocks, int stage, int from_desc, int64_t step,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL((stage_kernel<T, DYN, N>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl,
+                       stage, from_desc, step);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_stage_p(int dyn, int ndim, const SolveDesc *d, const uint32_t *ts,
+                                 const uint32_t *tl, uint32_t nb, int stage, int fd, int64_t step,
+                                 hipStream_t st) {
+    switch (dyn) {
+    case 1: return launch_stage_t<T, 1, 3>(d, ts, tl, nb, stage, fd, step, st);
+    case 2: return launch_stage_t<T, 2, 4>(d, ts, tl, nb, stage, fd, step, st);
+    case 3: return launch_stage_t<T, 3, 6>(d, ts, tl, nb, stage, fd, step, st);
+    case 0:
+        switch (ndim) {
+        case 1: return launch_stage_t<T, 0, 1>(d, ts, tl, nb, stage, fd, step, st);
+        case 2: return launch_stage_t<T, 0, 2>(d, ts, tl, nb, stage, fd, step, st);
+        case 3: return launch_stage_t<T, 0, 3>(d, ts, tl, nb, stage, fd, step, st);
+        case 4: return launch_stage_t<T, 0, 4>(d, ts, tl, nb, stage, fd, step, st);
+        case 5: return launch_stage_t<T, 0, 5>(d, ts, tl, nb, stage, fd, step, st);
+        case 6: return launch_stage_t<T, 0, 6>(d, ts, tl, nb, stage, fd, step, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_stage(int precision, int dyn, int ndim, const SolveDesc *d, const uint32_t *ts,
+                        const uint32_t *tl, uint32_t nblocks, int stage, int from_desc,
+                        int64_t step, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    if (precision == 32) return launch_stage_p<float>(dyn, ndim, d, ts, tl, nblocks, stage, from_desc, step, st);
+    return launch_stage_p<double>(dyn, ndim, d, ts, tl, nblocks, stage, from_desc, step, st);
+}
+
+template <int DYN, int N>
+static hipError_t launch_alpha_t(const SolveDesc *d, int nsolves, int bps, hipStream_t st) {
+    hipLaunchKernelGGL((alpha_kernel<DYN, N>), dim3(bps, nsolves), dim3(kBlock), 0, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_alpha(int dyn, int ndim, const SolveDesc *d, int nsolves, int blocks_per_solve,
+                        hipStream_t st) {
+    switch (dyn) {
+    case 1: return launch_alpha_t<1, 3>(d, nsolves, blocks_per_solve, st);
+    case 2: return launch_alpha_t<2, 4>(d, nsolves, blocks_per_solve, st);
+    case 3: return launch_alpha_t<3, 6>(d, nsolves, blocks_per_solve, st);
+    case 0:
+        switch (ndim) {
+        case 1: return launch_alpha_t<0, 1>(d, nsolves, blocks_per_solve, st);
+        case 2: return launch_alpha_t<0, 2>(d, nsolves, blocks_per_solve, st);
+        case 3: return launch_alpha_t<0, 3>(d, nsolves, blocks_per_solve, st);
+        case 4: return launch_alpha_t<0, 4>(d, nsolves, blocks_per_solve, st);
+        case 5: return launch_alpha_t<0, 5>(d, nsolves, blocks_per_solve, st);
+        case 6: return launch_alpha_t<0, 6>(d, nsolves, blocks_per_solve, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_init(const SolveDesc *d, int nsolves, hipStream_t st) {
+    hipLaunchKernelGGL(init_kernel, dim3((nsolves + 255) / 256), dim3(256), 0, st, d, nsolves);
+    return hipGetLastError();
+}
+
+hipError_t launch_sched(const SolveDesc *d, int nsolves, hipStream_t st) {
+    hipLaunchKernelGGL(sched_kernel, dim3((nsolves + 63) / 64), dim3(64), 0, st, d, nsolves);
+    return hipGetLastError();
+}
+
+hipError_t launch_start_copy(int precision, const SolveDesc *d, const uint32_t *ts,
+                             const uint32_t *tl, uint32_t nblocks, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    if (precision == 32)
+        hipLaunchKernelGGL(start_copy_kernel<float>, dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl);
+    else
+        hipLaunchKernelGGL(start_copy_kernel<double>, dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(const SolveDesc *d, int nsolves, hipStream_t st) {
+    hipLaunchKernelGGL(advance_kernel, dim3((nsolves + 255) / 256), dim3(256), 0, st, d, nsolves);
+    return hipGetLastError();
+}
+
+}  // namespace odp

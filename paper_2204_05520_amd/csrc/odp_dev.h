@@ -1,0 +1,81 @@
+// Shared host/device layout of libodp's solve descriptors.
+//
+// A solve is described once (SolveDesc, in device memory) and every stage
+// launch covers a list of solves: a single solve is a list of one, a batch
+// or a server tick is a list of many.  Blocks map to (solve, tile) through a
+// tile table; a tile is a run of `chunk` planes of axis 0 times 256
+// consecutive points of the hyperplane spanned by axes 1..ndim-1.
+#pragma once
+
+#include <stdint.h>
+
+namespace odp {
+
+constexpr int kMaxDim = 6;
+constexpr int kBlock = 256;          // threads per stage block (4 wave64s)
+constexpr int kNumXcd = 8;           // MI355X: 8 XCDs, blocks dealt round robin
+
+// n / d for n < 2^31 as (mulhi(n, m) + n) >> s (round-up magic number).
+struct FastDiv {
+    uint32_t d, m, s, pad_;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+    uint32_t s = 0;
+    while ((uint64_t(1) << s) < d) ++s;
+    uint64_t m = ((uint64_t(1) << 32) * ((uint64_t(1) << s) - d)) / d + 1;
+    return FastDiv{d, uint32_t(m), s, 0};
+}
+
+// Per-axis tables in float64: coordinate x_k, cos x_k, sin x_k.
+struct AxisTab {
+    int32_t off;  // first entry of this axis in the table buffer (x at off,
+                  // cos at off + n, sin at off + 2n)
+    int32_t n;
+};
+
+struct SolveDesc {
+    // ---- shape
+    int32_t ndim;
+    int32_t n0;              // nodes on axis 0 (the marched axis)
+    uint32_t Q;              // points per hyperplane of axes 1..ndim-1
+    uint32_t periodic;       // bit d set: axis d periodic
+    int64_t s0;              // stride of axis 0 (= Q)
+    int64_t npts;
+    int32_t n[kMaxDim];      // nodes per axis
+    int32_t stride[kMaxDim]; // strides of axes 1..ndim-1 (entry 0 unused)
+    FastDiv div[kMaxDim];    // divisors n[d] for the in-plane decomposition
+    double inv2dx[kMaxDim];  // 1 / (2 dx_d)
+    double dx[kMaxDim];
+    AxisTab tab[kMaxDim];
+    // ---- tiling
+    int32_t chunk;           // planes of axis 0 per tile
+    uint32_t nqb;            // 256-point blocks per hyperplane
+    uint32_t tiles;          // nqb * ceil(n0 / chunk)
+    int32_t rk_order;
+    // ---- dynamics
+    int32_t dyn;
+    int32_t u_mode, d_mode;
+    int32_t global_alpha;
+    double p[16];
+    // ---- device memory (element type per launch)
+    void *A;                 // V^n (caller's V_out)
+    void *B;                 // stage 1 output / ping-pong partner
+    void *C;                 // stage 2 output (RK3)
+    const void *V0;
+    const double *tabd;      // axis tables (float64)
+    double *amax;            // alpha^max per axis (float64 bits, atomically maxed)
+    double *dt_sched;        // dt of every step
+    int32_t *land;           // tau index reached by each step, -1 if none
+    int64_t *nsteps;         // device: step count of the schedule
+    int64_t *step;           // device: next step to take (server ticks)
+    int32_t *flags;          // bit 0: non-finite value produced
+    int32_t brt;
+    int32_t ntau;
+    const double *tau;       // output times (device copy)
+    double cfl;
+    double max_dt;
+    int64_t max_steps;       // capacity of dt_sched / land
+};
+
+}  // namespace odp

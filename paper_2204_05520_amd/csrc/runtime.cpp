@@ -1,0 +1,298 @@
+// Host side of libodp: argument checks, grids, per-solve device images, the
+// single-solve driver and the batched driver.
+#include "runtime.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+namespace odp {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return ODP_OK;
+    return set_error(ODP_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static int dyn_ndim(int id) {
+    switch (id) {
+    case ODP_DYN_DUBINS3D: return 3;
+    case ODP_DYN_DYNCAR4D: return 4;
+    case ODP_DYN_TWODUBINS6D: return 6;
+    default: return 0;
+    }
+}
+
+int validate_dyn(const odp_grid *g, const odp_dynamics *dyn) {
+    if (!dyn) return set_error(ODP_EINVAL, "dynamics is NULL");
+    if (dyn->id < 0 || dyn->id > 3) return set_error(ODP_EINVAL, "unknown dynamics id");
+    if (dyn->id != ODP_DYN_SINGLE_INTEGRATOR && dyn_ndim(dyn->id) != g->ndim)
+        return set_error(ODP_EINVAL, "dynamics dimension does not match the grid");
+    if ((dyn->u_mode != 0 && dyn->u_mode != 1) || (dyn->d_mode != 0 && dyn->d_mode != 1))
+        return set_error(ODP_EINVAL, "u_mode / d_mode must be 0 or 1");
+    for (int k = 0; k < 16; ++k)
+        if (!std::isfinite(dyn->p[k])) return set_error(ODP_EINVAL, "non-finite dynamics parameter");
+    switch (dyn->id) {
+    case ODP_DYN_SINGLE_INTEGRATOR:
+        if (dyn->p[0] < 0) return set_error(ODP_EINVAL, "u_max must be >= 0");
+        break;
+    case ODP_DYN_DUBINS3D:
+        if (dyn->p[1] < 0) return set_error(ODP_EINVAL, "w_max must be >= 0");
+        if (!g->periodic[2]) return set_error(ODP_EINVAL, "the heading axis must be periodic");
+        break;
+    case ODP_DYN_DYNCAR4D:
+        if (dyn->p[0] < 0 || dyn->p[1] < 0) return set_error(ODP_EINVAL, "input bounds must be >= 0");
+        if (!g->periodic[3]) return set_error(ODP_EINVAL, "the heading axis must be periodic");
+        break;
+    case ODP_DYN_TWODUBINS6D:
+        if (dyn->p[1] < 0 || dyn->p[3] < 0) return set_error(ODP_EINVAL, "input bounds must be >= 0");
+        if (!g->periodic[2] || !g->periodic[5])
+            return set_error(ODP_EINVAL, "the heading axes must be periodic");
+        break;
+    }
+    return ODP_OK;
+}
+
+int validate_opts(const odp_solve_opts *o) {
+    if (!o) return set_error(ODP_EINVAL, "opts is NULL");
+    if (o->precision != 32 && o->precision != 64) return set_error(ODP_EINVAL, "precision must be 32 or 64");
+    if (o->rk_order < 1 || o->rk_order > 3) return set_error(ODP_EINVAL, "rk_order must be 1, 2 or 3");
+    if (!(o->cfl > 0.0 && o->cfl <= 1.0)) return set_error(ODP_EINVAL, "cfl must be in (0, 1]");
+    if (o->mode != ODP_BRS && o->mode != ODP_BRT) return set_error(ODP_EINVAL, "mode must be BRS or BRT");
+    if (o->dissipation != 0 && o->dissipation != 1) return set_error(ODP_EINVAL, "dissipation must be 0 or 1");
+    if (!(o->max_dt >= 0.0) || !std::isfinite(o->max_dt)) return set_error(ODP_EINVAL, "max_dt must be >= 0");
+    if (o->save_all != 0 && o->save_all != 1) return set_error(ODP_EINVAL, "save_all must be 0 or 1");
+    if (o->tile_chunk < 0) return set_error(ODP_EINVAL, "tile_chunk must be >= 0");
+    return ODP_OK;
+}
+
+int validate_tau(const double *tau, int ntau) {
+    if (!tau || ntau < 2) return set_error(ODP_EINVAL, "tau needs at least two times");
+    if (!(tau[0] >= 0.0) || !std::isfinite(tau[0])) return set_error(ODP_EINVAL, "tau[0] must be >= 0");
+    for (int k = 1; k < ntau; ++k)
+        if (!(tau[k] > tau[k - 1]) || !std::isfinite(tau[k]))
+            return set_error(ODP_EINVAL, "tau must be finite and strictly increasing");
+    return ODP_OK;
+}
+
+// Upper bound of max_i alpha_d(z_i) from the parameters and the domain
+// (sizes the dt schedule; the schedule itself uses the device reduction).
+static void alpha_bound(const odp_grid *g, const odp_dynamics *dyn, double *ab) {
+    for (int d = 0; d < kMaxDim; ++d) ab[d] = 0.0;
+    const double *p = dyn->p;
+    switch (dyn->id) {
+    case ODP_DYN_SINGLE_INTEGRATOR:
+        for (int d = 0; d < g->ndim; ++d) ab[d] = std::fabs(p[1 + d]) + p[0];
+        break;
+    case ODP_DYN_DUBINS3D:
+        ab[0] = ab[1] = std::fabs(p[0]);
+        ab[2] = p[1];
+        break;
+    case ODP_DYN_DYNCAR4D: {
+        const double vm = std::max(std::fabs(g->lo[2]), std::fabs(g->hi[2]));
+        ab[0] = ab[1] = vm;
+        ab[2] = p[0];
+        ab[3] = p[1];
+        break;
+    }
+    case ODP_DYN_TWODUBINS6D:
+        ab[0] = ab[1] = std::fabs(p[0]);
+        ab[2] = p[1];
+        ab[3] = ab[4] = std::fabs(p[2]);
+        ab[5] = p[3];
+        break;
+    }
+}
+
+SolveLayout solve_layout(const odp_grid *g, int precision, int rk_order, int ntau, double tau_span,
+                         const odp_dynamics *dyn, double cfl, double max_dt) {
+    SolveLayout L{};
+    double ab[kMaxDim];
+    alpha_bound(g, dyn, ab);
+    double s = 0.0;
+    for (int d = 0; d < g->ndim; ++d) s += ab[d] / g->dx[d];
+    double dt_lo = s > 0.0 ? cfl / s : INFINITY;
+    if (max_dt > 0.0) dt_lo = std::min(dt_lo, max_dt);
+    double est = std::isfinite(dt_lo) ? std::ceil(tau_span / dt_lo) : 0.0;
+    // landing steps and a rounding slack per output interval
+    L.max_steps = int64_t(std::min(est, 1e9)) + 2 * int64_t(ntau) + 8;
+    L.tab_entries = 0;
+    for (int d = 0; d < g->ndim; ++d) L.tab_entries += 3 * int(g->n[d]);
+    const size_t b = precision == 32 ? 4 : 8;
+    const size_t arr = align256(size_t(g->npts) * b);
+    size_t off = 0;
+    L.desc = off; off += align256(sizeof(SolveDesc));
+    L.state = off; off += align256(kMaxDim * 8 + 3 * 8 + 8);
+    L.tab = off; off += align256(size_t(L.tab_entries) * 8);
+    L.tau = off; off += align256(size_t(ntau) * 8);
+    L.head = off;
+    L.sched = off; off += align256(size_t(L.max_steps) * 8);
+    L.land = off; off += align256(size_t(L.max_steps) * 4);
+    L.B = off; off += arr;
+    L.C = off; off += rk_order == 3 ? arr : 0;
+    L.total = off;
+    return L;
+}
+
+int default_chunk(const odp_grid *g) {
+    const int64_t Q = g->npts / g->n[0];
+    const int64_t nqb = (Q + kBlock - 1) / kBlock;
+    int64_t c = (g->n[0] * nqb) / 8192;
+    return int(std::max<int64_t>(1, std::min<int64_t>(c, 8)));
+}
+
+uint32_t solve_tiles(const odp_grid *g, int chunk) {
+    const int64_t Q = g->npts / g->n[0];
+    const int64_t nqb = (Q + kBlock - 1) / kBlock;
+    return uint32_t(nqb * ((g->n[0] + chunk - 1) / chunk));
+}
+
+double alg_bytes_per_step(int precision, int rk_order, int brt, int64_t npts) {
+    // each stage reads its stencil input once and writes its output once;
+    // stages after the first also read V^n; the tube clamp reads V0
+    const double b = precision == 32 ? 4.0 : 8.0;
+    double per = 2.0 * rk_order + (rk_order - 1) + (brt ? 1 : 0);
+    return per * b * double(npts);
+}
+
+void build_solve_image(std::vector<unsigned char> &img, const SolveLayout &L, unsigned char *base,
+                       const odp_grid *g, const odp_dynamics *dyn, const odp_solve_opts *o,
+                       const double *tau, int ntau, const void *V0, void *A, int chunk) {
+    img.assign(L.head, 0);
+    SolveDesc s;
+    std::memset(&s, 0, sizeof(s));
+    s.ndim = g->ndim;
+    s.n0 = int32_t(g->n[0]);
+    s.Q = uint32_t(g->npts / g->n[0]);
+    s.s0 = int64_t(s.Q);
+    s.npts = g->npts;
+    s.periodic = 0;
+    int64_t st = 1;
+    for (int d = g->ndim - 1; d >= 0; --d) {
+        s.n[d] = int32_t(g->n[d]);
+        s.stride[d] = d > 0 ? int32_t(st) : 0;
+        s.div[d] = make_fastdiv(uint32_t(g->n[d]));
+        s.dx[d] = g->dx[d];
+        s.inv2dx[d] = 1.0 / (2.0 * g->dx[d]);
+        if (g->periodic[d]) s.periodic |= 1u << d;
+        st *= g->n[d];
+    }
+    s.chunk = chunk;
+    s.nqb = uint32_t((s.Q + kBlock - 1) / kBlock);
+    s.tiles = solve_tiles(g, chunk);
+    s.rk_order = o->rk_order;
+    s.dyn = dyn->id;
+    s.u_mode = dyn->u_mode;
+    s.d_mode = dyn->d_mode;
+    s.global_alpha = o->dissipation;
+    for (int k = 0; k < 16; ++k) s.p[k] = dyn->p[k];
+    s.A = A;
+    s.B = base + L.B;
+    s.C = o->rk_order == 3 ? base + L.C : nullptr;
+    s.V0 = V0;
+    s.tabd = (const double *)(base + L.tab);
+    unsigned char *state = base + L.state;
+    s.amax = (double *)state;
+    s.nsteps = (int64_t *)(state + kMaxDim * 8);
+    s.step = (int64_t *)(state + kMaxDim * 8 + 8);
+    s.flags = (int32_t *)(state + kMaxDim * 8 + 16);
+    s.dt_sched = (double *)(base + L.sched);
+    s.land = (int32_t *)(base + L.land);
+    s.brt = o->mode == ODP_BRT;
+    s.ntau = ntau;
+    s.tau = (const double *)(base + L.tau);
+    s.cfl = o->cfl;
+    s.max_dt = o->max_dt;
+    s.max_steps = L.max_steps;
+    // axis tables: coordinate, cos, sin (float64, computed once on the host)
+    double *tab = (double *)(img.data() + L.tab);
+    int off = 0;
+    for (int d = 0; d < g->ndim; ++d) {
+        const int n = int(g->n[d]);
+        s.tab[d].off = off;
+        s.tab[d].n = n;
+        for (int k = 0; k < n; ++k) {
+            const double x = g->lo[d] + double(k) * g->dx[d];
+            tab[off + k] = x;
+            tab[off + n + k] = std::cos(x);
+            tab[off + 2 * n + k] = std::sin(x);
+        }
+        off += 3 * n;
+    }
+    std::memcpy(img.data() + L.desc, &s, sizeof(s));
+    std::memcpy(img.data() + L.tau, tau, size_t(ntau) * 8);
+}
+
+}  // namespace odp
+
+using namespace odp;
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char *odp_strerror(int code) {
+    switch (code) {
+    case ODP_OK: return "ok";
+    case ODP_PENDING: return "pending";
+    case ODP_EINVAL: return "invalid argument";
+    case ODP_ENOMEM: return "out of memory or workspace too small";
+    case ODP_EHIP: return "HIP runtime error";
+    case ODP_EUNSUPPORTED: return "unsupported combination";
+    case ODP_EAGAIN: return "queue full, try again";
+    case ODP_ENONFINITE: return "non-finite value in the value function";
+    case ODP_ECANCELED: return "request cancelled";
+    default: return "unknown error code";
+    }
+}
+
+const char *odp_last_error(void) { return g_last_error.c_str(); }
+
+int odp_grid_create(int ndim, const int64_t *n, const double *lo, const double *hi,
+                    const uint8_t *periodic, odp_grid **out) {
+    if (!out) return set_error(ODP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (ndim < 1 || ndim > kMaxDim) return set_error(ODP_EINVAL, "ndim must be in [1, 6]");
+    if (!n || !lo || !hi) return set_error(ODP_EINVAL, "n, lo and hi are required");
+    std::unique_ptr<odp_grid> g(new odp_grid());
+    g->ndim = ndim;
+    g->npts = 1;
+    for (int d = 0; d < ndim; ++d) {
+        if (n[d] < 3 || n[d] > (int64_t(1) << 30))
+            return set_error(ODP_EINVAL, "every axis needs between 3 and 2^30 nodes");
+        if (!std::isfinite(lo[d]) || !std::isfinite(hi[d]) || !(hi[d] > lo[d]))
+            return set_error(ODP_EINVAL, "bounds must be finite with lo < hi");
+        g->n[d] = n[d];
+        g->lo[d] = lo[d];
+        g->hi[d] = hi[d];
+        g->periodic[d] = periodic && periodic[d] ? 1 : 0;
+        g->dx[d] = g->periodic[d] ? (hi[d] - lo[d]) / double(n[d]) : (hi[d] - lo[d]) / double(n[d] - 1);
+        if (g->npts > (int64_t(1) << 40) / n[d]) return set_error(ODP_EINVAL, "grid too large");
+        g->npts *= n[d];
+    }
+    if (g->npts / g->n[0] >= (int64_t(1) << 31))
+        return set_error(ODP_EINVAL, "a hyperplane of axes 1..ndim-1 must hold < 2^31 points");
+    *out = g.release();
+    return ODP_OK;
+}
+
+void odp_grid_destroy(odp_grid *grid) { delete grid; }
+
+int64_t odp_grid_points(const odp_grid *grid) { return grid ? grid->npts : 0; }
+
+}  // extern "C"

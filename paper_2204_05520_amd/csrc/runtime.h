@@ -1,0 +1,63 @@
+// Internal host-side interfaces of libodp (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/odp.h"
+#include "odp_dev.h"
+
+struct odp_grid {
+    int ndim;
+    int64_t n[odp::kMaxDim];
+    double lo[odp::kMaxDim], hi[odp::kMaxDim];
+    int periodic[odp::kMaxDim];
+    double dx[odp::kMaxDim];
+    int64_t npts;
+};
+
+namespace odp {
+
+// kernels.hip
+hipError_t launch_stage(int precision, int dyn, int ndim, const SolveDesc *d, const uint32_t *ts,
+                        const uint32_t *tl, uint32_t nblocks, int stage, int from_desc,
+                        int64_t step, hipStream_t st);
+hipError_t launch_alpha(int dyn, int ndim, const SolveDesc *d, int nsolves, int blocks_per_solve,
+                        hipStream_t st);
+hipError_t launch_init(const SolveDesc *d, int nsolves, hipStream_t st);
+hipError_t launch_sched(const SolveDesc *d, int nsolves, hipStream_t st);
+hipError_t launch_advance(const SolveDesc *d, int nsolves, hipStream_t st);
+hipError_t launch_start_copy(int precision, const SolveDesc *d, const uint32_t *ts,
+                             const uint32_t *tl, uint32_t nblocks, hipStream_t st);
+
+// runtime.cpp
+int set_error(int code, const std::string &msg);
+int check_hip(hipError_t e, const char *what);
+int validate_dyn(const odp_grid *g, const odp_dynamics *dyn);
+int validate_opts(const odp_solve_opts *o);
+int validate_tau(const double *tau, int ntau);
+
+// Per-solve device memory layout inside a workspace (byte offsets from the
+// solve's base, 256-byte aligned regions).
+struct SolveLayout {
+    size_t desc, state, tab, tau, sched, land, B, C, total;
+    size_t head;          // bytes of [desc, tau] uploaded from the host
+    int64_t max_steps;
+    int tab_entries;
+};
+SolveLayout solve_layout(const odp_grid *g, int precision, int rk_order, int ntau,
+                         double tau_span, const odp_dynamics *dyn, double cfl, double max_dt);
+
+// Fill the host image [desc .. tau] of a solve placed at device address
+// base; V0/A are caller buffers.
+void build_solve_image(std::vector<unsigned char> &img, const SolveLayout &L, unsigned char *base,
+                       const odp_grid *g, const odp_dynamics *dyn, const odp_solve_opts *o,
+                       const double *tau, int ntau, const void *V0, void *A, int chunk);
+
+int default_chunk(const odp_grid *g);
+uint32_t solve_tiles(const odp_grid *g, int chunk);
+double alg_bytes_per_step(int precision, int rk_order, int brt, int64_t npts);
+
+}  // namespace odp

@@ -1,0 +1,148 @@
+"""GPU parity: the HIP path (through the C ABI) against the float64 oracle.
+
+Bars: float64 GPU within 1e-9 * S of the oracle, float32 GPU within 1e-4 * S
+(S = largest non-periodic extent), the same step count, element by element
+on the whole grid.  Sizes span several 256-point tiles with ragged tails and
+axis-0 chunks that do not divide the axis.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2204_05520_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {64: 1e-9, 32: 1e-4}
+
+
+@pytest.fixture(scope="module")
+def odp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2204_05520_amd as odp
+    odp.lib()
+    return odp
+
+
+def _dtype(prec):
+    import torch
+    return torch.float64 if prec == 64 else torch.float32
+
+
+def gpu_solve(odp, spec, V0, prec, **kw):
+    import torch
+    print(f"[gpu] {spec.name} fp{prec} n={spec.grid.n} rk={spec.rk_order} {kw}", flush=True)
+    dev = torch.device("cuda:0")
+    t = torch.tensor(V0, dtype=_dtype(prec), device=dev)
+    vi = kw.pop("V_init", None)
+    if vi is not None:
+        vi = torch.tensor(vi, dtype=_dtype(prec), device=dev)
+    res = odp.solve(spec, t, precision=prec, V_init=vi, **kw)
+    torch.cuda.synchronize()
+    return res
+
+
+def compare(odp, oracle_mod, spec, prec, V0=None, oracle_kw=None, **kw):
+    V0 = W.make_v0(spec) if V0 is None else V0
+    okw = dict(oracle_kw or {})
+    ref = oracle_mod.solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=spec.rk_order,
+                           cfl=spec.cfl, brt=spec.mode == W.BRT, **okw)
+    res = gpu_solve(odp, spec, V0, prec, **kw)
+    got = res.V.double().cpu().numpy()
+    S = spec.grid.domain_scale()
+    err = float(np.abs(got - ref.V).max())
+    loc = np.unravel_index(int(np.abs(got - ref.V).argmax()), got.shape)
+    print(f"    steps gpu={res.stats['steps']} oracle={ref.steps} max|err|={err:.3e} at {loc} "
+          f"(/S = {err / S:.3e}, limit {TOL[prec]:.0e})", flush=True)
+    assert res.stats["steps"] == ref.steps
+    assert math.isclose(res.stats["dt_max"], ref.dt_max, rel_tol=0, abs_tol=0)
+    assert err <= TOL[prec] * S
+    return res, ref
+
+
+CASES = [
+    ("dubins3d_60x60x36", lambda: W.config_dubins3d(), (64, 32)),
+    ("dubins3d_ragged", lambda: W.config_dubins3d(n=(37, 29, 22), T=1.3), (64, 32)),
+    ("dyncar4d_22x21x19x24_rk3", lambda: W.config_dyncar4d(n=[22, 21, 19, 24], T=0.6), (64, 32)),
+    ("game6d_9x8x8x7x9x8_rk2", lambda: W.config_game6d(n=[9, 8, 8, 7, 9, 8], T=0.5), (64, 32)),
+]
+
+
+@pytest.mark.parametrize("name,mk,precs", CASES, ids=[c[0] for c in CASES])
+def test_parity_workloads(odp, oracle_mod, name, mk, precs):
+    for prec in precs:
+        compare(odp, oracle_mod, mk(), prec)
+
+
+@pytest.mark.parametrize("ndim,n,drift,role,brt,periodic,rk", [
+    (1, 300, [0.6], W.MINIMISE, True, False, 1),
+    (1, 257, [-0.3], W.MAXIMISE, False, True, 3),
+    (2, 61, [0.5, -0.3], W.MINIMISE, True, False, 2),
+    (3, 23, [0.2, -0.3, 0.4], W.MAXIMISE, False, False, 3),
+    (4, 11, [0.1, 0.0, -0.2, 0.3], W.MINIMISE, True, True, 1),
+    (5, 7, [0.0] * 5, W.MAXIMISE, True, False, 2),
+    (6, 6, [0.1] * 6, W.MINIMISE, True, False, 1),
+])
+def test_parity_single_integrator(odp, oracle_mod, ndim, n, drift, role, brt, periodic, rk):
+    spec = W.single_integrator(ndim, n, 1.0, drift, role, 0.4, brt=brt, periodic=periodic,
+                               rk_order=rk)
+    for prec in (64, 32):
+        compare(odp, oracle_mod, spec, prec)
+
+
+def test_parity_global_alpha(odp, oracle_mod):
+    spec = W.config_dyncar4d(n=[15, 14, 9, 16], T=0.4)
+    for prec in (64, 32):
+        compare(odp, oracle_mod, spec, prec, oracle_kw={"global_alpha": True}, dissipation=1)
+
+
+def test_parity_tile_chunks_bitwise(odp):
+    """Every chunking of axis 0 gives the same bits (the arithmetic per point
+    does not depend on the launch shape)."""
+    import torch
+    spec = W.config_dyncar4d(n=[13, 17, 9, 20], T=0.2)
+    V0 = W.make_v0(spec)
+    for prec in (64, 32):
+        outs = [gpu_solve(odp, spec, V0, prec, tile_chunk=c).V.cpu() for c in (1, 3, 5, 13)]
+        same = [bool(torch.equal(o, outs[0])) for o in outs[1:]]
+        assert all(same), same
+
+
+def test_parity_save_all_and_restart(odp, oracle_mod):
+    import torch
+    spec = W.config_dubins3d(n=(26, 24, 18), T=1.0)
+    V0 = W.make_v0(spec)
+    tau = [0.0, 0.23, 0.6, 1.0]
+    ref = oracle_mod.solve(spec.grid, spec.dyn, V0, tau, rk_order=1, cfl=0.8, brt=True,
+                           save_all=True)
+    res = gpu_solve(odp, spec, V0, 64, tau=tau, save_all=True)
+    allv = res.V_all.cpu().numpy()
+    assert np.abs(allv - ref.V_all).max() <= 1e-9 * 8
+    assert res.stats["steps"] == ref.steps
+    # restart from tau = 0.23 equals the single call, bit for bit
+    first = gpu_solve(odp, spec, V0, 64, tau=[0.0, 0.23])
+    second = gpu_solve(odp, spec, V0, 64, tau=[0.23, 0.6, 1.0], V_init=first.V.cpu().numpy())
+    same_final = torch.equal(second.V.cpu(), res.V.cpu())
+    same_mid = torch.equal(first.V.cpu(), res.V_all[1].cpu())
+    assert same_final and same_mid
+
+
+def test_parity_max_dt_and_rk_orders(odp, oracle_mod):
+    for rk in (1, 2, 3):
+        spec = W.config_dubins3d(n=(20, 19, 12), T=0.35)
+        spec.rk_order = rk
+        compare(odp, oracle_mod, spec, 64, oracle_kw={"max_dt": 0.013}, max_dt=0.013)
+
+
+def test_nonfinite_reported(odp):
+    import torch
+    spec = W.config_dubins3d(n=(12, 11, 8), T=0.2)
+    V0 = W.make_v0(spec)
+    V0[3, 4, 5] = np.nan
+    t = torch.tensor(V0, dtype=torch.float32, device="cuda:0")
+    with pytest.raises(odp.OdpError) as ei:
+        odp.solve(spec, t, precision=32)
+    assert ei.value.code == odp.ODP_ENONFINITE
