@@ -59,8 +59,14 @@ def _load():
         lib.oracle_step_at.argtypes = [
             ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
             _dp, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_long, _lp, _dp]
+        lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_num_threads.argtypes = []
         _lib = lib
     return _lib
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
 
 
 class use_library:

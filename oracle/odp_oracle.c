@@ -46,6 +46,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OG_MAXD 6
 
@@ -499,4 +502,14 @@ int oracle_step_at(int ndim, const long *n, const double *lo, const double *hi,
         out[j] = v;
     }
     return 0;
+}
+
+/* Threads the OpenMP loops above use (1 without OpenMP). */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

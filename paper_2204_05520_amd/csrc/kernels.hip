@@ -106,7 +106,8 @@ __device__ __forceinline__ void alpha_point(const SolveDesc &s, const int (&ii)[
 template <typename T, int DYN, int N>
 struct Coef {
     T a[N], b[N];
-    T sig_umax;  // ball input only
+    T h[DYN == 0 ? N : 1];  // ball input: 1 / (2 dx_d) for the costate norm
+    T sig_umax;             // ball input: sigma u_max
 };
 
 template <typename T, int DYN, int N>
@@ -123,6 +124,7 @@ __device__ __forceinline__ Coef<T, DYN, N> make_coef(const SolveDesc &s, const i
         for (int d = 0; d < N; ++d) {
             c.a[d] = T(f[d] * s.inv2dx[d]);   // drift part of H, on (dr + dl)
             c.b[d] = T(al[d] * s.inv2dx[d]);  // dissipation, on (dr - dl)
+            c.h[d] = T(s.inv2dx[d]);
         }
         c.sig_umax = T((s.u_mode ? 1.0 : -1.0) * s.p[0]);
     } else {
@@ -136,39 +138,43 @@ __device__ __forceinline__ Coef<T, DYN, N> make_coef(const SolveDesc &s, const i
                 c.b[d] = T(al[d] * s.inv2dx[d]);
             }
         }
+        c.h[0] = T(0);
         c.sig_umax = T(0);
     }
     return c;
 }
 
-// Folded Lax-Friedrichs Hamiltonian from the raw differences.
+// Running sum of the folded Lax-Friedrichs Hamiltonian.  Axes are always
+// added in the order 0, 1, ..., N-1, whatever the kernel, so every launch
+// form rounds identically.
+template <typename T>
+struct Acc {
+    T L, n2;
+};
+
 template <typename T, int DYN, int N>
-__device__ __forceinline__ T hhat(const Coef<T, DYN, N> &c, const T (&dl)[N], const T (&dr)[N],
-                                  const SolveDesc &s) {
-    T L = T(0);
+__device__ __forceinline__ void acc_axis(const Coef<T, DYN, N> &c, int d, T dl, T dr, Acc<T> &a) {
     if constexpr (DYN == 0) {
-        T n2 = T(0);
-        for (int d = 0; d < N; ++d) {
-            const T sum = dr[d] + dl[d];
-            const T pb = sum * T(s.inv2dx[d]);
-            n2 = fma_t(pb, pb, n2);
-            L = fma_t(c.a[d], sum, L);
-            L = fma_t(c.b[d], dr[d] - dl[d], L);
-        }
-        L = fma_t(c.sig_umax, sqrt(n2), L);
+        const T sum = dr + dl;
+        const T pb = sum * c.h[d];
+        a.n2 = fma_t(pb, pb, a.n2);
+        a.L = fma_t(c.a[d], sum, a.L);
+        a.L = fma_t(c.b[d], dr - dl, a.L);
     } else {
-#pragma unroll
-        for (int d = 0; d < N; ++d) {
-            if (axis_kind(DYN, d) == 0) {
-                L = fma_t(c.a[d], dr[d], L);
-                L = fma_t(c.b[d], dl[d], L);
-            } else {
-                L = fma_t(c.a[d], fabs(dr[d] + dl[d]), L);
-                L = fma_t(c.b[d], dr[d] - dl[d], L);
-            }
+        if (axis_kind(DYN, d) == 0) {
+            a.L = fma_t(c.a[d], dr, a.L);
+            a.L = fma_t(c.b[d], dl, a.L);
+        } else {
+            a.L = fma_t(c.a[d], fabs(dr + dl), a.L);
+            a.L = fma_t(c.b[d], dr - dl, a.L);
         }
     }
-    return L;
+}
+
+template <typename T, int DYN, int N>
+__device__ __forceinline__ T acc_finish(const Coef<T, DYN, N> &c, const Acc<T> &a) {
+    if constexpr (DYN == 0) return fma_t(c.sig_umax, sqrt(a.n2), a.L);
+    return a.L;
 }
 
 // TVD Runge-Kutta stage weights: out = a V^n + b (W + dt L).
@@ -276,15 +282,14 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const SolveDesc *__restri
     for (int i0 = i0b; i0 < i0e; ++i0) {
         const T *plane = W + int64_t(i0) * s0;
         const T wp = i0 + 1 < n0 ? plane[s0 + qq] : (per0 ? W[qq] : wc);
-        T dl[N], dr[N];
+        Acc<T> acc{T(0), T(0)};
         {
             T l0 = wm, r0 = wp;
             if (!per0) {
                 if (i0 == 0) l0 = ghost(wc, wp);
                 if (i0 == n0 - 1) r0 = ghost(wc, wm);
             }
-            dl[0] = wc - l0;
-            dr[0] = r0 - wc;
+            acc_axis<T, DYN, N>(cf, 0, wc - l0, r0 - wc, acc);
         }
 #pragma unroll
         for (int d = 1; d < N; ++d) {
@@ -292,10 +297,9 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const SolveDesc *__restri
             T wr = plane[qq + offR[d]];
             if (gl & (1u << d)) wl = ghost(wc, wr);
             if (gr & (1u << d)) wr = ghost(wc, wl);
-            dl[d] = wc - wl;
-            dr[d] = wr - wc;
+            acc_axis<T, DYN, N>(cf, d, wc - wl, wr - wc, acc);
         }
-        const T Lh = hhat<T, DYN, N>(cf, dl, dr, s);
+        const T Lh = acc_finish<T, DYN, N>(cf, acc);
         const int64_t o = int64_t(i0) * s0 + qq;
         T v = fma_t(dt, Lh, wc);
         if (wa != 0.0) v = fma_t(ra, Vn[o], rb * v);
@@ -307,6 +311,237 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const SolveDesc *__restri
         if (active) out[o] = v;
         wm = wc;
         wc = wp;
+    }
+    if (bad && active) atomicOr(s.flags, 1);
+}
+
+// VEC consecutive points of the last axis per thread (16-byte loads and
+// stores), for ndim >= 2 and n_last a multiple of VEC.  Each group of VEC
+// points lies inside one row of the last axis, so the middle axes' neighbours
+// of the whole group are one vector load each and share their ghost /
+// periodic status; the last axis takes its two outer neighbours with scalar
+// loads.  The next plane's centre values and pointwise operands are loaded
+// one iteration ahead, after the current plane's neighbour loads, so that
+// waiting for the neighbours does not wait for them.  KIND bit 0: the stage
+// reads V^n; bit 1: the stage ends with the tube clamp.
+#define ODP_GLOBAL __attribute__((address_space(1)))
+
+template <typename T, int VEC>
+struct alignas(sizeof(T) * VEC) Pack {
+    T v[VEC];
+};
+
+template <typename T, int VEC>
+__device__ __forceinline__ Pack<T, VEC> ldp(const ODP_GLOBAL T *p) {
+    Pack<T, VEC> r;
+    if constexpr (VEC == 1) {
+        r.v[0] = *p;
+    } else {
+        typedef T ev __attribute__((ext_vector_type(VEC)));
+        const ev x = *reinterpret_cast<const ODP_GLOBAL ev *>(p);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) r.v[j] = x[j];
+    }
+    return r;
+}
+
+// Streaming accesses (V^n, V0, the stage output) are non-temporal so that
+// they do not push the stencil input's neighbour rows out of L2.
+template <typename T, int VEC>
+__device__ __forceinline__ Pack<T, VEC> ldp_nt(const ODP_GLOBAL T *p) {
+    Pack<T, VEC> r;
+    if constexpr (VEC == 1) {
+        r.v[0] = __builtin_nontemporal_load(p);
+    } else {
+        typedef T ev __attribute__((ext_vector_type(VEC)));
+        const ev x = __builtin_nontemporal_load(reinterpret_cast<const ODP_GLOBAL ev *>(p));
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) r.v[j] = x[j];
+    }
+    return r;
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void stp_nt(ODP_GLOBAL T *p, const Pack<T, VEC> &r) {
+    if constexpr (VEC == 1) {
+        __builtin_nontemporal_store(r.v[0], p);
+    } else {
+        typedef T ev __attribute__((ext_vector_type(VEC)));
+        ev x;
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) x[j] = r.v[j];
+        __builtin_nontemporal_store(x, reinterpret_cast<ODP_GLOBAL ev *>(p));
+    }
+}
+
+template <typename T, int DYN, int N, int VEC, int KIND>
+__global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__restrict__ descs,
+                                                           const uint32_t *__restrict__ tile_solve,
+                                                           const uint32_t *__restrict__ tile_local,
+                                                           int stage, int step_from_desc,
+                                                           int64_t fixed_step) {
+    static_assert(N >= 2, "the last axis must differ from the marched axis");
+    constexpr bool kVn = KIND & 1;
+    constexpr bool kClamp = KIND & 2;
+    const uint32_t L = xcd_logical(blockIdx.x, gridDim.x);
+    const uint32_t si = tile_solve ? tile_solve[L] : 0u;
+    const uint32_t lt = tile_solve ? tile_local[L] : L;
+    const SolveDesc &s = descs[si];
+
+    const int64_t nsteps = *s.nsteps;
+    const int64_t k = step_from_desc ? *s.step : fixed_step;
+    if (k >= nsteps || stage >= s.rk_order) return;
+
+    const uint32_t cid = lt / s.nqb;
+    const uint32_t qb = lt - cid * s.nqb;
+    const uint32_t Qg = s.Q / VEC;
+    const uint32_t gi = qb * kBlock + threadIdx.x;
+    const bool active = gi < Qg;
+    const uint32_t q = (active ? gi : Qg - 1) * VEC;
+
+    int ii[N];
+    ii[0] = 0;
+    uint32_t rem = q;
+#pragma unroll
+    for (int d = N - 1; d >= 1; --d) {
+        const uint32_t t = fdiv(rem, s.div[d]);
+        ii[d] = int(rem - t * uint32_t(s.n[d]));
+        rem = t;
+    }
+    // middle axes 1..N-2: whole-group vector neighbours
+    int32_t offL[N], offR[N];
+    uint32_t gl = 0, gr = 0;
+#pragma unroll
+    for (int d = 1; d < N - 1; ++d) {
+        const int32_t st = s.stride[d], nd = s.n[d];
+        const bool per = (s.periodic >> d) & 1u;
+        if (ii[d] > 0) offL[d] = -st;
+        else if (per) offL[d] = (nd - 1) * st;
+        else { offL[d] = 0; gl |= 1u << d; }
+        if (ii[d] < nd - 1) offR[d] = st;
+        else if (per) offR[d] = -(nd - 1) * st;
+        else { offR[d] = 0; gr |= 1u << d; }
+    }
+    // last axis: outer neighbours of the group
+    const int nl = s.n[N - 1];
+    const int il = ii[N - 1];
+    const bool perl = (s.periodic >> (N - 1)) & 1u;
+    int32_t oxl, oxr;
+    bool gxl = false, gxr = false;
+    if (il > 0) oxl = -1;
+    else if (perl) oxl = nl - 1;
+    else { oxl = 0; gxl = true; }
+    if (il + VEC < nl) oxr = VEC;
+    else if (perl) oxr = VEC - nl;
+    else { oxr = VEC - 1; gxr = true; }
+
+    Coef<T, DYN, N> cf[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        int jj[N];
+#pragma unroll
+        for (int d = 0; d < N; ++d) jj[d] = ii[d];
+        jj[N - 1] = il + j;
+        cf[j] = make_coef<T, DYN, N>(s, jj);
+    }
+
+    const T *Wg, *Vng;
+    T *outg;
+    stage_buffers<T>(s, stage, k, Wg, Vng, outg);
+    const ODP_GLOBAL T *W = (const ODP_GLOBAL T *)Wg;
+    const ODP_GLOBAL T *Vn = (const ODP_GLOBAL T *)Vng;
+    const ODP_GLOBAL T *V0 = (const ODP_GLOBAL T *)s.V0;
+    ODP_GLOBAL T *out = (ODP_GLOBAL T *)outg;
+    double wa, wb;
+    rk_weights(s.rk_order, stage, wa, wb);
+    const T ra = T(wa), rb = T(wb);
+    const T dt = T(s.dt_sched[k]);
+
+    const int64_t s0 = s.s0;
+    const int n0 = s.n0;
+    const bool per0 = s.periodic & 1u;
+    const int i0b = int(cid) * s.chunk;
+    const int i0e = min(i0b + s.chunk, n0);
+    // plane index of the axis-0 neighbour beyond j (wrapped when periodic,
+    // clamped otherwise: the value is then replaced by a ghost or unused)
+    auto plane_of = [&](int j) -> int64_t {
+        if (j >= n0) j = per0 ? j - n0 : n0 - 1;
+        if (j < 0) j = per0 ? j + n0 : 0;
+        return int64_t(j) * s0;
+    };
+
+    using P = Pack<T, VEC>;
+    P wm = ldp<T, VEC>(W + plane_of(i0b - 1) + q);
+    P wc = ldp<T, VEC>(W + plane_of(i0b) + q);
+    P wp = ldp<T, VEC>(W + plane_of(i0b + 1) + q);
+    P vnx, zx;
+    if constexpr (kVn) vnx = ldp_nt<T, VEC>(Vn + int64_t(i0b) * s0 + q);
+    if constexpr (kClamp) zx = ldp_nt<T, VEC>(V0 + int64_t(i0b) * s0 + q);
+    int bad = 0;
+    for (int i0 = i0b; i0 < i0e; ++i0) {
+        const ODP_GLOBAL T *plane = W + int64_t(i0) * s0;
+        const int64_t o = int64_t(i0) * s0 + q;
+        const P vn = vnx, z = zx;
+        // this plane's in-plane neighbours
+        P wl[N], wr[N];
+#pragma unroll
+        for (int d = 1; d < N - 1; ++d) {
+            wl[d] = ldp<T, VEC>(plane + q + offL[d]);
+            wr[d] = ldp<T, VEC>(plane + q + offR[d]);
+        }
+        const T xl = plane[q + oxl];
+        const T xr = plane[q + oxr];
+        // one plane ahead
+        const P wn = ldp<T, VEC>(W + plane_of(i0 + 2) + q);
+        const int64_t on = (i0 + 1 < n0 ? int64_t(i0 + 1) * s0 : int64_t(i0) * s0) + q;
+        if constexpr (kVn) vnx = ldp_nt<T, VEC>(Vn + on);
+        if constexpr (kClamp) zx = ldp_nt<T, VEC>(V0 + on);
+
+        Acc<T> acc[VEC];
+        const bool g0l = !per0 && i0 == 0, g0r = !per0 && i0 == n0 - 1;
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            acc[j].L = T(0);
+            acc[j].n2 = T(0);
+            T l0 = wm.v[j], r0 = wp.v[j];
+            if (g0l) l0 = ghost(wc.v[j], wp.v[j]);
+            if (g0r) r0 = ghost(wc.v[j], wm.v[j]);
+            acc_axis<T, DYN, N>(cf[j], 0, wc.v[j] - l0, r0 - wc.v[j], acc[j]);
+        }
+#pragma unroll
+        for (int d = 1; d < N - 1; ++d) {
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                T a = wl[d].v[j], b = wr[d].v[j];
+                if (gl & (1u << d)) a = ghost(wc.v[j], wr[d].v[j]);
+                if (gr & (1u << d)) b = ghost(wc.v[j], wl[d].v[j]);
+                acc_axis<T, DYN, N>(cf[j], d, wc.v[j] - a, b - wc.v[j], acc[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            T a = j > 0 ? wc.v[j - 1] : xl;
+            T b = j < VEC - 1 ? wc.v[j + 1] : xr;
+            if (j == 0 && gxl) a = ghost(wc.v[0], VEC > 1 ? wc.v[VEC > 1 ? 1 : 0] : xr);
+            if (j == VEC - 1 && gxr) b = ghost(wc.v[VEC - 1], VEC > 1 ? wc.v[VEC > 1 ? VEC - 2 : 0] : xl);
+            acc_axis<T, DYN, N>(cf[j], N - 1, wc.v[j] - a, b - wc.v[j], acc[j]);
+        }
+        P res;
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const T Lh = acc_finish<T, DYN, N>(cf[j], acc[j]);
+            T v = fma_t(dt, Lh, wc.v[j]);
+            if constexpr (kVn) v = fma_t(ra, vn.v[j], rb * v);
+            if constexpr (kClamp) {
+                if (z.v[j] < v) v = z.v[j];
+            }
+            bad |= !isfinite(v);
+            res.v[j] = v;
+        }
+        if (active) stp_nt<T, VEC>(out + o, res);
+        wm = wc;
+        wc = wp;
+        wp = wn;
     }
     if (bad && active) atomicOr(s.flags, 1);
 }
@@ -413,56 +648,84 @@ __global__ __launch_bounds__(kBlock) void start_copy_kernel(const SolveDesc *__r
     const uint32_t lt = tile_solve ? tile_local[L] : L;
     const SolveDesc &s = descs[si];
     const uint32_t cid = lt / s.nqb;
-    const uint32_t q = (lt - cid * s.nqb) * kBlock + threadIdx.x;
-    if (q >= s.Q) return;
+    const uint32_t g = (lt - cid * s.nqb) * kBlock + threadIdx.x;
+    if (g >= s.Q / uint32_t(s.vec)) return;
+    const uint32_t q = g * uint32_t(s.vec);
     T *dst = (s.rk_order == 1 && ((*s.nsteps) & 1)) ? (T *)s.B : (T *)s.A;
     const T *src = (const T *)s.V0;
     const int i0b = int(cid) * s.chunk;
     const int i0e = min(i0b + s.chunk, s.n0);
     for (int i0 = i0b; i0 < i0e; ++i0) {
         const int64_t o = int64_t(i0) * s.s0 + q;
-        dst[o] = src[o];
+        for (int j = 0; j < s.vec; ++j) dst[o + j] = src[o + j];
     }
 }
 
 // --------------------------------------------------------- launchers
 
-template <typename T, int DYN, int N>
-static hipError_t launch_stage_t(const SolveDesc *d, const uint32_t *ts, const uint32_t *tl,
+template <typename T, int DYN, int N, int VEC>
+static hipError_t launch_stage_t(int kind, const SolveDesc *d, const uint32_t *ts, const uint32_t *tl,
                                  uint32_t nblocks, int stage, int from_desc, int64_t step,
                                  hipStream_t st) {
-    hipLaunchKernelGGL((stage_kernel<T, DYN, N>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl,
-                       stage, from_desc, step);
+    if constexpr (N == 1) {
+        hipLaunchKernelGGL((stage_kernel<T, DYN, N>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl,
+                           stage, from_desc, step);
+    } else {
+        switch (kind) {
+        case 0: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 0>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step); break;
+        case 1: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 1>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step); break;
+        case 2: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 2>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step); break;
+        default: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 3>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step); break;
+        }
+    }
     return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_stage_p(int dyn, int ndim, const SolveDesc *d, const uint32_t *ts,
+template <typename T, int DYN, int N>
+static hipError_t launch_stage_v(int vec, int kind, const SolveDesc *d, const uint32_t *ts,
                                  const uint32_t *tl, uint32_t nb, int stage, int fd, int64_t step,
                                  hipStream_t st) {
+    if constexpr (N == 1 || DYN == 0) {
+        return launch_stage_t<T, DYN, N, 1>(kind, d, ts, tl, nb, stage, fd, step, st);
+    } else {
+        if constexpr (sizeof(T) == 4) {
+            if (vec == 4) return launch_stage_t<T, DYN, N, 4>(kind, d, ts, tl, nb, stage, fd, step, st);
+        }
+        if (vec == 2) return launch_stage_t<T, DYN, N, 2>(kind, d, ts, tl, nb, stage, fd, step, st);
+        return launch_stage_t<T, DYN, N, 1>(kind, d, ts, tl, nb, stage, fd, step, st);
+    }
+}
+
+template <typename T>
+static hipError_t launch_stage_p(int dyn, int ndim, int vec, int kind, const SolveDesc *d,
+                                 const uint32_t *ts, const uint32_t *tl, uint32_t nb, int stage,
+                                 int fd, int64_t step, hipStream_t st) {
     switch (dyn) {
-    case 1: return launch_stage_t<T, 1, 3>(d, ts, tl, nb, stage, fd, step, st);
-    case 2: return launch_stage_t<T, 2, 4>(d, ts, tl, nb, stage, fd, step, st);
-    case 3: return launch_stage_t<T, 3, 6>(d, ts, tl, nb, stage, fd, step, st);
+    case 1: return launch_stage_v<T, 1, 3>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
+    case 2: return launch_stage_v<T, 2, 4>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
+    case 3: return launch_stage_v<T, 3, 6>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
     case 0:
         switch (ndim) {
-        case 1: return launch_stage_t<T, 0, 1>(d, ts, tl, nb, stage, fd, step, st);
-        case 2: return launch_stage_t<T, 0, 2>(d, ts, tl, nb, stage, fd, step, st);
-        case 3: return launch_stage_t<T, 0, 3>(d, ts, tl, nb, stage, fd, step, st);
-        case 4: return launch_stage_t<T, 0, 4>(d, ts, tl, nb, stage, fd, step, st);
-        case 5: return launch_stage_t<T, 0, 5>(d, ts, tl, nb, stage, fd, step, st);
-        case 6: return launch_stage_t<T, 0, 6>(d, ts, tl, nb, stage, fd, step, st);
+        case 1: return launch_stage_v<T, 0, 1>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
+        case 2: return launch_stage_v<T, 0, 2>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
+        case 3: return launch_stage_v<T, 0, 3>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
+        case 4: return launch_stage_v<T, 0, 4>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
+        case 5: return launch_stage_v<T, 0, 5>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
+        case 6: return launch_stage_v<T, 0, 6>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
         }
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_stage(int precision, int dyn, int ndim, const SolveDesc *d, const uint32_t *ts,
-                        const uint32_t *tl, uint32_t nblocks, int stage, int from_desc,
-                        int64_t step, hipStream_t st) {
+// kind: bit 0 the stage reads V^n (Runge-Kutta stages after the first),
+// bit 1 the stage ends with the tube clamp (last stage of a BRT step); it
+// must match what every listed solve does at this stage.
+hipError_t launch_stage(int precision, int dyn, int ndim, int vec, int kind, const SolveDesc *d,
+                        const uint32_t *ts, const uint32_t *tl, uint32_t nblocks, int stage,
+                        int from_desc, int64_t step, hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
-    if (precision == 32) return launch_stage_p<float>(dyn, ndim, d, ts, tl, nblocks, stage, from_desc, step, st);
-    return launch_stage_p<double>(dyn, ndim, d, ts, tl, nblocks, stage, from_desc, step, st);
+    if (precision == 32) return launch_stage_p<float>(dyn, ndim, vec, kind, d, ts, tl, nblocks, stage, from_desc, step, st);
+    return launch_stage_p<double>(dyn, ndim, vec, kind, d, ts, tl, nblocks, stage, from_desc, step, st);
 }
 
 template <int DYN, int N>

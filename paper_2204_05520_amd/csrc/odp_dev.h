@@ -50,9 +50,11 @@ struct SolveDesc {
     AxisTab tab[kMaxDim];
     // ---- tiling
     int32_t chunk;           // planes of axis 0 per tile
-    uint32_t nqb;            // 256-point blocks per hyperplane
+    int32_t vec;             // consecutive last-axis points per thread
+    uint32_t nqb;            // blocks per hyperplane (256 * vec points each)
     uint32_t tiles;          // nqb * ceil(n0 / chunk)
     int32_t rk_order;
+    int32_t pad0_;
     // ---- dynamics
     int32_t dyn;
     int32_t u_mode, d_mode;

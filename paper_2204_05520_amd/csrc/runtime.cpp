@@ -149,16 +149,36 @@ SolveLayout solve_layout(const odp_grid *g, int precision, int rk_order, int nta
     return L;
 }
 
-int default_chunk(const odp_grid *g) {
-    const int64_t Q = g->npts / g->n[0];
-    const int64_t nqb = (Q + kBlock - 1) / kBlock;
-    int64_t c = (g->n[0] * nqb) / 8192;
-    return int(std::max<int64_t>(1, std::min<int64_t>(c, 8)));
+int choose_vec(const odp_grid *g, int precision, int dyn) {
+    if (g->ndim < 2 || dyn == ODP_DYN_SINGLE_INTEGRATOR) return 1;
+    const int64_t nl = g->n[g->ndim - 1];
+    if (precision == 32 && nl % 4 == 0) return 4;
+    if (nl % 2 == 0) return 2;
+    return 1;
 }
 
-uint32_t solve_tiles(const odp_grid *g, int chunk) {
+// Planes of axis 0 marched per block.  Two limits: enough blocks to fill
+// the GPU about once (about 1024 resident blocks of 256 threads), and the
+// data streamed between a block and the block that holds its axis-1
+// neighbour rows ((chunk + 2) planes of ~3 arrays over axis-1 stride points)
+// must stay within about half of the 256 MB Infinity Cache, so that those
+// rows are re-read from the cache rather than from HBM.
+int default_chunk(const odp_grid *g, int vec, int precision) {
     const int64_t Q = g->npts / g->n[0];
-    const int64_t nqb = (Q + kBlock - 1) / kBlock;
+    const int64_t nqb = (Q + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec);
+    int64_t c = (g->n[0] * nqb + 1023) / 1024;
+    if (g->ndim >= 2) {
+        const int64_t s1 = Q / g->n[1];
+        const double per_plane = double(s1) * (precision == 32 ? 4.0 : 8.0) * 3.0;
+        const int64_t cap = int64_t(128e6 / per_plane) - 2;
+        c = std::min(c, std::max<int64_t>(cap, 1));
+    }
+    return int(std::max<int64_t>(1, std::min<int64_t>(c, g->n[0])));
+}
+
+uint32_t solve_tiles(const odp_grid *g, int chunk, int vec) {
+    const int64_t Q = g->npts / g->n[0];
+    const int64_t nqb = (Q + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec);
     return uint32_t(nqb * ((g->n[0] + chunk - 1) / chunk));
 }
 
@@ -172,7 +192,7 @@ double alg_bytes_per_step(int precision, int rk_order, int brt, int64_t npts) {
 
 void build_solve_image(std::vector<unsigned char> &img, const SolveLayout &L, unsigned char *base,
                        const odp_grid *g, const odp_dynamics *dyn, const odp_solve_opts *o,
-                       const double *tau, int ntau, const void *V0, void *A, int chunk) {
+                       const double *tau, int ntau, const void *V0, void *A, int chunk, int vec) {
     img.assign(L.head, 0);
     SolveDesc s;
     std::memset(&s, 0, sizeof(s));
@@ -193,8 +213,9 @@ void build_solve_image(std::vector<unsigned char> &img, const SolveLayout &L, un
         st *= g->n[d];
     }
     s.chunk = chunk;
-    s.nqb = uint32_t((s.Q + kBlock - 1) / kBlock);
-    s.tiles = solve_tiles(g, chunk);
+    s.vec = vec;
+    s.nqb = uint32_t((int64_t(s.Q) + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec));
+    s.tiles = solve_tiles(g, chunk, vec);
     s.rk_order = o->rk_order;
     s.dyn = dyn->id;
     s.u_mode = dyn->u_mode;

@@ -21,9 +21,9 @@ struct odp_grid {
 namespace odp {
 
 // kernels.hip
-hipError_t launch_stage(int precision, int dyn, int ndim, const SolveDesc *d, const uint32_t *ts,
-                        const uint32_t *tl, uint32_t nblocks, int stage, int from_desc,
-                        int64_t step, hipStream_t st);
+hipError_t launch_stage(int precision, int dyn, int ndim, int vec, int kind, const SolveDesc *d,
+                        const uint32_t *ts, const uint32_t *tl, uint32_t nblocks, int stage,
+                        int from_desc, int64_t step, hipStream_t st);
 hipError_t launch_alpha(int dyn, int ndim, const SolveDesc *d, int nsolves, int blocks_per_solve,
                         hipStream_t st);
 hipError_t launch_init(const SolveDesc *d, int nsolves, hipStream_t st);
@@ -54,10 +54,15 @@ SolveLayout solve_layout(const odp_grid *g, int precision, int rk_order, int nta
 // base; V0/A are caller buffers.
 void build_solve_image(std::vector<unsigned char> &img, const SolveLayout &L, unsigned char *base,
                        const odp_grid *g, const odp_dynamics *dyn, const odp_solve_opts *o,
-                       const double *tau, int ntau, const void *V0, void *A, int chunk);
+                       const double *tau, int ntau, const void *V0, void *A, int chunk, int vec);
 
-int default_chunk(const odp_grid *g);
-uint32_t solve_tiles(const odp_grid *g, int chunk);
+int default_chunk(const odp_grid *g, int vec, int precision);
+int choose_vec(const odp_grid *g, int precision, int dyn);
+uint32_t solve_tiles(const odp_grid *g, int chunk, int vec);
 double alg_bytes_per_step(int precision, int rk_order, int brt, int64_t npts);
+// Stage kind for launch_stage: bit 0 reads V^n, bit 1 tube clamp.
+inline int stage_kind(int rk_order, int stage, int brt) {
+    return (stage > 0 ? 1 : 0) | ((stage == rk_order - 1 && brt) ? 2 : 0);
+}
 
 }  // namespace odp

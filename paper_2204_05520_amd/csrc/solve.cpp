@@ -47,8 +47,8 @@ int alloc_workspace(DeviceBuffer &buf, void *given, size_t bytes, hipStream_t st
     return ODP_OK;
 }
 
-int chunk_for(const odp_grid *g, const odp_solve_opts *o) {
-    int c = o->tile_chunk > 0 ? o->tile_chunk : default_chunk(g);
+int chunk_for(const odp_grid *g, const odp_solve_opts *o, int vec) {
+    int c = o->tile_chunk > 0 ? o->tile_chunk : default_chunk(g, vec, o->precision);
     return std::min<int>(c, int(g->n[0]));
 }
 
@@ -92,11 +92,12 @@ int odp_hj_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_d
     DeviceBuffer ws;
     if ((rc = alloc_workspace(ws, workspace_dev, L.total, st))) return rc;
     unsigned char *base = (unsigned char *)ws.ptr;
-    const int chunk = chunk_for(grid, opts);
+    const int vec = choose_vec(grid, prec, dyn->id);
+    const int chunk = chunk_for(grid, opts, vec);
     std::vector<unsigned char> img;
-    build_solve_image(img, L, base, grid, dyn, opts, tau, ntau, V0_dev, V_out_dev, chunk);
+    build_solve_image(img, L, base, grid, dyn, opts, tau, ntau, V0_dev, V_out_dev, chunk, vec);
     const SolveDesc *d_desc = (const SolveDesc *)(base + L.desc);
-    const uint32_t tiles = solve_tiles(grid, chunk);
+    const uint32_t tiles = solve_tiles(grid, chunk, vec);
 
     if ((rc = check_hip(hipMemcpyAsync(base, img.data(), L.head, hipMemcpyHostToDevice, st), "upload")))
         return rc;
@@ -138,7 +139,9 @@ int odp_hj_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_d
     }
     for (int64_t k = 0; k < nsteps; ++k) {
         for (int j = 0; j < opts->rk_order; ++j) {
-            if ((rc = check_hip(launch_stage(prec, dyn->id, grid->ndim, d_desc, nullptr, nullptr, tiles,
+            if ((rc = check_hip(launch_stage(prec, dyn->id, grid->ndim, vec,
+                                             stage_kind(opts->rk_order, j, opts->mode == ODP_BRT), d_desc,
+                                             nullptr, nullptr, tiles,
                                              j, 0, k, st), "stage")))
                 return rc;
         }
