@@ -126,6 +126,7 @@ typedef struct {
     double alg_gbps;     /* alg_bytes / kernel time */
     double roofline_frac;/* alg_gbps / 8000 */
     double alpha_max[6]; /* grid-wide maximum dissipation coefficients */
+    double latency_ms;   /* server only: submit -> completion (host clock) */
     int32_t nonfinite;   /* 1 if a NaN / Inf was produced */
     int32_t pad_;
 } odp_solve_stats;
@@ -166,7 +167,7 @@ typedef struct {
     const void *V0_dev;    /* device, element type = common->precision */
     const double *tau;     /* host, strictly increasing, ntau >= 2 */
     int32_t ntau;
-    int32_t pad_;
+    int32_t rk_order;      /* 0: the common options' order; else 1, 2 or 3 */
     void *V_out_dev;       /* device, receives V(tau[ntau-1]) */
 } odp_solve_desc;
 

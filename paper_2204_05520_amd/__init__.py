@@ -65,7 +65,7 @@ class odp_solve_stats(ctypes.Structure):
                 ("t_final", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("alg_bytes", ctypes.c_double), ("alg_gbps", ctypes.c_double),
                 ("roofline_frac", ctypes.c_double), ("alpha_max", ctypes.c_double * 6),
-                ("nonfinite", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("latency_ms", ctypes.c_double), ("nonfinite", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: (list(getattr(self, k)) if k == "alpha_max" else getattr(self, k))
@@ -75,7 +75,7 @@ class odp_solve_stats(ctypes.Structure):
 class odp_solve_desc(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_void_p), ("dyn", odp_dynamics), ("V0_dev", ctypes.c_void_p),
                 ("tau", ctypes.POINTER(ctypes.c_double)), ("ntau", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("V_out_dev", ctypes.c_void_p)]
+                ("rk_order", ctypes.c_int32), ("V_out_dev", ctypes.c_void_p)]
 
 
 _lib = None
@@ -306,6 +306,7 @@ def batch(specs, V0s, precision=32, stream=None, tile_chunk=0, dissipation=0, ma
         descs[i].V0_dev = V0s[i].data_ptr()
         descs[i].tau = ctypes.cast(t, ctypes.POINTER(ctypes.c_double))
         descs[i].ntau = len(s.tau)
+        descs[i].rk_order = int(s.rk_order)
         descs[i].V_out_dev = outs[i].data_ptr()
     s0 = specs[0]
     opts = make_opts(precision, s0.rk_order, s0.cfl, s0.mode, dissipation, max_dt, 0, tile_chunk,
@@ -317,3 +318,69 @@ def batch(specs, V0s, precision=32, stream=None, tile_chunk=0, dissipation=0, ma
                             stats if want_stats else None)
     _check(rc)
     return outs, [stats[i].as_dict() for i in range(n)] if want_stats else None
+
+
+# ----------------------------------------------------------------- serve
+
+class Server:
+    """Continuous-batching server (odp_server_create / odp_serve_*).
+
+    Requests carry host V0 arrays (copied at submit); results come back as
+    host arrays.  rk_order of a request defaults to the server's."""
+
+    def __init__(self, budget_bytes: int, max_slots: int, precision=32, rk_order=1, cfl=0.8,
+                 mode=ODP_BRT, dissipation=0, tile_chunk=0):
+        self.precision = precision
+        opts = make_opts(precision, rk_order, cfl, mode, dissipation, 0.0, 0, tile_chunk, None)
+        h = ctypes.c_void_p()
+        _check(lib().odp_server_create(int(budget_bytes), int(max_slots), ctypes.byref(opts),
+                                       ctypes.byref(h)))
+        self.handle = h.value
+        self._dtype = np.float32 if precision == 32 else np.float64
+
+    def submit(self, spec, V0_host: np.ndarray, rk_order: int = 0) -> int:
+        arr = np.ascontiguousarray(V0_host, dtype=self._dtype)
+        grid = Grid.from_spec(spec.grid)
+        if arr.size != grid.npts:
+            raise ValueError("V0 does not match the grid")
+        t = _tau_array(spec.tau)
+        d = odp_solve_desc()
+        d.grid = grid.handle
+        d.dyn = make_dynamics(spec.dyn)
+        d.V0_dev = arr.ctypes.data
+        d.tau = ctypes.cast(t, ctypes.POINTER(ctypes.c_double))
+        d.ntau = len(spec.tau)
+        d.rk_order = int(rk_order)
+        d.V_out_dev = None
+        ticket = ctypes.c_uint64()
+        _check(lib().odp_serve_submit(self.handle, ctypes.byref(d), ctypes.byref(ticket)))
+        return int(ticket.value)
+
+    def poll(self, ticket: int, out: np.ndarray):
+        """Returns (status, stats dict or None); fills `out` when done."""
+        st = odp_solve_stats()
+        rc = lib().odp_serve_poll(self.handle, ctypes.c_uint64(ticket), out.ctypes.data,
+                                  out.nbytes, ctypes.byref(st))
+        if rc == ODP_PENDING:
+            return rc, None
+        _check(rc)
+        return rc, st.as_dict()
+
+    def cancel(self, ticket: int):
+        _check(lib().odp_serve_cancel(self.handle, ctypes.c_uint64(ticket)))
+
+    def counts(self):
+        q, r, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().odp_server_counts(self.handle, ctypes.byref(q), ctypes.byref(r), ctypes.byref(d)))
+        return q.value, r.value, d.value
+
+    def close(self):
+        if self.handle:
+            lib().odp_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -598,7 +598,7 @@ __global__ __launch_bounds__(kBlock) void alpha_kernel(const SolveDesc *__restri
 // The float64 CFL schedule of every listed solve (one thread per solve):
 // dt = cfl / sum_d alpha^max_d / dx_d, capped by max_dt, clipped so that the
 // time lands exactly on every tau[k].
-__global__ void sched_kernel(const SolveDesc *__restrict__ descs, int nsolves) {
+__global__ void sched_kernel(const SolveDesc *__restrict__ descs, int nsolves, int64_t *nsteps_all) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nsolves) return;
     const SolveDesc &s = descs[i];
@@ -628,17 +628,20 @@ __global__ void sched_kernel(const SolveDesc *__restrict__ descs, int nsolves) {
         if (land >= 0) ++k;
     }
     *s.nsteps = n;
+    if (nsteps_all) nsteps_all[i] = n;
 }
 
-// Server ticks: advance the step counter of every unfinished solve.
-__global__ void advance_kernel(const SolveDesc *__restrict__ descs, int nsolves) {
+// Server ticks: advance the step counter of every listed unfinished solve.
+__global__ void advance_kernel(const SolveDesc *__restrict__ descs, const int32_t *__restrict__ list,
+                               int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nsolves) return;
-    const SolveDesc &s = descs[i];
+    if (i >= n) return;
+    const SolveDesc &s = descs[list[i]];
     if (*s.step < *s.nsteps) *s.step += 1;
 }
 
-// Copy V0 into the buffer the first step reads, for every listed solve.
+// Copy the start value into the buffer the first step reads, for every
+// listed solve.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void start_copy_kernel(const SolveDesc *__restrict__ descs,
                                                             const uint32_t *__restrict__ tile_solve,
@@ -652,7 +655,7 @@ __global__ __launch_bounds__(kBlock) void start_copy_kernel(const SolveDesc *__r
     if (g >= s.Q / uint32_t(s.vec)) return;
     const uint32_t q = g * uint32_t(s.vec);
     T *dst = (s.rk_order == 1 && ((*s.nsteps) & 1)) ? (T *)s.B : (T *)s.A;
-    const T *src = (const T *)s.V0;
+    const T *src = (const T *)s.Vinit;
     const int i0b = int(cid) * s.chunk;
     const int i0e = min(i0b + s.chunk, s.n0);
     for (int i0 = i0b; i0 < i0e; ++i0) {
@@ -758,8 +761,8 @@ hipError_t launch_init(const SolveDesc *d, int nsolves, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_sched(const SolveDesc *d, int nsolves, hipStream_t st) {
-    hipLaunchKernelGGL(sched_kernel, dim3((nsolves + 63) / 64), dim3(64), 0, st, d, nsolves);
+hipError_t launch_sched(const SolveDesc *d, int nsolves, int64_t *nsteps_all, hipStream_t st) {
+    hipLaunchKernelGGL(sched_kernel, dim3((nsolves + 63) / 64), dim3(64), 0, st, d, nsolves, nsteps_all);
     return hipGetLastError();
 }
 
@@ -773,8 +776,8 @@ hipError_t launch_start_copy(int precision, const SolveDesc *d, const uint32_t *
     return hipGetLastError();
 }
 
-hipError_t launch_advance(const SolveDesc *d, int nsolves, hipStream_t st) {
-    hipLaunchKernelGGL(advance_kernel, dim3((nsolves + 255) / 256), dim3(256), 0, st, d, nsolves);
+hipError_t launch_advance(const SolveDesc *d, const int32_t *list, int n, hipStream_t st) {
+    hipLaunchKernelGGL(advance_kernel, dim3((n + 255) / 256), dim3(256), 0, st, d, list, n);
     return hipGetLastError();
 }
 

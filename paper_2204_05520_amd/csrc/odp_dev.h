@@ -65,6 +65,7 @@ struct SolveDesc {
     void *B;                 // stage 1 output / ping-pong partner
     void *C;                 // stage 2 output (RK3)
     const void *V0;
+    const void *Vinit;       // start value (V0 unless restarting)
     const double *tabd;      // axis tables (float64)
     double *amax;            // alpha^max per axis (float64 bits, atomically maxed)
     double *dt_sched;        // dt of every step

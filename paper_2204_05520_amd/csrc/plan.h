@@ -1,0 +1,73 @@
+// A plan: a list of solves laid out in one device workspace, stepped together.
+//
+// Workspace layout (byte offsets, 256-aligned regions):
+//   descriptors   n x SolveDesc, contiguous (kernels index descs[i])
+//   step counts   n x int64 (gathered by the schedule kernel)
+//   aux           per solve: state (alpha^max, step counters, flags),
+//                 axis tables, tau
+//   --- everything above is uploaded from one host image ---
+//   tile tables   2 x total tiles x uint32 (solve index, local tile), uploaded
+//                 once the step counts are known (members sorted by steps)
+//   schedules     per solve: dt of every step (float64) and landing index
+//   arrays        per solve: B (and C for RK3)
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <vector>
+
+#include "runtime.h"
+
+namespace odp {
+
+struct PlanItem {
+    const odp_grid *g = nullptr;
+    odp_dynamics dyn{};
+    const void *V0 = nullptr;
+    const void *Vinit = nullptr;
+    void *A = nullptr;
+    std::vector<double> tau;
+    int rk_order = 0;                   // 0: the plan options' order
+    int vec = 1, chunk = 1;
+    uint32_t tiles = 0;
+    int64_t max_steps = 0;
+    int tab_entries = 0;
+    size_t aux_off = 0, sched_off = 0, land_off = 0, B_off = 0, C_off = 0;
+    int64_t nsteps = 0;
+};
+
+struct PlanGroup {
+    int dyn = 0, ndim = 0, vec = 1, rk = 1;
+    int first = 0, count = 0;           // descriptor range
+    std::vector<int> order;             // members sorted by step count, descending
+    std::vector<uint32_t> prefix;       // prefix[m] = tiles of order[0..m)
+    size_t tile_base = 0;               // first entry in the tile tables
+};
+
+struct Plan {
+    odp_solve_opts opts{};
+    std::vector<PlanItem> items;        // descriptor order (grouped)
+    std::vector<PlanGroup> groups;
+    size_t desc_off = 0, nsteps_off = 0, aux_begin = 0, upload_bytes = 0;
+    size_t tt_off = 0, total_tiles = 0, sched_begin = 0, arr_begin = 0, total = 0;
+    int64_t max_nsteps = 0;
+};
+
+// Order items by (dynamics, ndim, vector width, RK order), fill the layout.
+// Returns the permutation applied (new index -> caller index).
+std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solve_opts &opts,
+                            int tile_chunk);
+// Host image of [0, upload_bytes) for a workspace at device address base.
+void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &img);
+// Upload, alpha^max, schedules; reads back the step counts (one sync), sorts
+// group members and uploads the tile tables.
+int plan_prologue(Plan &p, unsigned char *base, hipStream_t st);
+// Start copies and every step of every solve (stream-ordered, no sync).
+// save_all: single-solve only; land[] of item 0 and the V_all buffer.
+int plan_steps(Plan &p, unsigned char *base, hipStream_t st, const std::vector<int32_t> *land,
+               void *V_all);
+// Fill per-item stats after the stream has been synchronised.
+int plan_stats(const Plan &p, unsigned char *base, double kernel_ms, odp_solve_stats *stats);
+
+
+}  // namespace odp

@@ -1,5 +1,4 @@
-// Host side of libodp: argument checks, grids, per-solve device images, the
-// single-solve driver and the batched driver.
+// Host side of libodp: errors, argument checks, grids, tiling choices.
 #include "runtime.h"
 
 #include <hip/hip_runtime_api.h>
@@ -27,7 +26,7 @@ int check_hip(hipError_t e, const char *what) {
     return set_error(ODP_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 static int dyn_ndim(int id) {
     switch (id) {
@@ -92,7 +91,7 @@ int validate_tau(const double *tau, int ntau) {
 
 // Upper bound of max_i alpha_d(z_i) from the parameters and the domain
 // (sizes the dt schedule; the schedule itself uses the device reduction).
-static void alpha_bound(const odp_grid *g, const odp_dynamics *dyn, double *ab) {
+void alpha_bound(const odp_grid *g, const odp_dynamics *dyn, double *ab) {
     for (int d = 0; d < kMaxDim; ++d) ab[d] = 0.0;
     const double *p = dyn->p;
     switch (dyn->id) {
@@ -117,36 +116,6 @@ static void alpha_bound(const odp_grid *g, const odp_dynamics *dyn, double *ab) 
         ab[5] = p[3];
         break;
     }
-}
-
-SolveLayout solve_layout(const odp_grid *g, int precision, int rk_order, int ntau, double tau_span,
-                         const odp_dynamics *dyn, double cfl, double max_dt) {
-    SolveLayout L{};
-    double ab[kMaxDim];
-    alpha_bound(g, dyn, ab);
-    double s = 0.0;
-    for (int d = 0; d < g->ndim; ++d) s += ab[d] / g->dx[d];
-    double dt_lo = s > 0.0 ? cfl / s : INFINITY;
-    if (max_dt > 0.0) dt_lo = std::min(dt_lo, max_dt);
-    double est = std::isfinite(dt_lo) ? std::ceil(tau_span / dt_lo) : 0.0;
-    // landing steps and a rounding slack per output interval
-    L.max_steps = int64_t(std::min(est, 1e9)) + 2 * int64_t(ntau) + 8;
-    L.tab_entries = 0;
-    for (int d = 0; d < g->ndim; ++d) L.tab_entries += 3 * int(g->n[d]);
-    const size_t b = precision == 32 ? 4 : 8;
-    const size_t arr = align256(size_t(g->npts) * b);
-    size_t off = 0;
-    L.desc = off; off += align256(sizeof(SolveDesc));
-    L.state = off; off += align256(kMaxDim * 8 + 3 * 8 + 8);
-    L.tab = off; off += align256(size_t(L.tab_entries) * 8);
-    L.tau = off; off += align256(size_t(ntau) * 8);
-    L.head = off;
-    L.sched = off; off += align256(size_t(L.max_steps) * 8);
-    L.land = off; off += align256(size_t(L.max_steps) * 4);
-    L.B = off; off += arr;
-    L.C = off; off += rk_order == 3 ? arr : 0;
-    L.total = off;
-    return L;
 }
 
 int choose_vec(const odp_grid *g, int precision, int dyn) {
@@ -188,75 +157,6 @@ double alg_bytes_per_step(int precision, int rk_order, int brt, int64_t npts) {
     const double b = precision == 32 ? 4.0 : 8.0;
     double per = 2.0 * rk_order + (rk_order - 1) + (brt ? 1 : 0);
     return per * b * double(npts);
-}
-
-void build_solve_image(std::vector<unsigned char> &img, const SolveLayout &L, unsigned char *base,
-                       const odp_grid *g, const odp_dynamics *dyn, const odp_solve_opts *o,
-                       const double *tau, int ntau, const void *V0, void *A, int chunk, int vec) {
-    img.assign(L.head, 0);
-    SolveDesc s;
-    std::memset(&s, 0, sizeof(s));
-    s.ndim = g->ndim;
-    s.n0 = int32_t(g->n[0]);
-    s.Q = uint32_t(g->npts / g->n[0]);
-    s.s0 = int64_t(s.Q);
-    s.npts = g->npts;
-    s.periodic = 0;
-    int64_t st = 1;
-    for (int d = g->ndim - 1; d >= 0; --d) {
-        s.n[d] = int32_t(g->n[d]);
-        s.stride[d] = d > 0 ? int32_t(st) : 0;
-        s.div[d] = make_fastdiv(uint32_t(g->n[d]));
-        s.dx[d] = g->dx[d];
-        s.inv2dx[d] = 1.0 / (2.0 * g->dx[d]);
-        if (g->periodic[d]) s.periodic |= 1u << d;
-        st *= g->n[d];
-    }
-    s.chunk = chunk;
-    s.vec = vec;
-    s.nqb = uint32_t((int64_t(s.Q) + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec));
-    s.tiles = solve_tiles(g, chunk, vec);
-    s.rk_order = o->rk_order;
-    s.dyn = dyn->id;
-    s.u_mode = dyn->u_mode;
-    s.d_mode = dyn->d_mode;
-    s.global_alpha = o->dissipation;
-    for (int k = 0; k < 16; ++k) s.p[k] = dyn->p[k];
-    s.A = A;
-    s.B = base + L.B;
-    s.C = o->rk_order == 3 ? base + L.C : nullptr;
-    s.V0 = V0;
-    s.tabd = (const double *)(base + L.tab);
-    unsigned char *state = base + L.state;
-    s.amax = (double *)state;
-    s.nsteps = (int64_t *)(state + kMaxDim * 8);
-    s.step = (int64_t *)(state + kMaxDim * 8 + 8);
-    s.flags = (int32_t *)(state + kMaxDim * 8 + 16);
-    s.dt_sched = (double *)(base + L.sched);
-    s.land = (int32_t *)(base + L.land);
-    s.brt = o->mode == ODP_BRT;
-    s.ntau = ntau;
-    s.tau = (const double *)(base + L.tau);
-    s.cfl = o->cfl;
-    s.max_dt = o->max_dt;
-    s.max_steps = L.max_steps;
-    // axis tables: coordinate, cos, sin (float64, computed once on the host)
-    double *tab = (double *)(img.data() + L.tab);
-    int off = 0;
-    for (int d = 0; d < g->ndim; ++d) {
-        const int n = int(g->n[d]);
-        s.tab[d].off = off;
-        s.tab[d].n = n;
-        for (int k = 0; k < n; ++k) {
-            const double x = g->lo[d] + double(k) * g->dx[d];
-            tab[off + k] = x;
-            tab[off + n + k] = std::cos(x);
-            tab[off + 2 * n + k] = std::sin(x);
-        }
-        off += 3 * n;
-    }
-    std::memcpy(img.data() + L.desc, &s, sizeof(s));
-    std::memcpy(img.data() + L.tau, tau, size_t(ntau) * 8);
 }
 
 }  // namespace odp

@@ -27,8 +27,8 @@ hipError_t launch_stage(int precision, int dyn, int ndim, int vec, int kind, con
 hipError_t launch_alpha(int dyn, int ndim, const SolveDesc *d, int nsolves, int blocks_per_solve,
                         hipStream_t st);
 hipError_t launch_init(const SolveDesc *d, int nsolves, hipStream_t st);
-hipError_t launch_sched(const SolveDesc *d, int nsolves, hipStream_t st);
-hipError_t launch_advance(const SolveDesc *d, int nsolves, hipStream_t st);
+hipError_t launch_sched(const SolveDesc *d, int nsolves, int64_t *nsteps_all, hipStream_t st);
+hipError_t launch_advance(const SolveDesc *d, const int32_t *list, int n, hipStream_t st);
 hipError_t launch_start_copy(int precision, const SolveDesc *d, const uint32_t *ts,
                              const uint32_t *tl, uint32_t nblocks, hipStream_t st);
 
@@ -39,22 +39,9 @@ int validate_dyn(const odp_grid *g, const odp_dynamics *dyn);
 int validate_opts(const odp_solve_opts *o);
 int validate_tau(const double *tau, int ntau);
 
-// Per-solve device memory layout inside a workspace (byte offsets from the
-// solve's base, 256-byte aligned regions).
-struct SolveLayout {
-    size_t desc, state, tab, tau, sched, land, B, C, total;
-    size_t head;          // bytes of [desc, tau] uploaded from the host
-    int64_t max_steps;
-    int tab_entries;
-};
-SolveLayout solve_layout(const odp_grid *g, int precision, int rk_order, int ntau,
-                         double tau_span, const odp_dynamics *dyn, double cfl, double max_dt);
-
-// Fill the host image [desc .. tau] of a solve placed at device address
-// base; V0/A are caller buffers.
-void build_solve_image(std::vector<unsigned char> &img, const SolveLayout &L, unsigned char *base,
-                       const odp_grid *g, const odp_dynamics *dyn, const odp_solve_opts *o,
-                       const double *tau, int ntau, const void *V0, void *A, int chunk, int vec);
+// Upper bound of max_i alpha_d(z_i) from the parameters and the domain.
+void alpha_bound(const odp_grid *g, const odp_dynamics *dyn, double *ab);
+size_t align256(size_t x);
 
 int default_chunk(const odp_grid *g, int vec, int precision);
 int choose_vec(const odp_grid *g, int precision, int dyn);

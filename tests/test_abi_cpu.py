@@ -1,0 +1,179 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/odp.h declares, and rejects bad arguments before any GPU work.
+(No compute call is made here: there is no GPU in this environment.)"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2204_05520_amd as odp
+from paper_2204_05520_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "odp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(odp_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(odp.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return odp.lib()
+
+
+def test_exports_every_declared_function(lib):
+    names = declared_functions()
+    assert len(names) >= 15, names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(odp.SYMBOLS) == names
+
+
+def test_strerror_covers_codes(lib):
+    for code in range(-7, 2):
+        assert odp.odp_strerror(code) != "unknown error code"
+    assert odp.odp_strerror(-99) == "unknown error code"
+
+
+@pytest.mark.parametrize("n,lo,hi,msg", [
+    ([2, 5], [0, 0], [1, 1], "nodes"),
+    ([5, 5], [0, 1], [1, 1], "lo < hi"),
+    ([5] * 7, [0] * 7, [1] * 7, "ndim"),
+    ([5, 5], [0, float("nan")], [1, 1], "finite"),
+])
+def test_grid_create_rejects(lib, n, lo, hi, msg):
+    with pytest.raises(odp.OdpError) as ei:
+        odp.Grid(n, lo, hi, [0] * len(n))
+    assert ei.value.code == odp.ODP_EINVAL
+    assert msg in str(ei.value)
+
+
+def test_grid_points_and_limits(lib):
+    g = odp.Grid([80, 80, 80, 80], [-5, -5, 0, -3.14], [5, 5, 4, 3.14], [0, 0, 0, 1])
+    assert g.npts == 80 ** 4
+    with pytest.raises(odp.OdpError):
+        odp.Grid([3, 1 << 16, 1 << 16], [0, 0, 0], [1, 1, 1], [0, 0, 0])  # hyperplane >= 2^31
+
+
+def _solve_rc(spec, precision=32, **kw):
+    """odp_hj_solve with fake (never dereferenced) device pointers: every case
+    here must fail validation before touching the GPU."""
+    grid = odp.Grid.from_spec(spec.grid)
+    d = odp.make_dynamics(spec.dyn)
+    tau = kw.pop("tau", spec.tau)
+    t = (ctypes.c_double * len(tau))(*tau)
+    opts = odp.make_opts(precision, kw.pop("rk", spec.rk_order), kw.pop("cfl", spec.cfl), spec.mode,
+                         kw.pop("diss", 0), kw.pop("max_dt", 0.0), kw.pop("save_all", 0), 0, None)
+    V0 = kw.pop("V0", ctypes.c_void_p(0x1000))
+    Vout = kw.pop("Vout", ctypes.c_void_p(0x2000))
+    rc = odp.lib().odp_hj_solve(grid.handle, ctypes.byref(d), V0, None, t, len(tau),
+                                ctypes.byref(opts), None, Vout, None, None)
+    return rc, odp.odp_last_error()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    ({"precision": 16}, "precision"),
+    ({"rk": 4}, "rk_order"),
+    ({"cfl": 1.5}, "cfl"),
+    ({"cfl": 0.0}, "cfl"),
+    ({"diss": 2}, "dissipation"),
+    ({"max_dt": -1.0}, "max_dt"),
+    ({"tau": [0.0]}, "tau"),
+    ({"tau": [0.0, 1.0, 1.0]}, "increasing"),
+    ({"tau": [-1.0, 1.0]}, "tau[0]"),
+    ({"save_all": 1}, "V_all"),
+    ({"V0": None}, "V0"),
+    ({"Vout": ctypes.c_void_p(0x1000)}, "alias"),
+])
+def test_solve_rejects_before_gpu(lib, kw, msg):
+    spec = W.config_dubins3d(n=(10, 10, 8))
+    rc, err = _solve_rc(spec, **kw)
+    assert rc == odp.ODP_EINVAL
+    assert msg in err
+
+
+def test_dynamics_checks(lib):
+    spec = W.config_dubins3d(n=(10, 10, 8))
+    spec.dyn.params = [1.0, -1.0]
+    rc, err = _solve_rc(spec)
+    assert rc == odp.ODP_EINVAL and "w_max" in err
+    spec = W.config_dubins3d(n=(10, 10, 8))
+    spec.grid.periodic = [0, 0, 0]
+    rc, err = _solve_rc(spec)
+    assert rc == odp.ODP_EINVAL and "periodic" in err
+    spec = W.config_dubins3d(n=(10, 10, 8))
+    spec.dyn.id = W.DYN_DYNCAR4D
+    rc, err = _solve_rc(spec)
+    assert rc == odp.ODP_EINVAL and "dimension" in err
+    spec.dyn.id = 7
+    rc, err = _solve_rc(spec)
+    assert rc == odp.ODP_EINVAL
+
+
+def test_workspace_bytes(lib):
+    spec = W.config_dyncar4d()
+    grid = odp.Grid.from_spec(spec.grid)
+    o32 = odp.make_opts(32, 3)
+    o64 = odp.make_opts(64, 3)
+    b32 = odp.odp_hj_workspace_bytes(grid, spec.dyn, spec.tau, o32)
+    b64 = odp.odp_hj_workspace_bytes(grid, spec.dyn, spec.tau, o64)
+    P = 80 ** 4
+    # RK3: two stage buffers beside the caller's arrays, plus schedule/tables
+    assert 2 * 4 * P <= b32 < 2 * 4 * P + (8 << 20)
+    assert 2 * 8 * P <= b64 < 2 * 8 * P + (8 << 20)
+    o1 = odp.make_opts(32, 1)
+    b1 = odp.odp_hj_workspace_bytes(grid, spec.dyn, spec.tau, o1)
+    assert 4 * P <= b1 < 4 * P + (8 << 20)
+    assert odp.odp_hj_workspace_bytes(grid, spec.dyn, [1.0, 0.5], o32) == 0
+
+
+def test_batch_and_server_reject(lib):
+    specs = [W.config_dubins3d(n=(10, 10, 8))]
+    descs = (odp.odp_solve_desc * 1)()
+    grid = odp.Grid.from_spec(specs[0].grid)
+    descs[0].grid = grid.handle
+    descs[0].dyn = odp.make_dynamics(specs[0].dyn)
+    descs[0].V0_dev = 0x1000
+    t = (ctypes.c_double * 2)(0.0, 1.0)
+    descs[0].tau = ctypes.cast(t, ctypes.POINTER(ctypes.c_double))
+    descs[0].ntau = 2
+    descs[0].V_out_dev = 0x1000  # aliases V0
+    opts = odp.make_opts(32, 1)
+    rc = lib.odp_hj_batch(1, descs, ctypes.byref(opts), None, 0, None)
+    assert rc == odp.ODP_EINVAL
+    assert lib.odp_hj_batch(0, descs, ctypes.byref(opts), None, 0, None) == odp.ODP_EINVAL
+    bad = odp.make_opts(32, 1, save_all=1)
+    h = ctypes.c_void_p()
+    assert lib.odp_server_create(1 << 20, 4, ctypes.byref(bad), ctypes.byref(h)) == odp.ODP_EUNSUPPORTED
+    assert lib.odp_server_create(1 << 20, 0, ctypes.byref(opts), ctypes.byref(h)) == odp.ODP_EINVAL
+    assert lib.odp_server_create(0, 4, ctypes.byref(opts), ctypes.byref(h)) == odp.ODP_EINVAL
+
+
+def test_fastdiv_magic_numbers():
+    """The round-up magic-number division the kernels use for the in-plane
+    index (host formula, checked against integer division)."""
+    rng = np.random.default_rng(0)
+    for d in list(range(1, 300)) + [36 ** 4, 80 ** 3, 6400, 46656]:
+        s = 0
+        while (1 << s) < d:
+            s += 1
+        m = ((1 << 32) * ((1 << s) - d)) // d + 1
+        for n in [0, d - 1, d, d + 1, (1 << 31) - 1] + list(rng.integers(0, 1 << 31, 50)):
+            assert ((((int(n) * m) >> 32) + int(n)) >> s) == int(n) // d
+
+
+def test_product_path_has_no_oracle_import():
+    """The library binding never imports the oracle (test infrastructure)."""
+    for f in ("__init__.py", "workloads.py", "build.py"):
+        src = open(os.path.join(ROOT, "paper_2204_05520_amd", f)).read()
+        assert "import oracle" not in src and "from oracle" not in src
+    for f in os.listdir(os.path.join(ROOT, "paper_2204_05520_amd", "csrc")):
+        src = open(os.path.join(ROOT, "paper_2204_05520_amd", "csrc", f)).read()
+        assert "oracle" not in src.lower(), f

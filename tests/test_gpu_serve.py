@@ -1,0 +1,113 @@
+"""GPU continuous-batching server: requests that arrive while others run join
+the running set, and every served result equals the same request solved
+alone through odp_hj_solve, bit for bit (mixed dynamics, RK orders, sizes)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2204_05520_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def odp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2204_05520_amd as odp
+    odp.lib()
+    return odp
+
+
+def mixed_requests(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        T = float(rng.uniform(0.1, 0.5))
+        if rng.uniform() < 0.6:
+            n = [int(x) for x in rng.integers(10, 30, size=3)]
+            g = W.GridSpec(n, [-4.0, -4.0, -np.pi], [4.0, 4.0, np.pi], [0, 0, 1])
+            d = W.DynSpec(W.DYN_DUBINS3D, [float(rng.uniform(0.5, 1.5)), float(rng.uniform(0.5, 2.0))],
+                          W.MAXIMISE, W.MINIMISE)
+            spec = W.SolveSpec(g, d, [0.0, T], rk_order=1, radius=float(rng.uniform(0.3, 1.2)), name=f"s{i}")
+        else:
+            n = [int(x) for x in rng.integers(8, 16, size=4)]
+            g = W.GridSpec(n, [-5.0, -5.0, 0.0, -np.pi], [5.0, 5.0, 4.0, np.pi], [0, 0, 0, 1])
+            d = W.DynSpec(W.DYN_DYNCAR4D, [float(rng.uniform(0.5, 1.5)), float(rng.uniform(0.5, 2.0))],
+                          W.MAXIMISE, W.MINIMISE)
+            spec = W.SolveSpec(g, d, [0.0, T], rk_order=3, radius=float(rng.uniform(0.3, 1.2)), name=f"s{i}")
+        out.append(spec)
+    return out
+
+
+def alone(odp, spec, V0):
+    import torch
+    t = torch.tensor(V0, dtype=torch.float32, device="cuda:0")
+    return odp.solve(spec, t, precision=32).V.cpu().numpy()
+
+
+def test_serve_equals_alone(odp):
+    specs = mixed_requests(24, 3)
+    V0s = [W.make_v0(s).astype(np.float32) for s in specs]
+    srv = odp.Server(budget_bytes=1 << 30, max_slots=8, precision=32, rk_order=1)
+    print(f"[gpu] serve {len(specs)} mixed requests, 8 slots", flush=True)
+    tickets = []
+    for i, (s, v) in enumerate(zip(specs, V0s)):
+        tickets.append(srv.submit(s, v, rk_order=s.rk_order))
+        if i % 5 == 4:
+            time.sleep(0.003)  # staggered arrivals join a running set
+    outs = [np.empty_like(v) for v in V0s]
+    pending = set(range(len(specs)))
+    deadline = time.time() + 60
+    stats = [None] * len(specs)
+    while pending and time.time() < deadline:
+        for i in list(pending):
+            rc, st = srv.poll(tickets[i], outs[i])
+            if rc == 0:
+                stats[i] = st
+                pending.discard(i)
+        time.sleep(0.001)
+    srv.close()
+    assert not pending
+    for i, s in enumerate(specs):
+        ref = alone(odp, s, V0s[i])
+        same = bool(np.array_equal(ref, outs[i]))
+        assert same, (i, s.name, float(np.abs(ref - outs[i]).max()))
+        assert stats[i]["latency_ms"] > 0
+
+
+def test_serve_budget_and_cancel(odp):
+    spec = mixed_requests(1, 9)[0]
+    V0 = W.make_v0(spec).astype(np.float32)
+    srv = odp.Server(budget_bytes=1 << 16, max_slots=2, precision=32)
+    with pytest.raises(odp.OdpError) as ei:
+        srv.submit(spec, V0)
+    assert ei.value.code == odp.ODP_ENOMEM
+    srv.close()
+    srv = odp.Server(budget_bytes=1 << 30, max_slots=1, precision=32)
+    big = W.config_dyncar4d(n=[20, 20, 12, 16], T=2.0)
+    Vb = W.make_v0(big).astype(np.float32)
+    t1 = srv.submit(big, Vb, rk_order=3)
+    t2 = srv.submit(spec, V0, rk_order=spec.rk_order)
+    srv.cancel(t2)  # still queued behind the single slot
+    out = np.empty_like(V0)
+    deadline = time.time() + 60
+    while time.time() < deadline:
+        try:
+            rc, _ = srv.poll(t2, out)
+        except odp.OdpError as e:
+            assert e.code == odp.ODP_ECANCELED
+            break
+        time.sleep(0.002)
+    else:
+        pytest.fail("cancelled request never finished")
+    ob = np.empty_like(Vb)
+    while time.time() < deadline:
+        rc, st = srv.poll(t1, ob)
+        if rc == 0:
+            break
+        time.sleep(0.002)
+    assert rc == 0
+    srv.close()
