@@ -16,7 +16,6 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -29,14 +28,6 @@ METRIC = "grid-point updates/s FP32 vs FP64 + % HBM roofline; p50/p99 solve late
 HBM_PEAK_GBPS = 8000.0
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "odp_dev.h"):
-        with open(os.path.join(ROOT, "paper_2204_05520_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or
     None when there is none or the kernel source changed since."""
@@ -45,6 +36,7 @@ def measured_traffic(kernel: str, workload: str):
         return None
     with open(path) as fh:
         rec = json.load(fh)
+    from paper_2204_05520_amd.profiling import kernel_source_hash
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
@@ -97,7 +89,7 @@ def bench_single(args, W, odp):
     dev = torch.device("cuda:0")
     if args.workload == "dyncar4d":
         spec = W.config_dyncar4d(n=args.n or 80)
-        kname, precs = "stage_dyncar4d", (32, 64)
+        kname, precs = "stage_dyncar4d", ((32,) if args.fp32_only else (32, 64))
     elif args.workload == "game6d":
         spec = W.config_game6d(n=args.n or 36)
         kname, precs = "stage_game6d", (32,)
@@ -296,6 +288,9 @@ def main():
     ap.add_argument("--tile-chunk", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first issue one plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--fp32-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU sharding is a design "
@@ -308,6 +303,12 @@ def main():
     import paper_2204_05520_amd as odp
     from paper_2204_05520_amd import workloads as W
     odp.lib()
+    if args.calib_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if args.workload in ("dyncar4d", "game6d", "dubins3d"):
         line = bench_single(args, W, odp)
     elif args.workload == "batch":

@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const SolveDesc *__restri
 #pragma unroll
     for (int d = N - 1; d >= 1; --d) {
         const uint32_t t = fdiv(rem, s.div[d]);
-        ii[d] = int(rem - t * uint32_t(s.n[d]));
+        ii[d] = int(rem - t * s.div[d].d);
         rem = t;
     }
     int32_t offL[N], offR[N];
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__re
 #pragma unroll
     for (int d = N - 1; d >= 1; --d) {
         const uint32_t t = fdiv(rem, s.div[d]);
-        ii[d] = int(rem - t * uint32_t(s.n[d]));
+        ii[d] = int(rem - t * s.div[d].d);
         rem = t;
     }
     // middle axes 1..N-2: whole-group vector neighbours
@@ -422,18 +422,20 @@ __global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__re
         else if (per) offR[d] = -(nd - 1) * st;
         else { offR[d] = 0; gr |= 1u << d; }
     }
-    // last axis: outer neighbours of the group
+    // last axis: a row holds nl points in a pitch of s.pitch elements (a
+    // multiple of VEC); group elements past the row end (j > jend) are padding
     const int nl = s.n[N - 1];
     const int il = ii[N - 1];
+    const int jend = nl - 1 - il;
     const bool perl = (s.periodic >> (N - 1)) & 1u;
     int32_t oxl, oxr;
     bool gxl = false, gxr = false;
     if (il > 0) oxl = -1;
     else if (perl) oxl = nl - 1;
     else { oxl = 0; gxl = true; }
-    if (il + VEC < nl) oxr = VEC;
-    else if (perl) oxr = VEC - nl;
-    else { oxr = VEC - 1; gxr = true; }
+    if (jend >= VEC) oxr = VEC;
+    else if (perl) oxr = -il;
+    else { oxr = 0; gxr = true; }
 
     Coef<T, DYN, N> cf[VEC];
 #pragma unroll
@@ -520,10 +522,10 @@ __global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__re
         }
 #pragma unroll
         for (int j = 0; j < VEC; ++j) {
-            T a = j > 0 ? wc.v[j - 1] : xl;
-            T b = j < VEC - 1 ? wc.v[j + 1] : xr;
-            if (j == 0 && gxl) a = ghost(wc.v[0], VEC > 1 ? wc.v[VEC > 1 ? 1 : 0] : xr);
-            if (j == VEC - 1 && gxr) b = ghost(wc.v[VEC - 1], VEC > 1 ? wc.v[VEC > 1 ? VEC - 2 : 0] : xl);
+            T a = j > 0 ? wc.v[j > 0 ? j - 1 : 0] : xl;
+            T b = (j < jend && j < VEC - 1) ? wc.v[j < VEC - 1 ? j + 1 : j] : xr;
+            if (j == 0 && gxl) a = ghost(wc.v[0], b);
+            if (j == jend && gxr) b = ghost(wc.v[j], a);
             acc_axis<T, DYN, N>(cf[j], N - 1, wc.v[j] - a, b - wc.v[j], acc[j]);
         }
         P res;
@@ -535,7 +537,7 @@ __global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__re
             if constexpr (kClamp) {
                 if (z.v[j] < v) v = z.v[j];
             }
-            bad |= !isfinite(v);
+            if (j <= jend) bad |= !isfinite(v);
             res.v[j] = v;
         }
         if (active) stp_nt<T, VEC>(out + o, res);
@@ -570,9 +572,10 @@ __global__ __launch_bounds__(kBlock) void alpha_kernel(const SolveDesc *__restri
         uint32_t rem = q;
         for (int d = N - 1; d >= 1; --d) {
             const uint32_t t = fdiv(rem, s.div[d]);
-            ii[d] = int(rem - t * uint32_t(s.n[d]));
+            ii[d] = int(rem - t * s.div[d].d);
             rem = t;
         }
+        if (N > 1 && ii[N - 1] >= s.n[N - 1]) continue;  // row padding
         for (int i0 = 0; i0 < s.n0; ++i0) {
             ii[0] = i0;
             double a[N];

@@ -38,13 +38,16 @@ struct SolveDesc {
     // ---- shape
     int32_t ndim;
     int32_t n0;              // nodes on axis 0 (the marched axis)
-    uint32_t Q;              // points per hyperplane of axes 1..ndim-1
+    uint32_t Q;              // elements per hyperplane of axes 1..ndim-1 (with padding)
     uint32_t periodic;       // bit d set: axis d periodic
+    int32_t pitch;           // elements per last-axis row in memory (>= n[ndim-1];
+                             // the elements beyond n[ndim-1] are padding)
+    int32_t pad1_;
     int64_t s0;              // stride of axis 0 (= Q)
     int64_t npts;
     int32_t n[kMaxDim];      // nodes per axis
     int32_t stride[kMaxDim]; // strides of axes 1..ndim-1 (entry 0 unused)
-    FastDiv div[kMaxDim];    // divisors n[d] for the in-plane decomposition
+    FastDiv div[kMaxDim];    // divisors of the in-plane decomposition (pitch for the last axis)
     double inv2dx[kMaxDim];  // 1 / (2 dx_d)
     double dx[kMaxDim];
     AxisTab tab[kMaxDim];

@@ -45,9 +45,13 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
     const int n = int(items.size());
     for (auto &it : items) {
         if (it.rk_order <= 0) it.rk_order = opts.rk_order;
-        it.vec = choose_vec(it.g, prec, it.dyn.id);
+        const int64_t nl = it.g->n[it.g->ndim - 1];
+        if (it.pitch <= 0 || it.g->ndim < 2) it.pitch = int(nl);
+        it.qpad = it.g->ndim < 2 ? 1 : (it.g->npts / it.g->n[0] / nl) * it.pitch;
+        it.ppad = it.qpad * it.g->n[0];
+        it.vec = choose_vec(it.g, prec, it.dyn.id, it.pitch);
         it.chunk = balanced_chunk(it.g, tile_chunk > 0 ? tile_chunk : default_chunk(it.g, it.vec, prec));
-        it.tiles = solve_tiles(it.g, it.chunk, it.vec);
+        it.tiles = solve_tiles(it.g->n[0], it.qpad, it.chunk, it.vec);
         it.max_steps = step_capacity(it.g, &it.dyn, it.tau, opts.cfl, opts.max_dt);
         it.tab_entries = 0;
         for (int d = 0; d < it.g->ndim; ++d) it.tab_entries += 3 * int(it.g->n[d]);
@@ -101,7 +105,7 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
     }
     p.arr_begin = off;
     for (auto &it : p.items) {
-        const size_t arr = align256(size_t(it.g->npts) * eb);
+        const size_t arr = align256(size_t(it.ppad) * eb);
         it.B_off = off;
         off += arr;
         it.C_off = off;
@@ -121,18 +125,21 @@ void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &
         std::memset(&s, 0, sizeof(s));
         s.ndim = g->ndim;
         s.n0 = int32_t(g->n[0]);
-        s.Q = uint32_t(g->npts / g->n[0]);
+        s.Q = uint32_t(it.qpad);
         s.s0 = int64_t(s.Q);
         s.npts = g->npts;
+        s.pitch = it.pitch;
         int64_t st = 1;
         for (int d = g->ndim - 1; d >= 0; --d) {
+            // the last axis occupies `pitch` elements per row in memory
+            const int64_t ext = (d == g->ndim - 1 && d > 0) ? it.pitch : g->n[d];
             s.n[d] = int32_t(g->n[d]);
             s.stride[d] = d > 0 ? int32_t(st) : 0;
-            s.div[d] = make_fastdiv(uint32_t(g->n[d]));
+            s.div[d] = make_fastdiv(uint32_t(ext));
             s.dx[d] = g->dx[d];
             s.inv2dx[d] = 1.0 / (2.0 * g->dx[d]);
             if (g->periodic[d]) s.periodic |= 1u << d;
-            st *= g->n[d];
+            st *= ext;
         }
         s.chunk = it.chunk;
         s.vec = it.vec;

@@ -28,6 +28,8 @@ struct PlanItem {
     void *A = nullptr;
     std::vector<double> tau;
     int rk_order = 0;                   // 0: the plan options' order
+    int pitch = 0;                      // last-axis row pitch in memory (0: dense)
+    int64_t qpad = 0, ppad = 0;         // hyperplane / array elements with padding
     int vec = 1, chunk = 1;
     uint32_t tiles = 0;
     int64_t max_steps = 0;

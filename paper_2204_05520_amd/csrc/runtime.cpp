@@ -118,11 +118,10 @@ void alpha_bound(const odp_grid *g, const odp_dynamics *dyn, double *ab) {
     }
 }
 
-int choose_vec(const odp_grid *g, int precision, int dyn) {
+int choose_vec(const odp_grid *g, int precision, int dyn, int64_t pitch) {
     if (g->ndim < 2 || dyn == ODP_DYN_SINGLE_INTEGRATOR) return 1;
-    const int64_t nl = g->n[g->ndim - 1];
-    if (precision == 32 && nl % 4 == 0) return 4;
-    if (nl % 2 == 0) return 2;
+    if (precision == 32 && pitch % 4 == 0) return 4;
+    if (pitch % 2 == 0) return 2;
     return 1;
 }
 
@@ -145,10 +144,9 @@ int default_chunk(const odp_grid *g, int vec, int precision) {
     return int(std::max<int64_t>(1, std::min<int64_t>(c, g->n[0])));
 }
 
-uint32_t solve_tiles(const odp_grid *g, int chunk, int vec) {
-    const int64_t Q = g->npts / g->n[0];
-    const int64_t nqb = (Q + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec);
-    return uint32_t(nqb * ((g->n[0] + chunk - 1) / chunk));
+uint32_t solve_tiles(int64_t n0, int64_t qpad, int chunk, int vec) {
+    const int64_t nqb = (qpad + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec);
+    return uint32_t(nqb * ((n0 + chunk - 1) / chunk));
 }
 
 double alg_bytes_per_step(int precision, int rk_order, int brt, int64_t npts) {

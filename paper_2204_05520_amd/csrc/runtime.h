@@ -44,8 +44,11 @@ void alpha_bound(const odp_grid *g, const odp_dynamics *dyn, double *ab);
 size_t align256(size_t x);
 
 int default_chunk(const odp_grid *g, int vec, int precision);
-int choose_vec(const odp_grid *g, int precision, int dyn);
-uint32_t solve_tiles(const odp_grid *g, int chunk, int vec);
+// Points per thread along the last axis: the largest of 4 (float32 only), 2
+// and 1 that divides the row pitch (1 for ndim 1 and the ball-input test
+// dynamics).
+int choose_vec(const odp_grid *g, int precision, int dyn, int64_t pitch);
+uint32_t solve_tiles(int64_t n0, int64_t qpad, int chunk, int vec);
 double alg_bytes_per_step(int precision, int rk_order, int brt, int64_t npts);
 // Stage kind for launch_stage: bit 0 reads V^n, bit 1 tube clamp.
 inline int stage_kind(int rk_order, int stage, int brt) {

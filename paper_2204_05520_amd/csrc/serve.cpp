@@ -57,7 +57,8 @@ struct Req {
         if (host_pinned) (void)hipHostFree(host);
         else delete[] host;
     }
-    size_t bytes = 0;                   // one grid array
+    size_t bytes = 0;                   // one grid array (dense, host)
+    size_t row = 0, row_pitch = 0, rows = 0;  // last-axis rows: bytes, device pitch, count
     size_t footprint = 0;               // device bytes while running
     int state = R_QUEUED;
     int rc = ODP_OK;
@@ -110,19 +111,30 @@ struct Group {
     size_t tile_base = 0, list_base = 0;
 };
 
+// The server keeps its own copies of V0 and V on the device, so it stores
+// last-axis rows with a pitch padded to the 16-byte vector width: every
+// request then runs the widest vector kernel whatever its row length.
 size_t request_layout(Req &r, const odp_solve_opts &o) {
     PlanItem it;
     it.g = &r.grid;
     it.dyn = r.dyn;
     it.tau = r.tau;
     it.rk_order = r.rk_order;
+    const int64_t nl = r.grid.n[r.grid.ndim - 1];
+    const int64_t w = o.precision == 32 ? 4 : 2;
+    it.pitch = int((nl + w - 1) / w * w);
     std::vector<PlanItem> items{it};
     plan_build(r.plan, std::move(items), o, o.tile_chunk);
+    const PlanItem &pi = r.plan.items[0];
+    r.row = size_t(nl) * (o.precision == 32 ? 4 : 8);
+    r.row_pitch = size_t(pi.pitch) * (o.precision == 32 ? 4 : 8);
+    r.rows = size_t(r.grid.npts / nl);
+    const size_t padded = size_t(pi.ppad) * (o.precision == 32 ? 4 : 8);
     size_t off = r.plan.total;
     r.off_v0 = off;
-    off += align256(r.bytes);
+    off += align256(padded);
     r.off_a = off;
-    off += align256(r.bytes);
+    off += align256(padded);
     return off;
 }
 
@@ -188,7 +200,8 @@ int admit(odp_server *s, std::vector<std::shared_ptr<Req>> &admitted) {
         plan_image(r->plan, r->dmem, imgs.back());
         SolveDesc *slot = s->d_slots + r->slot;
         int rc;
-        if ((rc = check_hip(hipMemcpyAsync(r->dmem + r->off_v0, r->host, r->bytes, hipMemcpyHostToDevice, s->st), "V0")) ||
+        if ((rc = check_hip(hipMemcpy2DAsync(r->dmem + r->off_v0, r->row_pitch, r->host, r->row, r->row, r->rows,
+                                             hipMemcpyHostToDevice, s->st), "V0")) ||
             (rc = check_hip(hipMemcpyAsync(r->dmem, imgs.back().data(), imgs.back().size(), hipMemcpyHostToDevice, s->st), "image")) ||
             (rc = check_hip(hipMemcpyAsync(slot, imgs.back().data() + r->plan.desc_off, sizeof(SolveDesc),
                                            hipMemcpyHostToDevice, s->st), "slot")) ||
@@ -310,7 +323,8 @@ int retire_done(odp_server *s, std::vector<std::shared_ptr<Req>> &fin) {
         const auto &r = fin[i];
         const PlanItem &it = r->plan.items[0];
         back[i].dts.resize(static_cast<size_t>(r->nsteps));
-        if ((rc = check_hip(hipMemcpyAsync(r->host, r->dmem + r->off_a, r->bytes, hipMemcpyDeviceToHost, s->st), "result")) ||
+        if ((rc = check_hip(hipMemcpy2DAsync(r->host, r->row, r->dmem + r->off_a, r->row_pitch, r->row, r->rows,
+                                             hipMemcpyDeviceToHost, s->st), "result")) ||
             (rc = check_hip(hipMemcpyAsync(back[i].state, r->dmem + it.aux_off, sizeof(back[i].state),
                                            hipMemcpyDeviceToHost, s->st), "state")) ||
             (rc = check_hip(hipMemcpyAsync(back[i].dts.data(), r->dmem + it.sched_off, back[i].dts.size() * 8,
