@@ -42,11 +42,11 @@ def measured_traffic(kernel: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def time_solves(odp, spec, V0, precision, steps, warmup, stream, tile_chunk=0):
+def time_solves(odp, spec, V0, precision, steps, warmup, stream, tile_chunk=0, xcd_group=0):
     import torch
     grid = odp.Grid.from_spec(spec.grid)
     opts = odp.make_opts(precision, spec.rk_order, spec.cfl, spec.mode, 0, 0.0, 0, tile_chunk,
-                         odp._stream_handle(stream))
+                         odp._stream_handle(stream), xcd_group)
     wsb = odp.odp_hj_workspace_bytes(grid, spec.dyn, spec.tau, opts)
     ws = torch.empty(wsb, dtype=torch.uint8, device=V0.device)
     out = torch.empty_like(V0)
@@ -165,14 +165,17 @@ def bench_batch(args, W, odp):
     specs = W.batch_dubins3d()
     stream = torch.cuda.Stream()
     V32 = [torch.tensor(W.make_v0(s), dtype=torch.float32, device=dev) for s in specs]
+    outs = [torch.empty_like(v) for v in V32]
+    plan = odp.BatchPlan(specs, V32, outs, precision=32, tile_chunk=args.tile_chunk)
+    ws = torch.empty(plan.workspace_bytes(), dtype=torch.uint8, device=dev)
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
-            outs, stats = odp.batch(specs, V32, precision=32, stream=stream)
+            stats = plan.run(stream, ws)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         kms = []
         for _ in range(args.steps):
-            outs, stats = odp.batch(specs, V32, precision=32, stream=stream)
+            stats = plan.run(stream, ws)
             kms.append(stats[0]["kernel_ms"])
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / args.steps

@@ -116,6 +116,10 @@ typedef struct {
     int32_t save_all;    /* 1: also write V at every tau[k] into V_all_dev */
     int32_t tile_chunk;  /* 0: library default; else planes marched per block */
     void *stream;        /* hipStream_t for every launch (NULL: null stream) */
+    int32_t xcd_group;   /* 0: library default (one contiguous run of tiles per
+                            XCD; runs of 64 for grids of 2^28 points or more);
+                            g > 0: runs of g tiles dealt round robin to XCDs */
+    int32_t pad_;
 } odp_solve_opts;
 
 typedef struct {

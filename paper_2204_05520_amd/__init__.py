@@ -57,7 +57,7 @@ class odp_solve_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("rk_order", ctypes.c_int32), ("cfl", ctypes.c_double),
                 ("mode", ctypes.c_int32), ("dissipation", ctypes.c_int32), ("max_dt", ctypes.c_double),
                 ("save_all", ctypes.c_int32), ("tile_chunk", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("xcd_group", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class odp_solve_stats(ctypes.Structure):
@@ -201,7 +201,7 @@ def make_dynamics(dyn) -> odp_dynamics:
 
 
 def make_opts(precision=32, rk_order=1, cfl=0.8, mode=ODP_BRT, dissipation=0, max_dt=0.0,
-              save_all=0, tile_chunk=0, stream=None) -> odp_solve_opts:
+              save_all=0, tile_chunk=0, stream=None, xcd_group=0) -> odp_solve_opts:
     o = odp_solve_opts()
     o.precision = precision
     o.rk_order = rk_order
@@ -212,6 +212,7 @@ def make_opts(precision=32, rk_order=1, cfl=0.8, mode=ODP_BRT, dissipation=0, ma
     o.save_all = save_all
     o.tile_chunk = tile_chunk
     o.stream = stream
+    o.xcd_group = xcd_group
     return o
 
 
@@ -270,7 +271,7 @@ def check_device_tensor(x, precision, npts, name):
 
 def solve(spec, V0, precision=32, V_init=None, tau=None, stream=None, save_all=False,
           dissipation=0, max_dt=0.0, tile_chunk=0, workspace=None, rk_order=None, cfl=None,
-          mode=None) -> SolveResult:
+          mode=None, xcd_group=0) -> SolveResult:
     """One solve of a workloads.SolveSpec with a device V0 tensor."""
     import torch
     grid = Grid.from_spec(spec.grid)
@@ -281,43 +282,64 @@ def solve(spec, V0, precision=32, V_init=None, tau=None, stream=None, save_all=F
     tau = list(spec.tau if tau is None else tau)
     opts = make_opts(precision, spec.rk_order if rk_order is None else rk_order,
                      spec.cfl if cfl is None else cfl, spec.mode if mode is None else mode,
-                     dissipation, max_dt, 1 if save_all else 0, tile_chunk, _stream_handle(stream))
+                     dissipation, max_dt, 1 if save_all else 0, tile_chunk, _stream_handle(stream),
+                     xcd_group)
     out = torch.empty_like(V0)
     vall = torch.empty((len(tau),) + tuple(V0.shape), dtype=V0.dtype, device=V0.device) if save_all else None
     st = odp_hj_solve(grid, spec.dyn, V0, V_init, tau, opts, workspace, out, vall)
     return SolveResult(out, st.as_dict(), vall)
 
 
+class BatchPlan:
+    """Prebuilt odp_hj_batch arguments (grid handles, descriptors, tau arrays)
+    for repeated calls on the same solves."""
+
+    def __init__(self, specs, V0s, outs, precision=32, tile_chunk=0, dissipation=0, max_dt=0.0,
+                 xcd_group=0):
+        n = len(specs)
+        self.n = n
+        self.grids = [Grid.from_spec(s.grid) for s in specs]
+        self.outs = outs
+        self.descs = (odp_solve_desc * n)()
+        self.taus = []
+        for i, s in enumerate(specs):
+            check_device_tensor(V0s[i], precision, self.grids[i].npts, f"V0[{i}]")
+            check_device_tensor(outs[i], precision, self.grids[i].npts, f"V_out[{i}]")
+            t = _tau_array(s.tau)
+            self.taus.append(t)
+            d = self.descs[i]
+            d.grid = self.grids[i].handle
+            d.dyn = make_dynamics(s.dyn)
+            d.V0_dev = V0s[i].data_ptr()
+            d.tau = ctypes.cast(t, ctypes.POINTER(ctypes.c_double))
+            d.ntau = len(s.tau)
+            d.rk_order = int(s.rk_order)
+            d.V_out_dev = outs[i].data_ptr()
+        s0 = specs[0]
+        self.opts = make_opts(precision, s0.rk_order, s0.cfl, s0.mode, dissipation, max_dt, 0,
+                              tile_chunk, None, xcd_group)
+        self.stats = (odp_solve_stats * n)()
+
+    def workspace_bytes(self) -> int:
+        return int(lib().odp_hj_batch_workspace_bytes(self.n, self.descs, ctypes.byref(self.opts)))
+
+    def run(self, stream=None, workspace=None, want_stats=True):
+        self.opts.stream = _stream_handle(stream)
+        ws = None if workspace is None else ctypes.c_void_p(workspace.data_ptr())
+        wsb = 0 if workspace is None else workspace.numel() * workspace.element_size()
+        _check(lib().odp_hj_batch(self.n, self.descs, ctypes.byref(self.opts), ws, wsb,
+                                  self.stats if want_stats else None))
+        return [self.stats[i].as_dict() for i in range(self.n)] if want_stats else None
+
+
 def batch(specs, V0s, precision=32, stream=None, tile_chunk=0, dissipation=0, max_dt=0.0,
           workspace=None, want_stats=True):
-    """odp_hj_batch over a list of SolveSpecs (common RK order / CFL / mode)."""
+    """odp_hj_batch over a list of SolveSpecs (common CFL / mode; each spec's
+    own RK order)."""
     import torch
-    n = len(specs)
-    grids = [Grid.from_spec(s.grid) for s in specs]
     outs = [torch.empty_like(v) for v in V0s]
-    descs = (odp_solve_desc * n)()
-    taus = []
-    for i, s in enumerate(specs):
-        check_device_tensor(V0s[i], precision, grids[i].npts, f"V0[{i}]")
-        t = _tau_array(s.tau)
-        taus.append(t)
-        descs[i].grid = grids[i].handle
-        descs[i].dyn = make_dynamics(s.dyn)
-        descs[i].V0_dev = V0s[i].data_ptr()
-        descs[i].tau = ctypes.cast(t, ctypes.POINTER(ctypes.c_double))
-        descs[i].ntau = len(s.tau)
-        descs[i].rk_order = int(s.rk_order)
-        descs[i].V_out_dev = outs[i].data_ptr()
-    s0 = specs[0]
-    opts = make_opts(precision, s0.rk_order, s0.cfl, s0.mode, dissipation, max_dt, 0, tile_chunk,
-                     _stream_handle(stream))
-    stats = (odp_solve_stats * n)()
-    rc = lib().odp_hj_batch(n, descs, ctypes.byref(opts), None if workspace is None else
-                            ctypes.c_void_p(workspace.data_ptr()),
-                            0 if workspace is None else workspace.numel() * workspace.element_size(),
-                            stats if want_stats else None)
-    _check(rc)
-    return outs, [stats[i].as_dict() for i in range(n)] if want_stats else None
+    plan = BatchPlan(specs, V0s, outs, precision, tile_chunk, dissipation, max_dt)
+    return outs, plan.run(stream, workspace, want_stats)
 
 
 # ----------------------------------------------------------------- serve

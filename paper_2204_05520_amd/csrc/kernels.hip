@@ -30,13 +30,20 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f) {
     return (__umulhi(n, f.m) + n) >> f.s;
 }
 
-// Blocks are dealt round robin to the 8 XCDs; renumber them so that each
-// XCD works on one contiguous range of tiles (neighbouring tiles then share
-// that XCD's L2).
-__device__ __forceinline__ uint32_t xcd_logical(uint32_t p, uint32_t nb) {
-    const uint32_t per = nb / kNumXcd, rem = nb % kNumXcd;
+// Blocks are dealt round robin to the 8 XCDs.  Renumber them so that each
+// XCD works on runs of `group` consecutive tiles (neighbouring tiles then
+// share that XCD's L2) while the 8 XCDs advance through the tile range
+// together (one shared working set for the Infinity Cache).  group == 0: one
+// contiguous run per XCD.
+__device__ __forceinline__ uint32_t xcd_logical(uint32_t p, uint32_t nb, uint32_t group) {
     const uint32_t x = p % kNumXcd, k = p / kNumXcd;
-    return x * per + min(x, rem) + k;
+    if (group == 0) {
+        const uint32_t per = nb / kNumXcd, rem = nb % kNumXcd;
+        return x * per + min(x, rem) + k;
+    }
+    const uint32_t span = kNumXcd * group;
+    if (p >= (nb / span) * span) return p;  // the ragged tail keeps its order
+    return ((k / group) * kNumXcd + x) * group + (k % group);
 }
 
 template <typename T>
@@ -218,8 +225,8 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const SolveDesc *__restri
                                                        const uint32_t *__restrict__ tile_solve,
                                                        const uint32_t *__restrict__ tile_local,
                                                        int stage, int step_from_desc,
-                                                       int64_t fixed_step) {
-    const uint32_t L = xcd_logical(blockIdx.x, gridDim.x);
+                                                       int64_t fixed_step, int xgroup) {
+    const uint32_t L = xcd_logical(blockIdx.x, gridDim.x, uint32_t(xgroup));
     const uint32_t si = tile_solve ? tile_solve[L] : 0u;
     const uint32_t lt = tile_solve ? tile_local[L] : L;
     const SolveDesc &s = descs[si];
@@ -379,11 +386,11 @@ __global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__re
                                                            const uint32_t *__restrict__ tile_solve,
                                                            const uint32_t *__restrict__ tile_local,
                                                            int stage, int step_from_desc,
-                                                           int64_t fixed_step) {
+                                                           int64_t fixed_step, int xgroup) {
     static_assert(N >= 2, "the last axis must differ from the marched axis");
     constexpr bool kVn = KIND & 1;
     constexpr bool kClamp = KIND & 2;
-    const uint32_t L = xcd_logical(blockIdx.x, gridDim.x);
+    const uint32_t L = xcd_logical(blockIdx.x, gridDim.x, uint32_t(xgroup));
     const uint32_t si = tile_solve ? tile_solve[L] : 0u;
     const uint32_t lt = tile_solve ? tile_local[L] : L;
     const SolveDesc &s = descs[si];
@@ -649,7 +656,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void start_copy_kernel(const SolveDesc *__restrict__ descs,
                                                             const uint32_t *__restrict__ tile_solve,
                                                             const uint32_t *__restrict__ tile_local) {
-    const uint32_t L = xcd_logical(blockIdx.x, gridDim.x);
+    const uint32_t L = xcd_logical(blockIdx.x, gridDim.x, 0u);
     const uint32_t si = tile_solve ? tile_solve[L] : 0u;
     const uint32_t lt = tile_solve ? tile_local[L] : L;
     const SolveDesc &s = descs[si];
@@ -671,17 +678,17 @@ __global__ __launch_bounds__(kBlock) void start_copy_kernel(const SolveDesc *__r
 
 template <typename T, int DYN, int N, int VEC>
 static hipError_t launch_stage_t(int kind, const SolveDesc *d, const uint32_t *ts, const uint32_t *tl,
-                                 uint32_t nblocks, int stage, int from_desc, int64_t step,
+                                 uint32_t nblocks, int stage, int from_desc, int64_t step, int xg,
                                  hipStream_t st) {
     if constexpr (N == 1) {
         hipLaunchKernelGGL((stage_kernel<T, DYN, N>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl,
-                           stage, from_desc, step);
+                           stage, from_desc, step, xg);
     } else {
         switch (kind) {
-        case 0: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 0>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step); break;
-        case 1: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 1>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step); break;
-        case 2: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 2>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step); break;
-        default: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 3>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step); break;
+        case 0: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 0>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
+        case 1: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 1>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
+        case 2: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 2>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
+        default: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 3>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
         }
     }
     return hipGetLastError();
@@ -690,34 +697,34 @@ static hipError_t launch_stage_t(int kind, const SolveDesc *d, const uint32_t *t
 template <typename T, int DYN, int N>
 static hipError_t launch_stage_v(int vec, int kind, const SolveDesc *d, const uint32_t *ts,
                                  const uint32_t *tl, uint32_t nb, int stage, int fd, int64_t step,
-                                 hipStream_t st) {
+                                 int xg, hipStream_t st) {
     if constexpr (N == 1 || DYN == 0) {
-        return launch_stage_t<T, DYN, N, 1>(kind, d, ts, tl, nb, stage, fd, step, st);
+        return launch_stage_t<T, DYN, N, 1>(kind, d, ts, tl, nb, stage, fd, step, xg, st);
     } else {
         if constexpr (sizeof(T) == 4) {
-            if (vec == 4) return launch_stage_t<T, DYN, N, 4>(kind, d, ts, tl, nb, stage, fd, step, st);
+            if (vec == 4) return launch_stage_t<T, DYN, N, 4>(kind, d, ts, tl, nb, stage, fd, step, xg, st);
         }
-        if (vec == 2) return launch_stage_t<T, DYN, N, 2>(kind, d, ts, tl, nb, stage, fd, step, st);
-        return launch_stage_t<T, DYN, N, 1>(kind, d, ts, tl, nb, stage, fd, step, st);
+        if (vec == 2) return launch_stage_t<T, DYN, N, 2>(kind, d, ts, tl, nb, stage, fd, step, xg, st);
+        return launch_stage_t<T, DYN, N, 1>(kind, d, ts, tl, nb, stage, fd, step, xg, st);
     }
 }
 
 template <typename T>
 static hipError_t launch_stage_p(int dyn, int ndim, int vec, int kind, const SolveDesc *d,
                                  const uint32_t *ts, const uint32_t *tl, uint32_t nb, int stage,
-                                 int fd, int64_t step, hipStream_t st) {
+                                 int fd, int64_t step, int xg, hipStream_t st) {
     switch (dyn) {
-    case 1: return launch_stage_v<T, 1, 3>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
-    case 2: return launch_stage_v<T, 2, 4>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
-    case 3: return launch_stage_v<T, 3, 6>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
+    case 1: return launch_stage_v<T, 1, 3>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
+    case 2: return launch_stage_v<T, 2, 4>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
+    case 3: return launch_stage_v<T, 3, 6>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
     case 0:
         switch (ndim) {
-        case 1: return launch_stage_v<T, 0, 1>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
-        case 2: return launch_stage_v<T, 0, 2>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
-        case 3: return launch_stage_v<T, 0, 3>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
-        case 4: return launch_stage_v<T, 0, 4>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
-        case 5: return launch_stage_v<T, 0, 5>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
-        case 6: return launch_stage_v<T, 0, 6>(vec, kind, d, ts, tl, nb, stage, fd, step, st);
+        case 1: return launch_stage_v<T, 0, 1>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
+        case 2: return launch_stage_v<T, 0, 2>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
+        case 3: return launch_stage_v<T, 0, 3>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
+        case 4: return launch_stage_v<T, 0, 4>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
+        case 5: return launch_stage_v<T, 0, 5>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
+        case 6: return launch_stage_v<T, 0, 6>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
         }
     }
     return hipErrorInvalidValue;
@@ -728,10 +735,10 @@ static hipError_t launch_stage_p(int dyn, int ndim, int vec, int kind, const Sol
 // must match what every listed solve does at this stage.
 hipError_t launch_stage(int precision, int dyn, int ndim, int vec, int kind, const SolveDesc *d,
                         const uint32_t *ts, const uint32_t *tl, uint32_t nblocks, int stage,
-                        int from_desc, int64_t step, hipStream_t st) {
+                        int from_desc, int64_t step, int xgroup, hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
-    if (precision == 32) return launch_stage_p<float>(dyn, ndim, vec, kind, d, ts, tl, nblocks, stage, from_desc, step, st);
-    return launch_stage_p<double>(dyn, ndim, vec, kind, d, ts, tl, nblocks, stage, from_desc, step, st);
+    if (precision == 32) return launch_stage_p<float>(dyn, ndim, vec, kind, d, ts, tl, nblocks, stage, from_desc, step, xgroup, st);
+    return launch_stage_p<double>(dyn, ndim, vec, kind, d, ts, tl, nblocks, stage, from_desc, step, xgroup, st);
 }
 
 template <int DYN, int N>

@@ -40,9 +40,12 @@ int balanced_chunk(const odp_grid *g, int c) {
 std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solve_opts &opts,
                             int tile_chunk) {
     p.opts = opts;
+    p.xcd_group = opts.xcd_group > 0 ? opts.xcd_group
+                                     : (items.size() == 1 ? default_xcd_group(items[0].g) : 0);
     const int prec = opts.precision;
     const size_t eb = prec == 32 ? 4 : 8;
     const int n = int(items.size());
+    int64_t total = 0;
     for (auto &it : items) {
         if (it.rk_order <= 0) it.rk_order = opts.rk_order;
         const int64_t nl = it.g->n[it.g->ndim - 1];
@@ -50,7 +53,19 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         it.qpad = it.g->ndim < 2 ? 1 : (it.g->npts / it.g->n[0] / nl) * it.pitch;
         it.ppad = it.qpad * it.g->n[0];
         it.vec = choose_vec(it.g, prec, it.dyn.id, it.pitch);
-        it.chunk = balanced_chunk(it.g, tile_chunk > 0 ? tile_chunk : default_chunk(it.g, it.vec, prec));
+        total += it.ppad;
+    }
+    for (auto &it : items) {
+        int c = tile_chunk;
+        if (c <= 0) {
+            if (items.size() == 1) {
+                c = default_chunk(it.g, it.vec, prec);
+            } else {
+                // many solves share every launch: about 8192 blocks in all
+                c = int(std::max<int64_t>(1, total / (int64_t(kBlock) * it.vec * 8192)));
+            }
+        }
+        it.chunk = balanced_chunk(it.g, c);
         it.tiles = solve_tiles(it.g->n[0], it.qpad, it.chunk, it.vec);
         it.max_steps = step_capacity(it.g, &it.dyn, it.tau, opts.cfl, opts.max_dt);
         it.tab_entries = 0;
@@ -282,7 +297,7 @@ int plan_steps(Plan &p, unsigned char *base, hipStream_t st, const std::vector<i
             const uint32_t *tl = tld ? tld + gr.tile_base : nullptr;
             for (int j = 0; j < gr.rk; ++j) {
                 if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, stage_kind(gr.rk, j, brt),
-                                                 descs, ts, tl, nb, j, 0, k, st), "stage")))
+                                                 descs, ts, tl, nb, j, 0, k, p.xcd_group, st), "stage")))
                     return rc;
             }
         }

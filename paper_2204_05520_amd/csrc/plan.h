@@ -53,6 +53,7 @@ struct Plan {
     size_t desc_off = 0, nsteps_off = 0, aux_begin = 0, upload_bytes = 0;
     size_t tt_off = 0, total_tiles = 0, sched_begin = 0, arr_begin = 0, total = 0;
     int64_t max_nsteps = 0;
+    int xcd_group = 0;                  // tile runs per XCD for the stage launches
 };
 
 // Order items by (dynamics, ndim, vector width, RK order), fill the layout.

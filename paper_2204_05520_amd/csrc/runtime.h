@@ -23,7 +23,7 @@ namespace odp {
 // kernels.hip
 hipError_t launch_stage(int precision, int dyn, int ndim, int vec, int kind, const SolveDesc *d,
                         const uint32_t *ts, const uint32_t *tl, uint32_t nblocks, int stage,
-                        int from_desc, int64_t step, hipStream_t st);
+                        int from_desc, int64_t step, int xgroup, hipStream_t st);
 hipError_t launch_alpha(int dyn, int ndim, const SolveDesc *d, int nsolves, int blocks_per_solve,
                         hipStream_t st);
 hipError_t launch_init(const SolveDesc *d, int nsolves, hipStream_t st);
@@ -44,6 +44,7 @@ void alpha_bound(const odp_grid *g, const odp_dynamics *dyn, double *ab);
 size_t align256(size_t x);
 
 int default_chunk(const odp_grid *g, int vec, int precision);
+int default_xcd_group(const odp_grid *g);
 // Points per thread along the last axis: the largest of 4 (float32 only), 2
 // and 1 that divides the row pitch (1 for ndim 1 and the ball-input test
 // dynamics).

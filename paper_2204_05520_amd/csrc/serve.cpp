@@ -297,7 +297,8 @@ int tick(odp_server *s, const std::vector<Group> &groups) {
             for (int j = 0; j < g.rk; ++j) {
                 if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, stage_kind(g.rk, j, brt),
                                                  s->d_slots, s->d_tiles + g.tile_base,
-                                                 s->d_tiles + s->tile_cap + g.tile_base, g.tiles, j, 1, 0, s->st),
+                                                 s->d_tiles + s->tile_cap + g.tile_base, g.tiles, j, 1, 0,
+                                                 s->opts.xcd_group, s->st),
                                     "stage")))
                     return rc;
             }
