@@ -119,7 +119,10 @@ typedef struct {
     int32_t xcd_group;   /* 0: library default (one contiguous run of tiles per
                             XCD; runs of 64 for grids of 2^28 points or more);
                             g > 0: runs of g tiles dealt round robin to XCDs */
-    int32_t pad_;
+    int32_t graph;       /* time stepping recorded into one HIP graph and
+                            replayed: 0 auto (small grids on a non-null
+                            stream), 1 always (non-null stream), 2 never.
+                            With a graph the call returns after completion. */
 } odp_solve_opts;
 
 typedef struct {

@@ -57,7 +57,7 @@ class odp_solve_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("rk_order", ctypes.c_int32), ("cfl", ctypes.c_double),
                 ("mode", ctypes.c_int32), ("dissipation", ctypes.c_int32), ("max_dt", ctypes.c_double),
                 ("save_all", ctypes.c_int32), ("tile_chunk", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("xcd_group", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("stream", ctypes.c_void_p), ("xcd_group", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class odp_solve_stats(ctypes.Structure):
@@ -201,7 +201,7 @@ def make_dynamics(dyn) -> odp_dynamics:
 
 
 def make_opts(precision=32, rk_order=1, cfl=0.8, mode=ODP_BRT, dissipation=0, max_dt=0.0,
-              save_all=0, tile_chunk=0, stream=None, xcd_group=0) -> odp_solve_opts:
+              save_all=0, tile_chunk=0, stream=None, xcd_group=0, graph=0) -> odp_solve_opts:
     o = odp_solve_opts()
     o.precision = precision
     o.rk_order = rk_order
@@ -213,6 +213,7 @@ def make_opts(precision=32, rk_order=1, cfl=0.8, mode=ODP_BRT, dissipation=0, ma
     o.tile_chunk = tile_chunk
     o.stream = stream
     o.xcd_group = xcd_group
+    o.graph = graph
     return o
 
 
@@ -271,7 +272,7 @@ def check_device_tensor(x, precision, npts, name):
 
 def solve(spec, V0, precision=32, V_init=None, tau=None, stream=None, save_all=False,
           dissipation=0, max_dt=0.0, tile_chunk=0, workspace=None, rk_order=None, cfl=None,
-          mode=None, xcd_group=0) -> SolveResult:
+          mode=None, xcd_group=0, graph=0) -> SolveResult:
     """One solve of a workloads.SolveSpec with a device V0 tensor."""
     import torch
     grid = Grid.from_spec(spec.grid)
@@ -283,7 +284,7 @@ def solve(spec, V0, precision=32, V_init=None, tau=None, stream=None, save_all=F
     opts = make_opts(precision, spec.rk_order if rk_order is None else rk_order,
                      spec.cfl if cfl is None else cfl, spec.mode if mode is None else mode,
                      dissipation, max_dt, 1 if save_all else 0, tile_chunk, _stream_handle(stream),
-                     xcd_group)
+                     xcd_group, graph)
     out = torch.empty_like(V0)
     vall = torch.empty((len(tau),) + tuple(V0.shape), dtype=V0.dtype, device=V0.device) if save_all else None
     st = odp_hj_solve(grid, spec.dyn, V0, V_init, tau, opts, workspace, out, vall)

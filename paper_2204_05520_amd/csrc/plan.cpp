@@ -270,8 +270,8 @@ int plan_prologue(Plan &p, unsigned char *base, hipStream_t st) {
     return ODP_OK;
 }
 
-int plan_steps(Plan &p, unsigned char *base, hipStream_t st, const std::vector<int32_t> *land,
-               void *V_all) {
+static int plan_enqueue(Plan &p, unsigned char *base, hipStream_t st, const std::vector<int32_t> *land,
+                        void *V_all) {
     int rc;
     const odp_solve_opts &o = p.opts;
     const int prec = o.precision;
@@ -341,6 +341,45 @@ int plan_stats(const Plan &p, unsigned char *base, double kernel_ms, odp_solve_s
     }
     if (worst != ODP_OK) return set_error(worst, "NaN or Inf in the value function");
     return ODP_OK;
+}
+
+}  // namespace odp
+
+namespace odp {
+
+// Launch-bound plans (small grids, many steps) are recorded into one HIP
+// graph and replayed with a single launch; the call then waits for the
+// graph to finish before it frees the executable graph.
+bool plan_wants_graph(const Plan &p) {
+    if (p.opts.graph == 2 || p.opts.stream == nullptr) return false;
+    if (p.opts.graph == 1) return true;
+    int64_t pts = 0;
+    for (const auto &it : p.items) pts = std::max<int64_t>(pts, it.ppad);
+    return pts <= (int64_t(1) << 22) && p.max_nsteps * int64_t(p.groups.size()) >= 8;
+}
+
+int plan_steps(Plan &p, unsigned char *base, hipStream_t st, const std::vector<int32_t> *land,
+               void *V_all) {
+    if (!plan_wants_graph(p)) return plan_enqueue(p, base, st, land, V_all);
+    int rc;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if ((rc = check_hip(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture")))
+        return rc;
+    const int erc = plan_enqueue(p, base, st, land, V_all);
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (erc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return erc;
+    }
+    if ((rc = check_hip(ec, "end capture"))) return rc;
+    rc = check_hip(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
+    (void)hipGraphDestroy(graph);
+    if (rc) return rc;
+    rc = check_hip(hipGraphLaunch(exec, st), "graph launch");
+    if (!rc) rc = check_hip(hipStreamSynchronize(st), "sync");
+    (void)hipGraphExecDestroy(exec);
+    return rc;
 }
 
 }  // namespace odp

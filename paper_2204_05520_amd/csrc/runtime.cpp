@@ -78,6 +78,7 @@ int validate_opts(const odp_solve_opts *o) {
     if (o->save_all != 0 && o->save_all != 1) return set_error(ODP_EINVAL, "save_all must be 0 or 1");
     if (o->tile_chunk < 0) return set_error(ODP_EINVAL, "tile_chunk must be >= 0");
     if (o->xcd_group < 0) return set_error(ODP_EINVAL, "xcd_group must be >= 0");
+    if (o->graph < 0 || o->graph > 2) return set_error(ODP_EINVAL, "graph must be 0, 1 or 2");
     return ODP_OK;
 }
 

@@ -146,3 +146,20 @@ def test_nonfinite_reported(odp):
     with pytest.raises(odp.OdpError) as ei:
         odp.solve(spec, t, precision=32)
     assert ei.value.code == odp.ODP_ENONFINITE
+
+
+def test_graph_replays_equal_eager(odp):
+    """The time stepping recorded into a HIP graph (small grids on a stream)
+    gives the eager launches' bits, call after call, with eager work and
+    synchronisations in between."""
+    import torch
+    stream = torch.cuda.Stream()
+    for spec in (W.config_dubins3d(n=(30, 28, 20), T=0.8), W.config_dyncar4d(n=[12, 11, 9, 16], T=0.3)):
+        V0 = W.make_v0(spec)
+        for prec in (64, 32):
+            eager = gpu_solve(odp, spec, V0, prec, graph=2, stream=stream).V.cpu()
+            for rep in range(3):
+                g = gpu_solve(odp, spec, V0, prec, graph=1, stream=stream).V.cpu()
+                e = gpu_solve(odp, spec, V0, prec, graph=2, stream=stream).V.cpu()
+                same = bool(torch.equal(g, eager)) and bool(torch.equal(e, eager))
+                assert same, (spec.name, prec, rep)
