@@ -314,20 +314,22 @@ static int plan_enqueue(Plan &p, unsigned char *base, hipStream_t st, const std:
 int plan_stats(const Plan &p, unsigned char *base, double kernel_ms, odp_solve_stats *stats) {
     int rc;
     const odp_solve_opts &o = p.opts;
+    // two bulk copies: every solve's state/tables/tau, every schedule
+    std::vector<unsigned char> aux(p.upload_bytes - p.aux_begin), sched(p.arr_begin - p.sched_begin);
+    if ((rc = check_hip(hipMemcpy(aux.data(), base + p.aux_begin, aux.size(), hipMemcpyDeviceToHost), "read state")) ||
+        (rc = check_hip(hipMemcpy(sched.data(), base + p.sched_begin, sched.size(), hipMemcpyDeviceToHost),
+                        "read schedules")))
+        return rc;
     int worst = ODP_OK;
     for (size_t i = 0; i < p.items.size(); ++i) {
         const PlanItem &it = p.items[i];
-        unsigned char state[kMaxDim * 8 + 24];
-        std::vector<double> dts(static_cast<size_t>(it.nsteps));
-        if ((rc = check_hip(hipMemcpy(state, base + it.aux_off, sizeof(state), hipMemcpyDeviceToHost), "read state")) ||
-            (rc = check_hip(hipMemcpy(dts.data(), base + it.sched_off, dts.size() * 8, hipMemcpyDeviceToHost),
-                            "read schedule")))
-            return rc;
+        const unsigned char *state = aux.data() + (it.aux_off - p.aux_begin);
+        const double *dts = (const double *)(sched.data() + (it.sched_off - p.sched_begin));
         odp_solve_stats &sx = stats[i];
         std::memset(&sx, 0, sizeof(sx));
         sx.steps = it.nsteps;
-        sx.dt_min = *std::min_element(dts.begin(), dts.end());
-        sx.dt_max = *std::max_element(dts.begin(), dts.end());
+        sx.dt_min = *std::min_element(dts, dts + it.nsteps);
+        sx.dt_max = *std::max_element(dts, dts + it.nsteps);
         sx.t_final = it.tau.back();
         sx.kernel_ms = kernel_ms;
         sx.alg_bytes = alg_bytes_per_step(o.precision, it.rk_order, o.mode == ODP_BRT, it.g->npts) * double(it.nsteps);

@@ -123,8 +123,14 @@ size_t request_layout(Req &r, const odp_solve_opts &o) {
     const int64_t nl = r.grid.n[r.grid.ndim - 1];
     const int64_t w = o.precision == 32 ? 4 : 2;
     it.pitch = int((nl + w - 1) / w * w);
+    // many requests share every launch: march at least 8 planes per block
+    int chunk = o.tile_chunk;
+    if (chunk <= 0) {
+        int vec = choose_vec(&r.grid, o.precision, r.dyn.id, it.pitch);
+        chunk = std::max(default_chunk(&r.grid, vec, o.precision), int(std::min<int64_t>(8, r.grid.n[0])));
+    }
     std::vector<PlanItem> items{it};
-    plan_build(r.plan, std::move(items), o, o.tile_chunk);
+    plan_build(r.plan, std::move(items), o, chunk);
     const PlanItem &pi = r.plan.items[0];
     r.row = size_t(nl) * (o.precision == 32 ? 4 : 8);
     r.row_pitch = size_t(pi.pitch) * (o.precision == 32 ? 4 : 8);
