@@ -226,6 +226,7 @@ def bench_serve(args, W, odp):
     lat = [None] * len(reqs)
     steps = [0] * len(reqs)
     pts = [0] * len(reqs)
+    algb = [0.0] * len(reqs)
     lock = threading.Lock()
     t0 = time.perf_counter()
 
@@ -257,6 +258,7 @@ def bench_serve(args, W, odp):
                 lat[i] = st["latency_ms"]
                 steps[i] = st["steps"]
                 pts[i] = reqs[i].spec.grid.npts * st["steps"]
+                algb[i] = st["alg_bytes"]
                 remaining.discard(i)
                 progressed = True
     wall = time.perf_counter() - t0
@@ -276,6 +278,8 @@ def bench_serve(args, W, odp):
         "latency_ms": {"p50": float(np.percentile(meas, 50)), "p90": float(np.percentile(meas, 90)),
                        "p99": float(np.percentile(meas, 99)), "max": float(meas.max())},
         "completed_per_s": nreq / span,
+        "alg_tbps_over_run": sum(algb[warm:]) / span / 1e12,
+        "offered_alg_tbps": sum(algb[warm:]) / (reqs[-1].arrival_s - t_first) / 1e12,
     }
     return line
 

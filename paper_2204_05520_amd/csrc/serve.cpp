@@ -7,9 +7,10 @@
 //      request's device footprint fits the HBM budget (allocation, V0 upload,
 //      alpha^max and float64 schedule on the device, one synchronisation for
 //      the step counts);
-//   2. runs one tick: every active solve advances by up to kStepsPerTick
-//      steps, one batched launch per RK stage and kernel group, each solve
-//      reading its own step counter on the device;
+//   2. runs one tick: the active solves with the least remaining work (up to
+//      a work budget) advance by up to kStepsPerTick steps, one batched
+//      launch per RK stage and kernel group, each solve reading its own step
+//      counter on the device;
 //   3. retires finished solves (result copied to the host, memory freed).
 // Requests that arrive while others run therefore join at the next tick and
 // share every launch with them.  The per-point arithmetic is the same as in
@@ -37,6 +38,8 @@ using namespace odp;
 namespace {
 
 constexpr int kStepsPerTick = 8;
+constexpr double kTickWork = 2.0e9;   // point-stage updates per tick (a few ms)
+constexpr double kMaxWaitMs = 1500.0;
 constexpr size_t kMaxQueue = 1 << 16;
 
 enum { R_QUEUED = 0, R_RUNNING = 1, R_DONE = 2 };
@@ -242,10 +245,10 @@ int admit(odp_server *s, std::vector<std::shared_ptr<Req>> &admitted) {
     return ODP_OK;
 }
 
-int build_groups(odp_server *s, std::vector<Group> &groups) {
+int build_groups(odp_server *s, const std::vector<std::shared_ptr<Req>> &sel, std::vector<Group> &groups) {
     groups.clear();
     std::map<std::tuple<int, int, int, int>, size_t> idx;
-    for (auto &r : s->active) {
+    for (auto &r : sel) {
         const PlanItem &it = r->plan.items[0];
         auto key = std::make_tuple(r->dyn.id, r->grid.ndim, it.vec, it.rk_order);
         auto f = idx.find(key);
@@ -259,7 +262,7 @@ int build_groups(odp_server *s, std::vector<Group> &groups) {
     std::vector<uint32_t> ts, tl;
     std::vector<int32_t> list;
     std::vector<const Req *> by_slot(size_t(s->max_slots), nullptr);
-    for (auto &r : s->active) by_slot[size_t(r->slot)] = r.get();
+    for (auto &r : sel) by_slot[size_t(r->slot)] = r.get();
     for (Group &g : groups) {
         g.tile_base = ts.size();
         g.list_base = list.size();
@@ -381,6 +384,7 @@ void fail_all(odp_server *s, int rc) {
 void scheduler(odp_server *s) {
     (void)hipSetDevice(s->device);
     std::vector<Group> groups;
+    std::vector<uint64_t> last_sel;
     bool dirty = true;
     for (;;) {
         {
@@ -417,11 +421,36 @@ void scheduler(odp_server *s) {
             }
         }
         if (s->active.empty()) continue;
+        // This tick advances the requests with the least remaining work
+        // first, up to about kTickWork point-stage updates (at least one
+        // request; any request waiting longer than kMaxWaitMs joins anyway),
+        // so that small requests are not held behind large ones.
+        std::vector<std::shared_ptr<Req>> order = s->active, sel;
+        auto work = [](const std::shared_ptr<Req> &r, int64_t steps) {
+            return double(steps) * double(r->plan.items[0].ppad) * double(r->plan.items[0].rk_order);
+        };
+        std::stable_sort(order.begin(), order.end(), [&](const std::shared_ptr<Req> &a, const std::shared_ptr<Req> &b) {
+            return work(a, a->nsteps - a->step) < work(b, b->nsteps - b->step);
+        });
+        const auto now = Clock::now();
+        double acc = 0.0;
+        for (auto &r : order) {
+            const double w = work(r, std::min<int64_t>(kStepsPerTick, r->nsteps - r->step));
+            const double age = std::chrono::duration<double, std::milli>(now - r->t_submit).count();
+            if (sel.empty() || acc + w <= kTickWork || age > kMaxWaitMs) {
+                sel.push_back(r);
+                acc += w;
+            }
+        }
+        std::vector<uint64_t> sel_ids;
+        for (auto &r : sel) sel_ids.push_back(r->ticket);
+        if (sel_ids != last_sel) dirty = true;
         if (dirty) {
-            if (build_groups(s, groups) != ODP_OK) {
+            if (build_groups(s, sel, groups) != ODP_OK) {
                 fail_all(s, ODP_EHIP);
                 continue;
             }
+            last_sel = sel_ids;
             dirty = false;
         }
         if (tick(s, groups) != ODP_OK) {
@@ -430,9 +459,9 @@ void scheduler(odp_server *s) {
             continue;
         }
         std::vector<std::shared_ptr<Req>> fin;
+        for (auto &r : sel) r->step = std::min<int64_t>(r->step + kStepsPerTick, r->nsteps);
         for (size_t i = 0; i < s->active.size();) {
             auto &r = s->active[i];
-            r->step = std::min<int64_t>(r->step + kStepsPerTick, r->nsteps);
             if (r->step >= r->nsteps) {
                 fin.push_back(r);
                 s->active.erase(s->active.begin() + long(i));
