@@ -1,20 +1,26 @@
 // Continuous-batching server: odp_server_create / odp_serve_submit /
-// odp_serve_poll / odp_serve_cancel / odp_server_destroy.
+// odp_serve_poll / odp_serve_cancel / odp_server_counts / odp_server_destroy.
 //
-// A scheduler thread owns a device slot table of solve descriptors.  Each
-// iteration it
-//   1. admits queued requests in arrival order while a slot is free and the
-//      request's device footprint fits the HBM budget (allocation, V0 upload,
-//      alpha^max and float64 schedule on the device, one synchronisation for
-//      the step counts);
-//   2. runs one tick: the active solves with the least remaining work (up to
-//      a work budget) advance by up to kStepsPerTick steps, one batched
-//      launch per RK stage and kernel group, each solve reading its own step
-//      counter on the device;
-//   3. retires finished solves (result copied to the host, memory freed).
-// Requests that arrive while others run therefore join at the next tick and
-// share every launch with them.  The per-point arithmetic is the same as in
-// odp_hj_solve, so a served result equals the solve run alone, bit for bit.
+// A scheduler thread owns a device slot table of solve descriptors and three
+// streams, so that uploads, downloads and the per-request prologue overlap
+// the time stepping of the requests already running:
+//   admission (upload stream): in arrival order, while a slot is free and the
+//     request's device footprint fits the HBM budget: allocation, V0 upload,
+//     descriptor, alpha^max and the float64 schedule on the device, the start
+//     copy and the step count read back; an event marks it ready;
+//   tick (compute stream): the ready requests with the least remaining work
+//     (up to a work budget; long-waiting ones always) advance by up to
+//     kStepsPerTick steps, one batched launch per RK stage and kernel group,
+//     each solve reading its own step counter on the device; at most two
+//     ticks are in flight while the host prepares the next;
+//   retirement (download stream, after the tick that finished the request):
+//     result, state and schedule to pinned host memory; an event marks it
+//     done, then the device memory and the slot are released.
+// The host mirrors every solve's step count, so it knows which tick finishes
+// a request without reading the device.  Requests that arrive while others
+// run join at a later tick and share every launch with them.  The per-point
+// arithmetic is the same as in odp_hj_solve, so a served result equals the
+// solve run alone, bit for bit.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -38,9 +44,11 @@ using namespace odp;
 namespace {
 
 constexpr int kStepsPerTick = 8;
+constexpr int kTicksInFlight = 2;
 constexpr double kTickWork = 2.0e9;   // point-stage updates per tick (a few ms)
 constexpr double kMaxWaitMs = 1500.0;
 constexpr size_t kMaxQueue = 1 << 16;
+constexpr size_t kStateBytes = kMaxDim * 8 + 24;  // alpha^max, time, flags
 
 enum { R_QUEUED = 0, R_RUNNING = 1, R_DONE = 2 };
 
@@ -52,17 +60,13 @@ struct Req {
     odp_dynamics dyn{};
     std::vector<double> tau;
     int rk_order = 1;
-    // Host copy of V0 in pinned memory (so that the scheduler's upload is an
+    // Host copy of V0 in pinned memory (so that the upload is an
     // asynchronous DMA); the same buffer later receives V(tau_last).
     unsigned char *host = nullptr;
     bool host_pinned = false;
-    ~Req() {
-        if (host_pinned) (void)hipHostFree(host);
-        else delete[] host;
-    }
-    size_t bytes = 0;                   // one grid array (dense, host)
+    size_t bytes = 0;                         // one grid array (dense, host)
     size_t row = 0, row_pitch = 0, rows = 0;  // last-axis rows: bytes, device pitch, count
-    size_t footprint = 0;               // device bytes while running
+    size_t footprint = 0;                     // device bytes while running
     int state = R_QUEUED;
     int rc = ODP_OK;
     bool cancel = false;
@@ -74,6 +78,20 @@ struct Req {
     int slot = -1;
     Plan plan;
     int64_t nsteps = 0, step = 0;
+    hipEvent_t ev = nullptr;  // admission, then retirement, done
+    ~Req() {
+        if (host_pinned) (void)hipHostFree(host);
+        else delete[] host;
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
+
+// Pinned host staging whose last transfer is marked by an event.
+struct Staging {
+    unsigned char *p = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
 };
 
 }  // namespace
@@ -83,12 +101,19 @@ struct odp_server {
     size_t budget = 0;
     int max_slots = 0;
     int device = 0;
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr;   // ticks
+    hipStream_t ust = nullptr;  // admissions
+    hipStream_t dst = nullptr;  // retirements
     SolveDesc *d_slots = nullptr;
     int64_t *d_nsteps = nullptr;
+    int64_t *h_nsteps = nullptr;  // pinned, one per slot
     uint32_t *d_tiles = nullptr;  // [cap] solve slot, [cap] local tile
     int32_t *d_list = nullptr;    // [max_slots] per-group member slots
     size_t tile_cap = 0;
+    Staging tab[2];               // tile tables on their way to the device
+    int tab_next = 0;
+    std::vector<Staging> up;      // per slot: descriptor image sent up
+    std::vector<Staging> back;    // per slot: state and schedule read back
 
     std::mutex mu;
     std::condition_variable cv;
@@ -99,7 +124,9 @@ struct odp_server {
     int running = 0, done = 0;
 
     // scheduler thread only
-    std::vector<std::shared_ptr<Req>> active;
+    std::vector<std::shared_ptr<Req>> admitting, active, retiring;
+    std::deque<hipEvent_t> ticks;
+    std::vector<hipEvent_t> ev_pool;
     std::vector<int> free_slots;
     size_t used = 0;
     std::thread th;
@@ -113,6 +140,37 @@ struct Group {
     uint32_t tiles = 0;
     size_t tile_base = 0, list_base = 0;
 };
+
+int get_event(odp_server *s, hipEvent_t *ev) {
+    if (!s->ev_pool.empty()) {
+        *ev = s->ev_pool.back();
+        s->ev_pool.pop_back();
+        return ODP_OK;
+    }
+    return check_hip(hipEventCreateWithFlags(ev, hipEventDisableTiming), "event");
+}
+
+void put_event(odp_server *s, hipEvent_t &ev) {
+    if (ev) s->ev_pool.push_back(ev);
+    ev = nullptr;
+}
+
+// Grow a pinned staging buffer after its last transfer has finished.
+int stage_reserve(Staging &b, size_t need) {
+    int rc;
+    if (b.pending) {
+        if ((rc = check_hip(hipEventSynchronize(b.ev), "staging"))) return rc;
+        b.pending = false;
+    }
+    if (need <= b.cap) return ODP_OK;
+    if (b.p) (void)hipHostFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    const size_t cap = std::max<size_t>(need, 4096);
+    if ((rc = check_hip(hipHostMalloc((void **)&b.p, cap, hipHostMallocDefault), "pinned staging"))) return rc;
+    b.cap = cap;
+    return ODP_OK;
+}
 
 // The server keeps its own copies of V0 and V on the device, so it stores
 // last-axis rows with a pitch padded to the 16-byte vector width: every
@@ -156,16 +214,20 @@ void finish(odp_server *s, const std::shared_ptr<Req> &r, int rc) {
     s->done++;
 }
 
+// Release the request's device memory and slot.  Callers guarantee that no
+// work still in flight on any stream touches either (the last use has
+// completed, or every stream has been synchronised).
 void release(odp_server *s, const std::shared_ptr<Req> &r) {
-    if (r->dmem) (void)hipFreeAsync(r->dmem, s->st);
+    if (r->dmem) (void)hipFreeAsync(r->dmem, s->ust);
     r->dmem = nullptr;
     if (r->slot >= 0) s->free_slots.push_back(r->slot);
     r->slot = -1;
     s->used -= r->footprint;
+    put_event(s, r->ev);
 }
 
-// Admit what fits; returns the admitted requests (already launched).
-int admit(odp_server *s, std::vector<std::shared_ptr<Req>> &admitted) {
+// Enqueue the admission of every queued request that fits (upload stream).
+void admit(odp_server *s) {
     std::vector<std::shared_ptr<Req>> take;
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -190,11 +252,10 @@ int admit(odp_server *s, std::vector<std::shared_ptr<Req>> &admitted) {
         }
     }
     const odp_solve_opts &o = s->opts;
-    std::vector<std::vector<unsigned char>> imgs;
-    std::vector<std::shared_ptr<Req>> launched;
     for (auto &r : take) {
         void *mem = nullptr;
-        if (hipMallocAsync(&mem, r->footprint, s->st) != hipSuccess) {
+        if (hipMallocAsync(&mem, r->footprint, s->ust) != hipSuccess) {
+            (void)hipGetLastError();
             finish(s, r, set_error(ODP_ENOMEM, "server: device allocation failed"));
             continue;
         }
@@ -205,46 +266,116 @@ int admit(odp_server *s, std::vector<std::shared_ptr<Req>> &admitted) {
         PlanItem &it = r->plan.items[0];
         it.V0 = r->dmem + r->off_v0;
         it.A = r->dmem + r->off_a;
-        imgs.emplace_back();
-        plan_image(r->plan, r->dmem, imgs.back());
+        std::vector<unsigned char> img;
+        plan_image(r->plan, r->dmem, img);
         SolveDesc *slot = s->d_slots + r->slot;
-        int rc;
-        if ((rc = check_hip(hipMemcpy2DAsync(r->dmem + r->off_v0, r->row_pitch, r->host, r->row, r->row, r->rows,
-                                             hipMemcpyHostToDevice, s->st), "V0")) ||
-            (rc = check_hip(hipMemcpyAsync(r->dmem, imgs.back().data(), imgs.back().size(), hipMemcpyHostToDevice, s->st), "image")) ||
-            (rc = check_hip(hipMemcpyAsync(slot, imgs.back().data() + r->plan.desc_off, sizeof(SolveDesc),
-                                           hipMemcpyHostToDevice, s->st), "slot")) ||
-            (rc = check_hip(launch_init(slot, 1, s->st), "init")) ||
+        // every source is pinned, so each copy is a DMA in stream order; the
+        // slot's staging is reused only after this admission has finished
+        Staging &up = s->up[size_t(r->slot)];
+        int rc = stage_reserve(up, img.size());
+        if (rc == ODP_OK) std::memcpy(up.p, img.data(), img.size());
+        if (rc ||
+            (rc = check_hip(hipMemcpy2DAsync(r->dmem + r->off_v0, r->row_pitch, r->host, r->row, r->row, r->rows,
+                                             hipMemcpyHostToDevice, s->ust), "V0")) ||
+            (rc = check_hip(hipMemcpyAsync(r->dmem, up.p, img.size(), hipMemcpyHostToDevice, s->ust), "image")) ||
+            (rc = check_hip(hipMemcpyAsync(slot, up.p + r->plan.desc_off, sizeof(SolveDesc),
+                                           hipMemcpyHostToDevice, s->ust), "slot")) ||
+            (rc = check_hip(launch_init(slot, 1, s->ust), "init")) ||
             (rc = check_hip(launch_alpha(r->dyn.id, r->grid.ndim, slot, 1,
-                                         int(std::min<int64_t>(2048, (r->grid.npts / r->grid.n[0] + kBlock - 1) / kBlock)),
-                                         s->st), "alpha")) ||
-            (rc = check_hip(launch_sched(slot, 1, s->d_nsteps + r->slot, s->st), "schedule")) ||
-            (rc = check_hip(launch_start_copy(o.precision, slot, nullptr, nullptr, it.tiles, s->st), "start copy"))) {
+                                         int(std::min<int64_t>(2048, (it.qpad + kBlock - 1) / kBlock)), s->ust),
+                            "alpha")) ||
+            (rc = check_hip(launch_sched(slot, 1, s->d_nsteps + r->slot, s->ust), "schedule")) ||
+            (rc = check_hip(launch_start_copy(o.precision, slot, nullptr, nullptr, it.tiles, s->ust), "start copy")) ||
+            (rc = check_hip(hipMemcpyAsync(s->h_nsteps + r->slot, s->d_nsteps + r->slot, 8, hipMemcpyDeviceToHost,
+                                           s->ust), "steps")) ||
+            (rc = get_event(s, &r->ev)) || (rc = check_hip(hipEventRecord(r->ev, s->ust), "record"))) {
+            (void)hipStreamSynchronize(s->ust);
             release(s, r);
             finish(s, r, rc);
             continue;
         }
-        launched.push_back(r);
+        s->admitting.push_back(r);
     }
-    if (launched.empty()) return ODP_OK;
-    std::vector<int64_t> ns(size_t(s->max_slots));
-    int rc;
-    if ((rc = check_hip(hipMemcpyAsync(ns.data(), s->d_nsteps, ns.size() * 8, hipMemcpyDeviceToHost, s->st), "steps")) ||
-        (rc = check_hip(hipStreamSynchronize(s->st), "sync")))
-        return rc;
-    for (auto &r : launched) {
-        r->nsteps = ns[size_t(r->slot)];
-        r->step = 0;
-        if (r->nsteps <= 0) {
-            release(s, r);
-            finish(s, r, set_error(ODP_EHIP, "server: schedule overflow"));
+}
+
+// Admissions whose prologue has finished join the active set.
+bool poll_admissions(odp_server *s) {
+    bool joined = false;
+    for (size_t i = 0; i < s->admitting.size();) {
+        auto r = s->admitting[i];
+        if (hipEventQuery(r->ev) != hipSuccess) {
+            ++i;
             continue;
         }
-        admitted.push_back(r);
+        put_event(s, r->ev);
+        s->admitting.erase(s->admitting.begin() + long(i));
+        bool cancel;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            cancel = r->cancel;
+        }
+        r->nsteps = s->h_nsteps[r->slot];
+        r->step = 0;
+        if (cancel || r->nsteps <= 0) {
+            release(s, r);
+            finish(s, r, cancel ? ODP_ECANCELED : set_error(ODP_EHIP, "server: schedule overflow"));
+            continue;
+        }
+        s->active.push_back(r);
+        joined = true;
     }
+    return joined;
+}
+
+// Enqueue the read-back of a request that the tick marked by `after`
+// finishes (download stream).
+int start_retire(odp_server *s, const std::shared_ptr<Req> &r, hipEvent_t after) {
+    const PlanItem &it = r->plan.items[0];
+    Staging &b = s->back[size_t(r->slot)];
+    int rc;
+    if ((rc = stage_reserve(b, kStateBytes + size_t(r->nsteps) * 8)) ||
+        (rc = check_hip(hipStreamWaitEvent(s->dst, after, 0), "wait")) ||
+        (rc = check_hip(hipMemcpy2DAsync(r->host, r->row, r->dmem + r->off_a, r->row_pitch, r->row, r->rows,
+                                         hipMemcpyDeviceToHost, s->dst), "result")) ||
+        (rc = check_hip(hipMemcpyAsync(b.p, r->dmem + it.aux_off, kStateBytes, hipMemcpyDeviceToHost, s->dst),
+                        "state")) ||
+        (rc = check_hip(hipMemcpyAsync(b.p + kStateBytes, r->dmem + it.sched_off, size_t(r->nsteps) * 8,
+                                       hipMemcpyDeviceToHost, s->dst), "schedule")) ||
+        (rc = get_event(s, &r->ev)) || (rc = check_hip(hipEventRecord(r->ev, s->dst), "record")))
+        return rc;
+    s->retiring.push_back(r);
     return ODP_OK;
 }
 
+// Retirements whose read-back has finished: statistics, release, done.
+void poll_retirements(odp_server *s) {
+    for (size_t i = 0; i < s->retiring.size();) {
+        auto r = s->retiring[i];
+        if (hipEventQuery(r->ev) != hipSuccess) {
+            ++i;
+            continue;
+        }
+        s->retiring.erase(s->retiring.begin() + long(i));
+        const unsigned char *b = s->back[size_t(r->slot)].p;
+        const double *dts = (const double *)(b + kStateBytes);
+        odp_solve_stats &sx = r->stats;
+        sx.steps = r->nsteps;
+        sx.dt_min = *std::min_element(dts, dts + r->nsteps);
+        sx.dt_max = *std::max_element(dts, dts + r->nsteps);
+        sx.t_final = r->tau.back();
+        sx.alg_bytes = alg_bytes_per_step(s->opts.precision, r->rk_order, s->opts.mode == ODP_BRT, r->grid.npts) *
+                       double(r->nsteps);
+        std::memcpy(sx.alpha_max, b, sizeof(sx.alpha_max));
+        int32_t flags;
+        std::memcpy(&flags, b + kMaxDim * 8 + 16, 4);
+        sx.nonfinite = flags & 1;
+        release(s, r);
+        finish(s, r, sx.nonfinite ? ODP_ENONFINITE : ODP_OK);
+    }
+}
+
+// Kernel groups and tile tables of the selected requests; the tables go to
+// the device on the compute stream, after the ticks already in flight.
 int build_groups(odp_server *s, const std::vector<std::shared_ptr<Req>> &sel, std::vector<Group> &groups) {
     groups.clear();
     std::map<std::tuple<int, int, int, int>, size_t> idx;
@@ -259,45 +390,52 @@ int build_groups(odp_server *s, const std::vector<std::shared_ptr<Req>> &sel, st
         }
         groups[f->second].slots.push_back(r->slot);
     }
-    std::vector<uint32_t> ts, tl;
-    std::vector<int32_t> list;
+    size_t ntiles = 0;
+    for (auto &r : sel) ntiles += r->plan.items[0].tiles;
+    int rc;
+    if (ntiles > s->tile_cap) {
+        // the old tables may still be read by a tick in flight
+        if ((rc = check_hip(hipStreamSynchronize(s->st), "sync"))) return rc;
+        const size_t cap = std::max(ntiles, 2 * s->tile_cap);
+        if (s->d_tiles) (void)hipFree(s->d_tiles);
+        s->d_tiles = nullptr;
+        s->tile_cap = 0;
+        if ((rc = check_hip(hipMalloc(&s->d_tiles, cap * 8), "tile tables"))) return rc;
+        s->tile_cap = cap;
+    }
+    Staging &b = s->tab[s->tab_next];
+    s->tab_next ^= 1;
+    if ((rc = stage_reserve(b, ntiles * 8 + sel.size() * 4))) return rc;
+    uint32_t *ts = (uint32_t *)b.p, *tl = ts + ntiles;
+    int32_t *list = (int32_t *)(tl + ntiles);
     std::vector<const Req *> by_slot(size_t(s->max_slots), nullptr);
     for (auto &r : sel) by_slot[size_t(r->slot)] = r.get();
+    size_t nt = 0, nl = 0;
     for (Group &g : groups) {
-        g.tile_base = ts.size();
-        g.list_base = list.size();
+        g.tile_base = nt;
+        g.list_base = nl;
         for (int sl : g.slots) {
             const uint32_t t = by_slot[size_t(sl)]->plan.items[0].tiles;
             for (uint32_t k = 0; k < t; ++k) {
-                ts.push_back(uint32_t(sl));
-                tl.push_back(k);
+                ts[nt] = uint32_t(sl);
+                tl[nt++] = k;
             }
-            list.push_back(sl);
+            list[nl++] = sl;
         }
-        g.tiles = uint32_t(ts.size() - g.tile_base);
+        g.tiles = uint32_t(nt - g.tile_base);
     }
-    int rc;
-    if (ts.size() > s->tile_cap) {
-        if ((rc = check_hip(hipStreamSynchronize(s->st), "sync"))) return rc;
-        if (s->d_tiles) (void)hipFree(s->d_tiles);
-        s->tile_cap = std::max(ts.size(), 2 * s->tile_cap);
-        if ((rc = check_hip(hipMalloc(&s->d_tiles, s->tile_cap * 8), "tile tables"))) {
-            s->d_tiles = nullptr;
-            s->tile_cap = 0;
-            return rc;
-        }
-    }
-    if (!ts.empty()) {
-        if ((rc = check_hip(hipMemcpyAsync(s->d_tiles, ts.data(), ts.size() * 4, hipMemcpyHostToDevice, s->st), "tiles")) ||
-            (rc = check_hip(hipMemcpyAsync(s->d_tiles + s->tile_cap, tl.data(), tl.size() * 4, hipMemcpyHostToDevice, s->st), "tiles")) ||
-            (rc = check_hip(hipMemcpyAsync(s->d_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, s->st), "list")) ||
-            (rc = check_hip(hipStreamSynchronize(s->st), "sync")))
-            return rc;
-    }
+    if (ntiles == 0) return ODP_OK;
+    if ((rc = check_hip(hipMemcpyAsync(s->d_tiles, ts, ntiles * 4, hipMemcpyHostToDevice, s->st), "tiles")) ||
+        (rc = check_hip(hipMemcpyAsync(s->d_tiles + s->tile_cap, tl, ntiles * 4, hipMemcpyHostToDevice, s->st),
+                        "tiles")) ||
+        (rc = check_hip(hipMemcpyAsync(s->d_list, list, nl * 4, hipMemcpyHostToDevice, s->st), "list")) ||
+        (rc = check_hip(hipEventRecord(b.ev, s->st), "record")))
+        return rc;
+    b.pending = true;
     return ODP_OK;
 }
 
-int tick(odp_server *s, const std::vector<Group> &groups) {
+int enqueue_tick(odp_server *s, const std::vector<Group> &groups, hipEvent_t *done) {
     const odp_solve_opts &o = s->opts;
     const int brt = o.mode == ODP_BRT;
     int rc;
@@ -307,7 +445,7 @@ int tick(odp_server *s, const std::vector<Group> &groups) {
                 if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, stage_kind(g.rk, j, brt),
                                                  s->d_slots, s->d_tiles + g.tile_base,
                                                  s->d_tiles + s->tile_cap + g.tile_base, g.tiles, j, 1, 0,
-                                                 s->opts.xcd_group, s->st),
+                                                 o.xcd_group, s->st),
                                     "stage")))
                     return rc;
             }
@@ -316,69 +454,31 @@ int tick(odp_server *s, const std::vector<Group> &groups) {
                 return rc;
         }
     }
-    return check_hip(hipStreamSynchronize(s->st), "sync");
-}
-
-// Copy the results of finished requests to their host buffers (one
-// synchronisation for all of them), fill their statistics and free them.
-int retire_done(odp_server *s, std::vector<std::shared_ptr<Req>> &fin) {
-    if (fin.empty()) return ODP_OK;
-    struct Back {
-        unsigned char state[kMaxDim * 8 + 24];
-        std::vector<double> dts;
-    };
-    std::vector<Back> back(fin.size());
-    int rc = ODP_OK;
-    for (size_t i = 0; i < fin.size() && rc == ODP_OK; ++i) {
-        const auto &r = fin[i];
-        const PlanItem &it = r->plan.items[0];
-        back[i].dts.resize(static_cast<size_t>(r->nsteps));
-        if ((rc = check_hip(hipMemcpy2DAsync(r->host, r->row, r->dmem + r->off_a, r->row_pitch, r->row, r->rows,
-                                             hipMemcpyDeviceToHost, s->st), "result")) ||
-            (rc = check_hip(hipMemcpyAsync(back[i].state, r->dmem + it.aux_off, sizeof(back[i].state),
-                                           hipMemcpyDeviceToHost, s->st), "state")) ||
-            (rc = check_hip(hipMemcpyAsync(back[i].dts.data(), r->dmem + it.sched_off, back[i].dts.size() * 8,
-                                           hipMemcpyDeviceToHost, s->st), "schedule")))
-            break;
-    }
-    if (rc == ODP_OK) rc = check_hip(hipStreamSynchronize(s->st), "sync");
-    for (size_t i = 0; i < fin.size(); ++i) {
-        const auto &r = fin[i];
-        int rr = rc;
-        if (rc == ODP_OK) {
-            odp_solve_stats &sx = r->stats;
-            const auto &dts = back[i].dts;
-            sx.steps = r->nsteps;
-            sx.dt_min = *std::min_element(dts.begin(), dts.end());
-            sx.dt_max = *std::max_element(dts.begin(), dts.end());
-            sx.t_final = r->tau.back();
-            sx.alg_bytes = alg_bytes_per_step(s->opts.precision, r->rk_order, s->opts.mode == ODP_BRT,
-                                              r->grid.npts) * double(r->nsteps);
-            std::memcpy(sx.alpha_max, back[i].state, sizeof(sx.alpha_max));
-            int32_t flags;
-            std::memcpy(&flags, back[i].state + kMaxDim * 8 + 16, 4);
-            sx.nonfinite = flags & 1;
-            rr = sx.nonfinite ? ODP_ENONFINITE : ODP_OK;
-        }
-        release(s, r);
-        finish(s, r, rr);
-    }
-    fin.clear();
+    if ((rc = get_event(s, done))) return rc;
+    if ((rc = check_hip(hipEventRecord(*done, s->st), "record"))) put_event(s, *done);
     return rc;
 }
 
-int retire_cancelled(odp_server *s, const std::shared_ptr<Req> &r) {
-    release(s, r);
-    finish(s, r, ODP_ECANCELED);
-    return ODP_OK;
+void drain(odp_server *s) {
+    (void)hipStreamSynchronize(s->st);
+    (void)hipStreamSynchronize(s->ust);
+    (void)hipStreamSynchronize(s->dst);
+    for (hipEvent_t &e : s->ticks) put_event(s, e);
+    s->ticks.clear();
 }
 
+// Finish every request the scheduler holds with `rc` (after the device has
+// drained; completed retirements keep their own result).
 void fail_all(odp_server *s, int rc) {
-    for (auto &r : s->active) {
-        release(s, r);
-        finish(s, r, rc);
+    drain(s);
+    poll_retirements(s);
+    for (auto *v : {&s->admitting, &s->active, &s->retiring}) {
+        for (auto &r : *v) {
+            release(s, r);
+            finish(s, r, rc);
+        }
+        v->clear();
     }
-    s->active.clear();
 }
 
 void scheduler(odp_server *s) {
@@ -390,37 +490,51 @@ void scheduler(odp_server *s) {
         {
             std::unique_lock<std::mutex> lk(s->mu);
             if (s->stop) break;
-            if (s->active.empty() && s->queue.empty()) {
+            if (s->active.empty() && s->queue.empty() && s->admitting.empty() && s->retiring.empty()) {
                 s->cv.wait_for(lk, std::chrono::milliseconds(20));
                 continue;
             }
         }
-        std::vector<std::shared_ptr<Req>> admitted;
-        if (admit(s, admitted) != ODP_OK) {
-            fail_all(s, ODP_EHIP);
+        poll_retirements(s);
+        admit(s);
+        if (poll_admissions(s)) dirty = true;
+        // cancellations of running requests
+        bool cancelled = false;
+        for (auto &r : s->active) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            cancelled |= r->cancel;
+        }
+        if (cancelled) {
+            (void)hipStreamSynchronize(s->st);  // no tick may still read them
+            for (hipEvent_t &e : s->ticks) put_event(s, e);
+            s->ticks.clear();
+            for (size_t i = 0; i < s->active.size();) {
+                auto r = s->active[i];
+                bool c;
+                {
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    c = r->cancel;
+                }
+                if (c) {
+                    s->active.erase(s->active.begin() + long(i));
+                    release(s, r);
+                    finish(s, r, ODP_ECANCELED);
+                } else {
+                    ++i;
+                }
+            }
             dirty = true;
+        }
+        if (s->active.empty()) {
+            if (!s->admitting.empty() || !s->retiring.empty())
+                std::this_thread::sleep_for(std::chrono::microseconds(50));
             continue;
         }
-        if (!admitted.empty()) {
-            for (auto &r : admitted) s->active.push_back(r);
-            dirty = true;
+        while (int(s->ticks.size()) >= kTicksInFlight) {
+            (void)hipEventSynchronize(s->ticks.front());
+            put_event(s, s->ticks.front());
+            s->ticks.pop_front();
         }
-        // cancellations of running requests
-        for (size_t i = 0; i < s->active.size();) {
-            bool c;
-            {
-                std::lock_guard<std::mutex> lk(s->mu);
-                c = s->active[i]->cancel;
-            }
-            if (c) {
-                retire_cancelled(s, s->active[i]);
-                s->active.erase(s->active.begin() + long(i));
-                dirty = true;
-            } else {
-                ++i;
-            }
-        }
-        if (s->active.empty()) continue;
         // This tick advances the requests with the least remaining work
         // first, up to about kTickWork point-stage updates (at least one
         // request; any request waiting longer than kMaxWaitMs joins anyway),
@@ -448,42 +562,72 @@ void scheduler(odp_server *s) {
         if (dirty) {
             if (build_groups(s, sel, groups) != ODP_OK) {
                 fail_all(s, ODP_EHIP);
+                last_sel.clear();
                 continue;
             }
             last_sel = sel_ids;
             dirty = false;
         }
-        if (tick(s, groups) != ODP_OK) {
+        hipEvent_t tick_done = nullptr;
+        if (enqueue_tick(s, groups, &tick_done) != ODP_OK) {
             fail_all(s, ODP_EHIP);
             dirty = true;
             continue;
         }
-        std::vector<std::shared_ptr<Req>> fin;
+        s->ticks.push_back(tick_done);
         for (auto &r : sel) r->step = std::min<int64_t>(r->step + kStepsPerTick, r->nsteps);
         for (size_t i = 0; i < s->active.size();) {
-            auto &r = s->active[i];
+            auto r = s->active[i];
             if (r->step >= r->nsteps) {
-                fin.push_back(r);
                 s->active.erase(s->active.begin() + long(i));
                 dirty = true;
+                if (start_retire(s, r, tick_done) != ODP_OK) {
+                    (void)hipStreamSynchronize(s->st);
+                    (void)hipStreamSynchronize(s->dst);
+                    release(s, r);
+                    finish(s, r, ODP_EHIP);
+                }
             } else {
                 ++i;
             }
         }
-        if (retire_done(s, fin) != ODP_OK) {
-            fail_all(s, ODP_EHIP);
-            dirty = true;
-        }
     }
-    // shutdown: cancel whatever is still running or queued
-    for (auto &r : s->active) retire_cancelled(s, r);
-    s->active.clear();
+    // shutdown: let the device drain, keep finished results, cancel the rest
+    drain(s);
+    poll_retirements(s);
+    for (auto *v : {&s->admitting, &s->active, &s->retiring}) {
+        for (auto &r : *v) {
+            release(s, r);
+            finish(s, r, ODP_ECANCELED);
+        }
+        v->clear();
+    }
+    (void)hipStreamSynchronize(s->ust);
     std::lock_guard<std::mutex> lk(s->mu);
     for (auto &r : s->queue) {
         r->rc = ODP_ECANCELED;
         r->state = R_DONE;
     }
     s->queue.clear();
+}
+
+void destroy_resources(odp_server *s) {
+    if (s->d_tiles) (void)hipFree(s->d_tiles);
+    if (s->d_slots) (void)hipFree(s->d_slots);
+    if (s->d_nsteps) (void)hipFree(s->d_nsteps);
+    if (s->d_list) (void)hipFree(s->d_list);
+    if (s->h_nsteps) (void)hipHostFree(s->h_nsteps);
+    for (Staging &b : s->tab) {
+        if (b.p) (void)hipHostFree(b.p);
+        if (b.ev) (void)hipEventDestroy(b.ev);
+    }
+    for (auto *v : {&s->up, &s->back})
+        for (Staging &b : *v)
+            if (b.p) (void)hipHostFree(b.p);
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+    s->ev_pool.clear();
+    for (hipStream_t *q : {&s->st, &s->ust, &s->dst})
+        if (*q) (void)hipStreamDestroy(*q);
 }
 
 }  // namespace
@@ -503,15 +647,19 @@ int odp_server_create(size_t hbm_budget_bytes, int max_slots, const odp_solve_op
     s->opts.stream = nullptr;
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
+    s->up.resize(size_t(max_slots));
+    s->back.resize(size_t(max_slots));
     if ((rc = check_hip(hipGetDevice(&s->device), "device")) ||
-        (rc = check_hip(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking), "stream")))
-        return rc;
-    if ((rc = check_hip(hipMalloc(&s->d_slots, sizeof(SolveDesc) * size_t(max_slots)), "slots")) ||
+        (rc = check_hip(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking), "stream")) ||
+        (rc = check_hip(hipStreamCreateWithFlags(&s->ust, hipStreamNonBlocking), "stream")) ||
+        (rc = check_hip(hipStreamCreateWithFlags(&s->dst, hipStreamNonBlocking), "stream")) ||
+        (rc = check_hip(hipMalloc(&s->d_slots, sizeof(SolveDesc) * size_t(max_slots)), "slots")) ||
         (rc = check_hip(hipMalloc(&s->d_nsteps, 8 * size_t(max_slots)), "slots")) ||
-        (rc = check_hip(hipMalloc(&s->d_list, 4 * size_t(max_slots)), "slots"))) {
-        if (s->d_slots) (void)hipFree(s->d_slots);
-        if (s->d_nsteps) (void)hipFree(s->d_nsteps);
-        (void)hipStreamDestroy(s->st);
+        (rc = check_hip(hipMalloc(&s->d_list, 4 * size_t(max_slots)), "slots")) ||
+        (rc = check_hip(hipHostMalloc((void **)&s->h_nsteps, 8 * size_t(max_slots), hipHostMallocDefault), "pinned")) ||
+        (rc = check_hip(hipEventCreateWithFlags(&s->tab[0].ev, hipEventDisableTiming), "event")) ||
+        (rc = check_hip(hipEventCreateWithFlags(&s->tab[1].ev, hipEventDisableTiming), "event"))) {
+        destroy_resources(s.get());
         return rc;
     }
     for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
@@ -608,12 +756,9 @@ void odp_server_destroy(odp_server *srv) {
     }
     srv->cv.notify_all();
     if (srv->th.joinable()) srv->th.join();
-    (void)hipStreamSynchronize(srv->st);
-    if (srv->d_tiles) (void)hipFree(srv->d_tiles);
-    (void)hipFree(srv->d_slots);
-    (void)hipFree(srv->d_nsteps);
-    (void)hipFree(srv->d_list);
-    (void)hipStreamDestroy(srv->st);
+    drain(srv);
+    destroy_resources(srv);
+    // requests still held by clients keep their host buffers until released
     delete srv;
 }
 
