@@ -20,6 +20,8 @@
 // batch, server tick) give the same bits for the same point.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "odp_dev.h"
 
 namespace odp {
@@ -479,80 +481,168 @@ __global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__re
         return int64_t(j) * s0;
     };
 
-    using P = Pack<T, VEC>;
-    P wm = ldp<T, VEC>(W + plane_of(i0b - 1) + q);
-    P wc = ldp<T, VEC>(W + plane_of(i0b) + q);
-    P wp = ldp<T, VEC>(W + plane_of(i0b + 1) + q);
-    P vnx, zx;
-    if constexpr (kVn) vnx = ldp_nt<T, VEC>(Vn + int64_t(i0b) * s0 + q);
-    if constexpr (kClamp) zx = ldp_nt<T, VEC>(V0 + int64_t(i0b) * s0 + q);
-    int bad = 0;
-    for (int i0 = i0b; i0 < i0e; ++i0) {
-        const ODP_GLOBAL T *plane = W + int64_t(i0) * s0;
-        const int64_t o = int64_t(i0) * s0 + q;
-        const P vn = vnx, z = zx;
-        // this plane's in-plane neighbours
-        P wl[N], wr[N];
+    // Every access is a uniform plane base plus this thread's 32-bit element
+    // offset inside the plane (a plane holds fewer than 2^31 elements), so
+    // the per-lane address arithmetic is done once, before the march.
+    uint32_t qL[N], qR[N];
 #pragma unroll
-        for (int d = 1; d < N - 1; ++d) {
-            wl[d] = ldp<T, VEC>(plane + q + offL[d]);
-            wr[d] = ldp<T, VEC>(plane + q + offR[d]);
-        }
-        const T xl = plane[q + oxl];
-        const T xr = plane[q + oxr];
-        // one plane ahead
-        const P wn = ldp<T, VEC>(W + plane_of(i0 + 2) + q);
-        const int64_t on = (i0 + 1 < n0 ? int64_t(i0 + 1) * s0 : int64_t(i0) * s0) + q;
-        if constexpr (kVn) vnx = ldp_nt<T, VEC>(Vn + on);
-        if constexpr (kClamp) zx = ldp_nt<T, VEC>(V0 + on);
+    for (int d = 1; d < N - 1; ++d) {
+        qL[d] = uint32_t(int32_t(q) + offL[d]);
+        qR[d] = uint32_t(int32_t(q) + offR[d]);
+    }
+    const uint32_t qxl = uint32_t(int32_t(q) + oxl), qxr = uint32_t(int32_t(q) + oxr);
 
-        Acc<T> acc[VEC];
-        const bool g0l = !per0 && i0 == 0, g0r = !per0 && i0 == n0 - 1;
+    // Waves with no lane on a non-periodic face of a middle or the last axis
+    // (almost all of them) take a march without ghost logic; `ragged`: some
+    // lane's group extends past the end of its row (padded rows).
+    const bool lane_edge = (gl | gr) != 0 || gxl || gxr;
+    const bool lane_ragged = jend < VEC - 1;
+    const bool edge = __builtin_amdgcn_ballot_w64(lane_edge) != 0;
+    const bool ragged = __builtin_amdgcn_ballot_w64(lane_ragged) != 0;
+
+    using P = Pack<T, VEC>;
+    const int wlast = i0e, vlast = i0e - 1;
+    T nanacc = T(0);
+
+    // The march is software pipelined: while plane i is computed, the loads
+    // for plane i+1 (its in-plane neighbours, V^n and V0) and the stencil
+    // input of plane i+2 are in flight.  Registers have fixed roles over a
+    // 4-plane cycle (unrolled by hand), so that no register that a load in
+    // flight will write is ever copied (a copy would wait for the load).
+    // Indexes past the chunk end are clamped to its last plane (L2 hits).
+    // A difference shared by two points (W(i+1) - W(i) between consecutive
+    // planes, W_{j+1} - W_j inside the group) is computed once: it is the
+    // same subtraction, so the bits do not change.
+    auto march = [&](auto edge_c, auto ragged_c) {
+        constexpr bool kEdge = decltype(edge_c)::value;
+        constexpr bool kRag = decltype(ragged_c)::value;
+        constexpr int NM = N > 2 ? N - 2 : 1;  // middle axes 1..N-2
+        struct Nb {
+            P l[NM], r[NM];
+            T xl, xr;
+        };
+        P w[4];          // stencil-input ring: planes i-1, i, i+1 and the one loading
+        Nb nb[2];        // in-plane neighbours: plane i, plane i+1 (loading)
+        P vq[2], zq[2];  // V^n and V0: plane i, plane i+1 (loading)
+        auto load_nb = [&](int i, Nb &o) {
+            const ODP_GLOBAL T *plane = W + int64_t(i) * s0;
 #pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            acc[j].L = T(0);
-            acc[j].n2 = T(0);
-            T l0 = wm.v[j], r0 = wp.v[j];
-            if (g0l) l0 = ghost(wc.v[j], wp.v[j]);
-            if (g0r) r0 = ghost(wc.v[j], wm.v[j]);
-            acc_axis<T, DYN, N>(cf[j], 0, wc.v[j] - l0, r0 - wc.v[j], acc[j]);
-        }
+            for (int d = 1; d < N - 1; ++d) {
+                o.l[d - 1] = ldp<T, VEC>(plane + qL[d]);
+                o.r[d - 1] = ldp<T, VEC>(plane + qR[d]);
+            }
+            o.xl = plane[qxl];
+            o.xr = plane[qxr];
+        };
+        auto load_pw = [&](int i, P &ov, P &oz) {
+            const int64_t o = int64_t(i) * s0 + q;
+            if constexpr (kVn) ov = ldp_nt<T, VEC>(Vn + o);
+            if constexpr (kClamp) oz = ldp_nt<T, VEC>(V0 + o);
+        };
+        w[0] = ldp<T, VEC>(W + plane_of(i0b - 1) + q);
+        w[1] = ldp<T, VEC>(W + plane_of(i0b) + q);
+        w[2] = ldp<T, VEC>(W + plane_of(i0b + 1) + q);
+        load_nb(i0b, nb[0]);
+        load_pw(i0b, vq[0], zq[0]);
+        P dm;  // W(i) - W(i-1)
 #pragma unroll
-        for (int d = 1; d < N - 1; ++d) {
+        for (int j = 0; j < VEC; ++j) dm.v[j] = w[1].v[j] - w[0].v[j];
+
+        auto step = [&](auto kc, int i) {
+            constexpr int K = decltype(kc)::value;
+            const P &wm = w[K % 4], &wc = w[(K + 1) % 4], &wp = w[(K + 2) % 4];
+            const Nb &cur = nb[K % 2];
+            const P &vn = vq[K % 2], &z = zq[K % 2];
+            // loads for the planes ahead
+            const int in = min(i + 1, vlast);
+            load_nb(in, nb[(K + 1) % 2]);
+            load_pw(in, vq[(K + 1) % 2], zq[(K + 1) % 2]);
+            w[(K + 3) % 4] = ldp<T, VEC>(W + plane_of(min(i + 2, wlast)) + q);
+
+            Acc<T> acc[VEC];
+            P dp;  // W(i+1) - W(i)
+            const bool g0l = !per0 && i == 0, g0r = !per0 && i == n0 - 1;
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
-                T a = wl[d].v[j], b = wr[d].v[j];
-                if (gl & (1u << d)) a = ghost(wc.v[j], wr[d].v[j]);
-                if (gr & (1u << d)) b = ghost(wc.v[j], wl[d].v[j]);
-                acc_axis<T, DYN, N>(cf[j], d, wc.v[j] - a, b - wc.v[j], acc[j]);
+                acc[j].L = T(0);
+                acc[j].n2 = T(0);
+                dp.v[j] = wp.v[j] - wc.v[j];
+                T dl = dm.v[j], dr = dp.v[j];
+                if (g0l) dl = wc.v[j] - ghost(wc.v[j], wp.v[j]);
+                if (g0r) dr = ghost(wc.v[j], wm.v[j]) - wc.v[j];
+                acc_axis<T, DYN, N>(cf[j], 0, dl, dr, acc[j]);
             }
-        }
 #pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            T a = j > 0 ? wc.v[j > 0 ? j - 1 : 0] : xl;
-            T b = (j < jend && j < VEC - 1) ? wc.v[j < VEC - 1 ? j + 1 : j] : xr;
-            if (j == 0 && gxl) a = ghost(wc.v[0], b);
-            if (j == jend && gxr) b = ghost(wc.v[j], a);
-            acc_axis<T, DYN, N>(cf[j], N - 1, wc.v[j] - a, b - wc.v[j], acc[j]);
-        }
-        P res;
+            for (int d = 1; d < N - 1; ++d) {
 #pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            const T Lh = acc_finish<T, DYN, N>(cf[j], acc[j]);
-            T v = fma_t(dt, Lh, wc.v[j]);
-            if constexpr (kVn) v = fma_t(ra, vn.v[j], rb * v);
-            if constexpr (kClamp) {
-                if (z.v[j] < v) v = z.v[j];
+                for (int j = 0; j < VEC; ++j) {
+                    T a = cur.l[d - 1].v[j], b = cur.r[d - 1].v[j];
+                    if constexpr (kEdge) {
+                        if (gl & (1u << d)) a = ghost(wc.v[j], cur.r[d - 1].v[j]);
+                        if (gr & (1u << d)) b = ghost(wc.v[j], cur.l[d - 1].v[j]);
+                    }
+                    acc_axis<T, DYN, N>(cf[j], d, wc.v[j] - a, b - wc.v[j], acc[j]);
+                }
             }
-            if (j <= jend) bad |= !isfinite(v);
-            res.v[j] = v;
+            if constexpr (!kEdge && !kRag) {
+                T dx[VEC + 1];
+                dx[0] = wc.v[0] - cur.xl;
+#pragma unroll
+                for (int j = 1; j < VEC; ++j) dx[j] = wc.v[j] - wc.v[j - 1];
+                dx[VEC] = cur.xr - wc.v[VEC - 1];
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) acc_axis<T, DYN, N>(cf[j], N - 1, dx[j], dx[j + 1], acc[j]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) {
+                    T a = j > 0 ? wc.v[j > 0 ? j - 1 : 0] : cur.xl;
+                    T b = (j < jend && j < VEC - 1) ? wc.v[j < VEC - 1 ? j + 1 : j] : cur.xr;
+                    if constexpr (kEdge) {
+                        if (j == 0 && gxl) a = ghost(wc.v[0], b);
+                        if (j == jend && gxr) b = ghost(wc.v[j], a);
+                    }
+                    acc_axis<T, DYN, N>(cf[j], N - 1, wc.v[j] - a, b - wc.v[j], acc[j]);
+                }
+            }
+            P res;
+            T nan_here = T(0);
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                const T Lh = acc_finish<T, DYN, N>(cf[j], acc[j]);
+                T v = fma_t(dt, Lh, wc.v[j]);
+                if constexpr (kVn) v = fma_t(ra, vn.v[j], rb * v);
+                if constexpr (kClamp) {
+                    if (z.v[j] < v) v = z.v[j];
+                }
+                // v * 0 is NaN exactly when v is not finite
+                nan_here = fma_t(kRag && j > jend ? T(0) : v, T(0), nan_here);
+                res.v[j] = v;
+            }
+            if (i < i0e) {
+                nanacc += nan_here;
+                if (active) stp_nt<T, VEC>(out + int64_t(i) * s0 + q, res);
+            }
+            dm = dp;
+        };
+        using K0 = std::integral_constant<int, 0>;
+        using K1 = std::integral_constant<int, 1>;
+        using K2 = std::integral_constant<int, 2>;
+        using K3 = std::integral_constant<int, 3>;
+        // whole 4-plane cycles; planes past the chunk end are computed from
+        // clamped loads and neither stored nor checked
+        for (int i = i0b; i < i0e; i += 4) {
+            step(K0{}, i);
+            step(K1{}, i + 1);
+            step(K2{}, i + 2);
+            step(K3{}, i + 3);
         }
-        if (active) stp_nt<T, VEC>(out + o, res);
-        wm = wc;
-        wc = wp;
-        wp = wn;
-    }
-    if (bad && active) atomicOr(s.flags, 1);
+    };
+    using TT = std::true_type;
+    using FF = std::false_type;
+    if (edge) march(TT{}, TT{});
+    else if (ragged) march(FF{}, TT{});
+    else march(FF{}, FF{});
+    if (nanacc != nanacc && active) atomicOr(s.flags, 1);
 }
 
 // Zero alpha^max, the flags and the step counter of every listed solve.

@@ -28,11 +28,16 @@ int64_t step_capacity(const odp_grid *g, const odp_dynamics *dyn, const std::vec
     return int64_t(std::min(est, 1e9)) + 2 * int64_t(tau.size()) + 8;
 }
 
-int balanced_chunk(const odp_grid *g, int c) {
+// Planes per block for a requested c: chunks of (nearly) equal length; for
+// the default choice also a multiple of 4, the marching kernel's register
+// cycle (planes past the end of a shorter chunk are computed and dropped).
+int balanced_chunk(const odp_grid *g, int c, bool cycle4) {
     const int n0 = int(g->n[0]);
     c = std::max(1, std::min(c, n0));
     const int nchunks = (n0 + c - 1) / c;
-    return (n0 + nchunks - 1) / nchunks;
+    int b = (n0 + nchunks - 1) / nchunks;
+    if (cycle4 && g->ndim >= 2) b = std::min((b + 3) / 4 * 4, (n0 + 3) / 4 * 4);
+    return b;
 }
 
 }  // namespace
@@ -65,7 +70,7 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
                 c = int(std::max<int64_t>(1, total / (int64_t(kBlock) * it.vec * 8192)));
             }
         }
-        it.chunk = balanced_chunk(it.g, c);
+        it.chunk = balanced_chunk(it.g, c, tile_chunk <= 0);
         it.tiles = solve_tiles(it.g->n[0], it.qpad, it.chunk, it.vec);
         it.max_steps = step_capacity(it.g, &it.dyn, it.tau, opts.cfl, opts.max_dt);
         it.tab_entries = 0;
