@@ -371,6 +371,33 @@ __device__ __forceinline__ Pack<T, VEC> ldp_nt(const ODP_GLOBAL T *p) {
 }
 
 template <typename T, int VEC>
+__device__ __forceinline__ void stp_lds(T *p, const Pack<T, VEC> &r) {
+    if constexpr (VEC == 1) {
+        *p = r.v[0];
+    } else {
+        typedef T ev __attribute__((ext_vector_type(VEC)));
+        ev x;
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) x[j] = r.v[j];
+        *reinterpret_cast<ev *>(p) = x;
+    }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ Pack<T, VEC> ldp_lds(const T *p) {
+    Pack<T, VEC> r;
+    if constexpr (VEC == 1) {
+        r.v[0] = *p;
+    } else {
+        typedef T ev __attribute__((ext_vector_type(VEC)));
+        const ev x = *reinterpret_cast<const ev *>(p);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) r.v[j] = x[j];
+    }
+    return r;
+}
+
+template <typename T, int VEC>
 __device__ __forceinline__ void stp_nt(ODP_GLOBAL T *p, const Pack<T, VEC> &r) {
     if constexpr (VEC == 1) {
         __builtin_nontemporal_store(r.v[0], p);
@@ -392,6 +419,7 @@ __global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__re
     static_assert(N >= 2, "the last axis must differ from the marched axis");
     constexpr bool kVn = KIND & 1;
     constexpr bool kClamp = KIND & 2;
+    constexpr bool kLdsK = (KIND & 4) && N >= 3;
     const uint32_t L = xcd_logical(blockIdx.x, gridDim.x, uint32_t(xgroup));
     const uint32_t si = tile_solve ? tile_solve[L] : 0u;
     const uint32_t lt = tile_solve ? tile_local[L] : L;
@@ -492,156 +520,193 @@ __global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__re
     }
     const uint32_t qxl = uint32_t(int32_t(q) + oxl), qxr = uint32_t(int32_t(q) + oxr);
 
-    // Waves with no lane on a non-periodic face of a middle or the last axis
-    // (almost all of them) take a march without ghost logic; `ragged`: some
-    // lane's group extends past the end of its row (padded rows).
-    const bool lane_edge = (gl | gr) != 0 || gxl || gxr;
-    const bool lane_ragged = jend < VEC - 1;
-    const bool edge = __builtin_amdgcn_ballot_w64(lane_edge) != 0;
-    const bool ragged = __builtin_amdgcn_ballot_w64(lane_ragged) != 0;
+    // Wave-uniform switches (almost every wave has none of them set): a lane
+    // on a non-periodic face of a middle axis, of the last axis, or a group
+    // that extends past the end of its row (padded rows).  The ghost and row
+    // end logic sits in branches that such waves skip.
+    const bool anyg = __builtin_amdgcn_ballot_w64((gl | gr) != 0) != 0;
+    const bool rowx = __builtin_amdgcn_ballot_w64(gxl || gxr || jend < VEC - 1) != 0;
 
     using P = Pack<T, VEC>;
     const int wlast = i0e, vlast = i0e - 1;
     T nanacc = T(0);
 
+    // Block-level exchange through LDS (KIND bit 2, chosen by the host for
+    // ndim >= 3 and a row pitch H <= 128 VEC): each plane's values of the
+    // block's range [q0, q0 + B) of the hyperplane, with one row of H
+    // elements beyond each end (loaded by 2 H / VEC threads one plane ahead),
+    // are written to a double-buffered tile, from which every lane reads its
+    // neighbours along axis N-2 (+-H) and along the last axis (same row,
+    // wrapped when periodic).  Lanes on the first or last row of axis N-2
+    // replace that value by a ghost, or, when the axis is periodic, by a
+    // load of the wrapped row.
+    constexpr int B = kBlock * VEC;
+    constexpr int kTile = kLdsK ? 2 * B : 1;  // B + 2 H with H <= B / 2
+    __shared__ __attribute__((aligned(16))) T tile[2][kTile];
+    const int H = s.pitch;
+    const uint32_t q0 = qb * uint32_t(B);
+    const int me = int(q - q0) + H;
+    const int nh = H / VEC;
+    const int th = int(threadIdx.x);
+    const bool hl = kLdsK && th < 2 * nh;
+    int hsrc = th < nh ? int(q0) - H + th * VEC : int(q0) + B + (th - nh) * VEC;
+    hsrc = min(max(hsrc, 0), int(s.Q) - VEC);  // rows outside the hyperplane are never read
+    const int hdst = th < nh ? th * VEC : H + B + (th - nh) * VEC;
+    bool lane_wrap = false;
+    if constexpr (kLdsK)
+        lane_wrap = ((s.periodic >> (N - 2)) & 1u) && (ii[N - 2] == 0 || ii[N - 2] == s.n[N - 2] - 1);
+    const bool anywrap = __builtin_amdgcn_ballot_w64(lane_wrap) != 0;
+
     // The march is software pipelined: while plane i is computed, the loads
-    // for plane i+1 (its in-plane neighbours, V^n and V0) and the stencil
-    // input of plane i+2 are in flight.  Registers have fixed roles over a
-    // 4-plane cycle (unrolled by hand), so that no register that a load in
-    // flight will write is ever copied (a copy would wait for the load).
-    // Indexes past the chunk end are clamped to its last plane (L2 hits).
-    // A difference shared by two points (W(i+1) - W(i) between consecutive
-    // planes, W_{j+1} - W_j inside the group) is computed once: it is the
-    // same subtraction, so the bits do not change.
-    auto march = [&](auto edge_c, auto ragged_c) {
-        constexpr bool kEdge = decltype(edge_c)::value;
-        constexpr bool kRag = decltype(ragged_c)::value;
-        constexpr int NM = N > 2 ? N - 2 : 1;  // middle axes 1..N-2
-        struct Nb {
-            P l[NM], r[NM];
-            T xl, xr;
-        };
-        P w[4];          // stencil-input ring: planes i-1, i, i+1 and the one loading
-        Nb nb[2];        // in-plane neighbours: plane i, plane i+1 (loading)
-        P vq[2], zq[2];  // V^n and V0: plane i, plane i+1 (loading)
-        auto load_nb = [&](int i, Nb &o) {
-            const ODP_GLOBAL T *plane = W + int64_t(i) * s0;
+    // for plane i+1 (its in-plane neighbours, V^n, V0 and the halo rows) and
+    // the stencil input of plane i+2 are in flight.  Registers have fixed
+    // roles over a 4-plane cycle (unrolled by hand), so that no register
+    // that a load in flight will write is ever copied (a copy would wait for
+    // the load).  Indexes past the chunk end are clamped to its last plane
+    // (L2 hits).  A difference shared by two points (W(i+1) - W(i) between
+    // consecutive planes, W_{j+1} - W_j inside the group) is computed once:
+    // it is the same subtraction, so the bits do not change.
+    constexpr int NM = N > 2 ? N - 2 : 1;       // middle axes 1..N-2
+    constexpr int NG = kLdsK ? N - 3 : N - 2;   // middle axes loaded from memory
+    struct Nb {
+        P l[NM], r[NM];
+        T xl, xr;
+    };
+    P w[4];          // stencil-input ring: planes i-1, i, i+1 and the one loading
+    Nb nb[2];        // in-plane neighbours: plane i, plane i+1 (loading)
+    P vq[2], zq[2];  // V^n and V0: plane i, plane i+1 (loading)
+    P hq[2];         // halo rows: plane i, plane i+1 (loading)
+    auto load_nb = [&](int i, Nb &o) {
+        const ODP_GLOBAL T *plane = W + int64_t(i) * s0;
 #pragma unroll
-            for (int d = 1; d < N - 1; ++d) {
-                o.l[d - 1] = ldp<T, VEC>(plane + qL[d]);
-                o.r[d - 1] = ldp<T, VEC>(plane + qR[d]);
-            }
+        for (int d = 1; d <= NG; ++d) {
+            o.l[d - 1] = ldp<T, VEC>(plane + qL[d]);
+            o.r[d - 1] = ldp<T, VEC>(plane + qR[d]);
+        }
+        if constexpr (!kLdsK) {
             o.xl = plane[qxl];
             o.xr = plane[qxr];
-        };
-        auto load_pw = [&](int i, P &ov, P &oz) {
-            const int64_t o = int64_t(i) * s0 + q;
-            if constexpr (kVn) ov = ldp_nt<T, VEC>(Vn + o);
-            if constexpr (kClamp) oz = ldp_nt<T, VEC>(V0 + o);
-        };
-        w[0] = ldp<T, VEC>(W + plane_of(i0b - 1) + q);
-        w[1] = ldp<T, VEC>(W + plane_of(i0b) + q);
-        w[2] = ldp<T, VEC>(W + plane_of(i0b + 1) + q);
-        load_nb(i0b, nb[0]);
-        load_pw(i0b, vq[0], zq[0]);
-        P dm;  // W(i) - W(i-1)
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) dm.v[j] = w[1].v[j] - w[0].v[j];
-
-        auto step = [&](auto kc, int i) {
-            constexpr int K = decltype(kc)::value;
-            const P &wm = w[K % 4], &wc = w[(K + 1) % 4], &wp = w[(K + 2) % 4];
-            const Nb &cur = nb[K % 2];
-            const P &vn = vq[K % 2], &z = zq[K % 2];
-            // loads for the planes ahead
-            const int in = min(i + 1, vlast);
-            load_nb(in, nb[(K + 1) % 2]);
-            load_pw(in, vq[(K + 1) % 2], zq[(K + 1) % 2]);
-            w[(K + 3) % 4] = ldp<T, VEC>(W + plane_of(min(i + 2, wlast)) + q);
-
-            Acc<T> acc[VEC];
-            P dp;  // W(i+1) - W(i)
-            const bool g0l = !per0 && i == 0, g0r = !per0 && i == n0 - 1;
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                acc[j].L = T(0);
-                acc[j].n2 = T(0);
-                dp.v[j] = wp.v[j] - wc.v[j];
-                T dl = dm.v[j], dr = dp.v[j];
-                if (g0l) dl = wc.v[j] - ghost(wc.v[j], wp.v[j]);
-                if (g0r) dr = ghost(wc.v[j], wm.v[j]) - wc.v[j];
-                acc_axis<T, DYN, N>(cf[j], 0, dl, dr, acc[j]);
-            }
-#pragma unroll
-            for (int d = 1; d < N - 1; ++d) {
-#pragma unroll
-                for (int j = 0; j < VEC; ++j) {
-                    T a = cur.l[d - 1].v[j], b = cur.r[d - 1].v[j];
-                    if constexpr (kEdge) {
-                        if (gl & (1u << d)) a = ghost(wc.v[j], cur.r[d - 1].v[j]);
-                        if (gr & (1u << d)) b = ghost(wc.v[j], cur.l[d - 1].v[j]);
-                    }
-                    acc_axis<T, DYN, N>(cf[j], d, wc.v[j] - a, b - wc.v[j], acc[j]);
-                }
-            }
-            if constexpr (!kEdge && !kRag) {
-                T dx[VEC + 1];
-                dx[0] = wc.v[0] - cur.xl;
-#pragma unroll
-                for (int j = 1; j < VEC; ++j) dx[j] = wc.v[j] - wc.v[j - 1];
-                dx[VEC] = cur.xr - wc.v[VEC - 1];
-#pragma unroll
-                for (int j = 0; j < VEC; ++j) acc_axis<T, DYN, N>(cf[j], N - 1, dx[j], dx[j + 1], acc[j]);
-            } else {
-#pragma unroll
-                for (int j = 0; j < VEC; ++j) {
-                    T a = j > 0 ? wc.v[j > 0 ? j - 1 : 0] : cur.xl;
-                    T b = (j < jend && j < VEC - 1) ? wc.v[j < VEC - 1 ? j + 1 : j] : cur.xr;
-                    if constexpr (kEdge) {
-                        if (j == 0 && gxl) a = ghost(wc.v[0], b);
-                        if (j == jend && gxr) b = ghost(wc.v[j], a);
-                    }
-                    acc_axis<T, DYN, N>(cf[j], N - 1, wc.v[j] - a, b - wc.v[j], acc[j]);
-                }
-            }
-            P res;
-            T nan_here = T(0);
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                const T Lh = acc_finish<T, DYN, N>(cf[j], acc[j]);
-                T v = fma_t(dt, Lh, wc.v[j]);
-                if constexpr (kVn) v = fma_t(ra, vn.v[j], rb * v);
-                if constexpr (kClamp) {
-                    if (z.v[j] < v) v = z.v[j];
-                }
-                // v * 0 is NaN exactly when v is not finite
-                nan_here = fma_t(kRag && j > jend ? T(0) : v, T(0), nan_here);
-                res.v[j] = v;
-            }
-            if (i < i0e) {
-                nanacc += nan_here;
-                if (active) stp_nt<T, VEC>(out + int64_t(i) * s0 + q, res);
-            }
-            dm = dp;
-        };
-        using K0 = std::integral_constant<int, 0>;
-        using K1 = std::integral_constant<int, 1>;
-        using K2 = std::integral_constant<int, 2>;
-        using K3 = std::integral_constant<int, 3>;
-        // whole 4-plane cycles; planes past the chunk end are computed from
-        // clamped loads and neither stored nor checked
-        for (int i = i0b; i < i0e; i += 4) {
-            step(K0{}, i);
-            step(K1{}, i + 1);
-            step(K2{}, i + 2);
-            step(K3{}, i + 3);
         }
     };
-    using TT = std::true_type;
-    using FF = std::false_type;
-    if (edge) march(TT{}, TT{});
-    else if (ragged) march(FF{}, TT{});
-    else march(FF{}, FF{});
+    auto load_pw = [&](int i, P &ov, P &oz) {
+        const int64_t o = int64_t(i) * s0 + q;
+        if constexpr (kVn) ov = ldp_nt<T, VEC>(Vn + o);
+        if constexpr (kClamp) oz = ldp_nt<T, VEC>(V0 + o);
+    };
+    w[0] = ldp<T, VEC>(W + plane_of(i0b - 1) + q);
+    w[1] = ldp<T, VEC>(W + plane_of(i0b) + q);
+    w[2] = ldp<T, VEC>(W + plane_of(i0b + 1) + q);
+    load_nb(i0b, nb[0]);
+    load_pw(i0b, vq[0], zq[0]);
+    if (hl) hq[0] = ldp<T, VEC>(W + int64_t(i0b) * s0 + hsrc);
+    P dm;  // W(i) - W(i-1)
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) dm.v[j] = w[1].v[j] - w[0].v[j];
+
+    auto step = [&](auto kc, int i) {
+        constexpr int K = decltype(kc)::value;
+        const P &wm = w[K % 4], &wc = w[(K + 1) % 4], &wp = w[(K + 2) % 4];
+        Nb &cur = nb[K % 2];
+        const P &vn = vq[K % 2], &z = zq[K % 2];
+        T *tb = &tile[K & 1][0];
+        if constexpr (kLdsK) {
+            stp_lds<T, VEC>(tb + me, wc);
+            if (hl) stp_lds<T, VEC>(tb + hdst, hq[K % 2]);
+        }
+        // loads for the planes ahead
+        const int in = min(i + 1, vlast);
+        load_nb(in, nb[(K + 1) % 2]);
+        load_pw(in, vq[(K + 1) % 2], zq[(K + 1) % 2]);
+        if (hl) hq[(K + 1) % 2] = ldp<T, VEC>(W + int64_t(in) * s0 + hsrc);
+        w[(K + 3) % 4] = ldp<T, VEC>(W + plane_of(min(i + 2, wlast)) + q);
+        if constexpr (kLdsK) {
+            __syncthreads();
+            cur.l[N - 3] = ldp_lds<T, VEC>(tb + me - H);
+            cur.r[N - 3] = ldp_lds<T, VEC>(tb + me + H);
+            cur.xl = tb[me + oxl];
+            cur.xr = tb[me + oxr];
+            if (anywrap && lane_wrap) {
+                const ODP_GLOBAL T *plane = W + int64_t(min(i, vlast)) * s0;
+                cur.l[N - 3] = ldp<T, VEC>(plane + qL[N - 2]);
+                cur.r[N - 3] = ldp<T, VEC>(plane + qR[N - 2]);
+            }
+        }
+
+        Acc<T> acc[VEC];
+        P dp;  // W(i+1) - W(i)
+        const bool g0l = !per0 && i == 0, g0r = !per0 && i == n0 - 1;
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            acc[j].L = T(0);
+            acc[j].n2 = T(0);
+            dp.v[j] = wp.v[j] - wc.v[j];
+            T dl = dm.v[j], dr = dp.v[j];
+            if (g0l) dl = wc.v[j] - ghost(wc.v[j], wp.v[j]);
+            if (g0r) dr = ghost(wc.v[j], wm.v[j]) - wc.v[j];
+            acc_axis<T, DYN, N>(cf[j], 0, dl, dr, acc[j]);
+        }
+#pragma unroll
+        for (int d = 1; d < N - 1; ++d) {
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                T a = cur.l[d - 1].v[j], b = cur.r[d - 1].v[j];
+                if (anyg) {
+                    if (gl & (1u << d)) a = ghost(wc.v[j], cur.r[d - 1].v[j]);
+                    if (gr & (1u << d)) b = ghost(wc.v[j], cur.l[d - 1].v[j]);
+                }
+                acc_axis<T, DYN, N>(cf[j], d, wc.v[j] - a, b - wc.v[j], acc[j]);
+            }
+        }
+        if (!rowx) {
+            T dx[VEC + 1];
+            dx[0] = wc.v[0] - cur.xl;
+#pragma unroll
+            for (int j = 1; j < VEC; ++j) dx[j] = wc.v[j] - wc.v[j - 1];
+            dx[VEC] = cur.xr - wc.v[VEC - 1];
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) acc_axis<T, DYN, N>(cf[j], N - 1, dx[j], dx[j + 1], acc[j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                T a = j > 0 ? wc.v[j > 0 ? j - 1 : 0] : cur.xl;
+                T b = (j < jend && j < VEC - 1) ? wc.v[j < VEC - 1 ? j + 1 : j] : cur.xr;
+                if (j == 0 && gxl) a = ghost(wc.v[0], b);
+                if (j == jend && gxr) b = ghost(wc.v[j], a);
+                acc_axis<T, DYN, N>(cf[j], N - 1, wc.v[j] - a, b - wc.v[j], acc[j]);
+            }
+        }
+        P res;
+        T nan_here = T(0);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const T Lh = acc_finish<T, DYN, N>(cf[j], acc[j]);
+            T v = fma_t(dt, Lh, wc.v[j]);
+            if constexpr (kVn) v = fma_t(ra, vn.v[j], rb * v);
+            if constexpr (kClamp) {
+                if (z.v[j] < v) v = z.v[j];
+            }
+            // v * 0 is NaN exactly when v is not finite (padding excluded)
+            nan_here = fma_t(j > jend ? T(0) : v, T(0), nan_here);
+            res.v[j] = v;
+        }
+        if (i < i0e) {
+            nanacc += nan_here;
+            if (active) stp_nt<T, VEC>(out + int64_t(i) * s0 + q, res);
+        }
+        dm = dp;
+    };
+    using K0 = std::integral_constant<int, 0>;
+    using K1 = std::integral_constant<int, 1>;
+    using K2 = std::integral_constant<int, 2>;
+    using K3 = std::integral_constant<int, 3>;
+    // whole 4-plane cycles; planes past the chunk end are computed from
+    // clamped loads and neither stored nor checked
+    for (int i = i0b; i < i0e; i += 4) {
+        step(K0{}, i);
+        step(K1{}, i + 1);
+        step(K2{}, i + 2);
+        step(K3{}, i + 3);
+    }
     if (nanacc != nanacc && active) atomicOr(s.flags, 1);
 }
 
@@ -778,7 +843,18 @@ static hipError_t launch_stage_t(int kind, const SolveDesc *d, const uint32_t *t
         case 0: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 0>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
         case 1: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 1>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
         case 2: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 2>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
-        default: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 3>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
+        case 3: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 3>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
+        default:
+            if constexpr (N >= 3) {
+                switch (kind) {
+                case 4: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 4>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
+                case 5: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 5>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
+                case 6: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 6>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
+                default: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 7>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
+                }
+            } else {
+                return hipErrorInvalidValue;
+            }
         }
     }
     return hipGetLastError();

@@ -42,7 +42,8 @@ struct SolveDesc {
     uint32_t periodic;       // bit d set: axis d periodic
     int32_t pitch;           // elements per last-axis row in memory (>= n[ndim-1];
                              // the elements beyond n[ndim-1] are padding)
-    int32_t pad1_;
+    int32_t lds;             // 1: the marching kernel exchanges each plane of a
+                             // block's range through LDS (ndim >= 3, pitch <= 128 vec)
     int64_t s0;              // stride of axis 0 (= Q)
     int64_t npts;
     int32_t n[kMaxDim];      // nodes per axis

@@ -58,6 +58,7 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         it.qpad = it.g->ndim < 2 ? 1 : (it.g->npts / it.g->n[0] / nl) * it.pitch;
         it.ppad = it.qpad * it.g->n[0];
         it.vec = choose_vec(it.g, prec, it.dyn.id, it.pitch);
+        it.lds = uses_lds(it.g->ndim, it.pitch, it.vec);
         total += it.ppad;
     }
     for (auto &it : items) {
@@ -80,7 +81,7 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
     std::vector<int> perm(n);
     std::iota(perm.begin(), perm.end(), 0);
     auto key = [&](int i) {
-        return std::make_tuple(items[i].dyn.id, items[i].g->ndim, items[i].vec, items[i].rk_order);
+        return std::make_tuple(items[i].dyn.id, items[i].g->ndim, items[i].vec, items[i].rk_order, items[i].lds);
     };
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key(a) < key(b); });
     p.items.clear();
@@ -89,12 +90,13 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
     for (int i = 0; i < n; ++i) {
         const PlanItem &it = p.items[i];
         if (p.groups.empty() || p.groups.back().dyn != it.dyn.id || p.groups.back().ndim != it.g->ndim ||
-            p.groups.back().vec != it.vec || p.groups.back().rk != it.rk_order) {
+            p.groups.back().vec != it.vec || p.groups.back().rk != it.rk_order || p.groups.back().lds != it.lds) {
             PlanGroup gr;
             gr.dyn = it.dyn.id;
             gr.ndim = it.g->ndim;
             gr.vec = it.vec;
             gr.rk = it.rk_order;
+            gr.lds = it.lds;
             gr.first = i;
             p.groups.push_back(gr);
         }
@@ -149,6 +151,7 @@ void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &
         s.s0 = int64_t(s.Q);
         s.npts = g->npts;
         s.pitch = it.pitch;
+        s.lds = it.lds;
         int64_t st = 1;
         for (int d = g->ndim - 1; d >= 0; --d) {
             // the last axis occupies `pitch` elements per row in memory
@@ -301,7 +304,7 @@ static int plan_enqueue(Plan &p, unsigned char *base, hipStream_t st, const std:
             const uint32_t *ts = tsd ? tsd + gr.tile_base : nullptr;
             const uint32_t *tl = tld ? tld + gr.tile_base : nullptr;
             for (int j = 0; j < gr.rk; ++j) {
-                if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, stage_kind(gr.rk, j, brt),
+                if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, stage_kind(gr.rk, j, brt, gr.lds),
                                                  descs, ts, tl, nb, j, 0, k, p.xcd_group, st), "stage")))
                     return rc;
             }

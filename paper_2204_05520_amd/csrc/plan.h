@@ -31,6 +31,7 @@ struct PlanItem {
     int pitch = 0;                      // last-axis row pitch in memory (0: dense)
     int64_t qpad = 0, ppad = 0;         // hyperplane / array elements with padding
     int vec = 1, chunk = 1;
+    int lds = 0;                        // the stage kernel's LDS plane exchange
     uint32_t tiles = 0;
     int64_t max_steps = 0;
     int tab_entries = 0;
@@ -39,7 +40,7 @@ struct PlanItem {
 };
 
 struct PlanGroup {
-    int dyn = 0, ndim = 0, vec = 1, rk = 1;
+    int dyn = 0, ndim = 0, vec = 1, rk = 1, lds = 0;
     int first = 0, count = 0;           // descriptor range
     std::vector<int> order;             // members sorted by step count, descending
     std::vector<uint32_t> prefix;       // prefix[m] = tiles of order[0..m)

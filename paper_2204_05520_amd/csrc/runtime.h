@@ -51,9 +51,12 @@ int default_xcd_group(const odp_grid *g);
 int choose_vec(const odp_grid *g, int precision, int dyn, int64_t pitch);
 uint32_t solve_tiles(int64_t n0, int64_t qpad, int chunk, int vec);
 double alg_bytes_per_step(int precision, int rk_order, int brt, int64_t npts);
-// Stage kind for launch_stage: bit 0 reads V^n, bit 1 tube clamp.
-inline int stage_kind(int rk_order, int stage, int brt) {
-    return (stage > 0 ? 1 : 0) | ((stage == rk_order - 1 && brt) ? 2 : 0);
+// Stage kind for launch_stage: bit 0 reads V^n, bit 1 tube clamp, bit 2 the
+// LDS plane exchange (every listed solve must have SolveDesc::lds set).
+inline int stage_kind(int rk_order, int stage, int brt, int lds = 0) {
+    return (stage > 0 ? 1 : 0) | ((stage == rk_order - 1 && brt) ? 2 : 0) | (lds ? 4 : 0);
 }
+// Whether a solve of this shape uses the LDS plane exchange.
+inline int uses_lds(int ndim, int64_t pitch, int vec) { return ndim >= 3 && pitch <= 128 * int64_t(vec) ? 1 : 0; }
 
 }  // namespace odp

@@ -135,7 +135,7 @@ struct odp_server {
 namespace {
 
 struct Group {
-    int dyn, ndim, vec, rk;
+    int dyn, ndim, vec, rk, lds;
     std::vector<int> slots;
     uint32_t tiles = 0;
     size_t tile_base = 0, list_base = 0;
@@ -378,14 +378,14 @@ void poll_retirements(odp_server *s) {
 // the device on the compute stream, after the ticks already in flight.
 int build_groups(odp_server *s, const std::vector<std::shared_ptr<Req>> &sel, std::vector<Group> &groups) {
     groups.clear();
-    std::map<std::tuple<int, int, int, int>, size_t> idx;
+    std::map<std::tuple<int, int, int, int, int>, size_t> idx;
     for (auto &r : sel) {
         const PlanItem &it = r->plan.items[0];
-        auto key = std::make_tuple(r->dyn.id, r->grid.ndim, it.vec, it.rk_order);
+        auto key = std::make_tuple(r->dyn.id, r->grid.ndim, it.vec, it.rk_order, it.lds);
         auto f = idx.find(key);
         if (f == idx.end()) {
             idx[key] = groups.size();
-            groups.push_back(Group{r->dyn.id, r->grid.ndim, it.vec, it.rk_order, {}, 0, 0, 0});
+            groups.push_back(Group{r->dyn.id, r->grid.ndim, it.vec, it.rk_order, it.lds, {}, 0, 0, 0});
             f = idx.find(key);
         }
         groups[f->second].slots.push_back(r->slot);
@@ -442,7 +442,7 @@ int enqueue_tick(odp_server *s, const std::vector<Group> &groups, hipEvent_t *do
     for (int m = 0; m < kStepsPerTick; ++m) {
         for (const Group &g : groups) {
             for (int j = 0; j < g.rk; ++j) {
-                if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, stage_kind(g.rk, j, brt),
+                if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, stage_kind(g.rk, j, brt, g.lds),
                                                  s->d_slots, s->d_tiles + g.tile_base,
                                                  s->d_tiles + s->tile_cap + g.tile_base, g.tiles, j, 1, 0,
                                                  o.xcd_group, s->st),
