@@ -127,16 +127,15 @@ int choose_vec(const odp_grid *g, int precision, int dyn, int64_t pitch) {
     return 1;
 }
 
-// Planes of axis 0 marched per block: enough blocks to fill the GPU about
-// once (about 1024 resident blocks of 256 threads), but at most a quarter of
-// the axis (at least 4 planes) so that the 8 XCDs' working sets stay small
-// (measured on the 4D 80^4 and 6D 36^6 workloads).
+// Planes of axis 0 marched per block: about 2048 tiles per solve (two to
+// three rounds of resident blocks at the stage kernel's occupancy, measured
+// on the 4D 80^4 grid in both precisions and on the 6D 36^6 grid); the plan
+// rounds it to whole 4-plane cycles.
 int default_chunk(const odp_grid *g, int vec, int precision) {
     (void)precision;
     const int64_t Q = g->npts / g->n[0];
     const int64_t nqb = (Q + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec);
-    int64_t c = (g->n[0] * nqb + 1023) / 1024;
-    c = std::min<int64_t>(c, std::max<int64_t>(4, g->n[0] / 4));
+    const int64_t c = (g->n[0] * nqb + 2047) / 2048;
     return int(std::max<int64_t>(1, std::min<int64_t>(c, g->n[0])));
 }
 
