@@ -55,6 +55,14 @@ __device__ __forceinline__ T ghost(T vb, T vin) {
     return vb + sg * fabs(vb - vin);
 }
 
+// The same ghost from the difference vb - vin (computed by the caller with
+// the same subtraction, so the result is the same bits).
+template <typename T>
+__device__ __forceinline__ T ghost_d(T vb, T diff) {
+    const T sg = T((vb > T(0)) - (vb < T(0)));
+    return vb + sg * fabs(diff);
+}
+
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -410,8 +418,10 @@ __device__ __forceinline__ void stp_nt(ODP_GLOBAL T *p, const Pack<T, VEC> &r) {
     }
 }
 
+// The 4D float32 last stage (V^n, clamp and LDS exchange) is held to 128
+// VGPRs (occupancy 4; two values spill): measured faster than occupancy 3.
 template <typename T, int DYN, int N, int VEC, int KIND>
-__global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__restrict__ descs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((KIND & 7) == 7 && N == 4 && sizeof(T) == 4 ? 4 : 1))) void stage_vec_kernel(const SolveDesc *__restrict__ descs,
                                                            const uint32_t *__restrict__ tile_solve,
                                                            const uint32_t *__restrict__ tile_local,
                                                            int stage, int step_from_desc,
@@ -572,10 +582,14 @@ __global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__re
         P l[NM], r[NM];
         T xl, xr;
     };
-    P w[4];          // stencil-input ring: planes i-1, i, i+1 and the one loading
+    // Live registers per thread: the stencil input of planes i, i+1 and the
+    // one loading (plane i-1 survives only as the difference dm), the
+    // in-plane neighbours of planes i and i+1, one pack each of V^n, V0 and
+    // halo (reloaded once the previous plane's value has been used).
+    P w[4];          // stencil-input ring (planes i-1, i, i+1, i+2)
     Nb nb[2];        // in-plane neighbours: plane i, plane i+1 (loading)
-    P vq[2], zq[2];  // V^n and V0: plane i, plane i+1 (loading)
-    P hq[2];         // halo rows: plane i, plane i+1 (loading)
+    P vq, zq;        // V^n and V0 of plane i
+    P hq;            // halo rows of plane i
     auto load_nb = [&](int i, Nb &o) {
         const ODP_GLOBAL T *plane = W + int64_t(i) * s0;
 #pragma unroll
@@ -597,27 +611,27 @@ __global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__re
     w[1] = ldp<T, VEC>(W + plane_of(i0b) + q);
     w[2] = ldp<T, VEC>(W + plane_of(i0b + 1) + q);
     load_nb(i0b, nb[0]);
-    load_pw(i0b, vq[0], zq[0]);
-    if (hl) hq[0] = ldp<T, VEC>(W + int64_t(i0b) * s0 + hsrc);
+    load_pw(i0b, vq, zq);
+    if (hl) hq = ldp<T, VEC>(W + int64_t(i0b) * s0 + hsrc);
     P dm;  // W(i) - W(i-1)
 #pragma unroll
     for (int j = 0; j < VEC; ++j) dm.v[j] = w[1].v[j] - w[0].v[j];
 
     auto step = [&](auto kc, int i) {
         constexpr int K = decltype(kc)::value;
-        const P &wm = w[K % 4], &wc = w[(K + 1) % 4], &wp = w[(K + 2) % 4];
+        const P &wc = w[(K + 1) % 4], &wp = w[(K + 2) % 4];
         Nb &cur = nb[K % 2];
-        const P &vn = vq[K % 2], &z = zq[K % 2];
         T *tb = &tile[K & 1][0];
+        const int in = min(i + 1, vlast);
         if constexpr (kLdsK) {
             stp_lds<T, VEC>(tb + me, wc);
-            if (hl) stp_lds<T, VEC>(tb + hdst, hq[K % 2]);
+            if (hl) {
+                stp_lds<T, VEC>(tb + hdst, hq);
+                hq = ldp<T, VEC>(W + int64_t(in) * s0 + hsrc);
+            }
         }
         // loads for the planes ahead
-        const int in = min(i + 1, vlast);
         load_nb(in, nb[(K + 1) % 2]);
-        load_pw(in, vq[(K + 1) % 2], zq[(K + 1) % 2]);
-        if (hl) hq[(K + 1) % 2] = ldp<T, VEC>(W + int64_t(in) * s0 + hsrc);
         w[(K + 3) % 4] = ldp<T, VEC>(W + plane_of(min(i + 2, wlast)) + q);
         if constexpr (kLdsK) {
             __syncthreads();
@@ -642,7 +656,7 @@ __global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__re
             dp.v[j] = wp.v[j] - wc.v[j];
             T dl = dm.v[j], dr = dp.v[j];
             if (g0l) dl = wc.v[j] - ghost(wc.v[j], wp.v[j]);
-            if (g0r) dr = ghost(wc.v[j], wm.v[j]) - wc.v[j];
+            if (g0r) dr = ghost_d(wc.v[j], dm.v[j]) - wc.v[j];
             acc_axis<T, DYN, N>(cf[j], 0, dl, dr, acc[j]);
         }
 #pragma unroll
@@ -681,14 +695,16 @@ __global__ __launch_bounds__(kBlock) void stage_vec_kernel(const SolveDesc *__re
         for (int j = 0; j < VEC; ++j) {
             const T Lh = acc_finish<T, DYN, N>(cf[j], acc[j]);
             T v = fma_t(dt, Lh, wc.v[j]);
-            if constexpr (kVn) v = fma_t(ra, vn.v[j], rb * v);
+            if constexpr (kVn) v = fma_t(ra, vq.v[j], rb * v);
             if constexpr (kClamp) {
-                if (z.v[j] < v) v = z.v[j];
+                if (zq.v[j] < v) v = zq.v[j];
             }
             // v * 0 is NaN exactly when v is not finite (padding excluded)
             nan_here = fma_t(j > jend ? T(0) : v, T(0), nan_here);
             res.v[j] = v;
         }
+        // V^n and V0 of the next plane: a step of compute hides their latency
+        load_pw(in, vq, zq);
         if (i < i0e) {
             nanacc += nan_here;
             if (active) stp_nt<T, VEC>(out + int64_t(i) * s0 + q, res);
