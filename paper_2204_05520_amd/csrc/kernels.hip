@@ -610,7 +610,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((KIND & 
     w[0] = ldp<T, VEC>(W + plane_of(i0b - 1) + q);
     w[1] = ldp<T, VEC>(W + plane_of(i0b) + q);
     w[2] = ldp<T, VEC>(W + plane_of(i0b + 1) + q);
-    load_nb(i0b, nb[0]);
+    // ndim >= 5: the outer-axis neighbours are loaded in their own plane's
+    // step (three axes of pipelined neighbours would cost an occupancy level)
+    constexpr bool kPipeNb = N <= 4;
+    if constexpr (kPipeNb) load_nb(i0b, nb[0]);
     load_pw(i0b, vq, zq);
     if (hl) hq = ldp<T, VEC>(W + int64_t(i0b) * s0 + hsrc);
     P dm;  // W(i) - W(i-1)
@@ -631,7 +634,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((KIND & 
             }
         }
         // loads for the planes ahead
-        load_nb(in, nb[(K + 1) % 2]);
+        if constexpr (kPipeNb) load_nb(in, nb[(K + 1) % 2]);
+        else load_nb(min(i, vlast), cur);
         w[(K + 3) % 4] = ldp<T, VEC>(W + plane_of(min(i + 2, wlast)) + q);
         if constexpr (kLdsK) {
             __syncthreads();

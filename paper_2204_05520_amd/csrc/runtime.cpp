@@ -129,14 +129,17 @@ int choose_vec(const odp_grid *g, int precision, int dyn, int64_t pitch) {
 
 // Planes of axis 0 marched per block: about 2048 tiles per solve (two to
 // three rounds of resident blocks at the stage kernel's occupancy, measured
-// on the 4D 80^4 grid in both precisions and on the 6D 36^6 grid); the plan
-// rounds it to whole 4-plane cycles.
+// on the 4D 80^4 grid in both precisions), at most a third of the axis from
+// five dimensions on (measured on the 6D 36^6 grid: 12 planes beat 4, 8, 20
+// and 36); the plan rounds it to whole 4-plane cycles.
 int default_chunk(const odp_grid *g, int vec, int precision) {
     (void)precision;
-    const int64_t Q = g->npts / g->n[0];
+    const int64_t n0 = g->n[0];
+    const int64_t Q = g->npts / n0;
     const int64_t nqb = (Q + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec);
-    const int64_t c = (g->n[0] * nqb + 2047) / 2048;
-    return int(std::max<int64_t>(1, std::min<int64_t>(c, g->n[0])));
+    int64_t c = (n0 * nqb + 2047) / 2048;
+    if (g->ndim >= 5) c = std::min<int64_t>(c, (n0 + 2) / 3);
+    return int(std::max<int64_t>(1, std::min<int64_t>(c, n0)));
 }
 
 // Tile runs per XCD: one contiguous run, except for grids whose arrays are
