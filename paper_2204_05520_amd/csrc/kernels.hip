@@ -840,12 +840,61 @@ __global__ __launch_bounds__(kBlock) void start_copy_kernel(const SolveDesc *__r
     if (g >= s.Q / uint32_t(s.vec)) return;
     const uint32_t q = g * uint32_t(s.vec);
     T *dst = (s.rk_order == 1 && ((*s.nsteps) & 1)) ? (T *)s.B : (T *)s.A;
+    const int i0b = int(cid) * s.chunk;
+    const int i0e = min(i0b + s.chunk, s.n0);
+    if (s.Vsrc_dense) {
+        // padded copies of the caller's dense V0: V0 and the start buffer
+        // (padding elements set to zero)
+        const int nd = s.ndim, nl = s.n[nd - 1];
+        const uint32_t row = fdiv(q, s.div[nd - 1]);
+        const int c0 = int(q - row * uint32_t(s.pitch));
+        const int64_t dplane = int64_t(s.Q / uint32_t(s.pitch)) * nl;
+        const T *src = (const T *)s.Vsrc_dense;
+        T *v0 = (T *)s.V0;
+        for (int i0 = i0b; i0 < i0e; ++i0) {
+            const int64_t o = int64_t(i0) * s.s0 + q;
+            const int64_t od = int64_t(i0) * dplane + int64_t(row) * nl + c0;
+            for (int j = 0; j < s.vec; ++j) {
+                const T v = c0 + j < nl ? src[od + j] : T(0);
+                v0[o + j] = v;
+                dst[o + j] = v;
+            }
+        }
+        return;
+    }
     const T *src = (const T *)s.Vinit;
+    for (int i0 = i0b; i0 < i0e; ++i0) {
+        const int64_t o = int64_t(i0) * s.s0 + q;
+        for (int j = 0; j < s.vec; ++j) dst[o + j] = src[o + j];
+    }
+}
+
+// Padded members: the final A to the caller's dense V_out.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void finish_copy_kernel(const SolveDesc *__restrict__ descs,
+                                                             const uint32_t *__restrict__ tile_solve,
+                                                             const uint32_t *__restrict__ tile_local) {
+    const uint32_t L = xcd_logical(blockIdx.x, gridDim.x, 0u);
+    const uint32_t si = tile_solve ? tile_solve[L] : 0u;
+    const uint32_t lt = tile_solve ? tile_local[L] : L;
+    const SolveDesc &s = descs[si];
+    if (!s.Adst_dense) return;
+    const uint32_t cid = lt / s.nqb;
+    const uint32_t g = (lt - cid * s.nqb) * kBlock + threadIdx.x;
+    if (g >= s.Q / uint32_t(s.vec)) return;
+    const uint32_t q = g * uint32_t(s.vec);
+    const int nd = s.ndim, nl = s.n[nd - 1];
+    const uint32_t row = fdiv(q, s.div[nd - 1]);
+    const int c0 = int(q - row * uint32_t(s.pitch));
+    const int64_t dplane = int64_t(s.Q / uint32_t(s.pitch)) * nl;
+    const T *a = (const T *)s.A;
+    T *dst = (T *)s.Adst_dense;
     const int i0b = int(cid) * s.chunk;
     const int i0e = min(i0b + s.chunk, s.n0);
     for (int i0 = i0b; i0 < i0e; ++i0) {
         const int64_t o = int64_t(i0) * s.s0 + q;
-        for (int j = 0; j < s.vec; ++j) dst[o + j] = src[o + j];
+        const int64_t od = int64_t(i0) * dplane + int64_t(row) * nl + c0;
+        for (int j = 0; j < s.vec && c0 + j < nl; ++j) dst[od + j] = a[o + j];
     }
 }
 
@@ -969,6 +1018,16 @@ hipError_t launch_start_copy(int precision, const SolveDesc *d, const uint32_t *
         hipLaunchKernelGGL(start_copy_kernel<float>, dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl);
     else
         hipLaunchKernelGGL(start_copy_kernel<double>, dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_copy(int precision, const SolveDesc *d, const uint32_t *ts,
+                             const uint32_t *tl, uint32_t nblocks, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    if (precision == 32)
+        hipLaunchKernelGGL(finish_copy_kernel<float>, dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl);
+    else
+        hipLaunchKernelGGL(finish_copy_kernel<double>, dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl);
     return hipGetLastError();
 }
 

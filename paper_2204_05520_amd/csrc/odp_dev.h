@@ -70,6 +70,9 @@ struct SolveDesc {
     void *C;                 // stage 2 output (RK3)
     const void *V0;
     const void *Vinit;       // start value (V0 unless restarting)
+    const void *Vsrc_dense;  // caller's dense V0 when V0/A are padded copies (else null):
+                             // the start copy fills V0 and the start buffer from it
+    void *Adst_dense;        // caller's dense V_out when A is a padded copy (else null)
     const double *tabd;      // axis tables (float64)
     double *amax;            // alpha^max per axis (float64 bits, atomically maxed)
     double *dt_sched;        // dt of every step

@@ -132,6 +132,12 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         off += arr;
         it.C_off = off;
         off += it.rk_order == 3 ? arr : 0;
+        if (it.pad_io) {
+            it.V0p_off = off;
+            off += arr;
+            it.Ap_off = off;
+            off += arr;
+        }
     }
     p.total = off;
     return perm;
@@ -174,11 +180,13 @@ void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &
         s.d_mode = it.dyn.d_mode;
         s.global_alpha = o.dissipation;
         for (int k = 0; k < 16; ++k) s.p[k] = it.dyn.p[k];
-        s.A = it.A;
+        s.A = it.pad_io ? base + it.Ap_off : it.A;
         s.B = base + it.B_off;
         s.C = it.rk_order == 3 ? base + it.C_off : nullptr;
-        s.V0 = it.V0;
-        s.Vinit = it.Vinit ? it.Vinit : it.V0;
+        s.V0 = it.pad_io ? base + it.V0p_off : it.V0;
+        s.Vinit = it.pad_io ? base + it.V0p_off : (it.Vinit ? it.Vinit : it.V0);
+        s.Vsrc_dense = it.pad_io ? it.V0 : nullptr;
+        s.Adst_dense = it.pad_io ? it.A : nullptr;
         unsigned char *state = base + it.aux_off;
         s.amax = (double *)state;
         s.nsteps = (int64_t *)(state + kMaxDim * 8);
@@ -315,6 +323,16 @@ static int plan_enqueue(Plan &p, unsigned char *base, hipStream_t st, const std:
             unsigned char *dst = (unsigned char *)V_all + size_t((*land)[size_t(k)]) * bytes;
             if ((rc = check_hip(hipMemcpyAsync(dst, outb, bytes, hipMemcpyDeviceToDevice, st), "save"))) return rc;
         }
+    }
+    // padded members: the result back to the caller's dense array
+    for (const PlanGroup &gr : p.groups) {
+        bool any = false;
+        for (int i = gr.first; i < gr.first + gr.count; ++i) any = any || p.items[size_t(i)].pad_io;
+        if (!any) continue;
+        const uint32_t *ts = tsd ? tsd + gr.tile_base : nullptr;
+        const uint32_t *tl = tld ? tld + gr.tile_base : nullptr;
+        if ((rc = check_hip(launch_finish_copy(prec, descs, ts, tl, gr.prefix.back(), st), "finish copy")))
+            return rc;
     }
     return ODP_OK;
 }

@@ -32,6 +32,10 @@ struct PlanItem {
     int64_t qpad = 0, ppad = 0;         // hyperplane / array elements with padding
     int vec = 1, chunk = 1;
     int lds = 0;                        // the stage kernel's LDS plane exchange
+    // pad_io: the caller's V0 and A are dense while `pitch` pads the rows;
+    // the plan keeps padded copies (V0p, Ap) and copies in and out itself
+    bool pad_io = false;
+    size_t V0p_off = 0, Ap_off = 0;
     uint32_t tiles = 0;
     int64_t max_steps = 0;
     int tab_entries = 0;

@@ -150,6 +150,14 @@ static int batch_items(int nsolves, const odp_solve_desc *descs, const odp_solve
             return set_error(ODP_EINVAL, "batch entry " + std::to_string(i) + ": rk_order must be 0..3");
         items.push_back(make_item(d.grid, &d.dyn, d.V0_dev, nullptr, d.tau, d.ntau, d.V_out_dev));
         items.back().rk_order = d.rk_order;
+        // rows that are not a whole number of 16-byte vectors: the plan works
+        // on padded copies, so that every member runs the widest kernel
+        const int64_t nl = d.grid->n[d.grid->ndim - 1];
+        const int64_t w = common->precision == 32 ? 4 : 2;
+        if (d.grid->ndim >= 2 && d.dyn.id != ODP_DYN_SINGLE_INTEGRATOR && nl % w != 0) {
+            items.back().pitch = int((nl + w - 1) / w * w);
+            items.back().pad_io = true;
+        }
     }
     return ODP_OK;
 }
