@@ -61,6 +61,9 @@ const char *odp_last_error(void);
  * keeps the sign of the boundary node).  The total point count must stay
  * below 2^31 per hyperplane of axes 1..ndim-1 and below 2^40 overall.
  * On success *out owns a host object freed by odp_grid_destroy. */
+/* odp_solve_opts.tile_chunk: let the library time candidate tilings. */
+#define ODP_TILE_AUTOTUNE (-1)
+
 typedef struct odp_grid odp_grid;
 int odp_grid_create(int ndim, const int64_t *n, const double *lo, const double *hi,
                     const uint8_t *periodic, odp_grid **out);
@@ -114,7 +117,11 @@ typedef struct {
                             (the paper's cheaper approximation) */
     double max_dt;       /* 0: none; > 0 caps the CFL step (tests use it) */
     int32_t save_all;    /* 1: also write V at every tau[k] into V_all_dev */
-    int32_t tile_chunk;  /* 0: library default; else planes marched per block */
+    int32_t tile_chunk;  /* 0: library default; ODP_TILE_AUTOTUNE (-1): chosen by
+                            timing the stage launches of step 0 for a list of
+                            candidates on the first solve (or batch) of each
+                            problem shape, cached for the process (results do
+                            not depend on it); else planes marched per block */
     void *stream;        /* hipStream_t for every launch (NULL: null stream) */
     int32_t xcd_group;   /* 0: library default (one contiguous run of tiles per
                             XCD; runs of 64 for grids of 2^28 points or more);

@@ -21,6 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libodp.so")
 
+ODP_TILE_AUTOTUNE = -1  # odp_solve_opts.tile_chunk: timed candidates, cached per shape
 ODP_OK = 0
 ODP_PENDING = 1
 ODP_EINVAL = -1

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libodp.so")
 
-SOURCES = ["kernels.hip", "runtime.cpp", "plan.cpp", "solve.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "plan.cpp", "tune.cpp", "solve.cpp", "serve.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -43,7 +43,7 @@ int balanced_chunk(const odp_grid *g, int c, bool cycle4) {
 }  // namespace
 
 std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solve_opts &opts,
-                            int tile_chunk) {
+                            int tile_chunk, bool round4) {
     p.opts = opts;
     p.xcd_group = opts.xcd_group > 0 ? opts.xcd_group
                                      : (items.size() == 1 ? default_xcd_group(items[0].g) : 0);
@@ -71,7 +71,7 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
                 c = int(std::max<int64_t>(1, total / (int64_t(kBlock) * it.vec * 8192)));
             }
         }
-        it.chunk = balanced_chunk(it.g, c, tile_chunk <= 0);
+        it.chunk = balanced_chunk(it.g, c, tile_chunk <= 0 || round4);
         it.tiles = solve_tiles(it.g->n[0], it.qpad, it.chunk, it.vec);
         it.max_steps = step_capacity(it.g, &it.dyn, it.tau, opts.cfl, opts.max_dt);
         it.tab_entries = 0;
@@ -286,6 +286,32 @@ int plan_prologue(Plan &p, unsigned char *base, hipStream_t st) {
     return ODP_OK;
 }
 
+int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t k) {
+    int rc;
+    const int prec = p.opts.precision;
+    const int brt = p.opts.mode == ODP_BRT;
+    const SolveDesc *descs = (const SolveDesc *)(base + p.desc_off);
+    const bool single = p.items.size() == 1;
+    const uint32_t *tsd = single ? nullptr : (const uint32_t *)(base + p.tt_off);
+    const uint32_t *tld = single ? nullptr : tsd + align256(p.total_tiles * 4) / 4;
+    for (const PlanGroup &gr : p.groups) {
+        // members with more than k steps form a prefix of gr.order
+        size_t m = 0;
+        while (m < gr.order.size() && p.items[size_t(gr.order[m])].nsteps > k) ++m;
+        const uint32_t nb = gr.prefix[m];
+        if (nb == 0) continue;
+        const uint32_t *ts = tsd ? tsd + gr.tile_base : nullptr;
+        const uint32_t *tl = tld ? tld + gr.tile_base : nullptr;
+        for (int j = 0; j < gr.rk; ++j) {
+            if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, stage_kind(gr.rk, j, brt, gr.lds), descs,
+                                             ts, tl, nb, j, 0, k, p.xcd_group, st),
+                                "stage")))
+                return rc;
+        }
+    }
+    return ODP_OK;
+}
+
 static int plan_enqueue(Plan &p, unsigned char *base, hipStream_t st, const std::vector<int32_t> *land,
                         void *V_all) {
     int rc;
@@ -295,7 +321,6 @@ static int plan_enqueue(Plan &p, unsigned char *base, hipStream_t st, const std:
     const bool single = p.items.size() == 1;
     const uint32_t *tsd = single ? nullptr : (const uint32_t *)(base + p.tt_off);
     const uint32_t *tld = single ? nullptr : tsd + align256(p.total_tiles * 4) / 4;
-    const int brt = o.mode == ODP_BRT;
     for (const PlanGroup &gr : p.groups) {
         const uint32_t *ts = tsd ? tsd + gr.tile_base : nullptr;
         const uint32_t *tl = tld ? tld + gr.tile_base : nullptr;
@@ -303,20 +328,7 @@ static int plan_enqueue(Plan &p, unsigned char *base, hipStream_t st, const std:
     }
     const size_t bytes = single ? size_t(p.items[0].g->npts) * (prec == 32 ? 4 : 8) : 0;
     for (int64_t k = 0; k < p.max_nsteps; ++k) {
-        for (const PlanGroup &gr : p.groups) {
-            // members with more than k steps form a prefix of gr.order
-            size_t m = 0;
-            while (m < gr.order.size() && p.items[size_t(gr.order[m])].nsteps > k) ++m;
-            const uint32_t nb = gr.prefix[m];
-            if (nb == 0) continue;
-            const uint32_t *ts = tsd ? tsd + gr.tile_base : nullptr;
-            const uint32_t *tl = tld ? tld + gr.tile_base : nullptr;
-            for (int j = 0; j < gr.rk; ++j) {
-                if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, stage_kind(gr.rk, j, brt, gr.lds),
-                                                 descs, ts, tl, nb, j, 0, k, p.xcd_group, st), "stage")))
-                    return rc;
-            }
-        }
+        if ((rc = plan_launch_step(p, base, st, k))) return rc;
         if (land && V_all && (*land)[size_t(k)] >= 0) {
             const PlanItem &it = p.items[0];
             const void *outb = (it.rk_order == 1 && ((k + it.nsteps) & 1) == 0) ? base + it.B_off : it.A;

@@ -63,8 +63,12 @@ struct Plan {
 
 // Order items by (dynamics, ndim, vector width, RK order), fill the layout.
 // Returns the permutation applied (new index -> caller index).
+// round4: round the chunk to whole 4-plane cycles (always for the default).
 std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solve_opts &opts,
-                            int tile_chunk);
+                            int tile_chunk, bool round4 = false);
+// The stage launches of step k for every group (the members that have a
+// step k, as in the solve itself).
+int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t k);
 // Host image of [0, upload_bytes) for a workspace at device address base.
 void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &img);
 // Upload, alpha^max, schedules; reads back the step counts (one sync), sorts

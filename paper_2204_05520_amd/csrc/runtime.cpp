@@ -76,7 +76,8 @@ int validate_opts(const odp_solve_opts *o) {
     if (o->dissipation != 0 && o->dissipation != 1) return set_error(ODP_EINVAL, "dissipation must be 0 or 1");
     if (!(o->max_dt >= 0.0) || !std::isfinite(o->max_dt)) return set_error(ODP_EINVAL, "max_dt must be >= 0");
     if (o->save_all != 0 && o->save_all != 1) return set_error(ODP_EINVAL, "save_all must be 0 or 1");
-    if (o->tile_chunk < 0) return set_error(ODP_EINVAL, "tile_chunk must be >= 0");
+    if (o->tile_chunk < 0 && o->tile_chunk != ODP_TILE_AUTOTUNE)
+        return set_error(ODP_EINVAL, "tile_chunk must be >= 0 or ODP_TILE_AUTOTUNE");
     if (o->xcd_group < 0) return set_error(ODP_EINVAL, "xcd_group must be >= 0");
     if (o->graph < 0 || o->graph > 2) return set_error(ODP_EINVAL, "graph must be 0, 1 or 2");
     return ODP_OK;

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "plan.h"
+#include "tune.h"
 #include "runtime.h"
 
 using namespace odp;
@@ -75,6 +76,7 @@ size_t odp_hj_workspace_bytes(const odp_grid *grid, const odp_dynamics *dyn, con
         return 0;
     Plan p;
     std::vector<PlanItem> items{make_item(grid, dyn, nullptr, nullptr, tau, ntau, nullptr)};
+    if (opts->tile_chunk == ODP_TILE_AUTOTUNE) return tune_workspace_bytes(items, *opts);
     plan_build(p, std::move(items), *opts, opts->tile_chunk);
     return p.total;
 }
@@ -94,10 +96,23 @@ int odp_hj_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_d
 
     Plan p;
     std::vector<PlanItem> items{make_item(grid, dyn, V0_dev, V_init_dev, tau, ntau, V_out_dev)};
-    plan_build(p, std::move(items), *opts, opts->tile_chunk);
     DeviceBuffer ws;
-    if ((rc = alloc_workspace(ws, workspace_dev, SIZE_MAX, p.total, st))) return rc;
-    unsigned char *base = (unsigned char *)ws.ptr;
+    unsigned char *base = nullptr;
+    int chunk = opts->tile_chunk;
+    if (chunk == ODP_TILE_AUTOTUNE && tune_cached(items, *opts, &chunk)) {
+        plan_build(p, std::move(items), *opts, chunk, true);
+        if ((rc = alloc_workspace(ws, workspace_dev, SIZE_MAX, p.total, st))) return rc;
+        base = (unsigned char *)ws.ptr;
+    } else if (chunk == ODP_TILE_AUTOTUNE) {
+        if ((rc = alloc_workspace(ws, workspace_dev, SIZE_MAX, tune_workspace_bytes(items, *opts), st))) return rc;
+        base = (unsigned char *)ws.ptr;
+        if ((rc = tune_tile_chunk(items, *opts, base, st, &chunk))) return rc;
+        plan_build(p, std::move(items), *opts, chunk, true);
+    } else {
+        plan_build(p, std::move(items), *opts, chunk);
+        if ((rc = alloc_workspace(ws, workspace_dev, SIZE_MAX, p.total, st))) return rc;
+        base = (unsigned char *)ws.ptr;
+    }
     if ((rc = plan_prologue(p, base, st))) return rc;
 
     std::vector<int32_t> land;
@@ -165,6 +180,7 @@ static int batch_items(int nsolves, const odp_solve_desc *descs, const odp_solve
 size_t odp_hj_batch_workspace_bytes(int nsolves, const odp_solve_desc *descs, const odp_solve_opts *common) {
     std::vector<PlanItem> items;
     if (batch_items(nsolves, descs, common, items) != ODP_OK) return 0;
+    if (common->tile_chunk == ODP_TILE_AUTOTUNE) return tune_workspace_bytes(items, *common);
     Plan p;
     plan_build(p, std::move(items), *common, common->tile_chunk);
     return p.total;
@@ -177,10 +193,25 @@ int odp_hj_batch(int nsolves, const odp_solve_desc *descs, const odp_solve_opts 
     if ((rc = batch_items(nsolves, descs, common, items))) return rc;
     hipStream_t st = (hipStream_t)common->stream;
     Plan p;
-    const std::vector<int> perm = plan_build(p, std::move(items), *common, common->tile_chunk);
     DeviceBuffer ws;
-    if ((rc = alloc_workspace(ws, workspace_dev, workspace_bytes, p.total, st))) return rc;
-    unsigned char *base = (unsigned char *)ws.ptr;
+    unsigned char *base = nullptr;
+    std::vector<int> perm;
+    int chunk = common->tile_chunk;
+    if (chunk == ODP_TILE_AUTOTUNE && tune_cached(items, *common, &chunk)) {
+        perm = plan_build(p, std::move(items), *common, chunk, true);
+        if ((rc = alloc_workspace(ws, workspace_dev, workspace_bytes, p.total, st))) return rc;
+        base = (unsigned char *)ws.ptr;
+    } else if (chunk == ODP_TILE_AUTOTUNE) {
+        if ((rc = alloc_workspace(ws, workspace_dev, workspace_bytes, tune_workspace_bytes(items, *common), st)))
+            return rc;
+        base = (unsigned char *)ws.ptr;
+        if ((rc = tune_tile_chunk(items, *common, base, st, &chunk))) return rc;
+        perm = plan_build(p, std::move(items), *common, chunk, true);
+    } else {
+        perm = plan_build(p, std::move(items), *common, chunk);
+        if ((rc = alloc_workspace(ws, workspace_dev, workspace_bytes, p.total, st))) return rc;
+        base = (unsigned char *)ws.ptr;
+    }
     if ((rc = plan_prologue(p, base, st))) return rc;
     Timer tm;
     if (stats_per_solve) {

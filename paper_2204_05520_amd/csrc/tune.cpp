@@ -1,0 +1,136 @@
+// Tile autotuner for the stage kernel.
+//
+// The chunk (planes of axis 0 a block marches) decides how many tiles a
+// launch has, how many rounds of resident blocks it takes and how far apart
+// in time the blocks that share in-plane neighbours run; the best value
+// depends on the grid, the precision, the dimension and the mix of solves.
+// Results do not depend on it (every point's arithmetic is the same), so
+// the tuner times the real stage launches for a list of candidate chunks on
+// the real workspace, keeps the fastest, and caches it per problem shape for
+// the life of the process: for one solve, step 0 (every step launches the
+// same tiles); for a batch, every step (members drop out as they finish, so
+// later launches are smaller and may favour other chunks).
+#include "tune.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+
+namespace odp {
+
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, int> g_cache;
+
+std::string shape_key(const std::vector<PlanItem> &items, const odp_solve_opts &o) {
+    std::string k = "p" + std::to_string(o.precision) + "m" + std::to_string(o.mode) + "r" +
+                    std::to_string(o.rk_order) + "x" + std::to_string(o.xcd_group) + "|";
+    for (const PlanItem &it : items) {
+        k += std::to_string(it.dyn.id) + ":" + std::to_string(it.rk_order) + ":" + std::to_string(it.pitch) +
+             (it.pad_io ? "p" : "") + ":";
+        for (int d = 0; d < it.g->ndim; ++d) k += std::to_string(it.g->n[d]) + ",";
+        k += ";";
+    }
+    return k;
+}
+
+std::vector<int> candidates(const std::vector<PlanItem> &items) {
+    std::vector<int> c;
+    if (items.size() == 1) {
+        const int n0 = int(items[0].g->n[0]);
+        for (int v : {4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 64, 80, 96, 128})
+            if (v <= n0) c.push_back(v);
+        c.push_back(0);  // the library default
+    } else {
+        for (int v : {2, 4, 8, 12, 16, 24, 32}) c.push_back(v);
+        c.push_back(0);
+    }
+    return c;
+}
+
+struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+}  // namespace
+
+bool tune_cached(const std::vector<PlanItem> &items, const odp_solve_opts &opts, int *chunk) {
+    const std::string key = shape_key(items, opts);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto f = g_cache.find(key);
+    if (f == g_cache.end()) return false;
+    *chunk = f->second;
+    return true;
+}
+
+size_t tune_workspace_bytes(const std::vector<PlanItem> &items, const odp_solve_opts &opts) {
+    size_t most = 0;
+    for (int c : candidates(items)) {
+        Plan p;
+        plan_build(p, items, opts, c, true);
+        most = std::max(most, p.total);
+    }
+    return most;
+}
+
+int tune_tile_chunk(const std::vector<PlanItem> &items, const odp_solve_opts &opts, unsigned char *base,
+                    hipStream_t st, int *chunk) {
+    const std::string key = shape_key(items, opts);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto f = g_cache.find(key);
+        if (f != g_cache.end()) {
+            *chunk = f->second;
+            return ODP_OK;
+        }
+    }
+    int rc;
+    Events ev;
+    if ((rc = check_hip(hipEventCreate(&ev.a), "event")) || (rc = check_hip(hipEventCreate(&ev.b), "event")))
+        return rc;
+    constexpr int kReps = 3;
+    float best_ms = 0.f;
+    int best = 0;
+    std::vector<int> seen;  // chunk of the first item, to skip candidates that round alike
+    for (int c : candidates(items)) {
+        Plan p;
+        plan_build(p, items, opts, c, true);
+        if (items.size() == 1) {
+            if (std::find(seen.begin(), seen.end(), p.items[0].chunk) != seen.end()) continue;
+            seen.push_back(p.items[0].chunk);
+        }
+        if ((rc = plan_prologue(p, base, st)) || (rc = plan_launch_step(p, base, st, 0)) ||
+            (rc = check_hip(hipEventRecord(ev.a, st), "record")))
+            return rc;
+        if (items.size() == 1) {
+            for (int r = 0; r < kReps; ++r)
+                if ((rc = plan_launch_step(p, base, st, 0))) return rc;
+        } else {
+            for (int64_t k = 0; k < p.max_nsteps; ++k)
+                if ((rc = plan_launch_step(p, base, st, k))) return rc;
+        }
+        float ms = 0.f;
+        if ((rc = check_hip(hipEventRecord(ev.b, st), "record")) ||
+            (rc = check_hip(hipEventSynchronize(ev.b), "sync")) ||
+            (rc = check_hip(hipEventElapsedTime(&ms, ev.a, ev.b), "elapsed")))
+            return rc;
+        if (best_ms == 0.f || ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache[key] = best;
+    *chunk = best;
+    return ODP_OK;
+}
+
+}  // namespace odp

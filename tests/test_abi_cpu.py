@@ -70,7 +70,8 @@ def _solve_rc(spec, precision=32, **kw):
     tau = kw.pop("tau", spec.tau)
     t = (ctypes.c_double * len(tau))(*tau)
     opts = odp.make_opts(precision, kw.pop("rk", spec.rk_order), kw.pop("cfl", spec.cfl), spec.mode,
-                         kw.pop("diss", 0), kw.pop("max_dt", 0.0), kw.pop("save_all", 0), 0, None)
+                         kw.pop("diss", 0), kw.pop("max_dt", 0.0), kw.pop("save_all", 0),
+                         kw.pop("tile_chunk", 0), None)
     V0 = kw.pop("V0", ctypes.c_void_p(0x1000))
     Vout = kw.pop("Vout", ctypes.c_void_p(0x2000))
     rc = odp.lib().odp_hj_solve(grid.handle, ctypes.byref(d), V0, None, t, len(tau),
@@ -132,6 +133,19 @@ def test_workspace_bytes(lib):
     b1 = odp.odp_hj_workspace_bytes(grid, spec.dyn, spec.tau, o1)
     assert 4 * P <= b1 < 4 * P + (8 << 20)
     assert odp.odp_hj_workspace_bytes(grid, spec.dyn, [1.0, 0.5], o32) == 0
+
+
+def test_tile_chunk_values(lib):
+    """tile_chunk: >= 0 or the autotune sentinel; with autotune the workspace
+    query covers every candidate tiling."""
+    spec = W.config_dyncar4d(n=(24, 20, 16, 12))
+    grid = odp.Grid.from_spec(spec.grid)
+    fixed = odp.odp_hj_workspace_bytes(grid, spec.dyn, spec.tau, odp.make_opts(32, 3, tile_chunk=4))
+    auto = odp.odp_hj_workspace_bytes(grid, spec.dyn, spec.tau,
+                                      odp.make_opts(32, 3, tile_chunk=odp.ODP_TILE_AUTOTUNE))
+    assert fixed > 0 and auto >= fixed
+    rc, err = _solve_rc(spec, tile_chunk=-2)
+    assert rc == odp.ODP_EINVAL and "tile_chunk" in err
 
 
 def test_batch_and_server_reject(lib):

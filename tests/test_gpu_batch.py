@@ -52,6 +52,20 @@ def test_batch_equals_single(odp, prec):
         assert stats[i]["steps"] == single.stats["steps"]
 
 
+def test_batch_autotuned_equals_default(odp):
+    """Autotuned batch tiles (first call tunes, second hits the cache) give
+    the default tiling's bits for every member."""
+    import torch
+    specs = small_batch(17, 5)
+    V0s = [_dev(W.make_v0(s), 32) for s in specs]
+    ref, _ = odp.batch(specs, V0s, precision=32)
+    for _ in range(2):
+        got, st = odp.batch(specs, V0s, precision=32, tile_chunk=odp.ODP_TILE_AUTOTUNE)
+        torch.cuda.synchronize()
+        for i in range(len(specs)):
+            assert bool(torch.equal(got[i], ref[i])), i
+
+
 def test_batch_fp64_matches_oracle(odp, oracle_mod):
     import torch
     specs = small_batch(6, 5)

@@ -111,6 +111,20 @@ def test_parity_tile_chunks_bitwise(odp):
         assert all(same), same
 
 
+def test_autotuned_tiles_bitwise(odp):
+    """The autotuner times candidate tilings in the real workspace (and the
+    caller's output array) before the solve: the result equals the default
+    tiling's bit for bit, on the first call (tuning) and the second (cache)."""
+    import torch
+    spec = W.config_dyncar4d(n=[21, 17, 12, 20], T=0.3)
+    V0 = W.make_v0(spec)
+    for prec in (32, 64):
+        ref = gpu_solve(odp, spec, V0, prec).V.cpu()
+        for _ in range(2):
+            got = gpu_solve(odp, spec, V0, prec, tile_chunk=odp.ODP_TILE_AUTOTUNE).V.cpu()
+            assert bool(torch.equal(got, ref))
+
+
 def test_parity_save_all_and_restart(odp, oracle_mod):
     import torch
     spec = W.config_dubins3d(n=(26, 24, 18), T=1.0)
