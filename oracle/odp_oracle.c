@@ -18,7 +18,12 @@
  *     H  = pbar . f(z_i, u*, d*)
  *     Hh = H + 1/2 sum_d alpha_d (p+_d - p-_d)         (Lax-Friedrichs)
  *     stage output = a * V^n + b * (W + dt * Hh)        (TVD Runge-Kutta)
- *   after the last stage of a step, for a tube: V = min(V, V0)
+ *   after the last stage of a step, the computation method (paper: the
+ *   Computation Methods for Value Function table): a target-set operation
+ *   V = min or max of V and V0, V^n (the value before the step) or a target
+ *   array l, then an obstacle operation V = min or max of V and an obstacle
+ *   array g (reach-avoid: min with l, then max with g); a tube (BRT) is
+ *   min(V, V0)
  *   dt = CFL / sum_d (alpha^max_d / dx_d), clipped so that t lands exactly on
  *   every requested output time.
  *
@@ -31,7 +36,9 @@
  *    (equal to the costate-box maximum for bang-bang inputs, whose |f_d|
  *    does not depend on the costate);
  *  - dt carries the CFL number, which the printed step formula omits;
- *  - one dt per full step; min(V, V0) after every full step;
+ *  - one dt per full step; the computation method after every full step,
+ *    the target-set operation before the obstacle operation, the "value
+ *    over time" reference being V^n, the value at the start of the step;
  *  - ghost value beyond a non-periodic edge: V_b + sgn(V_b) |V_b - V_in|,
  *    sgn(0) = 0, so the ghost has the boundary node's sign;
  *  - bang-bang tie at a zero switching function: a maximiser takes +max, a
@@ -353,12 +360,43 @@ static int og_setup(og_grid *g, og_dyn *dy, int ndim, const long *n, const doubl
 
 /* ------------------------------------------------------------ solve */
 
+/* Computation method after a full step (paper: Computation Methods for
+ * Value Function table).  tmode: 0 none, 1 minVWithV0, 2 maxVWithV0,
+ * 3 minVWithVInit, 4 maxVWithVInit (reference V^n, the value before the
+ * step), 5 minVWithVTarget, 6 maxVWithVTarget (reference: target array);
+ * omode: 0 none, 1 minVWithObstacle, 2 maxVWithObstacle.  The target-set
+ * operation comes first (reach-avoid: max(min(V, l), g)). */
+static double og_clamp(double v, long i, int tmode, int omode, const double *V0, const double *Vn,
+                       const double *target, const double *obstacle)
+{
+    if (tmode) {
+        const double ref = (tmode <= 2) ? V0[i] : (tmode <= 4) ? Vn[i] : target[i];
+        if (tmode % 2 == 1) {
+            if (ref < v) v = ref;
+        } else {
+            if (ref > v) v = ref;
+        }
+    }
+    if (omode == 1 && obstacle[i] < v) v = obstacle[i];
+    if (omode == 2 && obstacle[i] > v) v = obstacle[i];
+    return v;
+}
+
+static int og_modes_ok(int tmode, int omode, const double *target, const double *obstacle)
+{
+    if (tmode < 0 || tmode > 6 || omode < 0 || omode > 2) return 0;
+    if (tmode >= 5 && !target) return 0;
+    if (omode && !obstacle) return 0;
+    return 1;
+}
+
 /* Full solve from tau[0] to tau[ntau-1].  V_all (nullable) receives V at
  * every tau[k] (ntau slices, slice 0 = the start value).  Returns 0 or -1. */
 int oracle_hj_solve(int ndim, const long *n, const double *lo, const double *hi,
                     const int *periodic, int dyn_id, int u_mode, int d_mode,
                     const double *params, const double *V0, const double *V_init,
-                    const double *tau, int ntau, int rk_order, double cfl, int brt,
+                    const double *tau, int ntau, int rk_order, double cfl, int tmode, int omode,
+                    const double *target, const double *obstacle,
                     int global_alpha, double max_dt, double *V_out, double *V_all,
                     long *steps_out, double *dt_first, double *dt_min, double *dt_max)
 {
@@ -366,6 +404,7 @@ int oracle_hj_solve(int ndim, const long *n, const double *lo, const double *hi,
     og_dyn dy;
     if (og_setup(&g, &dy, ndim, n, lo, hi, periodic, dyn_id, u_mode, d_mode, params)) return -1;
     if (rk_order < 1 || rk_order > 3 || ntau < 2 || !(cfl > 0.0)) return -1;
+    if (!og_modes_ok(tmode, omode, target, obstacle)) return -1;
     for (int k = 1; k < ntau; ++k)
         if (!(tau[k] > tau[k - 1])) return -1;
 
@@ -416,10 +455,10 @@ int oracle_hj_solve(int ndim, const long *n, const double *lo, const double *hi,
             }
             W = out;
         }
-        /* HJ variational inequality for a tube: V = min(V, V0) */
-        if (brt) {
-            for (long i = 0; i < P; ++i)
-                if (V0[i] < Nx[i]) Nx[i] = V0[i];
+        /* computation method (a tube: V = min(V, V0), the HJ variational
+         * inequality); Vn still holds the value before the step */
+        if (tmode || omode) {
+            for (long i = 0; i < P; ++i) Nx[i] = og_clamp(Nx[i], i, tmode, omode, V0, Vn, target, obstacle);
         }
         memcpy(Vn, Nx, sizeof(double) * (size_t)P);
 
@@ -486,20 +525,20 @@ static double og_stage_value(const og_field *self, long idx)
 int oracle_step_at(int ndim, const long *n, const double *lo, const double *hi,
                    const int *periodic, int dyn_id, int u_mode, int d_mode,
                    const double *params, const double *V, const double *V0, double dt,
-                   int rk_order, int brt, const double *alpha_glob, long m, const long *idx,
-                   double *out)
+                   int rk_order, int tmode, int omode, const double *target, const double *obstacle,
+                   const double *alpha_glob, long m, const long *idx, double *out)
 {
     og_grid g;
     og_dyn dy;
     if (og_setup(&g, &dy, ndim, n, lo, hi, periodic, dyn_id, u_mode, d_mode, params)) return -1;
     if (rk_order < 1 || rk_order > 3) return -1;
+    if (!og_modes_ok(tmode, omode, target, obstacle)) return -1;
     og_step_ctx c = {&g, &dy, V, rk_order, dt, alpha_glob};
 #pragma omp parallel for schedule(dynamic, 1)
     for (long j = 0; j < m; ++j) {
         og_field top = {og_stage_value, NULL, &c, rk_order};
-        double v = og_stage_value(&top, idx[j]);
-        if (brt && V0[idx[j]] < v) v = V0[idx[j]];
-        out[j] = v;
+        const double v = og_stage_value(&top, idx[j]);
+        out[j] = og_clamp(v, idx[j], tmode, omode, V0, V, target, obstacle);
     }
     return 0;
 }

@@ -8,6 +8,7 @@ moves a site makes this test fail loudly instead of silently passing.
 import os
 import subprocess
 
+import numpy as np
 import pytest
 
 import test_oracle_pins as pins
@@ -41,7 +42,12 @@ MUTANTS = [
     ("rk2_weight", "if (order == 2 && stage == 1) { *a = 0.5; *b = 0.5; }",
      "if (order == 2 && stage == 1) { *a = 0.0; *b = 1.0; }"),
     ("cfl_number_dropped", "double dt = cfl / s;", "double dt = 1.0 / s;"),
-    ("tube_clamp_max", "if (V0[i] < Nx[i]) Nx[i] = V0[i];", "if (V0[i] > Nx[i]) Nx[i] = V0[i];"),
+    ("tube_clamp_max", "if (ref < v) v = ref;", "if (ref > v) v = ref;"),
+    ("value_over_time_uses_v0", "(tmode <= 4) ? Vn[i] : target[i];", "(tmode <= 4) ? V0[i] : target[i];"),
+    ("target_uses_v0", "(tmode <= 4) ? Vn[i] : target[i];", "(tmode <= 4) ? Vn[i] : V0[i];"),
+    ("obstacle_max_as_min", "if (omode == 2 && obstacle[i] > v) v = obstacle[i];",
+     "if (omode == 2 && obstacle[i] < v) v = obstacle[i];"),
+    ("max_methods_as_min", "if (tmode % 2 == 1) {", "if (tmode % 2 == 0 || tmode == 1) {"),
     ("last_step_not_clipped", "dt = tau[k] - t;", "dt = dt + 0.0;"),
     ("control_bound_for_disturbance", "dd[0] = og_bang(pbar[5], dy->p[3], dy->d_mode);",
      "dd[0] = og_bang(pbar[5], dy->p[1], dy->d_mode);"),
@@ -65,6 +71,10 @@ FAST_PINS = [
     lambda o: [pins.test_pin8_rk_temporal_order(o, r) for r in (1, 2, 3)],
     lambda o: pins.test_golden_step_count_3d(o),
     lambda o: pins.test_restart_equals_single_call(o),
+    lambda o: [pins.test_pin9_computation_methods_closed_form(o, *c, f) for c in pins.CASES_PIN9
+               for f in (1.0, 0.5)],
+    lambda o: [pins.test_pin9_restart_reference(o, m, f) for m, f in
+               (("minVWithVInit", np.minimum), ("maxVWithVInit", np.maximum), ("minVWithV0", None))],
 ]
 
 

@@ -15,6 +15,12 @@ Each pin names what a plausible mistake would break:
   6  4D car with a_max = 0: every v-slice is a 3D Dubins solve with v = v_k.
   7  first-order convergence of pin 1 under grid refinement.
   8  temporal order 1/2/3 of TVD-RK1/2/3 on a linear problem.
+  9  computation methods (the paper's table): on a periodic advection at CFL
+     1 each step is an exact one-cell shift, so every method has a closed
+     form by direct recursion (V <- op(shift(V), reference)): running minima
+     / maxima over time (the V^n reference), min / max with V0 or a target
+     array, min / max with an obstacle array, and reach-avoid (target first,
+     then obstacle); plus equivalences (target = V0 gives the V0 methods).
   -  hand-derived CFL steps of the three single-solve workloads (golden file).
 """
 import json
@@ -436,3 +442,122 @@ def test_restart_equals_single_call(oracle_mod):
     assert np.array_equal(one.V_all[1], a.V)
     assert np.array_equal(one.V, b.V)
     assert one.steps == a.steps + b.steps
+
+
+# ------------------------------------------------------------------ pin 9
+
+def _advection_case():
+    """Periodic 1D advection z' = c (c > 0 moves data towards -x): at CFL
+    lambda one step is V_i + lambda (V_{i+1} - V_i) (pin 2), an exact
+    one-cell shift at lambda = 1; 9 steps to the horizon."""
+    g = W.GridSpec([30], [-4.0], [4.0], [1])
+    x = g.axis(0)
+    V0 = np.sin(2 * np.pi * x / 8) + 0.4 * np.cos(6 * np.pi * x / 8)
+    d = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [0.0, 0.6], W.MINIMISE, W.MINIMISE)
+    rng = np.random.default_rng(99)
+    target = 0.6 * np.cos(2 * np.pi * x / 8 + 1.0) + 0.1 * rng.standard_normal(x.size)
+    obstacle = np.where(np.abs(x - 1.5) < 1.0, 0.3, -5.0) + 0.05 * rng.standard_normal(x.size)
+    return g, d, V0, target, obstacle, 9
+
+
+def _recursion(V0, steps, op, lam=1.0):
+    V = V0.copy()
+    for _ in range(steps):
+        V = op(V + lam * (np.roll(V, -1) - V), V)
+    return V
+
+
+CASES_PIN9 = [
+    # tmode, omode, per-step operation op(shifted, V^n) with target l / obstacle g
+    ("minVWithV0", "none", lambda s, vn, V0, l, g: np.minimum(s, V0)),
+    ("maxVWithV0", "none", lambda s, vn, V0, l, g: np.maximum(s, V0)),
+    ("minVWithVInit", "none", lambda s, vn, V0, l, g: np.minimum(s, vn)),
+    ("maxVWithVInit", "none", lambda s, vn, V0, l, g: np.maximum(s, vn)),
+    ("minVWithVTarget", "none", lambda s, vn, V0, l, g: np.minimum(s, l)),
+    ("maxVWithVTarget", "none", lambda s, vn, V0, l, g: np.maximum(s, l)),
+    ("none", "minVWithObstacle", lambda s, vn, V0, l, g: np.minimum(s, g)),
+    ("none", "maxVWithObstacle", lambda s, vn, V0, l, g: np.maximum(s, g)),
+    ("minVWithVTarget", "maxVWithObstacle", lambda s, vn, V0, l, g: np.maximum(np.minimum(s, l), g)),
+    ("minVWithV0", "maxVWithObstacle", lambda s, vn, V0, l, g: np.maximum(np.minimum(s, V0), g)),
+]
+
+
+@pytest.mark.parametrize("tmode,omode,op", CASES_PIN9, ids=[f"{a}+{b}" for a, b, _ in CASES_PIN9])
+@pytest.mark.parametrize("cfl", [1.0, 0.5])
+def test_pin9_computation_methods_closed_form(oracle_mod, tmode, omode, op, cfl):
+    g, d, V0, l, ob, steps = _advection_case()
+    _, dt = oracle_mod.cfl_dt(g, d, cfl)
+    res = oracle_mod.solve(g, d, V0, [0.0, steps * dt * (1 - 1e-12)], rk_order=1, cfl=cfl,
+                           tmode=tmode, omode=omode, target=l, obstacle=ob)
+    assert res.steps == steps
+    expect = _recursion(V0, steps, lambda s, vn: op(s, vn, V0, l, ob), lam=cfl)
+    # the horizon sits 1e-12 short of 9 CFL steps, so the last step has
+    # lambda short by O(1e-11): hence the tolerance
+    assert np.abs(res.V - expect).max() < 1e-10
+    # every method changes the plain transport somewhere
+    plain = _recursion(V0, steps, lambda s, vn: s, lam=cfl)
+    assert np.abs(expect - plain).max() > 0.05
+
+
+@pytest.mark.parametrize("tmode,npop", [("minVWithVInit", np.minimum), ("maxVWithVInit", np.maximum),
+                                         ("minVWithV0", None)])
+def test_pin9_restart_reference(oracle_mod, tmode, npop):
+    """From a restart value V_init != V0 the value-over-time methods take
+    min/max with the previous step's value (which starts at V_init), the V0
+    method keeps using V0.  (From V_init = V0 a monotone scheme makes
+    min(S V^n, V^n) equal to min(S V^n, V0) by induction, so only a restart
+    tells the two references apart.)"""
+    g, d, V0, l, ob, steps = _advection_case()
+    x = np.arange(V0.size) / V0.size
+    Vi = V0 + 0.4 * np.cos(6 * np.pi * x) + 0.2
+    for cfl in (1.0, 0.5):
+        _, dt = oracle_mod.cfl_dt(g, d, cfl)
+        res = oracle_mod.solve(g, d, V0, [0.0, steps * dt * (1 - 1e-12)], rk_order=1, cfl=cfl,
+                               tmode=tmode, V_init=Vi)
+        if npop is None:
+            expect = _recursion(Vi, steps, lambda s_, vn: np.minimum(s_, V0), lam=cfl)
+        else:
+            expect = _recursion(Vi, steps, lambda s_, vn: npop(s_, vn), lam=cfl)
+        assert np.abs(res.V - expect).max() < 1e-10
+        other = _recursion(Vi, steps, lambda s_, vn: np.minimum(s_, Vi if npop is None else V0),
+                           lam=cfl)
+        assert np.abs(expect - other).max() > 0.05
+
+
+def test_pin9_target_equal_to_v0_is_the_v0_method(oracle_mod):
+    spec = W.config_dubins3d(n=(17, 15, 12), T=0.6)
+    V0 = W.make_v0(spec)
+    for a, b in (("minVWithVTarget", "minVWithV0"), ("maxVWithVTarget", "maxVWithV0")):
+        ra = oracle_mod.solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=2, tmode=a, target=V0).V
+        rb = oracle_mod.solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=2, tmode=b).V
+        assert np.array_equal(ra, rb)
+
+
+def test_pin9_value_over_time_monotone(oracle_mod):
+    """min / max with V^n: V(tau_k) is exactly non-increasing / non-decreasing."""
+    spec = W.config_dubins3d(n=(17, 15, 12), T=0.6)
+    V0 = W.make_v0(spec)
+    tau = [0.0, 0.15, 0.3, 0.45, 0.6]
+    lo = oracle_mod.solve(spec.grid, spec.dyn, V0, tau, rk_order=3, tmode="minVWithVInit",
+                          save_all=True).V_all
+    hi = oracle_mod.solve(spec.grid, spec.dyn, V0, tau, rk_order=3, tmode="maxVWithVInit",
+                          save_all=True).V_all
+    assert (lo[1:] <= lo[:-1]).all() and (hi[1:] >= hi[:-1]).all()
+    assert (lo[-1] < V0 - 1e-6).any() and (hi[-1] > V0 + 1e-6).any()
+
+
+def test_pin9_obstacle_bounds(oracle_mod):
+    """An obstacle below every value (max) or above every value (min) changes
+    nothing; max with a large constant gives that constant everywhere."""
+    spec = W.config_dubins3d(n=(17, 15, 12), T=0.6)
+    V0 = W.make_v0(spec)
+    ref = oracle_mod.solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=1, brt=True).V
+    lo = np.full(V0.shape, -1e30)
+    hi = np.full(V0.shape, 1e30)
+    a = oracle_mod.solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=1, brt=True,
+                         omode="maxVWithObstacle", obstacle=lo).V
+    b = oracle_mod.solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=1, brt=True,
+                         omode="minVWithObstacle", obstacle=hi).V
+    c = oracle_mod.solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=1, brt=True,
+                         omode="maxVWithObstacle", obstacle=np.full(V0.shape, 7.0)).V
+    assert np.array_equal(a, ref) and np.array_equal(b, ref) and (c == 7.0).all()
