@@ -105,14 +105,38 @@ typedef struct {
 
 /* ----------------------------------------------------------------- solve */
 
-typedef enum { ODP_BRS = 0, ODP_BRT = 1 } odp_mode;
+/* Computation method (the paper's table of computation methods, Sec. on the
+ * solver interface): after every full CFL step (the last Runge-Kutta stage)
+ * the new value V is compared, point by point, with a reference and replaced
+ * by the smaller (min) or larger (max) of the two.  NaN in V stays NaN. */
+typedef enum {
+    ODP_BRS = 0,          /* none: the plain PDE, a backward reachable set */
+    ODP_BRT = 1,          /* min with V0 (minVWithV0): the reachable tube,
+                             the HJ variational inequality */
+    ODP_MIN_V0 = 1,
+    ODP_MAX_V0 = 2,       /* max with V0 (maxVWithV0) */
+    ODP_MIN_VINIT = 3,    /* min with the value before the step (minVWithVInit:
+                             the running minimum over time) */
+    ODP_MAX_VINIT = 4,    /* max with the value before the step (maxVWithVInit) */
+    ODP_MIN_TARGET = 5,   /* min with the target array opts->target_dev
+                             (minVWithVTarget, reach-avoid) */
+    ODP_MAX_TARGET = 6    /* max with the target array (maxVWithVTarget) */
+} odp_mode;
+
+/* Obstacle method, applied after the target method of the same step. */
+typedef enum {
+    ODP_OBSTACLE_NONE = 0,
+    ODP_MIN_OBSTACLE = 1, /* min with opts->obstacle_dev (minVWithObstacle) */
+    ODP_MAX_OBSTACLE = 2  /* max with opts->obstacle_dev (maxVWithObstacle,
+                             reach-avoid: g(z) > 0 inside the obstacle) */
+} odp_obstacle_mode;
 
 typedef struct {
     int32_t precision;   /* 32 or 64: element type of every grid array */
     int32_t rk_order;    /* 1, 2 or 3 (TVD Runge-Kutta) */
     double cfl;          /* in (0, 1] */
-    int32_t mode;        /* odp_mode: BRS (plain PDE) or BRT (min with V0 after
-                            every full step: the HJ variational inequality) */
+    int32_t mode;        /* odp_mode: the computation method applied after
+                            every full step (ODP_BRS: none) */
     int32_t dissipation; /* 0: per-point alpha_d(z_i); 1: global alpha^max_d
                             (the paper's cheaper approximation) */
     double max_dt;       /* 0: none; > 0 caps the CFL step (tests use it) */
@@ -130,6 +154,13 @@ typedef struct {
                             replayed: 0 auto (small grids on a non-null
                             stream), 1 always (non-null stream), 2 never.
                             With a graph the call returns after completion. */
+    int32_t obstacle_mode; /* odp_obstacle_mode (0: none) */
+    int32_t pad_;
+    const void *target_dev;   /* device, grid-shaped, element type = precision:
+                                 l(z) of ODP_MIN_TARGET / ODP_MAX_TARGET (NULL
+                                 otherwise); read only, for the whole horizon */
+    const void *obstacle_dev; /* device, grid-shaped: g(z) of the obstacle
+                                 method (NULL when obstacle_mode is 0) */
 } odp_solve_opts;
 
 typedef struct {
@@ -159,7 +190,8 @@ size_t odp_hj_workspace_bytes(const odp_grid *grid, const odp_dynamics *dyn, con
  *              after the call) or at least odp_hj_workspace_bytes bytes,
  *              256-byte aligned, used exclusively by this call until the
  *              stream reaches its end.
- *  V_out_dev:  receives V(tau[ntau-1]); may not alias V0/V_init.
+ *  V_out_dev:  receives V(tau[ntau-1]); may not alias V0, V_init or the
+ *              target / obstacle arrays.
  *  V_all_dev:  NULL unless opts->save_all; then ntau slices, slice 0 =
  *              the start value, slice k = V(tau[k]).
  *  stats:      NULL, or filled after an internal stream synchronisation.
@@ -189,11 +221,13 @@ typedef struct {
 size_t odp_hj_batch_workspace_bytes(int nsolves, const odp_solve_desc *descs,
                                     const odp_solve_opts *common);
 
-/* Run nsolves independent solves in one persistent launch on
- * common->stream: each workgroup takes whole solves from a device queue,
- * longest first, and steps them with workgroup barriers only (no
- * cross-workgroup waits).  common->save_all must be 0.  workspace_dev may be
- * NULL (library allocates) or hold odp_hj_batch_workspace_bytes bytes.
+/* Run nsolves independent solves together on common->stream: every stage
+ * launch covers the tiles of all members that are still stepping (members
+ * are ordered by step count, longest first, and grouped by kernel shape).
+ * common->save_all must be 0; target and obstacle arrays are not available
+ * (ODP_EUNSUPPORTED: they belong to one grid), the other computation methods
+ * are.  workspace_dev may be NULL (library allocates) or hold
+ * odp_hj_batch_workspace_bytes bytes.
  * stats_per_solve: NULL or nsolves entries, filled after a synchronisation
  * (kernel_ms is the whole launch).  Results equal the same solves run one by
  * one through odp_hj_solve with the same options, bit for bit. */

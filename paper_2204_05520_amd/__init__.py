@@ -34,6 +34,14 @@ ODP_ECANCELED = -7
 
 ODP_BRS = 0
 ODP_BRT = 1
+ODP_MIN_V0, ODP_MAX_V0, ODP_MIN_VINIT, ODP_MAX_VINIT, ODP_MIN_TARGET, ODP_MAX_TARGET = 1, 2, 3, 4, 5, 6
+ODP_MIN_OBSTACLE, ODP_MAX_OBSTACLE = 1, 2
+# the computation methods of the paper's table, by name
+METHODS = {"None": ODP_BRS, "minVWithV0": ODP_MIN_V0, "maxVWithV0": ODP_MAX_V0,
+           "minVWithVInit": ODP_MIN_VINIT, "maxVWithVInit": ODP_MAX_VINIT,
+           "minVWithVTarget": ODP_MIN_TARGET, "maxVWithVTarget": ODP_MAX_TARGET}
+OBSTACLE_METHODS = {"None": 0, "minVWithObstacle": ODP_MIN_OBSTACLE,
+                    "maxVWithObstacle": ODP_MAX_OBSTACLE}
 
 SYMBOLS = [
     "odp_strerror", "odp_last_error", "odp_grid_create", "odp_grid_destroy", "odp_grid_points",
@@ -58,7 +66,9 @@ class odp_solve_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("rk_order", ctypes.c_int32), ("cfl", ctypes.c_double),
                 ("mode", ctypes.c_int32), ("dissipation", ctypes.c_int32), ("max_dt", ctypes.c_double),
                 ("save_all", ctypes.c_int32), ("tile_chunk", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("xcd_group", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("stream", ctypes.c_void_p), ("xcd_group", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("obstacle_mode", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("target_dev", ctypes.c_void_p), ("obstacle_dev", ctypes.c_void_p)]
 
 
 class odp_solve_stats(ctypes.Structure):
@@ -201,13 +211,30 @@ def make_dynamics(dyn) -> odp_dynamics:
     return d
 
 
+def method_code(mode) -> int:
+    """odp_mode from a computation-method name of the paper's table
+    ("minVWithV0", ...), "None", or an int."""
+    return METHODS[mode] if isinstance(mode, str) else int(mode)
+
+
+def obstacle_code(mode) -> int:
+    return OBSTACLE_METHODS[mode] if isinstance(mode, str) else int(mode)
+
+
 def make_opts(precision=32, rk_order=1, cfl=0.8, mode=ODP_BRT, dissipation=0, max_dt=0.0,
-              save_all=0, tile_chunk=0, stream=None, xcd_group=0, graph=0) -> odp_solve_opts:
+              save_all=0, tile_chunk=0, stream=None, xcd_group=0, graph=0, obstacle_mode=0,
+              target=None, obstacle=None) -> odp_solve_opts:
+    """target / obstacle: device tensors (or raw device addresses) of the grid's
+    shape for the target and obstacle methods."""
     o = odp_solve_opts()
     o.precision = precision
     o.rk_order = rk_order
     o.cfl = cfl
-    o.mode = mode
+    o.mode = method_code(mode)
+    o.obstacle_mode = obstacle_code(obstacle_mode)
+    addr = lambda x: None if x is None else (x if isinstance(x, int) else int(x.data_ptr()))
+    o.target_dev = addr(target)
+    o.obstacle_dev = addr(obstacle)
     o.dissipation = dissipation
     o.max_dt = max_dt
     o.save_all = save_all
@@ -273,19 +300,23 @@ def check_device_tensor(x, precision, npts, name):
 
 def solve(spec, V0, precision=32, V_init=None, tau=None, stream=None, save_all=False,
           dissipation=0, max_dt=0.0, tile_chunk=0, workspace=None, rk_order=None, cfl=None,
-          mode=None, xcd_group=0, graph=0) -> SolveResult:
-    """One solve of a workloads.SolveSpec with a device V0 tensor."""
+          mode=None, xcd_group=0, graph=0, obstacle_mode=0, target=None,
+          obstacle=None) -> SolveResult:
+    """One solve of a workloads.SolveSpec with a device V0 tensor.  mode and
+    obstacle_mode take the paper's method names or the odp codes; target /
+    obstacle are device tensors on the grid for the methods that use them."""
     import torch
     grid = Grid.from_spec(spec.grid)
     npts = grid.npts
     check_device_tensor(V0, precision, npts, "V0")
-    if V_init is not None:
-        check_device_tensor(V_init, precision, npts, "V_init")
+    for x, name in ((V_init, "V_init"), (target, "target"), (obstacle, "obstacle")):
+        if x is not None:
+            check_device_tensor(x, precision, npts, name)
     tau = list(spec.tau if tau is None else tau)
     opts = make_opts(precision, spec.rk_order if rk_order is None else rk_order,
                      spec.cfl if cfl is None else cfl, spec.mode if mode is None else mode,
                      dissipation, max_dt, 1 if save_all else 0, tile_chunk, _stream_handle(stream),
-                     xcd_group, graph)
+                     xcd_group, graph, obstacle_mode, target, obstacle)
     out = torch.empty_like(V0)
     vall = torch.empty((len(tau),) + tuple(V0.shape), dtype=V0.dtype, device=V0.device) if save_all else None
     st = odp_hj_solve(grid, spec.dyn, V0, V_init, tau, opts, workspace, out, vall)

@@ -279,12 +279,15 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const SolveDesc *__restri
     const T *W, *Vn;
     T *out;
     stage_buffers<T>(s, stage, k, W, Vn, out);
-    const T *V0 = (const T *)s.V0;
+    const T *Z = s.tvn ? Vn : (const T *)s.tref;
+    const T *G = (const T *)s.oref;
     double wa, wb;
     rk_weights(s.rk_order, stage, wa, wb);
     const T ra = T(wa), rb = T(wb);
     const bool last = stage == s.rk_order - 1;
-    const bool clamp = last && s.brt;
+    const bool clamp = last && s.tclamp;
+    const bool obst = last && s.obst;
+    const bool tmax = s.tmax, omax = s.omax;
     const T dt = T(s.dt_sched[k]);
 
     const int64_t s0 = s.s0;
@@ -321,8 +324,12 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const SolveDesc *__restri
         T v = fma_t(dt, Lh, wc);
         if (wa != 0.0) v = fma_t(ra, Vn[o], rb * v);
         if (clamp) {
-            const T z = V0[o];
-            if (z < v) v = z;
+            const T z = Z[o];
+            if (tmax ? z > v : z < v) v = z;
+        }
+        if (obst) {
+            const T g = G[o];
+            if (omax ? g > v : g < v) v = g;
         }
         bad |= !isfinite(v);
         if (active) out[o] = v;
@@ -340,7 +347,9 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const SolveDesc *__restri
 // loads.  The next plane's centre values and pointwise operands are loaded
 // one iteration ahead, after the current plane's neighbour loads, so that
 // waiting for the neighbours does not wait for them.  KIND bit 0: the stage
-// reads V^n; bit 1: the stage ends with the tube clamp.
+// reads V^n; bit 1: the stage ends with the computation method's comparison
+// (with V0, V^n, a target or an obstacle array: SolveDesc); bit 3: a second
+// comparison, with the obstacle array, follows.
 #define ODP_GLOBAL __attribute__((address_space(1)))
 
 template <typename T, int VEC>
@@ -421,7 +430,7 @@ __device__ __forceinline__ void stp_nt(ODP_GLOBAL T *p, const Pack<T, VEC> &r) {
 // The 4D float32 last stage (V^n, clamp and LDS exchange) is held to 128
 // VGPRs (occupancy 4; two values spill): measured faster than occupancy 3.
 template <typename T, int DYN, int N, int VEC, int KIND>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((KIND & 7) == 7 && N == 4 && sizeof(T) == 4 ? 4 : 1))) void stage_vec_kernel(const SolveDesc *__restrict__ descs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 7 && N == 4 && sizeof(T) == 4 ? 4 : 1))) void stage_vec_kernel(const SolveDesc *__restrict__ descs,
                                                            const uint32_t *__restrict__ tile_solve,
                                                            const uint32_t *__restrict__ tile_local,
                                                            int stage, int step_from_desc,
@@ -430,6 +439,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((KIND & 
     constexpr bool kVn = KIND & 1;
     constexpr bool kClamp = KIND & 2;
     constexpr bool kLdsK = (KIND & 4) && N >= 3;
+    constexpr bool kObst = (KIND & 8) && kClamp;
     const uint32_t L = xcd_logical(blockIdx.x, gridDim.x, uint32_t(xgroup));
     const uint32_t si = tile_solve ? tile_solve[L] : 0u;
     const uint32_t lt = tile_solve ? tile_local[L] : L;
@@ -499,7 +509,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((KIND & 
     stage_buffers<T>(s, stage, k, Wg, Vng, outg);
     const ODP_GLOBAL T *W = (const ODP_GLOBAL T *)Wg;
     const ODP_GLOBAL T *Vn = (const ODP_GLOBAL T *)Vng;
-    const ODP_GLOBAL T *V0 = (const ODP_GLOBAL T *)s.V0;
+    // reference of the comparison: an array, or (tvn) V^n, which is already
+    // in registers (the stencil centre for RK1, vq after the first stage)
+    const ODP_GLOBAL T *Zr = (const ODP_GLOBAL T *)s.tref;
+    const ODP_GLOBAL T *Gr = (const ODP_GLOBAL T *)s.oref;
+    const bool tmax = s.tmax, omax = s.omax, tvn = s.tvn;
     ODP_GLOBAL T *out = (ODP_GLOBAL T *)outg;
     double wa, wb;
     rk_weights(s.rk_order, stage, wa, wb);
@@ -588,7 +602,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((KIND & 
     // halo (reloaded once the previous plane's value has been used).
     P w[4];          // stencil-input ring (planes i-1, i, i+1, i+2)
     Nb nb[2];        // in-plane neighbours: plane i, plane i+1 (loading)
-    P vq, zq;        // V^n and V0 of plane i
+    P vq, zq;        // V^n and the comparison's reference of plane i
+    P gq;            // obstacle of plane i (KIND bit 3)
     P hq;            // halo rows of plane i
     auto load_nb = [&](int i, Nb &o) {
         const ODP_GLOBAL T *plane = W + int64_t(i) * s0;
@@ -602,10 +617,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((KIND & 
             o.xr = plane[qxr];
         }
     };
-    auto load_pw = [&](int i, P &ov, P &oz) {
+    auto load_pw = [&](int i, P &ov, P &oz, P &og) {
         const int64_t o = int64_t(i) * s0 + q;
         if constexpr (kVn) ov = ldp_nt<T, VEC>(Vn + o);
-        if constexpr (kClamp) oz = ldp_nt<T, VEC>(V0 + o);
+        if constexpr (kClamp) oz = ldp_nt<T, VEC>(Zr + o);
+        if constexpr (kObst) og = ldp_nt<T, VEC>(Gr + o);
     };
     w[0] = ldp<T, VEC>(W + plane_of(i0b - 1) + q);
     w[1] = ldp<T, VEC>(W + plane_of(i0b) + q);
@@ -614,7 +630,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((KIND & 
     // step (three axes of pipelined neighbours would cost an occupancy level)
     constexpr bool kPipeNb = N <= 4;
     if constexpr (kPipeNb) load_nb(i0b, nb[0]);
-    load_pw(i0b, vq, zq);
+    load_pw(i0b, vq, zq, gq);
     if (hl) hq = ldp<T, VEC>(W + int64_t(i0b) * s0 + hsrc);
     P dm;  // W(i) - W(i-1)
 #pragma unroll
@@ -701,14 +717,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((KIND & 
             T v = fma_t(dt, Lh, wc.v[j]);
             if constexpr (kVn) v = fma_t(ra, vq.v[j], rb * v);
             if constexpr (kClamp) {
-                if (zq.v[j] < v) v = zq.v[j];
+                const T z = tvn ? (kVn ? vq.v[j] : wc.v[j]) : zq.v[j];
+                if (tmax ? z > v : z < v) v = z;
+            }
+            if constexpr (kObst) {
+                if (omax ? gq.v[j] > v : gq.v[j] < v) v = gq.v[j];
             }
             // v * 0 is NaN exactly when v is not finite (padding excluded)
             nan_here = fma_t(j > jend ? T(0) : v, T(0), nan_here);
             res.v[j] = v;
         }
         // V^n and V0 of the next plane: a step of compute hides their latency
-        load_pw(in, vq, zq);
+        load_pw(in, vq, zq, gq);
         if (i < i0e) {
             nanacc += nan_here;
             if (active) stp_nt<T, VEC>(out + int64_t(i) * s0 + q, res);
@@ -908,23 +928,36 @@ static hipError_t launch_stage_t(int kind, const SolveDesc *d, const uint32_t *t
         hipLaunchKernelGGL((stage_kernel<T, DYN, N>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl,
                            stage, from_desc, step, xg);
     } else {
+#define ODP_STAGE_CASE(K)                                                                          \
+    case K:                                                                                        \
+        hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, K>), dim3(nblocks), dim3(kBlock), 0, st, \
+                           d, ts, tl, stage, from_desc, step, xg);                                 \
+        break;
+        // bit 3 (a second comparison) only comes with bit 1; bit 2 (LDS)
+        // only from three dimensions on
         switch (kind) {
-        case 0: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 0>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
-        case 1: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 1>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
-        case 2: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 2>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
-        case 3: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 3>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
+            ODP_STAGE_CASE(0)
+            ODP_STAGE_CASE(1)
+            ODP_STAGE_CASE(2)
+            ODP_STAGE_CASE(3)
+            ODP_STAGE_CASE(10)
+            ODP_STAGE_CASE(11)
         default:
             if constexpr (N >= 3) {
                 switch (kind) {
-                case 4: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 4>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
-                case 5: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 5>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
-                case 6: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 6>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
-                default: hipLaunchKernelGGL((stage_vec_kernel<T, DYN, N, VEC, 7>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl, stage, from_desc, step, xg); break;
+                    ODP_STAGE_CASE(4)
+                    ODP_STAGE_CASE(5)
+                    ODP_STAGE_CASE(6)
+                    ODP_STAGE_CASE(7)
+                    ODP_STAGE_CASE(14)
+                    ODP_STAGE_CASE(15)
+                default: return hipErrorInvalidValue;
                 }
             } else {
                 return hipErrorInvalidValue;
             }
         }
+#undef ODP_STAGE_CASE
     }
     return hipGetLastError();
 }
@@ -966,8 +999,9 @@ static hipError_t launch_stage_p(int dyn, int ndim, int vec, int kind, const Sol
 }
 
 // kind: bit 0 the stage reads V^n (Runge-Kutta stages after the first),
-// bit 1 the stage ends with the tube clamp (last stage of a BRT step); it
-// must match what every listed solve does at this stage.
+// bit 1 the stage ends with the computation method's comparison, bit 3 a
+// second one with the obstacle array (last stage of a step), bit 2 the LDS
+// plane exchange; it must match what every listed solve does at this stage.
 hipError_t launch_stage(int precision, int dyn, int ndim, int vec, int kind, const SolveDesc *d,
                         const uint32_t *ts, const uint32_t *tl, uint32_t nblocks, int stage,
                         int from_desc, int64_t step, int xgroup, hipStream_t st) {

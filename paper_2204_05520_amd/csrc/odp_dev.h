@@ -80,8 +80,19 @@ struct SolveDesc {
     int64_t *nsteps;         // device: step count of the schedule
     int64_t *step;           // device: next step to take (server ticks)
     int32_t *flags;          // bit 0: non-finite value produced
-    int32_t brt;
+    // ---- computation method: after every full step (the last stage) V is
+    // compared with a reference point by point and replaced by the smaller
+    // (or larger) of the two; then, optionally, again with an obstacle array
+    int32_t tclamp;          // 1: the last stage compares (kind bit 1)
+    int32_t tmax;            // 1: keep the larger value, 0: the smaller
+    int32_t tvn;             // 1: the reference is V^n, the value before the step
+                             // (then tref is any grid-sized array)
+    int32_t obst;            // 1: a second comparison with oref follows (kind bit 3)
+    int32_t omax;            // 1: keep the larger value, 0: the smaller
     int32_t ntau;
+    const void *tref;        // reference array when tvn == 0 (V0, a target array,
+                             // or the obstacle array of an obstacle-only method)
+    const void *oref;        // obstacle array when obst == 1
     const double *tau;       // output times (device copy)
     double cfl;
     double max_dt;

@@ -197,7 +197,26 @@ void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &
         s.tabd = (const double *)(base + tab_off);
         s.dt_sched = (double *)(base + it.sched_off);
         s.land = (int32_t *)(base + it.land_off);
-        s.brt = o.mode == ODP_BRT;
+        // computation method (an obstacle method alone takes the first
+        // comparison, with the obstacle array as its reference)
+        const int m = o.mode, om = o.obstacle_mode;
+        if (m != ODP_BRS) {
+            s.tclamp = 1;
+            s.tmax = m % 2 == 0;
+            s.tvn = m == ODP_MIN_VINIT || m == ODP_MAX_VINIT;
+            // (the value-over-time methods take V^n from registers; their
+            // tref is only a valid address for the kernel's unused load)
+            s.tref = m <= ODP_MAX_V0 ? s.V0 : (m >= ODP_MIN_TARGET ? o.target_dev : s.A);
+            if (om != ODP_OBSTACLE_NONE) {
+                s.obst = 1;
+                s.omax = om == ODP_MAX_OBSTACLE;
+                s.oref = o.obstacle_dev;
+            }
+        } else if (om != ODP_OBSTACLE_NONE) {
+            s.tclamp = 1;
+            s.tmax = om == ODP_MAX_OBSTACLE;
+            s.tref = o.obstacle_dev;
+        }
         s.ntau = int32_t(it.tau.size());
         s.tau = (const double *)(base + tau_off);
         s.cfl = o.cfl;
@@ -289,7 +308,7 @@ int plan_prologue(Plan &p, unsigned char *base, hipStream_t st) {
 int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t k) {
     int rc;
     const int prec = p.opts.precision;
-    const int brt = p.opts.mode == ODP_BRT;
+    const int mk = method_kind(p.opts);
     const SolveDesc *descs = (const SolveDesc *)(base + p.desc_off);
     const bool single = p.items.size() == 1;
     const uint32_t *tsd = single ? nullptr : (const uint32_t *)(base + p.tt_off);
@@ -303,7 +322,7 @@ int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t
         const uint32_t *ts = tsd ? tsd + gr.tile_base : nullptr;
         const uint32_t *tl = tld ? tld + gr.tile_base : nullptr;
         for (int j = 0; j < gr.rk; ++j) {
-            if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, stage_kind(gr.rk, j, brt, gr.lds), descs,
+            if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, stage_kind(gr.rk, j, mk, gr.lds), descs,
                                              ts, tl, nb, j, 0, k, p.xcd_group, st),
                                 "stage")))
                 return rc;
@@ -370,7 +389,7 @@ int plan_stats(const Plan &p, unsigned char *base, double kernel_ms, odp_solve_s
         sx.dt_max = *std::max_element(dts, dts + it.nsteps);
         sx.t_final = it.tau.back();
         sx.kernel_ms = kernel_ms;
-        sx.alg_bytes = alg_bytes_per_step(o.precision, it.rk_order, o.mode == ODP_BRT, it.g->npts) * double(it.nsteps);
+        sx.alg_bytes = alg_bytes_per_step(o.precision, it.rk_order, method_arrays(o), it.g->npts) * double(it.nsteps);
         sx.alg_gbps = kernel_ms > 0 ? sx.alg_bytes / (kernel_ms * 1e6) : 0.0;
         sx.roofline_frac = sx.alg_gbps / 8000.0;
         std::memcpy(sx.alpha_max, state, sizeof(sx.alpha_max));

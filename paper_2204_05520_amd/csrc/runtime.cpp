@@ -72,7 +72,16 @@ int validate_opts(const odp_solve_opts *o) {
     if (o->precision != 32 && o->precision != 64) return set_error(ODP_EINVAL, "precision must be 32 or 64");
     if (o->rk_order < 1 || o->rk_order > 3) return set_error(ODP_EINVAL, "rk_order must be 1, 2 or 3");
     if (!(o->cfl > 0.0 && o->cfl <= 1.0)) return set_error(ODP_EINVAL, "cfl must be in (0, 1]");
-    if (o->mode != ODP_BRS && o->mode != ODP_BRT) return set_error(ODP_EINVAL, "mode must be BRS or BRT");
+    if (o->mode < ODP_BRS || o->mode > ODP_MAX_TARGET) return set_error(ODP_EINVAL, "mode must be 0..6");
+    if (o->obstacle_mode < ODP_OBSTACLE_NONE || o->obstacle_mode > ODP_MAX_OBSTACLE)
+        return set_error(ODP_EINVAL, "obstacle_mode must be 0, 1 or 2");
+    const bool wants_target = o->mode == ODP_MIN_TARGET || o->mode == ODP_MAX_TARGET;
+    if (wants_target != (o->target_dev != nullptr))
+        return set_error(ODP_EINVAL, wants_target ? "the target method needs target_dev"
+                                                  : "target_dev is set but the method does not use it");
+    if ((o->obstacle_mode != 0) != (o->obstacle_dev != nullptr))
+        return set_error(ODP_EINVAL, o->obstacle_mode ? "the obstacle method needs obstacle_dev"
+                                                      : "obstacle_dev is set but obstacle_mode is 0");
     if (o->dissipation != 0 && o->dissipation != 1) return set_error(ODP_EINVAL, "dissipation must be 0 or 1");
     if (!(o->max_dt >= 0.0) || !std::isfinite(o->max_dt)) return set_error(ODP_EINVAL, "max_dt must be >= 0");
     if (o->save_all != 0 && o->save_all != 1) return set_error(ODP_EINVAL, "save_all must be 0 or 1");
@@ -153,12 +162,23 @@ uint32_t solve_tiles(int64_t n0, int64_t qpad, int chunk, int vec) {
     return uint32_t(nqb * ((n0 + chunk - 1) / chunk));
 }
 
-double alg_bytes_per_step(int precision, int rk_order, int brt, int64_t npts) {
+double alg_bytes_per_step(int precision, int rk_order, int narr, int64_t npts) {
     // each stage reads its stencil input once and writes its output once;
-    // stages after the first also read V^n; the tube clamp reads V0
+    // stages after the first also read V^n; the computation method reads
+    // narr more arrays (V0 for the tube)
     const double b = precision == 32 ? 4.0 : 8.0;
-    double per = 2.0 * rk_order + (rk_order - 1) + (brt ? 1 : 0);
+    double per = 2.0 * rk_order + (rk_order - 1) + narr;
     return per * b * double(npts);
+}
+
+int method_arrays(const odp_solve_opts &o) {
+    const int m = o.mode;
+    return ((m == 1 || m == 2 || m == 5 || m == 6) ? 1 : 0) + (o.obstacle_mode != 0 ? 1 : 0);
+}
+
+int method_kind(const odp_solve_opts &o) {
+    const bool t = o.mode != ODP_BRS, g = o.obstacle_mode != ODP_OBSTACLE_NONE;
+    return (t || g ? 2 : 0) | (t && g ? 8 : 0);
 }
 
 }  // namespace odp

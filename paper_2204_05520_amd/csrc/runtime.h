@@ -53,11 +53,22 @@ int default_xcd_group(const odp_grid *g);
 // dynamics).
 int choose_vec(const odp_grid *g, int precision, int dyn, int64_t pitch);
 uint32_t solve_tiles(int64_t n0, int64_t qpad, int chunk, int vec);
-double alg_bytes_per_step(int precision, int rk_order, int brt, int64_t npts);
-// Stage kind for launch_stage: bit 0 reads V^n, bit 1 tube clamp, bit 2 the
-// LDS plane exchange (every listed solve must have SolveDesc::lds set).
-inline int stage_kind(int rk_order, int stage, int brt, int lds = 0) {
-    return (stage > 0 ? 1 : 0) | ((stage == rk_order - 1 && brt) ? 2 : 0) | (lds ? 4 : 0);
+// narr: grid-sized arrays the computation method reads per step besides the
+// stencil input and V^n (method_arrays).
+double alg_bytes_per_step(int precision, int rk_order, int narr, int64_t npts);
+// Arrays the computation methods of o read per step: V0 or a target array
+// for ODP_MIN/MAX_V0 and ODP_MIN/MAX_TARGET, plus the obstacle array.  The
+// value-over-time methods compare with V^n, which the step reads anyway.
+int method_arrays(const odp_solve_opts &o);
+// Kind bits of the last stage of a step for these options: bit 1 one
+// comparison (a target method, or an obstacle method alone), bit 3 a
+// second one (target and obstacle methods together).
+int method_kind(const odp_solve_opts &o);
+// Stage kind for launch_stage: bit 0 reads V^n, bits 1 and 3 the comparisons
+// of the computation method (method_kind, last stage only), bit 2 the LDS
+// plane exchange (every listed solve must have SolveDesc::lds set).
+inline int stage_kind(int rk_order, int stage, int mkind, int lds = 0) {
+    return (stage > 0 ? 1 : 0) | (stage == rk_order - 1 ? mkind : 0) | (lds ? 4 : 0);
 }
 // Whether a solve of this shape uses the LDS plane exchange.
 inline int uses_lds(int ndim, int64_t pitch, int vec) { return ndim >= 3 && pitch <= 128 * int64_t(vec) ? 1 : 0; }

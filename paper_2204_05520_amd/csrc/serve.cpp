@@ -363,7 +363,7 @@ void poll_retirements(odp_server *s) {
         sx.dt_min = *std::min_element(dts, dts + r->nsteps);
         sx.dt_max = *std::max_element(dts, dts + r->nsteps);
         sx.t_final = r->tau.back();
-        sx.alg_bytes = alg_bytes_per_step(s->opts.precision, r->rk_order, s->opts.mode == ODP_BRT, r->grid.npts) *
+        sx.alg_bytes = alg_bytes_per_step(s->opts.precision, r->rk_order, method_arrays(s->opts), r->grid.npts) *
                        double(r->nsteps);
         std::memcpy(sx.alpha_max, b, sizeof(sx.alpha_max));
         int32_t flags;
@@ -437,12 +437,12 @@ int build_groups(odp_server *s, const std::vector<std::shared_ptr<Req>> &sel, st
 
 int enqueue_tick(odp_server *s, const std::vector<Group> &groups, hipEvent_t *done) {
     const odp_solve_opts &o = s->opts;
-    const int brt = o.mode == ODP_BRT;
+    const int mk = method_kind(o);
     int rc;
     for (int m = 0; m < kStepsPerTick; ++m) {
         for (const Group &g : groups) {
             for (int j = 0; j < g.rk; ++j) {
-                if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, stage_kind(g.rk, j, brt, g.lds),
+                if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, stage_kind(g.rk, j, mk, g.lds),
                                                  s->d_slots, s->d_tiles + g.tile_base,
                                                  s->d_tiles + s->tile_cap + g.tile_base, g.tiles, j, 1, 0,
                                                  o.xcd_group, s->st),
@@ -640,6 +640,8 @@ int odp_server_create(size_t hbm_budget_bytes, int max_slots, const odp_solve_op
     int rc;
     if ((rc = validate_opts(opts))) return rc;
     if (opts->save_all) return set_error(ODP_EUNSUPPORTED, "save_all is not available when serving");
+    if (opts->target_dev || opts->obstacle_dev)
+        return set_error(ODP_EUNSUPPORTED, "target and obstacle arrays belong to one grid: use odp_hj_solve");
     if (max_slots < 1 || max_slots > 4096) return set_error(ODP_EINVAL, "max_slots must be in [1, 4096]");
     if (hbm_budget_bytes == 0) return set_error(ODP_EINVAL, "the HBM budget must be positive");
     std::unique_ptr<odp_server> s(new odp_server());

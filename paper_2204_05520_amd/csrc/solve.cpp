@@ -91,6 +91,8 @@ int odp_hj_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_d
     if (!V0_dev || !V_out_dev) return set_error(ODP_EINVAL, "V0 and V_out are required");
     if (V_out_dev == V0_dev || V_out_dev == V_init_dev)
         return set_error(ODP_EINVAL, "V_out may not alias V0 or V_init");
+    if (V_out_dev == opts->target_dev || V_out_dev == opts->obstacle_dev)
+        return set_error(ODP_EINVAL, "V_out may not alias the target or obstacle array");
     if (opts->save_all && !V_all_dev) return set_error(ODP_EINVAL, "save_all needs V_all");
     hipStream_t st = (hipStream_t)opts->stream;
 
@@ -151,6 +153,8 @@ static int batch_items(int nsolves, const odp_solve_desc *descs, const odp_solve
     if (nsolves < 1 || !descs) return set_error(ODP_EINVAL, "empty batch");
     if ((rc = validate_opts(common))) return rc;
     if (common->save_all) return set_error(ODP_EUNSUPPORTED, "save_all is not available for batches");
+    if (common->target_dev || common->obstacle_dev)
+        return set_error(ODP_EUNSUPPORTED, "target and obstacle arrays belong to one grid: use odp_hj_solve");
     items.clear();
     for (int i = 0; i < nsolves; ++i) {
         const odp_solve_desc &d = descs[i];

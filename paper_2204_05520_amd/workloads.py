@@ -142,6 +142,22 @@ def make_v0(spec: SolveSpec) -> np.ndarray:
     return cylinder_v0(spec.grid, spec.radius, keep=(0, 1))
 
 
+def reach_avoid_sets(spec: SolveSpec):
+    """Target l(z) and obstacle g(z) for the target and obstacle computation
+    methods, as in the paper's reach-avoid example (a goal and an obstacle,
+    both cylinders over the position axes): l is the signed distance to a
+    disc (negative inside), g = minus the signed distance to another disc
+    (positive inside the obstacle).  Centres sit at fixed fractions of the
+    domain; float64 on the host."""
+    g = spec.grid
+    keep = (0, 1) if g.ndim >= 2 else (0,)
+    at = lambda f: [g.lo[d] + f[min(d, len(f) - 1)] * (g.hi[d] - g.lo[d]) for d in range(g.ndim)]
+    ext = min(g.hi[d] - g.lo[d] for d in keep)
+    target = cylinder_v0(g, 0.12 * ext, keep=keep, center=at([0.7, 0.62]))
+    obstacle = -cylinder_v0(g, 0.15 * ext, keep=keep, center=at([0.35, 0.45]))
+    return target, obstacle
+
+
 def make_v0_torch(spec: SolveSpec, device, dtype):
     """Same V0 as make_v0, built on `device` slab by slab (for grids too large
     for a host float64 copy, e.g. 36^6).  Evaluated in float64, then rounded."""

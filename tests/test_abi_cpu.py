@@ -69,9 +69,11 @@ def _solve_rc(spec, precision=32, **kw):
     d = odp.make_dynamics(spec.dyn)
     tau = kw.pop("tau", spec.tau)
     t = (ctypes.c_double * len(tau))(*tau)
-    opts = odp.make_opts(precision, kw.pop("rk", spec.rk_order), kw.pop("cfl", spec.cfl), spec.mode,
-                         kw.pop("diss", 0), kw.pop("max_dt", 0.0), kw.pop("save_all", 0),
-                         kw.pop("tile_chunk", 0), None)
+    opts = odp.make_opts(precision, kw.pop("rk", spec.rk_order), kw.pop("cfl", spec.cfl),
+                         kw.pop("mode", spec.mode), kw.pop("diss", 0), kw.pop("max_dt", 0.0),
+                         kw.pop("save_all", 0), kw.pop("tile_chunk", 0), None,
+                         obstacle_mode=kw.pop("obstacle_mode", 0), target=kw.pop("target", None),
+                         obstacle=kw.pop("obstacle", None))
     V0 = kw.pop("V0", ctypes.c_void_p(0x1000))
     Vout = kw.pop("Vout", ctypes.c_void_p(0x2000))
     rc = odp.lib().odp_hj_solve(grid.handle, ctypes.byref(d), V0, None, t, len(tau),
@@ -92,6 +94,16 @@ def _solve_rc(spec, precision=32, **kw):
     ({"save_all": 1}, "V_all"),
     ({"V0": None}, "V0"),
     ({"Vout": ctypes.c_void_p(0x1000)}, "alias"),
+    ({"mode": 7}, "mode"),
+    ({"mode": -1}, "mode"),
+    ({"obstacle_mode": 3, "obstacle": 0x3000}, "obstacle_mode"),
+    ({"mode": "minVWithVTarget"}, "needs target_dev"),
+    ({"mode": "maxVWithVTarget"}, "needs target_dev"),
+    ({"mode": "minVWithV0", "target": 0x3000}, "target_dev is set"),
+    ({"obstacle_mode": "maxVWithObstacle"}, "needs obstacle_dev"),
+    ({"obstacle": 0x3000}, "obstacle_dev is set"),
+    ({"mode": "minVWithVTarget", "target": 0x2000}, "alias"),
+    ({"obstacle_mode": 2, "obstacle": 0x2000}, "alias"),
 ])
 def test_solve_rejects_before_gpu(lib, kw, msg):
     spec = W.config_dubins3d(n=(10, 10, 8))
@@ -191,3 +203,56 @@ def test_product_path_has_no_oracle_import():
     for f in os.listdir(os.path.join(ROOT, "paper_2204_05520_amd", "csrc")):
         src = open(os.path.join(ROOT, "paper_2204_05520_amd", "csrc", f)).read()
         assert "oracle" not in src.lower(), f
+
+
+def test_struct_layout_matches_header(lib, tmp_path):
+    """The ctypes mirrors have the C structs' sizes and field offsets (checked
+    by compiling the header with gcc)."""
+    structs = {"odp_solve_opts": odp.odp_solve_opts, "odp_solve_stats": odp.odp_solve_stats,
+               "odp_dynamics": odp.odp_dynamics, "odp_solve_desc": odp.odp_solve_desc}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "odp.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            lines.append(f'printf("{name}.{f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f in cls._fields_:
+            assert int(got[f"{name}.{f[0]}"]) == getattr(cls, f[0]).offset, (name, f[0])
+
+
+def test_method_names(lib):
+    assert odp.method_code("None") == odp.ODP_BRS
+    assert odp.method_code("minVWithV0") == odp.ODP_BRT
+    assert [odp.method_code(m) for m in ("maxVWithV0", "minVWithVInit", "maxVWithVInit",
+                                         "minVWithVTarget", "maxVWithVTarget")] == [2, 3, 4, 5, 6]
+    assert odp.obstacle_code("maxVWithObstacle") == 2 and odp.obstacle_code("minVWithObstacle") == 1
+
+
+def test_batch_and_server_reject_method_arrays(lib):
+    spec = W.config_dubins3d(n=(10, 10, 8))
+    grid = odp.Grid.from_spec(spec.grid)
+    t = (ctypes.c_double * len(spec.tau))(*spec.tau)
+    desc = odp.odp_solve_desc()
+    desc.grid = grid.handle
+    desc.dyn = odp.make_dynamics(spec.dyn)
+    desc.V0_dev = 0x1000
+    desc.tau = ctypes.cast(t, ctypes.POINTER(ctypes.c_double))
+    desc.ntau = len(spec.tau)
+    desc.V_out_dev = 0x2000
+    for kw in ({"mode": 5, "target": 0x3000}, {"obstacle_mode": 2, "obstacle": 0x3000}):
+        opts = odp.make_opts(32, 1, 0.8, kw.get("mode", 1), obstacle_mode=kw.get("obstacle_mode", 0),
+                             target=kw.get("target"), obstacle=kw.get("obstacle"))
+        rc = odp.lib().odp_hj_batch(1, ctypes.byref(desc), ctypes.byref(opts), None, 0, None)
+        assert rc == odp.ODP_EUNSUPPORTED and "one grid" in odp.odp_last_error()
+        assert odp.lib().odp_hj_batch_workspace_bytes(1, ctypes.byref(desc), ctypes.byref(opts)) == 0
+        srv = ctypes.c_void_p()
+        rc = odp.lib().odp_server_create(1 << 30, 4, ctypes.byref(opts), ctypes.byref(srv))
+        assert rc == odp.ODP_EUNSUPPORTED and not srv.value
