@@ -50,7 +50,7 @@ def _load():
         lib.oracle_hj_solve.argtypes = [
             ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
             _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-            _dp, _dp, ctypes.c_int, ctypes.c_double, _dp, _dp, _lp, _dp, _dp, _dp]
+            _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _lp, _dp, _dp, _dp]
         lib.oracle_cfl_dt.restype = ctypes.c_int
         lib.oracle_cfl_dt.argtypes = [
             ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
@@ -127,22 +127,26 @@ TMODES = {"none": 0, "minVWithV0": 1, "maxVWithV0": 2, "minVWithVInit": 3, "maxV
 OMODES = {"none": 0, "minVWithObstacle": 1, "maxVWithObstacle": 2}
 
 
-def _modes(brt, tmode, omode, target, obstacle, P):
+def _modes(brt, tmode, omode, target, obstacle, P, ntau=1):
+    """Returns (tmode, omode, target, obstacle, slices): arrays of P points,
+    or of ntau slices of P points (time-varying sets, slice k at tau[k])."""
     tm = (1 if brt else 0) if tmode is None else (TMODES[tmode] if isinstance(tmode, str) else int(tmode))
     om = OMODES[omode] if isinstance(omode, str) else int(omode)
     tg = None if target is None else _arr(target, np.float64).reshape(-1)
     ob = None if obstacle is None else _arr(obstacle, np.float64).reshape(-1)
-    for a in (tg, ob):
-        if a is not None and a.size != P:
-            raise ValueError("target / obstacle size does not match the grid")
-    return tm, om, tg, ob
+    sizes = {a.size for a in (tg, ob) if a is not None}
+    if len(sizes) > 1 or (sizes and sizes.pop() not in (P, ntau * P)):
+        raise ValueError("target / obstacle must hold one grid, or one grid per tau point")
+    slices = ntau if any(a is not None and a.size == ntau * P != P for a in (tg, ob)) else 1
+    return tm, om, tg, ob, slices
 
 
 def solve(grid, dyn, V0: np.ndarray, tau: Sequence[float], rk_order=1, cfl=0.8, brt=True,
           global_alpha=False, max_dt=0.0, V_init: Optional[np.ndarray] = None,
           save_all=False, tmode=None, omode=0, target=None, obstacle=None) -> OracleResult:
     """tmode (overrides brt): a computation-method name or code (TMODES);
-    omode: obstacle method (OMODES); target / obstacle: arrays on the grid."""
+    omode: obstacle method (OMODES); target / obstacle: arrays on the grid,
+    or (time-varying sets) len(tau) grids, the set at each tau[k]."""
     lib = _load()
     n, lo, hi, per = _grid_args(grid)
     V0 = _arr(V0, np.float64).reshape(-1)
@@ -151,7 +155,7 @@ def solve(grid, dyn, V0: np.ndarray, tau: Sequence[float], rk_order=1, cfl=0.8, 
     P = int(np.prod(n))
     if V0.size != P:
         raise ValueError("V0 size does not match the grid")
-    tm, om, tg, ob = _modes(brt, tmode, omode, target, obstacle, P)
+    tm, om, tg, ob, slices = _modes(brt, tmode, omode, target, obstacle, P, len(tau))
     out = np.empty(P, dtype=np.float64)
     vall = np.empty((len(tau), P), dtype=np.float64) if save_all else None
     steps = ctypes.c_long(0)
@@ -162,7 +166,7 @@ def solve(grid, dyn, V0: np.ndarray, tau: Sequence[float], rk_order=1, cfl=0.8, 
         dyn.u_mode, dyn.d_mode, _ptr(p, _dp), _ptr(V0, _dp),
         _ptr(Vi, _dp) if Vi is not None else None, _ptr(tau, _dp), len(tau), rk_order, cfl,
         tm, om, _ptr(tg, _dp) if tg is not None else None, _ptr(ob, _dp) if ob is not None else None,
-        1 if global_alpha else 0, max_dt, _ptr(out, _dp),
+        slices, 1 if global_alpha else 0, max_dt, _ptr(out, _dp),
         _ptr(vall, _dp) if vall is not None else None, ctypes.byref(steps), ctypes.byref(d1),
         ctypes.byref(d2), ctypes.byref(d3))
     if rc != 0:
@@ -201,7 +205,7 @@ def step_at(grid, dyn, V: np.ndarray, V0: np.ndarray, dt: float, idx, rk_order=1
     n, lo, hi, per = _grid_args(grid)
     V = _arr(V, np.float64).reshape(-1)
     V0 = _arr(V0, np.float64).reshape(-1)
-    tm, om, tg, ob = _modes(brt, tmode, omode, target, obstacle, V.size)
+    tm, om, tg, ob, _ = _modes(brt, tmode, omode, target, obstacle, V.size)
     idx = _arr(idx, np.int64)
     out = np.empty(idx.size, dtype=np.float64)
     ag = None if alpha_glob is None else _arr(alpha_glob, np.float64)

@@ -391,12 +391,17 @@ static int og_modes_ok(int tmode, int omode, const double *target, const double 
 }
 
 /* Full solve from tau[0] to tau[ntau-1].  V_all (nullable) receives V at
- * every tau[k] (ntau slices, slice 0 = the start value).  Returns 0 or -1. */
+ * every tau[k] (ntau slices, slice 0 = the start value).  set_slices 0 or 1:
+ * target and obstacle are one grid array each, for the whole horizon;
+ * set_slices = ntau: time-varying sets l(z, t), g(z, t) (the paper's
+ * time-varying target and obstacle), slice k holds the set at tau[k] and the
+ * steps from tau[k-1] to tau[k] compare with slice k-1, the set at the time
+ * the interval starts (the table's index t-1).  Returns 0 or -1. */
 int oracle_hj_solve(int ndim, const long *n, const double *lo, const double *hi,
                     const int *periodic, int dyn_id, int u_mode, int d_mode,
                     const double *params, const double *V0, const double *V_init,
                     const double *tau, int ntau, int rk_order, double cfl, int tmode, int omode,
-                    const double *target, const double *obstacle,
+                    const double *target, const double *obstacle, int set_slices,
                     int global_alpha, double max_dt, double *V_out, double *V_all,
                     long *steps_out, double *dt_first, double *dt_min, double *dt_max)
 {
@@ -405,6 +410,7 @@ int oracle_hj_solve(int ndim, const long *n, const double *lo, const double *hi,
     if (og_setup(&g, &dy, ndim, n, lo, hi, periodic, dyn_id, u_mode, d_mode, params)) return -1;
     if (rk_order < 1 || rk_order > 3 || ntau < 2 || !(cfl > 0.0)) return -1;
     if (!og_modes_ok(tmode, omode, target, obstacle)) return -1;
+    if (set_slices != 0 && set_slices != 1 && set_slices != ntau) return -1;
     for (int k = 1; k < ntau; ++k)
         if (!(tau[k] > tau[k - 1])) return -1;
 
@@ -458,7 +464,10 @@ int oracle_hj_solve(int ndim, const long *n, const double *lo, const double *hi,
         /* computation method (a tube: V = min(V, V0), the HJ variational
          * inequality); Vn still holds the value before the step */
         if (tmode || omode) {
-            for (long i = 0; i < P; ++i) Nx[i] = og_clamp(Nx[i], i, tmode, omode, V0, Vn, target, obstacle);
+            const size_t off = set_slices > 1 ? (size_t)(k - 1) * (size_t)P : 0;
+            const double *lk = target ? target + off : NULL;
+            const double *gk = obstacle ? obstacle + off : NULL;
+            for (long i = 0; i < P; ++i) Nx[i] = og_clamp(Nx[i], i, tmode, omode, V0, Vn, lk, gk);
         }
         memcpy(Vn, Nx, sizeof(double) * (size_t)P);
 

@@ -48,6 +48,10 @@ MUTANTS = [
     ("obstacle_max_as_min", "if (omode == 2 && obstacle[i] > v) v = obstacle[i];",
      "if (omode == 2 && obstacle[i] < v) v = obstacle[i];"),
     ("max_methods_as_min", "if (tmode % 2 == 1) {", "if (tmode % 2 == 0 || tmode == 1) {"),
+    ("set_slice_off_by_one", "const size_t off = set_slices > 1 ? (size_t)(k - 1) * (size_t)P : 0;",
+     "const size_t off = set_slices > 1 ? (size_t)k * (size_t)P : 0;"),
+    ("set_slices_ignored", "const size_t off = set_slices > 1 ? (size_t)(k - 1) * (size_t)P : 0;",
+     "const size_t off = 0;"),
     ("last_step_not_clipped", "dt = tau[k] - t;", "dt = dt + 0.0;"),
     ("control_bound_for_disturbance", "dd[0] = og_bang(pbar[5], dy->p[3], dy->d_mode);",
      "dd[0] = og_bang(pbar[5], dy->p[1], dy->d_mode);"),
@@ -73,6 +77,7 @@ FAST_PINS = [
     lambda o: pins.test_restart_equals_single_call(o),
     lambda o: [pins.test_pin9_computation_methods_closed_form(o, *c, f) for c in pins.CASES_PIN9
                for f in (1.0, 0.5)],
+    lambda o: [pins.test_pin9_time_varying_sets(o, f) for f in (1.0, 0.5)],
     lambda o: [pins.test_pin9_restart_reference(o, m, f) for m, f in
                (("minVWithVInit", np.minimum), ("maxVWithVInit", np.maximum), ("minVWithV0", None))],
 ]

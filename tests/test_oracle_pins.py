@@ -524,6 +524,30 @@ def test_pin9_restart_reference(oracle_mod, tmode, npop):
         assert np.abs(expect - other).max() > 0.05
 
 
+@pytest.mark.parametrize("cfl", [1.0, 0.5])
+def test_pin9_time_varying_sets(oracle_mod, cfl):
+    """Time-varying target and obstacle: slice k holds the sets at tau[k];
+    the steps from tau[k-1] to tau[k] compare with slice k-1.  Three output
+    intervals of three steps each, slices that differ from one another."""
+    g, d, V0, l, ob, steps = _advection_case()
+    _, dt = oracle_mod.cfl_dt(g, d, cfl)
+    tau = [3 * k * dt * (1 - 1e-12) for k in range(4)]
+    L = np.stack([np.roll(l, 4 * k) - 0.1 * k for k in range(4)])
+    G = np.stack([np.roll(ob, -3 * k) + 0.05 * k for k in range(4)])
+    res = oracle_mod.solve(g, d, V0, tau, rk_order=1, cfl=cfl, tmode="minVWithVTarget",
+                           omode="maxVWithObstacle", target=L, obstacle=G)
+    assert res.steps == 9
+    V = V0.copy()
+    for st in range(9):
+        k = st // 3
+        V = np.maximum(np.minimum(V + cfl * (np.roll(V, -1) - V), L[k]), G[k])
+    assert np.abs(res.V - V).max() < 1e-10
+    # a static set (slice 0 throughout) gives another answer
+    static = oracle_mod.solve(g, d, V0, tau, rk_order=1, cfl=cfl, tmode="minVWithVTarget",
+                              omode="maxVWithObstacle", target=L[0], obstacle=G[0])
+    assert np.abs(static.V - V).max() > 0.05
+
+
 def test_pin9_target_equal_to_v0_is_the_v0_method(oracle_mod):
     spec = W.config_dubins3d(n=(17, 15, 12), T=0.6)
     V0 = W.make_v0(spec)
