@@ -155,12 +155,17 @@ typedef struct {
                             stream), 1 always (non-null stream), 2 never.
                             With a graph the call returns after completion. */
     int32_t obstacle_mode; /* odp_obstacle_mode (0: none) */
-    int32_t pad_;
-    const void *target_dev;   /* device, grid-shaped, element type = precision:
-                                 l(z) of ODP_MIN_TARGET / ODP_MAX_TARGET (NULL
-                                 otherwise); read only, for the whole horizon */
-    const void *obstacle_dev; /* device, grid-shaped: g(z) of the obstacle
-                                 method (NULL when obstacle_mode is 0) */
+    int32_t set_slices;    /* 0 or 1: target_dev / obstacle_dev hold one grid
+                              each, used for the whole horizon; ntau
+                              (odp_hj_solve only): time-varying sets l(z, t),
+                              g(z, t), ntau grids one after the other, grid k
+                              the set at tau[k]; the steps from tau[k-1] to
+                              tau[k] compare with grid k-1 */
+    const void *target_dev;   /* device, element type = precision: l(z) of
+                                 ODP_MIN_TARGET / ODP_MAX_TARGET (NULL
+                                 otherwise); read only */
+    const void *obstacle_dev; /* device: g(z) of the obstacle method (NULL
+                                 when obstacle_mode is 0); read only */
 } odp_solve_opts;
 
 typedef struct {

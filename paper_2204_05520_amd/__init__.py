@@ -67,7 +67,7 @@ class odp_solve_opts(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("dissipation", ctypes.c_int32), ("max_dt", ctypes.c_double),
                 ("save_all", ctypes.c_int32), ("tile_chunk", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("xcd_group", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("obstacle_mode", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("obstacle_mode", ctypes.c_int32), ("set_slices", ctypes.c_int32),
                 ("target_dev", ctypes.c_void_p), ("obstacle_dev", ctypes.c_void_p)]
 
 
@@ -223,9 +223,10 @@ def obstacle_code(mode) -> int:
 
 def make_opts(precision=32, rk_order=1, cfl=0.8, mode=ODP_BRT, dissipation=0, max_dt=0.0,
               save_all=0, tile_chunk=0, stream=None, xcd_group=0, graph=0, obstacle_mode=0,
-              target=None, obstacle=None) -> odp_solve_opts:
-    """target / obstacle: device tensors (or raw device addresses) of the grid's
-    shape for the target and obstacle methods."""
+              target=None, obstacle=None, set_slices=0) -> odp_solve_opts:
+    """target / obstacle: device tensors (or raw device addresses) for the
+    target and obstacle methods: one grid, or set_slices grids (time-varying
+    sets, one per tau point)."""
     o = odp_solve_opts()
     o.precision = precision
     o.rk_order = rk_order
@@ -235,6 +236,7 @@ def make_opts(precision=32, rk_order=1, cfl=0.8, mode=ODP_BRT, dissipation=0, ma
     addr = lambda x: None if x is None else (x if isinstance(x, int) else int(x.data_ptr()))
     o.target_dev = addr(target)
     o.obstacle_dev = addr(obstacle)
+    o.set_slices = set_slices
     o.dissipation = dissipation
     o.max_dt = max_dt
     o.save_all = save_all
@@ -304,19 +306,26 @@ def solve(spec, V0, precision=32, V_init=None, tau=None, stream=None, save_all=F
           obstacle=None) -> SolveResult:
     """One solve of a workloads.SolveSpec with a device V0 tensor.  mode and
     obstacle_mode take the paper's method names or the odp codes; target /
-    obstacle are device tensors on the grid for the methods that use them."""
+    obstacle are device tensors on the grid for the methods that use them, or
+    of shape (len(tau), *grid) for time-varying sets (slice k at tau[k])."""
     import torch
     grid = Grid.from_spec(spec.grid)
     npts = grid.npts
     check_device_tensor(V0, precision, npts, "V0")
-    for x, name in ((V_init, "V_init"), (target, "target"), (obstacle, "obstacle")):
-        if x is not None:
-            check_device_tensor(x, precision, npts, name)
     tau = list(spec.tau if tau is None else tau)
+    if V_init is not None:
+        check_device_tensor(V_init, precision, npts, "V_init")
+    sets = [x for x in (target, obstacle) if x is not None]
+    slices = 0
+    if sets:
+        slices = len(tau) if sets[0].numel() == len(tau) * npts and len(tau) * npts != npts else 0
+        for x, name in ((target, "target"), (obstacle, "obstacle")):
+            if x is not None:
+                check_device_tensor(x, precision, npts * max(slices, 1), name)
     opts = make_opts(precision, spec.rk_order if rk_order is None else rk_order,
                      spec.cfl if cfl is None else cfl, spec.mode if mode is None else mode,
                      dissipation, max_dt, 1 if save_all else 0, tile_chunk, _stream_handle(stream),
-                     xcd_group, graph, obstacle_mode, target, obstacle)
+                     xcd_group, graph, obstacle_mode, target, obstacle, slices)
     out = torch.empty_like(V0)
     vall = torch.empty((len(tau),) + tuple(V0.shape), dtype=V0.dtype, device=V0.device) if save_all else None
     st = odp_hj_solve(grid, spec.dyn, V0, V_init, tau, opts, workspace, out, vall)

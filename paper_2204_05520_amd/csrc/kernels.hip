@@ -836,6 +836,16 @@ __global__ void sched_kernel(const SolveDesc *__restrict__ descs, int nsolves, i
     if (nsteps_all) nsteps_all[i] = n;
 }
 
+// Time-varying sets: point the comparison references of solve 0 at slice iv
+// (the tau interval that the next steps lie in).
+template <typename T>
+__global__ void set_slice_kernel(SolveDesc *__restrict__ descs, int iv) {
+    if (threadIdx.x != 0) return;
+    SolveDesc &s = descs[0];
+    s.tref = (const T *)s.tref0 + int64_t(iv) * s.tstride;
+    s.oref = (const T *)s.oref0 + int64_t(iv) * s.ostride;
+}
+
 // Server ticks: advance the step counter of every listed unfinished solve.
 __global__ void advance_kernel(const SolveDesc *__restrict__ descs, const int32_t *__restrict__ list,
                                int n) {
@@ -1062,6 +1072,14 @@ hipError_t launch_finish_copy(int precision, const SolveDesc *d, const uint32_t 
         hipLaunchKernelGGL(finish_copy_kernel<float>, dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl);
     else
         hipLaunchKernelGGL(finish_copy_kernel<double>, dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_slice(int precision, SolveDesc *d, int iv, hipStream_t st) {
+    if (precision == 32)
+        hipLaunchKernelGGL(set_slice_kernel<float>, dim3(1), dim3(64), 0, st, d, iv);
+    else
+        hipLaunchKernelGGL(set_slice_kernel<double>, dim3(1), dim3(64), 0, st, d, iv);
     return hipGetLastError();
 }
 

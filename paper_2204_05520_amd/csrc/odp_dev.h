@@ -93,6 +93,13 @@ struct SolveDesc {
     const void *tref;        // reference array when tvn == 0 (V0, a target array,
                              // or the obstacle array of an obstacle-only method)
     const void *oref;        // obstacle array when obst == 1
+    // time-varying sets: tref / oref point at the slice of the current tau
+    // interval, set between steps from the slice-0 bases and the strides
+    // (elements between slices; 0 for a reference that does not vary)
+    const void *tref0;
+    const void *oref0;
+    int64_t tstride;
+    int64_t ostride;
     const double *tau;       // output times (device copy)
     double cfl;
     double max_dt;

@@ -217,6 +217,13 @@ void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &
             s.tmax = om == ODP_MAX_OBSTACLE;
             s.tref = o.obstacle_dev;
         }
+        if (o.set_slices > 1) {
+            const bool tsliced = m >= ODP_MIN_TARGET || (m == ODP_BRS && om != ODP_OBSTACLE_NONE);
+            s.tstride = tsliced ? g->npts : 0;
+            s.ostride = s.obst ? g->npts : 0;
+        }
+        s.tref0 = s.tref;
+        s.oref0 = s.oref;
         s.ntau = int32_t(it.tau.size());
         s.tau = (const double *)(base + tau_off);
         s.cfl = o.cfl;
@@ -346,7 +353,13 @@ static int plan_enqueue(Plan &p, unsigned char *base, hipStream_t st, const std:
         if ((rc = check_hip(launch_start_copy(prec, descs, ts, tl, gr.prefix.back(), st), "start copy"))) return rc;
     }
     const size_t bytes = single ? size_t(p.items[0].g->npts) * (prec == 32 ? 4 : 8) : 0;
+    // time-varying sets (single solves): the steps after landing on tau[j]
+    // compare with slice j
+    const bool sliced = single && o.set_slices > 1 && land;
     for (int64_t k = 0; k < p.max_nsteps; ++k) {
+        if (sliced && k > 0 && (*land)[size_t(k - 1)] >= 0 &&
+            (rc = check_hip(launch_set_slice(prec, (SolveDesc *)descs, (*land)[size_t(k - 1)], st), "slice")))
+            return rc;
         if ((rc = plan_launch_step(p, base, st, k))) return rc;
         if (land && V_all && (*land)[size_t(k)] >= 0) {
             const PlanItem &it = p.items[0];

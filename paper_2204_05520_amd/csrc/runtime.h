@@ -29,6 +29,8 @@ hipError_t launch_alpha(int dyn, int ndim, const SolveDesc *d, int nsolves, int 
 hipError_t launch_init(const SolveDesc *d, int nsolves, hipStream_t st);
 hipError_t launch_sched(const SolveDesc *d, int nsolves, int64_t *nsteps_all, hipStream_t st);
 hipError_t launch_advance(const SolveDesc *d, const int32_t *list, int n, hipStream_t st);
+// Time-varying sets of a single solve: references of descs[0] to slice iv.
+hipError_t launch_set_slice(int precision, SolveDesc *d, int iv, hipStream_t st);
 // Padded members (SolveDesc::Adst_dense set): A to the caller's dense array.
 hipError_t launch_finish_copy(int precision, const SolveDesc *d, const uint32_t *ts, const uint32_t *tl,
                               uint32_t nblocks, hipStream_t st);

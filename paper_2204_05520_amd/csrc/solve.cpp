@@ -93,6 +93,8 @@ int odp_hj_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_d
         return set_error(ODP_EINVAL, "V_out may not alias V0 or V_init");
     if (V_out_dev == opts->target_dev || V_out_dev == opts->obstacle_dev)
         return set_error(ODP_EINVAL, "V_out may not alias the target or obstacle array");
+    if (opts->set_slices > 1 && opts->set_slices != ntau)
+        return set_error(ODP_EINVAL, "set_slices must be 0, 1 or ntau");
     if (opts->save_all && !V_all_dev) return set_error(ODP_EINVAL, "save_all needs V_all");
     hipStream_t st = (hipStream_t)opts->stream;
 
@@ -118,13 +120,16 @@ int odp_hj_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_d
     if ((rc = plan_prologue(p, base, st))) return rc;
 
     std::vector<int32_t> land;
-    if (opts->save_all) {
+    const bool want_land = opts->save_all || opts->set_slices > 1;
+    if (want_land) {
         const PlanItem &it = p.items[0];
         land.resize(size_t(it.nsteps));
         if ((rc = check_hip(hipMemcpyAsync(land.data(), base + it.land_off, land.size() * 4,
                                            hipMemcpyDeviceToHost, st), "read landings")) ||
             (rc = check_hip(hipStreamSynchronize(st), "sync")))
             return rc;
+    }
+    if (opts->save_all) {
         const size_t bytes = size_t(grid->npts) * (opts->precision == 32 ? 4 : 8);
         const void *src = V_init_dev ? V_init_dev : V0_dev;
         if ((rc = check_hip(hipMemcpyAsync(V_all_dev, src, bytes, hipMemcpyDeviceToDevice, st), "save start")))
@@ -136,7 +141,8 @@ int odp_hj_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_d
             return rc;
         (void)hipEventRecord(tm.e0, st);
     }
-    if ((rc = plan_steps(p, base, st, opts->save_all ? &land : nullptr, V_all_dev))) return rc;
+    if ((rc = plan_steps(p, base, st, want_land ? &land : nullptr, opts->save_all ? V_all_dev : nullptr)))
+        return rc;
     if (stats) {
         (void)hipEventRecord(tm.e1, st);
         if ((rc = check_hip(hipEventSynchronize(tm.e1), "sync"))) return rc;

@@ -142,20 +142,28 @@ def make_v0(spec: SolveSpec) -> np.ndarray:
     return cylinder_v0(spec.grid, spec.radius, keep=(0, 1))
 
 
-def reach_avoid_sets(spec: SolveSpec):
+def reach_avoid_sets(spec: SolveSpec, t: float = 0.0):
     """Target l(z) and obstacle g(z) for the target and obstacle computation
     methods, as in the paper's reach-avoid example (a goal and an obstacle,
     both cylinders over the position axes): l is the signed distance to a
     disc (negative inside), g = minus the signed distance to another disc
     (positive inside the obstacle).  Centres sit at fixed fractions of the
-    domain; float64 on the host."""
+    domain at t = 0 and move with t (time-varying sets: call once per tau
+    point); float64 on the host."""
     g = spec.grid
     keep = (0, 1) if g.ndim >= 2 else (0,)
     at = lambda f: [g.lo[d] + f[min(d, len(f) - 1)] * (g.hi[d] - g.lo[d]) for d in range(g.ndim)]
     ext = min(g.hi[d] - g.lo[d] for d in keep)
-    target = cylinder_v0(g, 0.12 * ext, keep=keep, center=at([0.7, 0.62]))
-    obstacle = -cylinder_v0(g, 0.15 * ext, keep=keep, center=at([0.35, 0.45]))
+    target = cylinder_v0(g, 0.12 * ext, keep=keep, center=at([0.7 - 0.1 * t, 0.62]))
+    obstacle = -cylinder_v0(g, 0.15 * ext, keep=keep, center=at([0.35, 0.45 + 0.1 * t]))
     return target, obstacle
+
+
+def moving_sets(spec: SolveSpec, tau: Sequence[float]):
+    """reach_avoid_sets at every tau[k], stacked: arrays of shape
+    (len(tau), *grid)."""
+    ls, gs = zip(*(reach_avoid_sets(spec, float(t)) for t in tau))
+    return np.stack(ls), np.stack(gs)
 
 
 def make_v0_torch(spec: SolveSpec, device, dtype):

@@ -73,7 +73,7 @@ def _solve_rc(spec, precision=32, **kw):
                          kw.pop("mode", spec.mode), kw.pop("diss", 0), kw.pop("max_dt", 0.0),
                          kw.pop("save_all", 0), kw.pop("tile_chunk", 0), None,
                          obstacle_mode=kw.pop("obstacle_mode", 0), target=kw.pop("target", None),
-                         obstacle=kw.pop("obstacle", None))
+                         obstacle=kw.pop("obstacle", None), set_slices=kw.pop("set_slices", 0))
     V0 = kw.pop("V0", ctypes.c_void_p(0x1000))
     Vout = kw.pop("Vout", ctypes.c_void_p(0x2000))
     rc = odp.lib().odp_hj_solve(grid.handle, ctypes.byref(d), V0, None, t, len(tau),
@@ -104,6 +104,9 @@ def _solve_rc(spec, precision=32, **kw):
     ({"obstacle": 0x3000}, "obstacle_dev is set"),
     ({"mode": "minVWithVTarget", "target": 0x2000}, "alias"),
     ({"obstacle_mode": 2, "obstacle": 0x2000}, "alias"),
+    ({"set_slices": 2}, "set_slices needs"),
+    ({"set_slices": -1}, "set_slices needs"),
+    ({"mode": 5, "target": 0x3000, "set_slices": 3}, "set_slices must be"),
 ])
 def test_solve_rejects_before_gpu(lib, kw, msg):
     spec = W.config_dubins3d(n=(10, 10, 8))
