@@ -50,7 +50,8 @@ def _load():
         lib.oracle_hj_solve.argtypes = [
             ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
             _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-            _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _lp, _dp, _dp, _dp]
+            _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _lp, _dp,
+            _dp, _dp]
         lib.oracle_cfl_dt.restype = ctypes.c_int
         lib.oracle_cfl_dt.argtypes = [
             ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
@@ -59,7 +60,7 @@ def _load():
         lib.oracle_step_at.argtypes = [
             ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
             _dp, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp,
-            ctypes.c_long, _lp, _dp]
+            ctypes.c_int, ctypes.c_int, ctypes.c_long, _lp, _dp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         _lib = lib
@@ -143,8 +144,10 @@ def _modes(brt, tmode, omode, target, obstacle, P, ntau=1):
 
 def solve(grid, dyn, V0: np.ndarray, tau: Sequence[float], rk_order=1, cfl=0.8, brt=True,
           global_alpha=False, max_dt=0.0, V_init: Optional[np.ndarray] = None,
-          save_all=False, tmode=None, omode=0, target=None, obstacle=None) -> OracleResult:
-    """tmode (overrides brt): a computation-method name or code (TMODES);
+          save_all=False, tmode=None, omode=0, target=None, obstacle=None,
+          space_order=1) -> OracleResult:
+    """space_order: 1 first-order upwind, 2 second-order ENO differences.
+    tmode (overrides brt): a computation-method name or code (TMODES);
     omode: obstacle method (OMODES); target / obstacle: arrays on the grid,
     or (time-varying sets) len(tau) grids, the set at each tau[k]."""
     lib = _load()
@@ -166,7 +169,7 @@ def solve(grid, dyn, V0: np.ndarray, tau: Sequence[float], rk_order=1, cfl=0.8, 
         dyn.u_mode, dyn.d_mode, _ptr(p, _dp), _ptr(V0, _dp),
         _ptr(Vi, _dp) if Vi is not None else None, _ptr(tau, _dp), len(tau), rk_order, cfl,
         tm, om, _ptr(tg, _dp) if tg is not None else None, _ptr(ob, _dp) if ob is not None else None,
-        slices, 1 if global_alpha else 0, max_dt, _ptr(out, _dp),
+        slices, int(space_order), 1 if global_alpha else 0, max_dt, _ptr(out, _dp),
         _ptr(vall, _dp) if vall is not None else None, ctypes.byref(steps), ctypes.byref(d1),
         ctypes.byref(d2), ctypes.byref(d3))
     if rc != 0:
@@ -199,8 +202,11 @@ def cfl_dt(grid, dyn, cfl=0.8):
 
 
 def step_at(grid, dyn, V: np.ndarray, V0: np.ndarray, dt: float, idx, rk_order=1, brt=True,
-            alpha_glob=None, tmode=None, omode=0, target=None, obstacle=None) -> np.ndarray:
-    """One full time step of size dt from V, evaluated only at flat indices idx."""
+            alpha_glob=None, tmode=None, omode=0, target=None, obstacle=None, space_order=1,
+            eno_f32=False) -> np.ndarray:
+    """One full time step of size dt from V, evaluated only at flat indices
+    idx.  eno_f32: take the ENO stencil choices in float32 (from the
+    float32-rounded stencil), as a float32 solve does."""
     lib = _load()
     n, lo, hi, per = _grid_args(grid)
     V = _arr(V, np.float64).reshape(-1)
@@ -215,7 +221,8 @@ def step_at(grid, dyn, V: np.ndarray, V0: np.ndarray, dt: float, idx, rk_order=1
                             _ptr(V, _dp), _ptr(V0, _dp), dt, rk_order, tm, om,
                             _ptr(tg, _dp) if tg is not None else None,
                             _ptr(ob, _dp) if ob is not None else None,
-                            _ptr(ag, _dp) if ag is not None else None, idx.size,
+                            _ptr(ag, _dp) if ag is not None else None, int(space_order),
+                            1 if eno_f32 else 0, idx.size,
                             _ptr(idx, _lp), _ptr(out, _dp))
     if rc != 0:
         raise ValueError("oracle_step_at rejected its arguments")

@@ -13,6 +13,9 @@
  *   V(z, tau=tau_0) = V_init (V0 = l(z) unless a restart value is given)
  *   per time step, per Runge-Kutta stage, per grid point i (all independent):
  *     p-_d = (W_i - W_{i-e_d}) / dx_d,  p+_d = (W_{i+e_d} - W_i) / dx_d
+ *       (first-order upwind; or second-order ENO, Spatial Derivatives: the
+ *       one-sided difference corrected by half the smaller-magnitude second
+ *       difference of the two candidate stencils, over dx_d)
  *     pbar = (p+ + p-) / 2
  *     (u*, d*) = argmin_d argmax_u pbar . f(z_i, u, d)
  *     H  = pbar . f(z_i, u*, d*)
@@ -40,7 +43,10 @@
  *    the target-set operation before the obstacle operation, the "value
  *    over time" reference being V^n, the value at the start of the step;
  *  - ghost value beyond a non-periodic edge: V_b + sgn(V_b) |V_b - V_in|,
- *    sgn(0) = 0, so the ghost has the boundary node's sign;
+ *    sgn(0) = 0, so the ghost has the boundary node's sign; the second
+ *    ghost (second order) V_b + 2 sgn(V_b) |V_b - V_in|;
+ *  - ENO2 ties (equal magnitudes) take the stencil nearer the upwind side
+ *    (the first of the two candidates);
  *  - bang-bang tie at a zero switching function: a maximiser takes +max, a
  *    minimiser -max (the DubinsCapture listing's >= 0 branches);
  *  - third-order TVD-RK (Shu-Osher) added beside the paper's first and
@@ -248,7 +254,8 @@ static double og_get_array(const og_field *f, long idx) { return f->arr[idx]; }
 
 static double og_sgn(double x) { return (x > 0.0) - (x < 0.0); }
 
-/* W at the neighbour of point idx (multi-index ii) along axis d, side s. */
+/* W at the node s steps from point idx (multi-index ii) along axis d,
+ * |s| <= 2 (the second-order stencil reaches two nodes). */
 static double og_neighbor(const og_grid *g, const og_field *W, long idx, const long *ii,
                           int d, int s)
 {
@@ -258,18 +265,41 @@ static double og_neighbor(const og_grid *g, const og_field *W, long idx, const l
         long kw = (k + g->n[d]) % g->n[d];
         return W->get(W, idx + (kw - ii[d]) * g->stride[d]);
     }
-    /* ghost node beyond the edge: extrapolate away from zero so that the
-     * ghost keeps the sign of the boundary node */
-    double vb = W->get(W, idx);
-    double vin = W->get(W, idx - (long)s * g->stride[d]);
-    return vb + og_sgn(vb) * fabs(vb - vin);
+    /* m-th ghost node beyond the edge node b (m = 1, 2): extrapolate away
+     * from zero by m times the edge difference, so that every ghost keeps
+     * the sign of the edge node */
+    long b = k < 0 ? 0 : g->n[d] - 1;
+    long in = k < 0 ? 1 : g->n[d] - 2;
+    long m = k < 0 ? -k : k - b;
+    double vb = W->get(W, idx + (b - ii[d]) * g->stride[d]);
+    double vin = W->get(W, idx + (in - ii[d]) * g->stride[d]);
+    return vb + (double)m * og_sgn(vb) * fabs(vb - vin);
+}
+
+/* ENO stencil choice: the second difference of smaller magnitude (the first
+ * on a tie).  With f32 the magnitudes are compared as float32 values
+ * computed in float32 from the float32-rounded stencil (the precision of a
+ * float32 solve), which lets a single step be compared decision for
+ * decision with a float32 implementation. */
+static int og_eno_first(double x, double y)
+{
+    return fabs(x) <= fabs(y);
+}
+
+static int og_eno_first_f32(double w0, double w1, double w2, double w3)
+{
+    /* second differences (w2 - w1) - (w1 - w0) and (w3 - w2) - (w2 - w1) */
+    float a0 = (float)w0, a1 = (float)w1, a2 = (float)w2, a3 = (float)w3;
+    float d01 = a1 - a0, d12 = a2 - a1, d23 = a3 - a2;
+    float x = d12 - d01, y = d23 - d12;
+    return fabsf(x) <= fabsf(y);
 }
 
 /* Lax-Friedrichs numerical Hamiltonian at point idx (one pass of the body
  * of Algorithm 1's grid loops for one point). alpha_glob != NULL selects the
  * global-alpha approximation. */
 static double og_hhat(const og_grid *g, const og_dyn *dy, const og_field *W, long idx,
-                      const double *alpha_glob)
+                      const double *alpha_glob, int order, int eno_f32)
 {
     const int N = g->ndim;
     long ii[OG_MAXD];
@@ -282,8 +312,23 @@ static double og_hhat(const og_grid *g, const og_dyn *dy, const og_field *W, lon
     for (int d = 0; d < N; ++d) {
         double wl = og_neighbor(g, W, idx, ii, d, -1);
         double wr = og_neighbor(g, W, idx, ii, d, +1);
-        pm[d] = (wc - wl) / g->dx[d];
-        pp[d] = (wr - wc) / g->dx[d];
+        double dm = wc - wl, dp = wr - wc;
+        if (order == 2) {
+            /* second-order ENO (the level-set text's ENO2): one-sided
+             * difference plus half of the smaller second difference of the
+             * two stencils that contain it */
+            double wll = og_neighbor(g, W, idx, ii, d, -2);
+            double wrr = og_neighbor(g, W, idx, ii, d, +2);
+            double sm = dm - (wl - wll);   /* second difference at i-1 */
+            double s0 = dp - dm;           /* at i */
+            double sp = (wrr - wr) - dp;   /* at i+1 */
+            int fm = eno_f32 ? og_eno_first_f32(wll, wl, wc, wr) : og_eno_first(sm, s0);
+            int fp = eno_f32 ? og_eno_first_f32(wl, wc, wr, wrr) : og_eno_first(s0, sp);
+            dm = dm + 0.5 * (fm ? sm : s0);
+            dp = dp - 0.5 * (fp ? s0 : sp);
+        }
+        pm[d] = dm / g->dx[d];
+        pp[d] = dp / g->dx[d];
         pbar[d] = 0.5 * (pp[d] + pm[d]);
     }
 
@@ -402,13 +447,14 @@ int oracle_hj_solve(int ndim, const long *n, const double *lo, const double *hi,
                     const double *params, const double *V0, const double *V_init,
                     const double *tau, int ntau, int rk_order, double cfl, int tmode, int omode,
                     const double *target, const double *obstacle, int set_slices,
-                    int global_alpha, double max_dt, double *V_out, double *V_all,
+                    int space_order, int global_alpha, double max_dt, double *V_out, double *V_all,
                     long *steps_out, double *dt_first, double *dt_min, double *dt_max)
 {
     og_grid g;
     og_dyn dy;
     if (og_setup(&g, &dy, ndim, n, lo, hi, periodic, dyn_id, u_mode, d_mode, params)) return -1;
     if (rk_order < 1 || rk_order > 3 || ntau < 2 || !(cfl > 0.0)) return -1;
+    if (space_order != 1 && space_order != 2) return -1;
     if (!og_modes_ok(tmode, omode, target, obstacle)) return -1;
     if (set_slices != 0 && set_slices != 1 && set_slices != ntau) return -1;
     for (int k = 1; k < ntau; ++k)
@@ -456,7 +502,7 @@ int oracle_hj_solve(int ndim, const long *n, const double *lo, const double *hi,
             og_field Wf = {og_get_array, W, NULL, 0};
 #pragma omp parallel for schedule(static)
             for (long i = 0; i < P; ++i) {
-                double hh = og_hhat(&g, &dy, &Wf, i, aglob);
+                double hh = og_hhat(&g, &dy, &Wf, i, aglob, space_order, 0);
                 out[i] = og_combine(a, b, Vn[i], W[i], dt, hh);
             }
             W = out;
@@ -513,6 +559,8 @@ typedef struct {
     int rk_order;
     double dt;
     const double *aglob;
+    int order;
+    int eno_f32;
 } og_step_ctx;
 
 /* Value of Runge-Kutta stage `level` (0 = V^n) at idx, evaluated on demand
@@ -524,7 +572,7 @@ static double og_stage_value(const og_field *self, long idx)
     og_field prev = {og_stage_value, NULL, c, self->level - 1};
     double a, b;
     og_rk_weights(c->rk_order, self->level - 1, &a, &b);
-    double hh = og_hhat(c->g, c->dy, &prev, idx, c->aglob);
+    double hh = og_hhat(c->g, c->dy, &prev, idx, c->aglob, c->order, c->eno_f32);
     return og_combine(a, b, c->Vn[idx], og_stage_value(&prev, idx), c->dt, hh);
 }
 
@@ -535,14 +583,16 @@ int oracle_step_at(int ndim, const long *n, const double *lo, const double *hi,
                    const int *periodic, int dyn_id, int u_mode, int d_mode,
                    const double *params, const double *V, const double *V0, double dt,
                    int rk_order, int tmode, int omode, const double *target, const double *obstacle,
-                   const double *alpha_glob, long m, const long *idx, double *out)
+                   const double *alpha_glob, int space_order, int eno_f32, long m, const long *idx,
+                   double *out)
 {
     og_grid g;
     og_dyn dy;
     if (og_setup(&g, &dy, ndim, n, lo, hi, periodic, dyn_id, u_mode, d_mode, params)) return -1;
     if (rk_order < 1 || rk_order > 3) return -1;
+    if (space_order != 1 && space_order != 2) return -1;
     if (!og_modes_ok(tmode, omode, target, obstacle)) return -1;
-    og_step_ctx c = {&g, &dy, V, rk_order, dt, alpha_glob};
+    og_step_ctx c = {&g, &dy, V, rk_order, dt, alpha_glob, space_order, eno_f32};
 #pragma omp parallel for schedule(dynamic, 1)
     for (long j = 0; j < m; ++j) {
         og_field top = {og_stage_value, NULL, &c, rk_order};

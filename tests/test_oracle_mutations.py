@@ -21,11 +21,17 @@ MUTANTS = [
      "diss -= 0.5 * alpha[d] * (pp[d] - pm[d]);"),
     ("lf_dropped_on_last_axis", "for (int d = 0; d < N; ++d) diss += 0.5",
      "for (int d = 0; d < N - 1; ++d) diss += 0.5"),
-    ("one_sided_swapped", "pm[d] = (wc - wl) / g->dx[d];\n        pp[d] = (wr - wc) / g->dx[d];",
-     "pm[d] = (wr - wc) / g->dx[d];\n        pp[d] = (wc - wl) / g->dx[d];"),
+    ("one_sided_swapped", "double dm = wc - wl, dp = wr - wc;", "double dm = wr - wc, dp = wc - wl;"),
     ("costate_not_halved", "pbar[d] = 0.5 * (pp[d] + pm[d]);", "pbar[d] = (pp[d] + pm[d]);"),
-    ("ghost_toward_zero", "return vb + og_sgn(vb) * fabs(vb - vin);",
-     "return vb - og_sgn(vb) * fabs(vb - vin);"),
+    ("ghost_toward_zero", "return vb + (double)m * og_sgn(vb) * fabs(vb - vin);",
+     "return vb - (double)m * og_sgn(vb) * fabs(vb - vin);"),
+    ("second_ghost_like_first", "return vb + (double)m * og_sgn(vb) * fabs(vb - vin);",
+     "return vb + og_sgn(vb) * fabs(vb - vin);"),
+    ("eno_choice_inverted", "return fabs(x) <= fabs(y);", "return fabs(x) > fabs(y);"),
+    ("eno_correction_sign", "dm = dm + 0.5 * (fm ? sm : s0);", "dm = dm - 0.5 * (fm ? sm : s0);"),
+    ("eno_plus_side_stencils_shifted", "int fp = eno_f32 ? og_eno_first_f32(wl, wc, wr, wrr) : og_eno_first(s0, sp);\n            dm = dm + 0.5 * (fm ? sm : s0);\n            dp = dp - 0.5 * (fp ? s0 : sp);",
+     "int fp = eno_f32 ? og_eno_first_f32(wl, wc, wr, wrr) : og_eno_first(s0, sp);\n            dm = dm + 0.5 * (fm ? sm : s0);\n            dp = dp - 0.5 * (fp ? sm : s0);"),
+    ("eno_correction_not_halved", "dp = dp - 0.5 * (fp ? s0 : sp);", "dp = dp - (fp ? s0 : sp);"),
     ("periodic_wrap_off_by_one", "long kw = (k + g->n[d]) % g->n[d];",
      "long kw = (k + g->n[d] + 1) % g->n[d];"),
     ("cos_sin_swapped_3d", "f[0] = dy->p[0] * cos(z[2]);\n        f[1] = dy->p[0] * sin(z[2]);\n        f[2] = u[0];\n        break;\n    case OG_DYNCAR4D",
@@ -78,6 +84,10 @@ FAST_PINS = [
     lambda o: [pins.test_pin9_computation_methods_closed_form(o, *c, f) for c in pins.CASES_PIN9
                for f in (1.0, 0.5)],
     lambda o: [pins.test_pin9_time_varying_sets(o, f) for f in (1.0, 0.5)],
+    lambda o: [pins.test_pin10_eno2_exact_on_quadratics(o, n) for n in (1, 3)],
+    pins.test_pin10_eno2_picks_the_smooth_side,
+    pins.test_pin10_eno2_tie_takes_the_first_stencil,
+    pins.test_pin10_eno2_second_ghost,
     lambda o: [pins.test_pin9_restart_reference(o, m, f) for m, f in
                (("minVWithVInit", np.minimum), ("maxVWithVInit", np.maximum), ("minVWithV0", None))],
 ]

@@ -390,6 +390,120 @@ def test_pin8_rk_temporal_order(oracle_mod, rk):
         assert abs(r_ - rk) < 0.25, (rates, e)
 
 
+# ------------------------------------------------------------------ pin 10
+# Second-order ENO differences (the Spatial Derivatives subsection's ENO2).
+
+def _drift_1d(n, lo=-2.0, hi=2.0, c=0.7, periodic=0):
+    g = W.GridSpec([n], [lo], [hi], [periodic])
+    d = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [0.0, c], W.MAXIMISE, W.MINIMISE)
+    return g, d
+
+
+@pytest.mark.parametrize("ndim", [1, 3])
+def test_pin10_eno2_exact_on_quadratics(oracle_mod, ndim):
+    """ENO2 one-sided differences of a quadratic are its exact derivative, so
+    with the drift-only Hamiltonian H = c . p the LF term vanishes and one
+    step is V + dt c . grad q at every node two or more nodes from an edge.
+    First-order differences miss this by dt |c_d| q_d'' dx_d / 2."""
+    n = [23, 17, 19][:ndim]
+    lo, hi = [-2.0, -1.0, 0.5][:ndim], [2.0, 1.5, 3.0][:ndim]
+    cs = [0.7, -0.4, 0.25][:ndim]
+    qa, qb = [0.8, -1.3, 0.5][:ndim], [0.3, 0.1, -0.7][:ndim]
+    g = W.GridSpec(n, lo, hi, [0] * ndim)
+    d = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [0.0] + cs, W.MAXIMISE, W.MINIMISE)
+    ax = [g.axis(k) for k in range(ndim)]
+    mesh = np.meshgrid(*ax, indexing="ij")
+    V = sum(qa[k] * mesh[k] ** 2 + qb[k] * mesh[k] for k in range(ndim))
+    grad_c = sum(cs[k] * (2 * qa[k] * mesh[k] + qb[k]) for k in range(ndim))
+    inner = np.ones(V.shape, bool)
+    for k in range(ndim):
+        sl = [slice(None)] * ndim
+        for e in (0, 1, -1, -2):
+            sl[k] = e
+            inner[tuple(sl)] = False
+    idx = np.flatnonzero(inner.reshape(-1))
+    dt = 0.01
+    got = oracle_mod.step_at(g, d, V, V, dt, idx, brt=False, space_order=2)
+    expect = (V + dt * grad_c).reshape(-1)[idx]
+    assert np.abs(got - expect).max() < 1e-12
+    first = oracle_mod.step_at(g, d, V, V, dt, idx, brt=False, space_order=1)
+    assert np.abs(first - expect).max() > 1e-4
+
+
+def test_pin10_eno2_picks_the_smooth_side(oracle_mod):
+    """V = |x - x_k| with the kink on node k: away from the kink ENO2 takes
+    the stencil that does not cross it, so both one-sided differences equal
+    the exact slope +-1 and a drift step moves V by dt c sgn(x - x_k); on
+    the kink node p- = -1, p+ = +1 and the step adds dt |c| (LF term)."""
+    n, k = 41, 17
+    for c in (0.7, -0.45):
+        g, d = _drift_1d(n, c=c)
+        x = g.axis(0)
+        V = np.abs(x - x[k])
+        idx = np.arange(2, n - 2)
+        dt = 0.02
+        got = oracle_mod.step_at(g, d, V, V, dt, idx, brt=False, space_order=2)
+        expect = V[idx] + dt * c * np.sign(x[idx] - x[k])
+        expect[idx == k] = V[k] + dt * abs(c)
+        assert np.abs(got - expect).max() < 1e-12, c
+
+
+def test_pin10_eno2_tie_takes_the_first_stencil(oracle_mod):
+    """Equal-magnitude second differences of opposite sign around node i:
+    the reading takes the first candidate (the one nearer the upwind side of
+    each one-sided difference)."""
+    g, d = _drift_1d(11, lo=0.0, hi=10.0, c=1.0)
+    V = np.zeros(11)
+    i = 5
+    V[i - 2], V[i - 1], V[i], V[i + 1], V[i + 2] = 0.0, 1.0, 0.0, 1.0, 2.0
+    # at i: sm = (0-1)-(1-0) = -2, s0 = (1-0)-(0-1) = 2 (tie), sp = (2-1)-(1-0) = 0
+    # p- = (dm + sm/2)/dx = (-1 - 1) = -2; p+ = (dp - s0/2)/dx... s0 vs sp: |2| > 0 -> sp
+    # p+ = (1 - 0)/1 = 1; with c = 1: Hh = c pbar + |c|/2 (p+ - p-) = -0.5 + 1.5 = 1
+    dt = 0.1
+    got = oracle_mod.step_at(g, d, V, V, dt, [i], brt=False, space_order=2)
+    assert abs(got[0] - (V[i] + dt * 1.0)) < 1e-14
+
+
+def test_pin10_eno2_second_ghost(oracle_mod):
+    """Beyond a non-periodic edge the m-th ghost is V_b + m sgn(V_b)|V_b - V_in|.
+    V = 5 - x on [1, 3] (positive, decreasing): at the lower edge the ghosts
+    continue the line (the data grows away from zero there), so every node
+    but the last moves by the exact drift step -dt c; at the upper edge the
+    ghosts turn back up (2.1, 2.2 after 2.0), the last node's p- picks the
+    line (-1) and its p+ the two ghosts (+1: the stencil through the second
+    ghost is the straight one), so it moves by dt |c| (the LF term)."""
+    for c in (0.6, -0.6):
+        g, d = _drift_1d(21, lo=1.0, hi=3.0, c=c)
+        x = g.axis(0)
+        V = 5.0 - x
+        dt = 0.01
+        got = oracle_mod.step_at(g, d, V, V, dt, np.arange(21), brt=False, space_order=2)
+        expect = V - dt * c
+        expect[-1] = V[-1] + dt * abs(c)
+        assert np.abs(got - expect).max() < 1e-12, c
+
+
+def test_pin10_eno2_rk2_second_order_convergence(oracle_mod):
+    """Periodic advection of a smooth profile with ENO2 + TVD-RK2 (the
+    paper's second-order row) converges at second order; first order at
+    first order."""
+    def err(n, order):
+        g, d = _drift_1d(n, lo=0.0, hi=8.0, c=1.0, periodic=1)
+        x = g.axis(0)
+        V0 = np.sin(2 * np.pi * x / 8.0) + 0.5 * np.cos(4 * np.pi * x / 8.0)
+        T = 2.0
+        res = oracle_mod.solve(g, d, V0, [0.0, T], rk_order=2, cfl=0.5, brt=False,
+                               space_order=order)
+        xe = x + T   # z' = c + u: the profile moves by -c T in tau (V(z) = V0(z + c tau))
+        exact = np.sin(2 * np.pi * xe / 8.0) + 0.5 * np.cos(4 * np.pi * xe / 8.0)
+        return np.abs(res.V - exact).mean()
+    for order, lo_, hi_ in ((2, 1.7, 2.4), (1, 0.7, 1.3)):
+        e = [err(n, order) for n in (64, 128, 256)]
+        rates = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+        for r_ in rates:
+            assert lo_ <= r_ <= hi_, (order, rates, e)
+
+
 # ------------------------------------------------------------------ golden
 
 def test_golden_cfl_steps(oracle_mod):
