@@ -166,6 +166,13 @@ typedef struct {
                                  otherwise); read only */
     const void *obstacle_dev; /* device: g(z) of the obstacle method (NULL
                                  when obstacle_mode is 0); read only */
+    int32_t space_order;   /* spatial derivatives (Spatial Derivatives
+                              subsection): 0 or 1 first-order upwind; 2
+                              second-order ENO (the paper's second-order row
+                              pairs it with rk_order 2); beyond a
+                              non-periodic edge the second ghost node is
+                              V_b + 2 sgn(V_b) |V_b - V_in| */
+    int32_t pad2_;
 } odp_solve_opts;
 
 typedef struct {

@@ -68,7 +68,8 @@ class odp_solve_opts(ctypes.Structure):
                 ("save_all", ctypes.c_int32), ("tile_chunk", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("xcd_group", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("obstacle_mode", ctypes.c_int32), ("set_slices", ctypes.c_int32),
-                ("target_dev", ctypes.c_void_p), ("obstacle_dev", ctypes.c_void_p)]
+                ("target_dev", ctypes.c_void_p), ("obstacle_dev", ctypes.c_void_p),
+                ("space_order", ctypes.c_int32), ("pad2_", ctypes.c_int32)]
 
 
 class odp_solve_stats(ctypes.Structure):
@@ -223,7 +224,7 @@ def obstacle_code(mode) -> int:
 
 def make_opts(precision=32, rk_order=1, cfl=0.8, mode=ODP_BRT, dissipation=0, max_dt=0.0,
               save_all=0, tile_chunk=0, stream=None, xcd_group=0, graph=0, obstacle_mode=0,
-              target=None, obstacle=None, set_slices=0) -> odp_solve_opts:
+              target=None, obstacle=None, set_slices=0, space_order=1) -> odp_solve_opts:
     """target / obstacle: device tensors (or raw device addresses) for the
     target and obstacle methods: one grid, or set_slices grids (time-varying
     sets, one per tau point)."""
@@ -237,6 +238,7 @@ def make_opts(precision=32, rk_order=1, cfl=0.8, mode=ODP_BRT, dissipation=0, ma
     o.target_dev = addr(target)
     o.obstacle_dev = addr(obstacle)
     o.set_slices = set_slices
+    o.space_order = space_order
     o.dissipation = dissipation
     o.max_dt = max_dt
     o.save_all = save_all
@@ -303,7 +305,7 @@ def check_device_tensor(x, precision, npts, name):
 def solve(spec, V0, precision=32, V_init=None, tau=None, stream=None, save_all=False,
           dissipation=0, max_dt=0.0, tile_chunk=0, workspace=None, rk_order=None, cfl=None,
           mode=None, xcd_group=0, graph=0, obstacle_mode=0, target=None,
-          obstacle=None) -> SolveResult:
+          obstacle=None, space_order=1) -> SolveResult:
     """One solve of a workloads.SolveSpec with a device V0 tensor.  mode and
     obstacle_mode take the paper's method names or the odp codes; target /
     obstacle are device tensors on the grid for the methods that use them, or
@@ -325,7 +327,7 @@ def solve(spec, V0, precision=32, V_init=None, tau=None, stream=None, save_all=F
     opts = make_opts(precision, spec.rk_order if rk_order is None else rk_order,
                      spec.cfl if cfl is None else cfl, spec.mode if mode is None else mode,
                      dissipation, max_dt, 1 if save_all else 0, tile_chunk, _stream_handle(stream),
-                     xcd_group, graph, obstacle_mode, target, obstacle, slices)
+                     xcd_group, graph, obstacle_mode, target, obstacle, slices, space_order)
     out = torch.empty_like(V0)
     vall = torch.empty((len(tau),) + tuple(V0.shape), dtype=V0.dtype, device=V0.device) if save_all else None
     st = odp_hj_solve(grid, spec.dyn, V0, V_init, tau, opts, workspace, out, vall)
@@ -337,7 +339,7 @@ class BatchPlan:
     for repeated calls on the same solves."""
 
     def __init__(self, specs, V0s, outs, precision=32, tile_chunk=0, dissipation=0, max_dt=0.0,
-                 xcd_group=0):
+                 xcd_group=0, space_order=1):
         n = len(specs)
         self.n = n
         self.grids = [Grid.from_spec(s.grid) for s in specs]
@@ -359,7 +361,7 @@ class BatchPlan:
             d.V_out_dev = outs[i].data_ptr()
         s0 = specs[0]
         self.opts = make_opts(precision, s0.rk_order, s0.cfl, s0.mode, dissipation, max_dt, 0,
-                              tile_chunk, None, xcd_group)
+                              tile_chunk, None, xcd_group, space_order=space_order)
         self.stats = (odp_solve_stats * n)()
 
     def workspace_bytes(self) -> int:
@@ -375,12 +377,13 @@ class BatchPlan:
 
 
 def batch(specs, V0s, precision=32, stream=None, tile_chunk=0, dissipation=0, max_dt=0.0,
-          workspace=None, want_stats=True):
+          workspace=None, want_stats=True, space_order=1):
     """odp_hj_batch over a list of SolveSpecs (common CFL / mode; each spec's
     own RK order)."""
     import torch
     outs = [torch.empty_like(v) for v in V0s]
-    plan = BatchPlan(specs, V0s, outs, precision, tile_chunk, dissipation, max_dt)
+    plan = BatchPlan(specs, V0s, outs, precision, tile_chunk, dissipation, max_dt,
+                     space_order=space_order)
     return outs, plan.run(stream, workspace, want_stats)
 
 
@@ -393,9 +396,10 @@ class Server:
     host arrays.  rk_order of a request defaults to the server's."""
 
     def __init__(self, budget_bytes: int, max_slots: int, precision=32, rk_order=1, cfl=0.8,
-                 mode=ODP_BRT, dissipation=0, tile_chunk=0):
+                 mode=ODP_BRT, dissipation=0, tile_chunk=0, space_order=1):
         self.precision = precision
-        opts = make_opts(precision, rk_order, cfl, mode, dissipation, 0.0, 0, tile_chunk, None)
+        opts = make_opts(precision, rk_order, cfl, mode, dissipation, 0.0, 0, tile_chunk, None,
+                         space_order=space_order)
         h = ctypes.c_void_p()
         _check(lib().odp_server_create(int(budget_bytes), int(max_slots), ctypes.byref(opts),
                                        ctypes.byref(h)))

@@ -63,6 +63,14 @@ __device__ __forceinline__ T ghost_d(T vb, T diff) {
     return vb + sg * fabs(diff);
 }
 
+// The second ghost node (second-order stencils): twice as far from the edge
+// value, vb + 2 sgn(vb) |vb - vin|.
+template <typename T>
+__device__ __forceinline__ T ghost2(T vb, T vin) {
+    const T sg = T((vb > T(0)) - (vb < T(0)));
+    return vb + (T(2) * sg) * fabs(vb - vin);
+}
+
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -337,6 +345,166 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const SolveDesc *__restri
         wc = wp;
     }
     if (bad && active) atomicOr(s.flags, 1);
+}
+
+// Second-order ENO differences of one axis from the five nodes around the
+// point (ghosts already substituted): the raw one-sided differences with half
+// the smaller-magnitude second difference of the two stencils that contain
+// each of them, dl = (W_i - W_{i-1}) + sel(S_{i-1}, S_i) / 2 and
+// dr = (W_{i+1} - W_i) - sel(S_i, S_{i+1}) / 2 with S_j the second
+// difference (W_{j+1} - W_j) - (W_j - W_{j-1}); a tie takes the first.
+template <typename T>
+__device__ __forceinline__ void eno2_diffs(T l2, T l1, T c, T r1, T r2, T &dl, T &dr) {
+    const T dm = c - l1, dmm = l1 - l2, dp = r1 - c, dpp = r2 - r1;
+    const T sm = dm - dmm, s0 = dp - dm, sp = dpp - dp;
+    const T cm = fabs(sm) <= fabs(s0) ? sm : s0;
+    const T cp = fabs(s0) <= fabs(sp) ? s0 : sp;
+    dl = dm + T(0.5) * cm;
+    dr = dp - T(0.5) * cp;
+}
+
+// Stage of step k with second-order ENO differences (the Spatial Derivatives
+// subsection's ENO2; the paper pairs it with TVD-RK2), one point per lane.
+// Axis-0 neighbours (two on each side) ride in a register ring along the
+// march; the in-plane neighbours at distance 1 and 2 are loaded per plane.
+// Beyond a non-periodic edge the m-th ghost node is vb + m sgn(vb)|vb - vin|
+// (vb the edge node, vin its inner neighbour).  Rows may be padded (pitch >
+// n_last): padding lanes compute nothing that is stored.
+template <typename T, int DYN, int N>
+__global__ __launch_bounds__(kBlock) void stage_eno2_kernel(const SolveDesc *__restrict__ descs,
+                                                            const uint32_t *__restrict__ tile_solve,
+                                                            const uint32_t *__restrict__ tile_local,
+                                                            int stage, int step_from_desc,
+                                                            int64_t fixed_step, int xgroup) {
+    const uint32_t L = xcd_logical(blockIdx.x, gridDim.x, uint32_t(xgroup));
+    const uint32_t si = tile_solve ? tile_solve[L] : 0u;
+    const uint32_t lt = tile_solve ? tile_local[L] : L;
+    const SolveDesc &s = descs[si];
+
+    const int64_t nsteps = *s.nsteps;
+    const int64_t k = step_from_desc ? *s.step : fixed_step;
+    if (k >= nsteps || stage >= s.rk_order) return;
+
+    const uint32_t cid = lt / s.nqb;
+    const uint32_t qb = lt - cid * s.nqb;
+    const uint32_t q = qb * kBlock + threadIdx.x;
+    uint32_t qq = q < s.Q ? q : s.Q - 1;
+
+    int ii[N];
+    ii[0] = 0;
+    uint32_t rem = qq;
+#pragma unroll
+    for (int d = N - 1; d >= 1; --d) {
+        const uint32_t t = fdiv(rem, s.div[d]);
+        ii[d] = int(rem - t * s.div[d].d);
+        rem = t;
+    }
+    const bool active = q < s.Q && (N == 1 || ii[N - 1] < s.n[N - 1]);
+    if (N > 1 && ii[N - 1] >= s.n[N - 1]) {
+        // padding lane: stand on the row's last node, so that every
+        // neighbour offset below stays inside the row
+        qq -= uint32_t(ii[N - 1] - (s.n[N - 1] - 1));
+        ii[N - 1] = s.n[N - 1] - 1;
+    }
+
+    // in-plane offsets of the nodes at -2, -1, +1, +2 along axes 1..N-1
+    // (relative to the point; periodic wrap applied).  A node beyond a
+    // non-periodic edge is marked in gmask (bit 4d + j, j = 0..3 for -2, -1,
+    // +1, +2) and replaced by a ghost after the loads (its offset is 0).
+    int32_t off[N][4];
+    uint32_t gmask = 0;
+#pragma unroll
+    for (int d = 1; d < N; ++d) {
+        const int32_t st = s.stride[d], nd = s.n[d];
+        const bool per = (s.periodic >> d) & 1u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int sh = j < 2 ? j - 2 : j - 1;
+            const int kk = ii[d] + sh;
+            if (kk >= 0 && kk < nd) off[d][j] = sh * st;
+            else if (per) off[d][j] = ((kk + nd) % nd - ii[d]) * st;
+            else { off[d][j] = 0; gmask |= 1u << (4 * d + j); }
+        }
+    }
+    const Coef<T, DYN, N> cf = make_coef<T, DYN, N>(s, ii);
+
+    const T *W, *Vn;
+    T *out;
+    stage_buffers<T>(s, stage, k, W, Vn, out);
+    const T *Z = s.tvn ? Vn : (const T *)s.tref;
+    const T *G = (const T *)s.oref;
+    double wa, wb;
+    rk_weights(s.rk_order, stage, wa, wb);
+    const T ra = T(wa), rb = T(wb);
+    const bool last = stage == s.rk_order - 1;
+    const bool clamp = last && s.tclamp;
+    const bool obst = last && s.obst;
+    const bool tmax = s.tmax, omax = s.omax;
+    const T dt = T(s.dt_sched[k]);
+
+    const int64_t s0 = s.s0;
+    const int n0 = s.n0;
+    const bool per0 = s.periodic & 1u;
+    const int i0b = int(cid) * s.chunk;
+    const int i0e = min(i0b + s.chunk, n0);
+
+    // axis-0 node j (-2 <= j <= n0 + 1) of this lane: wrapped, or a ghost
+    auto ax0 = [&](int j) -> T {
+        if (j >= 0 && j < n0) return W[int64_t(j) * s0 + qq];
+        if (per0) return W[int64_t(j < 0 ? j + n0 : j - n0) * s0 + qq];
+        const int b = j < 0 ? 0 : n0 - 1, in = j < 0 ? 1 : n0 - 2;
+        const T vb = W[int64_t(b) * s0 + qq], vin = W[int64_t(in) * s0 + qq];
+        return (j == -1 || j == n0) ? ghost(vb, vin) : ghost2(vb, vin);
+    };
+    T r0 = ax0(i0b - 2), r1 = ax0(i0b - 1), r2 = ax0(i0b), r3 = ax0(i0b + 1), r4;
+    int bad = 0;
+    for (int i0 = i0b; i0 < i0e; ++i0) {
+        r4 = ax0(i0 + 2);
+        const T wc = r2;
+        const T *plane = W + int64_t(i0) * s0 + qq;
+        Acc<T> acc{T(0), T(0)};
+        {
+            T dl, dr;
+            eno2_diffs(r0, r1, wc, r3, r4, dl, dr);
+            acc_axis<T, DYN, N>(cf, 0, dl, dr, acc);
+        }
+#pragma unroll
+        for (int d = 1; d < N; ++d) {
+            T l2 = plane[off[d][0]], l1 = plane[off[d][1]];
+            T p1 = plane[off[d][2]], p2 = plane[off[d][3]];
+            const uint32_t gm = (gmask >> (4 * d)) & 15u;
+            if (gm) {
+                // near a non-periodic edge: the edge node is the point or its
+                // inner neighbour, both loaded above
+                if (gm & 2u) { l1 = ghost(wc, p1); l2 = ghost2(wc, p1); }
+                else if (gm & 1u) l2 = ghost(l1, wc);
+                if (gm & 4u) { p1 = ghost(wc, l1); p2 = ghost2(wc, l1); }
+                else if (gm & 8u) p2 = ghost(p1, wc);
+            }
+            T dl, dr;
+            eno2_diffs(l2, l1, wc, p1, p2, dl, dr);
+            acc_axis<T, DYN, N>(cf, d, dl, dr, acc);
+        }
+        const T Lh = acc_finish<T, DYN, N>(cf, acc);
+        const int64_t o = int64_t(i0) * s0 + qq;
+        T v = fma_t(dt, Lh, wc);
+        if (wa != 0.0) v = fma_t(ra, Vn[o], rb * v);
+        if (clamp) {
+            const T z = Z[o];
+            if (tmax ? z > v : z < v) v = z;
+        }
+        if (obst) {
+            const T g = G[o];
+            if (omax ? g > v : g < v) v = g;
+        }
+        bad |= active && !isfinite(v);
+        if (active) out[o] = v;
+        r0 = r1;
+        r1 = r2;
+        r2 = r3;
+        r3 = r4;
+    }
+    if (bad) atomicOr(s.flags, 1);
 }
 
 // VEC consecutive points of the last axis per thread (16-byte loads and
@@ -934,7 +1102,11 @@ template <typename T, int DYN, int N, int VEC>
 static hipError_t launch_stage_t(int kind, const SolveDesc *d, const uint32_t *ts, const uint32_t *tl,
                                  uint32_t nblocks, int stage, int from_desc, int64_t step, int xg,
                                  hipStream_t st) {
-    if constexpr (N == 1) {
+    if (kind & 16) {
+        // second-order ENO (one point per lane; method flags at run time)
+        hipLaunchKernelGGL((stage_eno2_kernel<T, DYN, N>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl,
+                           stage, from_desc, step, xg);
+    } else if constexpr (N == 1) {
         hipLaunchKernelGGL((stage_kernel<T, DYN, N>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl,
                            stage, from_desc, step, xg);
     } else {

@@ -59,6 +59,10 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         it.ppad = it.qpad * it.g->n[0];
         it.vec = choose_vec(it.g, prec, it.dyn.id, it.pitch);
         it.lds = uses_lds(it.g->ndim, it.pitch, it.vec);
+        if (opts.space_order == 2) {  // second-order ENO: one point per lane
+            it.vec = 1;
+            it.lds = 0;
+        }
         total += it.ppad;
     }
     for (auto &it : items) {
@@ -329,7 +333,7 @@ int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t
         const uint32_t *ts = tsd ? tsd + gr.tile_base : nullptr;
         const uint32_t *tl = tld ? tld + gr.tile_base : nullptr;
         for (int j = 0; j < gr.rk; ++j) {
-            if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, stage_kind(gr.rk, j, mk, gr.lds), descs,
+            if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, stage_kind(gr.rk, j, mk, gr.lds, p.opts.space_order == 2), descs,
                                              ts, tl, nb, j, 0, k, p.xcd_group, st),
                                 "stage")))
                 return rc;

@@ -82,6 +82,7 @@ int validate_opts(const odp_solve_opts *o) {
     if ((o->obstacle_mode != 0) != (o->obstacle_dev != nullptr))
         return set_error(ODP_EINVAL, o->obstacle_mode ? "the obstacle method needs obstacle_dev"
                                                       : "obstacle_dev is set but obstacle_mode is 0");
+    if (o->space_order < 0 || o->space_order > 2) return set_error(ODP_EINVAL, "space_order must be 0, 1 or 2");
     if (o->set_slices < 0 || (o->set_slices > 1 && !o->target_dev && !o->obstacle_dev))
         return set_error(ODP_EINVAL, "set_slices needs a target or obstacle array");
     if (o->dissipation != 0 && o->dissipation != 1) return set_error(ODP_EINVAL, "dissipation must be 0 or 1");

@@ -68,9 +68,10 @@ int method_arrays(const odp_solve_opts &o);
 int method_kind(const odp_solve_opts &o);
 // Stage kind for launch_stage: bit 0 reads V^n, bits 1 and 3 the comparisons
 // of the computation method (method_kind, last stage only), bit 2 the LDS
-// plane exchange (every listed solve must have SolveDesc::lds set).
-inline int stage_kind(int rk_order, int stage, int mkind, int lds = 0) {
-    return (stage > 0 ? 1 : 0) | (stage == rk_order - 1 ? mkind : 0) | (lds ? 4 : 0);
+// plane exchange (every listed solve must have SolveDesc::lds set), bit 4
+// second-order ENO differences (the point-per-lane kernel).
+inline int stage_kind(int rk_order, int stage, int mkind, int lds = 0, int eno2 = 0) {
+    return (stage > 0 ? 1 : 0) | (stage == rk_order - 1 ? mkind : 0) | (lds ? 4 : 0) | (eno2 ? 16 : 0);
 }
 // Whether a solve of this shape uses the LDS plane exchange.
 inline int uses_lds(int ndim, int64_t pitch, int vec) { return ndim >= 3 && pitch <= 128 * int64_t(vec) ? 1 : 0; }

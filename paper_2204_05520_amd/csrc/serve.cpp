@@ -442,7 +442,7 @@ int enqueue_tick(odp_server *s, const std::vector<Group> &groups, hipEvent_t *do
     for (int m = 0; m < kStepsPerTick; ++m) {
         for (const Group &g : groups) {
             for (int j = 0; j < g.rk; ++j) {
-                if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, stage_kind(g.rk, j, mk, g.lds),
+                if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, stage_kind(g.rk, j, mk, g.lds, o.space_order == 2),
                                                  s->d_slots, s->d_tiles + g.tile_base,
                                                  s->d_tiles + s->tile_cap + g.tile_base, g.tiles, j, 1, 0,
                                                  o.xcd_group, s->st),

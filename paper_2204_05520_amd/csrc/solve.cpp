@@ -179,7 +179,8 @@ static int batch_items(int nsolves, const odp_solve_desc *descs, const odp_solve
         // on padded copies, so that every member runs the widest kernel
         const int64_t nl = d.grid->n[d.grid->ndim - 1];
         const int64_t w = common->precision == 32 ? 4 : 2;
-        if (d.grid->ndim >= 2 && d.dyn.id != ODP_DYN_SINGLE_INTEGRATOR && nl % w != 0) {
+        if (d.grid->ndim >= 2 && d.dyn.id != ODP_DYN_SINGLE_INTEGRATOR && nl % w != 0 &&
+            common->space_order != 2) {
             items.back().pitch = int((nl + w - 1) / w * w);
             items.back().pad_io = true;
         }

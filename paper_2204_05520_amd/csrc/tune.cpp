@@ -28,7 +28,7 @@ std::map<std::string, int> g_cache;
 
 std::string shape_key(const std::vector<PlanItem> &items, const odp_solve_opts &o) {
     std::string k = "p" + std::to_string(o.precision) + "m" + std::to_string(o.mode) + "o" +
-                    std::to_string(o.obstacle_mode) + "r" +
+                    std::to_string(o.obstacle_mode) + "s" + std::to_string(o.space_order) + "r" +
                     std::to_string(o.rk_order) + "x" + std::to_string(o.xcd_group) + "|";
     for (const PlanItem &it : items) {
         k += std::to_string(it.dyn.id) + ":" + std::to_string(it.rk_order) + ":" + std::to_string(it.pitch) +

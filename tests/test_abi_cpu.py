@@ -73,7 +73,8 @@ def _solve_rc(spec, precision=32, **kw):
                          kw.pop("mode", spec.mode), kw.pop("diss", 0), kw.pop("max_dt", 0.0),
                          kw.pop("save_all", 0), kw.pop("tile_chunk", 0), None,
                          obstacle_mode=kw.pop("obstacle_mode", 0), target=kw.pop("target", None),
-                         obstacle=kw.pop("obstacle", None), set_slices=kw.pop("set_slices", 0))
+                         obstacle=kw.pop("obstacle", None), set_slices=kw.pop("set_slices", 0),
+                         space_order=kw.pop("space_order", 1))
     V0 = kw.pop("V0", ctypes.c_void_p(0x1000))
     Vout = kw.pop("Vout", ctypes.c_void_p(0x2000))
     rc = odp.lib().odp_hj_solve(grid.handle, ctypes.byref(d), V0, None, t, len(tau),
@@ -107,6 +108,8 @@ def _solve_rc(spec, precision=32, **kw):
     ({"set_slices": 2}, "set_slices needs"),
     ({"set_slices": -1}, "set_slices needs"),
     ({"mode": 5, "target": 0x3000, "set_slices": 3}, "set_slices must be"),
+    ({"space_order": 3}, "space_order"),
+    ({"space_order": -1}, "space_order"),
 ])
 def test_solve_rejects_before_gpu(lib, kw, msg):
     spec = W.config_dubins3d(n=(10, 10, 8))

@@ -1,0 +1,170 @@
+"""GPU parity of the second-order path: ENO2 spatial differences (the
+Spatial Derivatives subsection) with TVD-RK2 (the paper's second-order row)
+and the other RK orders, through the C ABI against the float64 oracle.
+
+Bars: float64 within 1e-9 S and float32 within 1e-4 S of the oracle on
+whole grids (ragged tails, several tiles, non-periodic and periodic axes,
+edges within two nodes of every face), the same step count.  The ENO
+stencil choice is a decision taken in floating point: a one-step check
+compares a float32 step with the oracle taking its choices in float32 from
+the same float32 input.
+"""
+import numpy as np
+import pytest
+
+from paper_2204_05520_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {64: 1e-9, 32: 1e-4}
+
+
+@pytest.fixture(scope="module")
+def odp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2204_05520_amd as odp
+    odp.lib()
+    return odp
+
+
+def _dev(x, prec):
+    import torch
+    return torch.tensor(x, dtype=torch.float64 if prec == 64 else torch.float32, device="cuda:0")
+
+
+def _compare(odp, oracle_mod, spec, precs=(64, 32), **kw):
+    import torch
+    V0 = W.make_v0(spec)
+    okw = {k: v for k, v in kw.items() if k in ("tmode", "omode", "target", "obstacle")}
+    ref = oracle_mod.solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=spec.rk_order, cfl=spec.cfl,
+                           brt=spec.mode == W.BRT, space_order=2, **okw)
+    S = spec.grid.domain_scale()
+    for prec in precs:
+        print(f"[gpu] eno2 {spec.name} n={spec.grid.n} rk={spec.rk_order} fp{prec}", flush=True)
+        res = odp.solve(spec, _dev(V0, prec), precision=prec, space_order=2)
+        torch.cuda.synchronize()
+        err = float(np.abs(res.V.double().cpu().numpy() - ref.V).max())
+        print(f"    steps gpu={res.stats['steps']} oracle={ref.steps} max|err|/S={err / S:.3e}", flush=True)
+        assert res.stats["steps"] == ref.steps
+        assert err <= TOL[prec] * S, (prec, err / S)
+    return ref
+
+
+def _rk(spec, r):
+    spec.rk_order = r
+    return spec
+
+
+CASES = [
+    ("si1d_300_rk2", lambda: W.single_integrator(1, 300, 1.0, [0.6], W.MINIMISE, 0.4, rk_order=2)),
+    ("si1d_257_periodic_rk3", lambda: W.single_integrator(1, 257, 0.5, [-0.3], W.MAXIMISE, 0.6,
+                                                          periodic=True, rk_order=3)),
+    ("si2d_61_rk2", lambda: W.single_integrator(2, 61, 1.0, [0.5, -0.3], W.MINIMISE, 0.4, brt=True,
+                                                rk_order=2)),
+    ("si3d_23_rk1", lambda: W.single_integrator(3, 23, 1.0, [0.2, -0.3, 0.4], W.MAXIMISE, 0.5)),
+    ("dubins3d_37x29x22_rk2", lambda: _rk(W.config_dubins3d(n=(37, 29, 22), T=0.8), 2)),
+    ("dubins3d_60x60x36_rk2", lambda: _rk(W.config_dubins3d(), 2)),
+    ("dyncar4d_22x21x19x24_rk2", lambda: _rk(W.config_dyncar4d(n=[22, 21, 19, 24], T=0.5), 2)),
+    ("game6d_9x8x8x7x9x8_rk2", lambda: W.config_game6d(n=[9, 8, 8, 7, 9, 8], T=0.5)),
+]
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+def test_eno2_parity(odp, oracle_mod, name, mk):
+    ref = _compare(odp, oracle_mod, mk())
+    first = oracle_mod.solve_spec(mk())
+    # the second-order solve differs from the first-order one
+    assert np.abs(first.V - ref.V).max() > 1e-4
+
+
+def test_eno2_one_step_decisions(odp, oracle_mod):
+    """One RK1 step in float32 from a float32 value function with kinks:
+    the oracle takes its ENO choices in float32 from the same input, so the
+    outputs agree to float32 rounding of the update."""
+    import torch
+    spec = W.config_dyncar4d(n=[17, 15, 13, 20], T=0.5)
+    spec.rk_order = 1
+    rng = np.random.default_rng(7)
+    V = W.make_v0(spec) + 0.05 * rng.standard_normal(tuple(spec.grid.n))
+    V = V.astype(np.float32).astype(np.float64)
+    _, dt = oracle_mod.cfl_dt(spec.grid, spec.dyn, spec.cfl)
+    tau = [0.0, 0.5 * dt]
+    res = odp.solve(spec, _dev(V, 32), precision=32, tau=tau, mode="None", space_order=2)
+    torch.cuda.synchronize()
+    assert res.stats["steps"] == 1
+    got = res.V.double().cpu().numpy().reshape(-1)
+    idx = np.arange(V.size)
+    ref32 = oracle_mod.step_at(spec.grid, spec.dyn, V, V, tau[1], idx, brt=False, space_order=2,
+                               eno_f32=True)
+    ref64 = oracle_mod.step_at(spec.grid, spec.dyn, V, V, tau[1], idx, brt=False, space_order=2)
+    scale = np.abs(V).max()
+    err = np.abs(got - ref32).max() / scale
+    print(f"    one step: |gpu - oracle(f32 choices)|/max|V| = {err:.3e}; choices that differ "
+          f"between float32 and float64: {int((np.abs(ref32 - ref64) > 1e-6 * scale).sum())}",
+          flush=True)
+    assert err < 2e-6
+
+
+def test_eno2_methods_and_restart(odp, oracle_mod):
+    """The computation methods run on the second-order path too."""
+    import torch
+    spec = _rk(W.config_dubins3d(n=(37, 29, 22), T=0.8), 2)
+    V0 = W.make_v0(spec)
+    target, obstacle = W.reach_avoid_sets(spec)
+    S = spec.grid.domain_scale()
+    ref = oracle_mod.solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=2, cfl=spec.cfl,
+                           tmode="minVWithVTarget", omode="maxVWithObstacle", target=target,
+                           obstacle=obstacle, space_order=2)
+    for prec in (64, 32):
+        res = odp.solve(spec, _dev(V0, prec), precision=prec, mode="minVWithVTarget",
+                        obstacle_mode="maxVWithObstacle", target=_dev(target, prec),
+                        obstacle=_dev(obstacle, prec), space_order=2)
+        torch.cuda.synchronize()
+        err = float(np.abs(res.V.double().cpu().numpy() - ref.V).max())
+        assert err <= TOL[prec] * S, (prec, err / S)
+
+
+def test_eno2_launch_shapes_bitwise(odp):
+    """Every axis-0 chunking and the batch give the same bits (one padded
+    batch member is not padded on this path: its rows are read as they are)."""
+    import torch
+    spec = _rk(W.config_dyncar4d(n=[13, 17, 9, 20], T=0.2), 2)
+    V0 = _dev(W.make_v0(spec), 32)
+    outs = [odp.solve(spec, V0, precision=32, tile_chunk=c, space_order=2).V.cpu() for c in (1, 3, 13)]
+    assert all(torch.equal(o, outs[0]) for o in outs[1:])
+    specs = [_rk(W.config_dubins3d(n=(21, 19, 15), T=0.5), 2), _rk(W.config_dubins3d(n=(17, 23, 13), T=0.7), 2)]
+    V0s = [_dev(W.make_v0(s), 32) for s in specs]
+    bouts, _ = odp.batch(specs, V0s, precision=32, space_order=2)
+    for s, v0, o in zip(specs, V0s, bouts):
+        one = odp.solve(s, v0, precision=32, space_order=2).V
+        torch.cuda.synchronize()
+        assert torch.equal(o, one), s.grid.n
+
+
+def test_eno2_server_equals_alone(odp):
+    """Served second-order requests (rows padded to the vector width on the
+    server's side) equal the same requests solved alone."""
+    import time
+    import torch
+    srv = odp.Server(1 << 30, 4, precision=32, rk_order=2, space_order=2)
+    try:
+        specs = [W.config_dubins3d(n=(21, 19, 15), T=0.5), W.config_dubins3d(n=(17, 23, 13), T=0.7)]
+        tickets = [srv.submit(s, W.make_v0(s), rk_order=2) for s in specs]
+        for s, t in zip(specs, tickets):
+            out = np.empty(tuple(s.grid.n), np.float32)
+            t0 = time.time()
+            while True:
+                rc, _ = srv.poll(t, out)
+                if rc != odp.ODP_PENDING:
+                    break
+                assert time.time() - t0 < 60
+                time.sleep(0.002)
+            assert rc == odp.ODP_OK
+            s.rk_order = 2
+            one = odp.solve(s, _dev(W.make_v0(s), 32), precision=32, space_order=2).V
+            torch.cuda.synchronize()
+            assert np.array_equal(out, one.cpu().numpy())
+    finally:
+        srv.close()
