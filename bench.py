@@ -10,6 +10,9 @@ Default workload: the 4D dynamic car, 80^4 nodes on [-5,5]^2 x [0,4] x
 [-pi,pi), |a| <= 1, |w| <= 1, disc target r = 0.5, TVD-RK3, CFL 0.8,
 horizon 3 s, tube (BRT).  Other workloads (--workload): dubins3d (60x60x36,
 float64 form), game6d (36^6, RK2), batch (512 Dubins solves), serve.
+--space-order 2 runs a single-solve workload with second-order ENO
+differences and, unless --rk says otherwise, TVD-RK2 (the paper's
+second-order pairing).
 
 Prints one JSON line.
 """
@@ -42,11 +45,12 @@ def measured_traffic(kernel: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def time_solves(odp, spec, V0, precision, steps, warmup, stream, tile_chunk=0, xcd_group=0):
+def time_solves(odp, spec, V0, precision, steps, warmup, stream, tile_chunk=0, xcd_group=0,
+                space_order=1):
     import torch
     grid = odp.Grid.from_spec(spec.grid)
     opts = odp.make_opts(precision, spec.rk_order, spec.cfl, spec.mode, 0, 0.0, 0, tile_chunk,
-                         odp._stream_handle(stream), xcd_group)
+                         odp._stream_handle(stream), xcd_group, space_order=space_order)
     wsb = odp.odp_hj_workspace_bytes(grid, spec.dyn, spec.tau, opts)
     ws = torch.empty(wsb, dtype=torch.uint8, device=V0.device)
     out = torch.empty_like(V0)
@@ -66,7 +70,7 @@ def time_solves(odp, spec, V0, precision, steps, warmup, stream, tile_chunk=0, x
     return wall, stats, kernel_ms, out
 
 
-def cpu_baseline(spec, V0_np, budget_steps=2):
+def cpu_baseline(spec, V0_np, budget_steps=2, space_order=1):
     """The oracle as it stands on the host cores, on a bounded sample: the
     first `budget_steps` CFL steps of the same workload."""
     import oracle
@@ -75,12 +79,13 @@ def cpu_baseline(spec, V0_np, budget_steps=2):
     tau = [0.0, budget_steps * dt * (1 - 1e-12)]
     t0 = time.perf_counter()
     res = oracle.solve(spec.grid, spec.dyn, V0_np, tau, rk_order=spec.rk_order, cfl=spec.cfl,
-                       brt=spec.mode == 1)
+                       brt=spec.mode == 1, space_order=space_order)
     wall = time.perf_counter() - t0
     pts = spec.grid.npts * res.steps
     return {"value": pts / wall, "unit": "grid-point updates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"first {res.steps} CFL steps (float64, RK{spec.rk_order}) of the same "
+            "sample": f"first {res.steps} CFL steps (float64, RK{spec.rk_order}"
+                      f"{', ENO2' if space_order == 2 else ''}) of the same "
                       f"{'x'.join(map(str, spec.grid.n))} solve, {wall:.1f} s"}
 
 
@@ -97,6 +102,14 @@ def bench_single(args, W, odp):
     else:
         spec = W.config_dubins3d()
         kname, precs = "stage_dubins3d", (64, 32)
+    if args.rk:
+        spec.rk_order = args.rk
+    if args.space_order == 2:
+        spec.rk_order = args.rk or 2
+        spec.name = spec.name.replace("_rk", "_eno2_rk").rsplit("_rk", 1)[0] + f"_rk{spec.rk_order}_brt"
+        kname = kname.replace("stage_", "stage_eno2_")
+    elif args.rk:
+        spec.name = spec.name.rsplit("_rk", 1)[0] + f"_rk{spec.rk_order}_brt"
     stream = torch.cuda.Stream()
     results = {}
     V0_np = None
@@ -109,7 +122,7 @@ def bench_single(args, W, odp):
             V0 = torch.tensor(V0_np, dtype=dt, device=dev)
         with torch.cuda.stream(stream):
             wall, st, kms, out = time_solves(odp, spec, V0, prec, args.steps, args.warmup, stream,
-                                             args.tile_chunk)
+                                             args.tile_chunk, space_order=args.space_order)
         P = spec.grid.npts
         nsteps = st.steps
         nlaunch = nsteps * spec.rk_order
@@ -132,7 +145,8 @@ def bench_single(args, W, odp):
     traffic = measured_traffic(f"{kname}_fp{head}", spec.name)
     roof = {"bound": "hbm", "achieved": r["achieved_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": r["achieved_gbps"] / HBM_PEAK_GBPS, "traffic": traffic,
-            "kernel": f"stage_kernel fp{head}", "avg_launch_us": r["avg_launch_us"],
+            "kernel": f"{'stage_eno2_kernel' if args.space_order == 2 else 'stage_kernel'} fp{head}",
+            "avg_launch_us": r["avg_launch_us"],
             "alg_bytes_per_launch": r["alg_bytes_per_launch"]}
     line = {
         "metric": METRIC, "value": r["pt_updates_per_s"], "unit": "grid-point updates/s",
@@ -142,6 +156,7 @@ def bench_single(args, W, odp):
         "config": {"workload": spec.name, "grid": spec.grid.n, "rk_order": spec.rk_order,
                    "tiles": "autotuned" if args.tile_chunk == -1 else args.tile_chunk,
                    "cfl": spec.cfl, "horizon": spec.tau[-1], "mode": "BRT",
+                   "space_order": args.space_order,
                    "cfl_steps_per_solve": r["steps"]},
         "roofline": roof,
     }
@@ -155,7 +170,7 @@ def bench_single(args, W, odp):
         if V0_np is None:
             V0_np = W.make_v0(spec) if spec.grid.npts <= 200_000_000 else None
         if V0_np is not None:
-            line["cpu_baseline"] = cpu_baseline(spec, V0_np)
+            line["cpu_baseline"] = cpu_baseline(spec, V0_np, space_order=args.space_order)
     return line
 
 
@@ -303,6 +318,10 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="first issue one plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--fp32-only", action="store_true")
+    ap.add_argument("--space-order", type=int, default=1, choices=[1, 2],
+                    help="2: second-order ENO differences (single-solve workloads)")
+    ap.add_argument("--rk", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="Runge-Kutta order override (0: the workload's; 2 with --space-order 2)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU sharding is a design "
