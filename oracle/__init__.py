@@ -61,6 +61,12 @@ def _load():
             ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
             _dp, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp,
             ctypes.c_int, ctypes.c_int, ctypes.c_long, _lp, _dp]
+        lib.oracle_alpha_box.restype = ctypes.c_int
+        lib.oracle_alpha_box.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+                                         ctypes.c_long, _dp, _dp, _dp, _dp, _dp]
+        lib.oracle_hamiltonian.restype = ctypes.c_int
+        lib.oracle_hamiltonian.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           _dp, ctypes.c_long, _dp, _dp, _dp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         _lib = lib
@@ -227,3 +233,34 @@ def step_at(grid, dyn, V: np.ndarray, V0: np.ndarray, dt: float, idx, rk_order=1
     if rc != 0:
         raise ValueError("oracle_step_at rejected its arguments")
     return out
+
+
+def alpha_box(dyn, ndim, z, dmin, dmax):
+    """Dissipation coefficients at states z (m x ndim) over the costate box
+    [dmin, dmax], and over all admissible inputs: (alpha_box, alpha_all)."""
+    lib = _load()
+    z = _arr(z, np.float64).reshape(-1, ndim)
+    dmin, dmax = _arr(dmin, np.float64), _arr(dmax, np.float64)
+    ab = np.empty_like(z)
+    aa = np.empty_like(z)
+    p = _params(dyn)
+    rc = lib.oracle_alpha_box(ndim, dyn.id, dyn.u_mode, dyn.d_mode, _ptr(p, _dp), z.shape[0],
+                              _ptr(z, _dp), _ptr(dmin, _dp), _ptr(dmax, _dp), _ptr(ab, _dp),
+                              _ptr(aa, _dp))
+    if rc != 0:
+        raise ValueError("oracle_alpha_box rejected its arguments")
+    return ab, aa
+
+
+def hamiltonian(dyn, ndim, z, p):
+    """p . f(z, u*(p), d*(p)) at states z for costates p (both m x ndim)."""
+    lib = _load()
+    z = _arr(z, np.float64).reshape(-1, ndim)
+    p_ = _arr(p, np.float64).reshape(-1, ndim)
+    H = np.empty(z.shape[0])
+    prm = _params(dyn)
+    rc = lib.oracle_hamiltonian(ndim, dyn.id, dyn.u_mode, dyn.d_mode, _ptr(prm, _dp), z.shape[0],
+                                _ptr(z, _dp), _ptr(p_, _dp), _ptr(H, _dp))
+    if rc != 0:
+        raise ValueError("oracle_hamiltonian rejected its arguments")
+    return H

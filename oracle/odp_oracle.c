@@ -119,7 +119,7 @@ static void og_state(const og_grid *g, const long *ii, double *z)
 
 /* ------------------------------------------------------------ dynamics */
 
-enum { OG_SI = 0, OG_DUBINS3D = 1, OG_DYNCAR4D = 2, OG_TWODUBINS6D = 3 };
+enum { OG_SI = 0, OG_DUBINS3D = 1, OG_DYNCAR4D = 2, OG_TWODUBINS6D = 3, OG_PE3D = 4 };
 
 typedef struct {
     int id;
@@ -135,6 +135,7 @@ static int og_dyn_ndim_ok(const og_dyn *dy, int ndim)
     case OG_DUBINS3D: return ndim == 3;
     case OG_DYNCAR4D: return ndim == 4;
     case OG_TWODUBINS6D: return ndim == 6;
+    case OG_PE3D: return ndim == 3;
     default: return 0;
     }
 }
@@ -175,6 +176,10 @@ static void og_opt_inputs(const og_dyn *dy, int ndim, const double *z, const dou
         u[0] = og_bang(pbar[2], dy->p[1], dy->u_mode);
         dd[0] = og_bang(pbar[5], dy->p[3], dy->d_mode);
         break;
+    case OG_PE3D: /* evader turn a: p_x y - p_y x - p_theta; pursuer turn b: p_theta */
+        u[0] = og_bang(pbar[0] * z[1] - pbar[1] * z[0] - pbar[2], dy->p[2], dy->u_mode);
+        dd[0] = og_bang(pbar[2], dy->p[3], dy->d_mode);
+        break;
     }
 }
 
@@ -205,6 +210,11 @@ static void og_dynamics(const og_dyn *dy, int ndim, const double *z, const doubl
         f[4] = dy->p[2] * sin(z[5]);
         f[5] = dd[0];
         break;
+    case OG_PE3D: /* relative pursuit-evasion: evader a, pursuer b, speeds v_a, v_b */
+        f[0] = -dy->p[0] + dy->p[1] * cos(z[2]) + u[0] * z[1];
+        f[1] = dy->p[1] * sin(z[2]) - u[0] * z[0];
+        f[2] = dd[0] - u[0];
+        break;
     }
 }
 
@@ -225,6 +235,7 @@ static void og_alpha(const og_dyn *dy, int ndim, const double *z, double *alpha)
     case OG_DUBINS3D: ub[0] = dy->p[1]; nu = 1; break;
     case OG_DYNCAR4D: ub[0] = dy->p[0]; ub[1] = dy->p[1]; nu = 2; break;
     case OG_TWODUBINS6D: ub[0] = dy->p[1]; db[0] = dy->p[3]; nu = 1; nd = 1; break;
+    case OG_PE3D: ub[0] = dy->p[2]; db[0] = dy->p[3]; nu = 1; nd = 1; break;
     }
     for (int d = 0; d < ndim; ++d) alpha[d] = 0.0;
     int nv = 1 << (nu + nd);
@@ -237,6 +248,94 @@ static void og_alpha(const og_dyn *dy, int ndim, const double *z, double *alpha)
             if (fabs(f[d]) > alpha[d]) alpha[d] = fabs(f[d]);
     }
 }
+
+/* Switching functions of the box inputs (controls first, then
+ * disturbances) at z: input j is bang-bang on the sign of c[j] . p.  coord[j]
+ * is k when c[j] is the unit vector e_k, else -1.  Returns the input count. */
+static int og_switching(const og_dyn *dy, int ndim, const double *z, double c[2][OG_MAXD],
+                        int *coord, double *bound, int *maximise)
+{
+    for (int j = 0; j < 2; ++j)
+        for (int d = 0; d < ndim; ++d) c[j][d] = 0.0;
+    switch (dy->id) {
+    case OG_DUBINS3D:
+        c[0][2] = 1.0; coord[0] = 2; bound[0] = dy->p[1]; maximise[0] = dy->u_mode;
+        return 1;
+    case OG_DYNCAR4D:
+        c[0][2] = 1.0; coord[0] = 2; bound[0] = dy->p[0]; maximise[0] = dy->u_mode;
+        c[1][3] = 1.0; coord[1] = 3; bound[1] = dy->p[1]; maximise[1] = dy->u_mode;
+        return 2;
+    case OG_TWODUBINS6D:
+        c[0][2] = 1.0; coord[0] = 2; bound[0] = dy->p[1]; maximise[0] = dy->u_mode;
+        c[1][5] = 1.0; coord[1] = 5; bound[1] = dy->p[3]; maximise[1] = dy->d_mode;
+        return 2;
+    case OG_PE3D:
+        c[0][0] = z[1]; c[0][1] = -z[0]; c[0][2] = -1.0; coord[0] = -1;
+        bound[0] = dy->p[2]; maximise[0] = dy->u_mode;
+        c[1][2] = 1.0; coord[1] = 2; bound[1] = dy->p[3]; maximise[1] = dy->d_mode;
+        return 2;
+    }
+    return 0;
+}
+
+/* alpha_d(z) over the costate box (Algorithm 1's dissipation: the largest
+ * |dH/dp_d| = |f_d(z, u*(p), d*(p))| for p in [dmin, dmax]).  Every input is
+ * bang-bang on the sign of its switching function, so only the input
+ * patterns (one sign per input) that some p in the box realises count.  A
+ * pattern is tested by restricting the box: a switching function that is a
+ * single coordinate p_k keeps p_k >= 0 (or p_k <= 0, closed at 0) of that
+ * coordinate's interval; a general linear form (at most one per dynamics
+ * here) is then ranged over the restricted box term by term, and its sign
+ * condition holds if the range reaches it (>= 0: max >= 0; < 0: min < 0). */
+static void og_alpha_box(const og_dyn *dy, int ndim, const double *z, const double *dmin,
+                         const double *dmax, double *alpha)
+{
+    double c[2][OG_MAXD], bound[2];
+    int coord[2], maximise[2];
+    const int ni = og_switching(dy, ndim, z, c, coord, bound, maximise);
+    const int nu = (dy->id == OG_TWODUBINS6D || dy->id == OG_PE3D) ? 1 : ni;
+    for (int d = 0; d < ndim; ++d) alpha[d] = 0.0;
+    for (int pat = 0; pat < (1 << ni); ++pat) {
+        double lo[OG_MAXD], hi[OG_MAXD];
+        for (int d = 0; d < ndim; ++d) { lo[d] = dmin[d]; hi[d] = dmax[d]; }
+        int ok = 1;
+        for (int j = 0; j < ni && ok; ++j) {
+            if (coord[j] < 0) continue;
+            const int k = coord[j];
+            if ((pat >> j) & 1) { if (lo[k] < 0.0) lo[k] = 0.0; }
+            else                { if (hi[k] > 0.0) hi[k] = 0.0; }
+            if (lo[k] > hi[k] || (!((pat >> j) & 1) && !(lo[k] < 0.0))) ok = 0;
+        }
+        for (int j = 0; j < ni && ok; ++j) {
+            if (coord[j] >= 0) continue;
+            double smin = 0.0, smax = 0.0;
+            for (int d = 0; d < ndim; ++d) {
+                const double a = c[j][d] * lo[d], b = c[j][d] * hi[d];
+                smin += a < b ? a : b;
+                smax += a < b ? b : a;
+            }
+            if ((pat >> j) & 1) ok = smax >= 0.0;
+            else ok = smin < 0.0;
+        }
+        if (!ok) continue;
+        double u[4] = {0}, dd[4] = {0}, f[OG_MAXD];
+        for (int j = 0; j < ni; ++j) {
+            const double v = og_bang(((pat >> j) & 1) ? 1.0 : -1.0, bound[j], maximise[j]);
+            if (j < nu) u[j] = v; else dd[j - nu] = v;
+        }
+        og_dynamics(dy, ndim, z, u, dd, f);
+        for (int d = 0; d < ndim; ++d)
+            if (fabs(f[d]) > alpha[d]) alpha[d] = fabs(f[d]);
+    }
+}
+
+/* Dynamics whose dissipation is taken over the costate box: the relative
+ * pursuit-evasion model, whose evader input enters three axes through a
+ * switching function that mixes the costate with the state.  (For the other
+ * box-input dynamics every input drives one axis with |f_d| equal to its
+ * bound whatever its sign, so the box gives the all-inputs alpha; a pin
+ * checks that equality.) */
+static int og_box_dynamics(const og_dyn *dy) { return dy->id == OG_PE3D; }
 
 /* --------------------------------------------------------------- fields */
 
@@ -295,20 +394,13 @@ static int og_eno_first_f32(double w0, double w1, double w2, double w3)
     return fabsf(x) <= fabsf(y);
 }
 
-/* Lax-Friedrichs numerical Hamiltonian at point idx (one pass of the body
- * of Algorithm 1's grid loops for one point). alpha_glob != NULL selects the
- * global-alpha approximation. */
-static double og_hhat(const og_grid *g, const og_dyn *dy, const og_field *W, long idx,
-                      const double *alpha_glob, int order, int eno_f32)
+/* One-sided derivatives p-, p+ and the costate pbar = (p+ + p-)/2 at point
+ * idx (multi-index ii), first-order or ENO2 (order 2). */
+static void og_costate(const og_grid *g, const og_field *W, long idx, const long *ii, int order,
+                       int eno_f32, double *pm, double *pp, double *pbar)
 {
     const int N = g->ndim;
-    long ii[OG_MAXD];
-    double z[OG_MAXD] = {0};
-    og_unravel(g, idx, ii);
-    og_state(g, ii, z);
-
     double wc = W->get(W, idx);
-    double pm[OG_MAXD], pp[OG_MAXD], pbar[OG_MAXD];
     for (int d = 0; d < N; ++d) {
         double wl = og_neighbor(g, W, idx, ii, d, -1);
         double wr = og_neighbor(g, W, idx, ii, d, +1);
@@ -331,6 +423,43 @@ static double og_hhat(const og_grid *g, const og_dyn *dy, const og_field *W, lon
         pp[d] = dp / g->dx[d];
         pbar[d] = 0.5 * (pp[d] + pm[d]);
     }
+}
+
+/* Costate box of Algorithm 1: D_min, D_max = the smallest and largest pbar_d
+ * over the grid, for field W (box[0..N) min, box[N..2N) max). */
+static void og_costate_box(const og_grid *g, const og_field *W, int order, double *box)
+{
+    const int N = g->ndim;
+    for (int d = 0; d < N; ++d) {
+        box[d] = INFINITY;
+        box[N + d] = -INFINITY;
+    }
+    for (long i = 0; i < g->npts; ++i) {
+        long ii[OG_MAXD] = {0};
+        double pm[OG_MAXD], pp[OG_MAXD], pbar[OG_MAXD];
+        og_unravel(g, i, ii);
+        og_costate(g, W, i, ii, order, 0, pm, pp, pbar);
+        for (int d = 0; d < N; ++d) {
+            if (pbar[d] < box[d]) box[d] = pbar[d];
+            if (pbar[d] > box[N + d]) box[N + d] = pbar[d];
+        }
+    }
+}
+
+/* Lax-Friedrichs numerical Hamiltonian at point idx (one pass of the body
+ * of Algorithm 1's grid loops for one point). alpha_glob != NULL selects the
+ * global-alpha approximation; box != NULL (dynamics whose dissipation depends
+ * on the costate) gives the costate box for alpha. */
+static double og_hhat(const og_grid *g, const og_dyn *dy, const og_field *W, long idx,
+                      const double *alpha_glob, int order, int eno_f32, const double *box)
+{
+    const int N = g->ndim;
+    long ii[OG_MAXD] = {0};
+    double z[OG_MAXD] = {0};
+    og_unravel(g, idx, ii);
+    og_state(g, ii, z);
+    double pm[OG_MAXD], pp[OG_MAXD], pbar[OG_MAXD];
+    og_costate(g, W, idx, ii, order, eno_f32, pm, pp, pbar);
 
     double u[OG_MAXD] = {0}, dd[OG_MAXD] = {0}, f[OG_MAXD];
     og_opt_inputs(dy, N, z, pbar, u, dd);
@@ -341,6 +470,8 @@ static double og_hhat(const og_grid *g, const og_dyn *dy, const og_field *W, lon
     double alpha[OG_MAXD];
     if (alpha_glob) {
         for (int d = 0; d < N; ++d) alpha[d] = alpha_glob[d];
+    } else if (box) {
+        og_alpha_box(dy, N, z, box, box + N, alpha);
     } else {
         og_alpha(dy, N, z, alpha);
     }
@@ -500,9 +631,14 @@ int oracle_hj_solve(int ndim, const long *n, const double *lo, const double *hi,
             double a, b;
             og_rk_weights(rk_order, s, &a, &b);
             og_field Wf = {og_get_array, W, NULL, 0};
+            /* costate box of this Hamiltonian evaluation (dynamics whose
+             * dissipation depends on it) */
+            double box[2 * OG_MAXD];
+            const int use_box = og_box_dynamics(&dy) && !aglob;
+            if (use_box) og_costate_box(&g, &Wf, space_order, box);
 #pragma omp parallel for schedule(static)
             for (long i = 0; i < P; ++i) {
-                double hh = og_hhat(&g, &dy, &Wf, i, aglob, space_order, 0);
+                double hh = og_hhat(&g, &dy, &Wf, i, aglob, space_order, 0, use_box ? box : NULL);
                 out[i] = og_combine(a, b, Vn[i], W[i], dt, hh);
             }
             W = out;
@@ -561,6 +697,7 @@ typedef struct {
     const double *aglob;
     int order;
     int eno_f32;
+    const double *box;
 } og_step_ctx;
 
 /* Value of Runge-Kutta stage `level` (0 = V^n) at idx, evaluated on demand
@@ -572,7 +709,7 @@ static double og_stage_value(const og_field *self, long idx)
     og_field prev = {og_stage_value, NULL, c, self->level - 1};
     double a, b;
     og_rk_weights(c->rk_order, self->level - 1, &a, &b);
-    double hh = og_hhat(c->g, c->dy, &prev, idx, c->aglob, c->order, c->eno_f32);
+    double hh = og_hhat(c->g, c->dy, &prev, idx, c->aglob, c->order, c->eno_f32, c->box);
     return og_combine(a, b, c->Vn[idx], og_stage_value(&prev, idx), c->dt, hh);
 }
 
@@ -592,12 +729,63 @@ int oracle_step_at(int ndim, const long *n, const double *lo, const double *hi,
     if (rk_order < 1 || rk_order > 3) return -1;
     if (space_order != 1 && space_order != 2) return -1;
     if (!og_modes_ok(tmode, omode, target, obstacle)) return -1;
-    og_step_ctx c = {&g, &dy, V, rk_order, dt, alpha_glob, space_order, eno_f32};
+    /* a costate box needs the whole stage input: one stage only (RK1) */
+    double box[2 * OG_MAXD];
+    const int use_box = og_box_dynamics(&dy) && !alpha_glob;
+    if (use_box) {
+        if (rk_order != 1) return -1;
+        og_field Vf = {og_get_array, V, NULL, 0};
+        og_costate_box(&g, &Vf, space_order, box);
+    }
+    og_step_ctx c = {&g, &dy, V, rk_order, dt, alpha_glob, space_order, eno_f32,
+                     use_box ? box : NULL};
 #pragma omp parallel for schedule(dynamic, 1)
     for (long j = 0; j < m; ++j) {
         og_field top = {og_stage_value, NULL, &c, rk_order};
         const double v = og_stage_value(&top, idx[j]);
         out[j] = og_clamp(v, idx[j], tmode, omode, V0, V, target, obstacle);
+    }
+    return 0;
+}
+
+/* alpha over a costate box and over all inputs at m states z (row-major,
+ * m x ndim): test access to the dissipation coefficients. */
+int oracle_alpha_box(int ndim, int dyn_id, int u_mode, int d_mode, const double *params, long m,
+                     const double *z, const double *dmin, const double *dmax, double *alpha_box,
+                     double *alpha_all)
+{
+    og_dyn dy;
+    memset(&dy, 0, sizeof(dy));
+    dy.id = dyn_id;
+    dy.u_mode = u_mode;
+    dy.d_mode = d_mode;
+    for (int k = 0; k < 16; ++k) dy.p[k] = params[k];
+    if (!og_dyn_ndim_ok(&dy, ndim) || dyn_id == OG_SI) return -1;
+    for (long j = 0; j < m; ++j) {
+        og_alpha_box(&dy, ndim, z + j * ndim, dmin, dmax, alpha_box + j * ndim);
+        og_alpha(&dy, ndim, z + j * ndim, alpha_all + j * ndim);
+    }
+    return 0;
+}
+
+/* Hamiltonian p . f(z, u*, d*) with the optimal inputs for costate p at m
+ * states (test access to the input choice). */
+int oracle_hamiltonian(int ndim, int dyn_id, int u_mode, int d_mode, const double *params, long m,
+                       const double *z, const double *p, double *H)
+{
+    og_dyn dy;
+    memset(&dy, 0, sizeof(dy));
+    dy.id = dyn_id;
+    dy.u_mode = u_mode;
+    dy.d_mode = d_mode;
+    for (int k = 0; k < 16; ++k) dy.p[k] = params[k];
+    if (!og_dyn_ndim_ok(&dy, ndim)) return -1;
+    for (long j = 0; j < m; ++j) {
+        double u[OG_MAXD] = {0}, dd[OG_MAXD] = {0}, f[OG_MAXD];
+        og_opt_inputs(&dy, ndim, z + j * ndim, p + j * ndim, u, dd);
+        og_dynamics(&dy, ndim, z + j * ndim, u, dd, f);
+        H[j] = 0.0;
+        for (int d = 0; d < ndim; ++d) H[j] += p[j * ndim + d] * f[d];
     }
     return 0;
 }

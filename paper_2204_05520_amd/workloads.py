@@ -28,6 +28,7 @@ DYN_SINGLE_INTEGRATOR = 0   # z' = c + u, |u|_2 <= u_max (test-only, N-D)
 DYN_DUBINS3D = 1            # (x, y, th): v cos th, v sin th, w, |w| <= w_max
 DYN_DYNCAR4D = 2            # (x, y, v, th): v cos th, v sin th, a, w
 DYN_TWODUBINS6D = 3         # evader (x,y,th) + pursuer (x,y,th), two Dubins cars
+DYN_PE3D = 4                # relative pursuit-evasion (x, y, th): evader a, pursuer b
 
 MAXIMISE = 1
 MINIMISE = 0
@@ -227,6 +228,18 @@ def config_game6d(n=36, T=2.0) -> SolveSpec:
     d = DynSpec(DYN_TWODUBINS6D, [1.0, 1.0, 1.0, 1.0], MAXIMISE, MINIMISE)
     return SolveSpec(g, d, [0.0, T], rk_order=2, cfl=0.8, mode=BRT, radius=0.5,
                      target="relative_distance", name=f"game6d_{'x'.join(map(str, ns))}_rk2_brt")
+
+
+def config_pe3d(n=100, T=1.5, rk_order=1) -> SolveSpec:
+    """3D relative pursuit-evasion (the paper's main example and its 100^3,
+    horizon 1.5 benchmark row): |x|, |y| <= 4, th in [-pi, pi), speeds
+    v_a = v_b = 1, turn bounds |a|, |b| <= 1; the evader a maximises, the
+    pursuer b minimises; capture radius 0.5; first order, CFL 0.8, tube."""
+    ns = list(n) if isinstance(n, (list, tuple)) else [n] * 3
+    g = GridSpec(ns, [-4.0, -4.0, -PI], [4.0, 4.0, PI], [0, 0, 1])
+    d = DynSpec(DYN_PE3D, [1.0, 1.0, 1.0, 1.0], MAXIMISE, MINIMISE)
+    return SolveSpec(g, d, [0.0, T], rk_order=rk_order, cfl=0.8, mode=BRT, radius=0.5,
+                     name=f"pe3d_{'x'.join(map(str, ns))}_rk{rk_order}_brt")
 
 
 def batch_dubins3d(count=512, seed=SEED_BATCH) -> List[SolveSpec]:

@@ -1,6 +1,11 @@
 """The pins have teeth: plant one plausible mistake at a time in a copy of
 the oracle's C source (on the CPU), build it, and check that some pin fails.
 
+(Ranging the evader's switching function over the whole costate box instead
+of the half the pursuer's branch leaves is an equivalent mutant for the
+pursuit-evasion game: any input pair it adds is matched by a realised pair
+with the same |f_d|, so no pin can see it; it is not listed.)
+
 Each mutant is a single textual change to oracle/odp_oracle.c; the test
 first asserts the original text is present, so a refactor of the oracle that
 moves a site makes this test fail loudly instead of silently passing.
@@ -58,6 +63,14 @@ MUTANTS = [
      "const size_t off = set_slices > 1 ? (size_t)k * (size_t)P : 0;"),
     ("set_slices_ignored", "const size_t off = set_slices > 1 ? (size_t)(k - 1) * (size_t)P : 0;",
      "const size_t off = 0;"),
+    ("pe3d_switching_mixed_sign", "u[0] = og_bang(pbar[0] * z[1] - pbar[1] * z[0] - pbar[2],",
+     "u[0] = og_bang(pbar[0] * z[1] + pbar[1] * z[0] - pbar[2],"),
+    ("pe3d_ydot_cos", "f[1] = dy->p[1] * sin(z[2]) - u[0] * z[0];", "f[1] = dy->p[1] * cos(z[2]) - u[0] * z[0];"),
+    ("pe3d_heading_rate_sign", "f[2] = dd[0] - u[0];", "f[2] = u[0] - dd[0];"),
+    ("pe3d_speeds_exchanged", "f[0] = -dy->p[0] + dy->p[1] * cos(z[2]) + u[0] * z[1];",
+     "f[0] = -dy->p[1] + dy->p[0] * cos(z[2]) + u[0] * z[1];"),
+    ("costate_box_not_used", "static int og_box_dynamics(const og_dyn *dy) { return dy->id == OG_PE3D; }",
+     "static int og_box_dynamics(const og_dyn *dy) { return dy->id < 0; }"),
     ("last_step_not_clipped", "dt = tau[k] - t;", "dt = dt + 0.0;"),
     ("control_bound_for_disturbance", "dd[0] = og_bang(pbar[5], dy->p[3], dy->d_mode);",
      "dd[0] = og_bang(pbar[5], dy->p[1], dy->d_mode);"),
@@ -88,6 +101,11 @@ FAST_PINS = [
     pins.test_pin10_eno2_picks_the_smooth_side,
     pins.test_pin10_eno2_tie_takes_the_first_stencil,
     pins.test_pin10_eno2_second_ghost,
+    pins.test_pin11_pe3d_hamiltonian_is_max_min,
+    pins.test_pin11_alpha_box_brute_force,
+    pins.test_pin11_pe3d_without_turning_is_drift,
+    pins.test_pin11_pe3d_one_step_with_known_box,
+    pins.test_pin11_pe3d_mirror_symmetry,
     lambda o: [pins.test_pin9_restart_reference(o, m, f) for m, f in
                (("minVWithVInit", np.minimum), ("maxVWithVInit", np.maximum), ("minVWithV0", None))],
 ]

@@ -504,6 +504,141 @@ def test_pin10_eno2_rk2_second_order_convergence(oracle_mod):
             assert lo_ <= r_ <= hi_, (order, rates, e)
 
 
+# ------------------------------------------------------------------ pin 11
+# Relative pursuit-evasion (the paper's main example) and the costate box.
+
+def _pe3d_f(z, a, b, va=1.0, vb=1.0):
+    """The paper's relative dynamics, for brute-force checks."""
+    x, y, th = z
+    return np.array([-va + vb * np.cos(th) + a * y, vb * np.sin(th) - a * x, b - a])
+
+
+def test_pin11_pe3d_hamiltonian_is_max_min(oracle_mod):
+    """H(z, p) = max over the evader's a in {-A, A} of min over the pursuer's
+    b in {-B, B} of p . f(z, a, b) (the game's Hamiltonian; bang-bang inputs
+    reach the extremes of an affine function)."""
+    rng = np.random.default_rng(11)
+    d = W.DynSpec(W.DYN_PE3D, [1.0, 1.0, 0.8, 1.3], W.MAXIMISE, W.MINIMISE)
+    z = np.column_stack([rng.uniform(-4, 4, 400), rng.uniform(-4, 4, 400), rng.uniform(-np.pi, np.pi, 400)])
+    p = rng.standard_normal((400, 3))
+    H = oracle_mod.hamiltonian(d, 3, z, p)
+    for j in range(400):
+        best = max(min(p[j] @ _pe3d_f(z[j], a, b) for b in (-1.3, 1.3)) for a in (-0.8, 0.8))
+        assert abs(H[j] - best) < 1e-12, j
+    # the roles swapped: the evader minimises, the pursuer maximises
+    d2 = W.DynSpec(W.DYN_PE3D, [1.0, 1.0, 0.8, 1.3], W.MINIMISE, W.MAXIMISE)
+    H2 = oracle_mod.hamiltonian(d2, 3, z, p)
+    for j in range(0, 400, 7):
+        best = min(max(p[j] @ _pe3d_f(z[j], a, b) for b in (-1.3, 1.3)) for a in (-0.8, 0.8))
+        assert abs(H2[j] - best) < 1e-12, j
+
+
+def test_pin11_alpha_box_brute_force(oracle_mod):
+    """alpha_d over the costate box equals its definition, the largest
+    |f_d(z, a*(p), b*(p))| over p in the box, found by brute force on a dense
+    sample of the box; for Dubins, the 4D car and the 6D game the box gives
+    the all-inputs alpha (every input drives one axis at its bound)."""
+    rng = np.random.default_rng(5)
+    d = W.DynSpec(W.DYN_PE3D, [1.0, 1.0, 1.0, 1.0], W.MAXIMISE, W.MINIMISE)
+    ticks = np.linspace(0.0, 1.0, 25)
+    smaller = 0
+    for case in range(80):
+        lo = rng.uniform(-1.0, 0.6, 3)
+        hi = lo + rng.uniform(0.05, 1.5, 3)
+        # half of the states near the origin, where the p_th term decides
+        # the evader's switching function and the split of the box on the
+        # sign of p_th (the pursuer's) matters
+        r = 4.0 if case < 40 else 0.25
+        z = np.array([rng.uniform(-r, r), rng.uniform(-r, r), rng.uniform(-np.pi, np.pi)])
+        ab, aa = oracle_mod.alpha_box(d, 3, z, lo, hi)
+        P = np.stack(np.meshgrid(*[lo[k] + ticks * (hi[k] - lo[k]) for k in range(3)],
+                                 indexing="ij"), -1).reshape(-1, 3)
+        if lo[2] < 0 < hi[2]:
+            P = np.vstack([P, np.column_stack([P[:, 0], P[:, 1], np.zeros(len(P))])])
+        s_a = P[:, 0] * z[1] - P[:, 1] * z[0] - P[:, 2]
+        a = np.where(s_a >= 0, 1.0, -1.0)
+        b = np.where(P[:, 2] >= 0, -1.0, 1.0)
+        F = np.abs(np.stack([-1 + np.cos(z[2]) + a * z[1], np.sin(z[2]) - a * z[0], b - a], 1))
+        brute = F.max(0)
+        assert np.abs(ab[0] - brute).max() < 1e-12, (case, ab, brute, lo, hi, z)
+        assert np.all(ab[0] <= aa[0] + 1e-15)
+        smaller += int(np.any(ab[0] < aa[0] - 1e-9))
+    assert smaller >= 5  # the box matters for this game
+    for dyn, nd in ((W.DynSpec(W.DYN_DUBINS3D, [1.0, 1.3], W.MAXIMISE, W.MINIMISE), 3),
+                    (W.DynSpec(W.DYN_DYNCAR4D, [0.7, 1.1], W.MAXIMISE, W.MINIMISE), 4),
+                    (W.DynSpec(W.DYN_TWODUBINS6D, [1.0, 1.2, 0.9, 0.8], W.MAXIMISE, W.MINIMISE), 6)):
+        for case in range(20):
+            lo = rng.uniform(-1.0, 0.6, nd)
+            hi = lo + rng.uniform(0.05, 1.5, nd)
+            z = rng.uniform(-3, 3, nd)
+            ab, aa = oracle_mod.alpha_box(dyn, nd, z, lo, hi)
+            assert np.array_equal(ab, aa)
+
+
+def test_pin11_pe3d_without_turning_is_drift(oracle_mod):
+    """With both turn bounds 0 the game is a drift (-v_a + v_b cos th,
+    v_b sin th, 0): every heading slice is a 2D drift solve with that
+    velocity (same step sizes)."""
+    ns = [21, 19, 12]
+    g = W.GridSpec(ns, [-4.0, -4.0, -np.pi], [4.0, 4.0, np.pi], [0, 0, 1])
+    d = W.DynSpec(W.DYN_PE3D, [0.7, 1.2, 0.0, 0.0], W.MAXIMISE, W.MINIMISE)
+    V0 = W.cylinder_v0(g, 1.0)
+    tau = [0.0, 0.6]
+    res = oracle_mod.solve(g, d, V0, tau, rk_order=2, cfl=0.8, brt=True, max_dt=0.04)
+    g2 = W.GridSpec(ns[:2], [-4.0, -4.0], [4.0, 4.0], [0, 0])
+    th = g.axis(2)
+    for k in (0, 3, 7, 11):
+        d2 = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [0.0, -0.7 + 1.2 * np.cos(th[k]), 1.2 * np.sin(th[k])],
+                       W.MAXIMISE, W.MINIMISE)
+        r2 = oracle_mod.solve(g2, d2, V0[:, :, k], tau, rk_order=2, cfl=0.8, brt=True, max_dt=0.04)
+        assert r2.steps == res.steps
+        assert np.abs(r2.V - res.V[:, :, k]).max() < 1e-12, k
+
+
+def test_pin11_pe3d_one_step_with_known_box(oracle_mod):
+    """V = x + c |y - y0| (kink on the node row y = y0): pbar = (1, +-c or 0,
+    0) everywhere, edges included, so the costate box is {1} x [-c, c] x {0}.
+    One step at every node off the y edges, written out from Algorithm 1:
+    H = pbar . f with the optimal inputs, plus the LF term, which only the
+    kink row has (p+_y - p-_y = 2c) with alpha_y from the box: the pursuer's
+    b = -B (p_th = 0), the evader's a = +A always and a = -A only where
+    y0 - c |x| < 0."""
+    c, y0, A, B, dt = 0.3, 0.5, 1.0, 1.0, 0.01
+    g = W.GridSpec([33, 17, 12], [-4.0, -4.0, -np.pi], [4.0, 4.0, np.pi], [0, 0, 1])
+    d = W.DynSpec(W.DYN_PE3D, [1.0, 1.0, A, B], W.MAXIMISE, W.MINIMISE)
+    x, y, th = (g.axis(k) for k in range(3))
+    X, Y, TH = np.meshgrid(x, y, th, indexing="ij")
+    V = X + c * np.abs(Y - y0)
+    rows = np.arange(1, 16)
+    idx = np.ravel_multi_index(np.meshgrid(np.arange(33), rows, np.arange(12), indexing="ij"),
+                               (33, 17, 12)).reshape(-1)
+    got = oracle_mod.step_at(g, d, V, V, dt, idx, brt=False)
+    Xs, Ys, Ts = X.reshape(-1)[idx], Y.reshape(-1)[idx], TH.reshape(-1)[idx]
+    kink = np.abs(Ys - y0) < 1e-12
+    py = np.where(kink, 0.0, c * np.sign(Ys - y0))
+    a = np.where(Ys - py * Xs >= 0, A, -A)
+    H = (-1.0 + np.cos(Ts) + a * Ys) + py * (np.sin(Ts) - a * Xs)
+    both = y0 - c * np.abs(Xs) < 0
+    alpha_y = np.where(both, np.abs(np.sin(Ts)) + A * np.abs(Xs), np.abs(np.sin(Ts) - A * Xs))
+    expect = V.reshape(-1)[idx] + dt * (H + np.where(kink, alpha_y * c, 0.0))
+    assert np.abs(got - expect).max() < 1e-12
+    # the all-inputs alpha would differ on the kink row
+    assert np.any(kink & ~both & (np.abs(np.sin(Ts) - A * Xs) < np.abs(np.sin(Ts)) + A * np.abs(Xs) - 1e-6))
+
+
+def test_pin11_pe3d_mirror_symmetry(oracle_mod):
+    """(x, y, th) -> (x, -y, -th) with (a, b) -> (-a, -b) maps the game to
+    itself and the capture target to itself, so the tube is symmetric."""
+    spec = W.config_pe3d(n=[23, 21, 16], T=0.5)
+    res = oracle_mod.solve_spec(spec)
+    V = res.V
+    k = (16 - np.arange(16)) % 16
+    M = V[:, ::-1, :][:, :, k]
+    assert np.abs(M - V).max() < 1e-12
+    # and the solve is not trivial
+    assert np.abs(V - W.make_v0(spec)).max() > 0.1
+
+
 # ------------------------------------------------------------------ golden
 
 def test_golden_cfl_steps(oracle_mod):
