@@ -9,7 +9,9 @@ the float64 form of the same solve is timed beside it.
 Default workload: the 4D dynamic car, 80^4 nodes on [-5,5]^2 x [0,4] x
 [-pi,pi), |a| <= 1, |w| <= 1, disc target r = 0.5, TVD-RK3, CFL 0.8,
 horizon 3 s, tube (BRT).  Other workloads (--workload): dubins3d (60x60x36,
-float64 form), game6d (36^6, RK2), batch (512 Dubins solves), serve.
+float64 form), game6d (36^6, RK2), pe3d (the 3D relative pursuit-evasion
+game, 100^3, horizon 1.5, first order, costate box per stage), batch (512
+Dubins solves), serve.
 --space-order 2 runs a single-solve workload with second-order ENO
 differences and, unless --rk says otherwise, TVD-RK2 (the paper's
 second-order pairing).
@@ -99,6 +101,9 @@ def bench_single(args, W, odp):
     elif args.workload == "game6d":
         spec = W.config_game6d(n=args.n or 36)
         kname, precs = "stage_game6d", (32,)
+    elif args.workload == "pe3d":
+        spec = W.config_pe3d(n=args.n or 100)
+        kname, precs = "stage_pe3d", (32, 64)
     else:
         spec = W.config_dubins3d()
         kname, precs = "stage_dubins3d", (64, 32)
@@ -145,7 +150,8 @@ def bench_single(args, W, odp):
     traffic = measured_traffic(f"{kname}_fp{head}", spec.name)
     roof = {"bound": "hbm", "achieved": r["achieved_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": r["achieved_gbps"] / HBM_PEAK_GBPS, "traffic": traffic,
-            "kernel": f"{'stage_eno2_kernel' if args.space_order == 2 else 'stage_kernel'} fp{head}",
+            "kernel": (f"{'stage_point_kernel' if args.space_order == 2 or args.workload == 'pe3d' else 'stage_kernel'}"
+                       f" fp{head}" + (" (costate-box pass + update per stage)" if args.workload == "pe3d" else "")),
             "avg_launch_us": r["avg_launch_us"],
             "alg_bytes_per_launch": r["alg_bytes_per_launch"]}
     line = {
@@ -308,7 +314,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dyncar4d",
-                    choices=["dyncar4d", "dubins3d", "game6d", "batch", "serve"])
+                    choices=["dyncar4d", "dubins3d", "game6d", "pe3d", "batch", "serve"])
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--tile-chunk", type=int, default=-1,
                     help="planes per block; -1 (default): the library's autotuner, which times "
@@ -340,7 +346,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    if args.workload in ("dyncar4d", "game6d", "dubins3d"):
+    if args.workload in ("dyncar4d", "game6d", "dubins3d", "pe3d"):
         line = bench_single(args, W, odp)
     elif args.workload == "batch":
         line = bench_batch(args, W, odp)

@@ -85,6 +85,15 @@ int64_t odp_grid_points(const odp_grid *grid);
  *      evader turns with the control u (|u| <= u_max), the pursuer with the
  *      disturbance d (|d| <= d_max); p[0] = v_e, p[1] = u_max, p[2] = v_p,
  *      p[3] = d_max.
+ *  PE3D (x, y, th): relative pursuit-evasion of two Dubins cars (the
+ *      paper's main example): x' = -v_a + v_b cos th + a y,
+ *      y' = v_b sin th - a x, th' = b - a; evader turn a (control,
+ *      |a| <= a_max), pursuer turn b (disturbance, |b| <= b_max);
+ *      p[0] = v_a, p[1] = v_b, p[2] = a_max, p[3] = b_max.  Its dissipation
+ *      is taken over the costate box of each Runge-Kutta stage (Algorithm
+ *      1's D_min / D_max: a grid-wide reduction before every stage update);
+ *      the step size uses the all-inputs bound.  Not available to the
+ *      server (ODP_EUNSUPPORTED).
  * u_mode / d_mode: 1 = that player maximises the Hamiltonian, 0 = minimises
  * (for a box input: maximiser picks +bound when its switching function is
  * >= 0, minimiser picks -bound). */
@@ -92,7 +101,8 @@ typedef enum {
     ODP_DYN_SINGLE_INTEGRATOR = 0,
     ODP_DYN_DUBINS3D = 1,
     ODP_DYN_DYNCAR4D = 2,
-    ODP_DYN_TWODUBINS6D = 3
+    ODP_DYN_TWODUBINS6D = 3,
+    ODP_DYN_PE3D = 4
 } odp_dyn_id;
 
 typedef struct {

@@ -434,14 +434,28 @@ static void og_costate_box(const og_grid *g, const og_field *W, int order, doubl
         box[d] = INFINITY;
         box[N + d] = -INFINITY;
     }
-    for (long i = 0; i < g->npts; ++i) {
-        long ii[OG_MAXD] = {0};
-        double pm[OG_MAXD], pp[OG_MAXD], pbar[OG_MAXD];
-        og_unravel(g, i, ii);
-        og_costate(g, W, i, ii, order, 0, pm, pp, pbar);
+#pragma omp parallel
+    {
+        double part[2 * OG_MAXD];
         for (int d = 0; d < N; ++d) {
-            if (pbar[d] < box[d]) box[d] = pbar[d];
-            if (pbar[d] > box[N + d]) box[N + d] = pbar[d];
+            part[d] = INFINITY;
+            part[N + d] = -INFINITY;
+        }
+#pragma omp for schedule(static)
+        for (long i = 0; i < g->npts; ++i) {
+            long ii[OG_MAXD] = {0};
+            double pm[OG_MAXD], pp[OG_MAXD], pbar[OG_MAXD];
+            og_unravel(g, i, ii);
+            og_costate(g, W, i, ii, order, 0, pm, pp, pbar);
+            for (int d = 0; d < N; ++d) {
+                if (pbar[d] < part[d]) part[d] = pbar[d];
+                if (pbar[d] > part[N + d]) part[N + d] = pbar[d];
+            }
+        }
+#pragma omp critical
+        for (int d = 0; d < N; ++d) {
+            if (part[d] < box[d]) box[d] = part[d];
+            if (part[N + d] > box[N + d]) box[N + d] = part[N + d];
         }
     }
 }

@@ -117,6 +117,15 @@ __device__ __forceinline__ void axis_terms(const SolveDesc &s, const int (&ii)[N
 // alpha_d(z): the largest |f_d| over the admissible inputs.
 template <int DYN, int N>
 __device__ __forceinline__ void alpha_point(const SolveDesc &s, const int (&ii)[N], double (&a)[N]) {
+    if constexpr (DYN == 4) {
+        // pursuit-evasion, all inputs admissible: |f_d| is largest at the
+        // evader's bound of the sign that adds to the drift
+        const double x = tab_x(s, 0, ii[0]), y = tab_x(s, 1, ii[1]);
+        a[0] = fabs(-s.p[0] + s.p[1] * tab_cos(s, 2, ii[2])) + s.p[2] * fabs(y);
+        a[1] = fabs(s.p[1] * tab_sin(s, 2, ii[2])) + s.p[2] * fabs(x);
+        a[2] = s.p[2] + s.p[3];
+        return;
+    }
     double f[N];
     axis_terms<DYN, N>(s, ii, f);
     if constexpr (DYN == 0) {
@@ -363,19 +372,70 @@ __device__ __forceinline__ void eno2_diffs(T l2, T l1, T c, T r1, T r2, T &dl, T
     dr = dp - T(0.5) * cp;
 }
 
-// Stage of step k with second-order ENO differences (the Spatial Derivatives
-// subsection's ENO2; the paper pairs it with TVD-RK2), one point per lane.
-// Axis-0 neighbours (two on each side) ride in a register ring along the
-// march; the in-plane neighbours at distance 1 and 2 are loaded per plane.
-// Beyond a non-periodic edge the m-th ghost node is vb + m sgn(vb)|vb - vin|
-// (vb the edge node, vin its inner neighbour).  Rows may be padded (pitch >
-// n_last): padding lanes compute nothing that is stored.
-template <typename T, int DYN, int N>
-__global__ __launch_bounds__(kBlock) void stage_eno2_kernel(const SolveDesc *__restrict__ descs,
-                                                            const uint32_t *__restrict__ tile_solve,
-                                                            const uint32_t *__restrict__ tile_local,
-                                                            int stage, int step_from_desc,
-                                                            int64_t fixed_step, int xgroup) {
+// Costate box keys: order-preserving unsigned images of doubles, so that
+// integer atomic min / max order them as the doubles.
+__device__ __forceinline__ uint64_t box_key(double v) {
+    const uint64_t u = uint64_t(__double_as_longlong(v));
+    return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+__device__ __forceinline__ double box_val(uint64_t k) {
+    return __longlong_as_double((long long)((k >> 63) ? (k & ~(1ull << 63)) : ~k));
+}
+
+__device__ __forceinline__ double bang_d(double sw, double bound, int maximise) {
+    return maximise ? (sw >= 0.0 ? bound : -bound) : (sw >= 0.0 ? -bound : bound);
+}
+
+// Pursuit-evasion dissipation over the costate box [bmin, bmax] at (x, y,
+// th): the largest |f_d| over the input pairs some costate in the box selects.
+// The pursuer's switching function is p_th, so each of its branches keeps the
+// half of the p_th interval of its sign (closed at 0); the evader's is
+// y p_x - x p_y - p_th, ranged over that half term by term.
+__device__ __forceinline__ void pe3d_alpha_box(const SolveDesc &s, double x, double y, double cth,
+                                               double sth, const double (&bmin)[3],
+                                               const double (&bmax)[3], double (&al)[3]) {
+    al[0] = al[1] = al[2] = 0.0;
+    const double c0 = y, c1 = -x;
+    const double m01 = fmin(c0 * bmin[0], c0 * bmax[0]) + fmin(c1 * bmin[1], c1 * bmax[1]);
+    const double M01 = fmax(c0 * bmin[0], c0 * bmax[0]) + fmax(c1 * bmin[1], c1 * bmax[1]);
+    for (int br = 1; br >= 0; --br) {
+        double lo = bmin[2], hi = bmax[2];
+        if (br) { if (lo < 0.0) lo = 0.0; }
+        else    { if (hi > 0.0) hi = 0.0; }
+        if (lo > hi || (!br && !(lo < 0.0))) continue;
+        const double bv = bang_d(br ? 1.0 : -1.0, s.p[3], s.d_mode);
+        const double smin = m01 + fmin(-lo, -hi), smax = M01 + fmax(-lo, -hi);
+        for (int ar = 1; ar >= 0; --ar) {
+            if (ar ? !(smax >= 0.0) : !(smin < 0.0)) continue;
+            const double av = bang_d(ar ? 1.0 : -1.0, s.p[2], s.u_mode);
+            const double f0 = -s.p[0] + s.p[1] * cth + av * y;
+            const double f1 = s.p[1] * sth - av * x;
+            const double f2 = bv - av;
+            al[0] = fmax(al[0], fabs(f0));
+            al[1] = fmax(al[1], fabs(f1));
+            al[2] = fmax(al[2], fabs(f2));
+        }
+    }
+}
+
+// Stage of step k for the point-per-lane forms: second-order ENO
+// differences (ORDER 2; the Spatial Derivatives subsection's ENO2, which the
+// paper pairs with TVD-RK2) and the pursuit-evasion model (DYN 4, either
+// order), whose evader input enters three axes.  One point per lane; axis-0
+// neighbours ride in a register ring along the march, the in-plane
+// neighbours are loaded per plane.  Beyond a non-periodic edge the m-th ghost
+// node is vb + m sgn(vb)|vb - vin| (vb the edge node, vin its inner
+// neighbour).  Rows may be padded (pitch > n_last): padding lanes store
+// nothing.  PASS 1 (pursuit-evasion only) computes no update: it reduces the
+// costate pbar of the stage input over the grid into the solve's box
+// (Algorithm 1's D_min / D_max), which the update pass then reads.
+template <typename T, int DYN, int N, int ORDER, int PASS>
+__global__ __launch_bounds__(kBlock) void stage_point_kernel(const SolveDesc *__restrict__ descs,
+                                                             const uint32_t *__restrict__ tile_solve,
+                                                             const uint32_t *__restrict__ tile_local,
+                                                             int stage, int step_from_desc,
+                                                             int64_t fixed_step, int xgroup) {
+    static_assert(DYN != 4 || N == 3, "pursuit-evasion is three-dimensional");
     const uint32_t L = xcd_logical(blockIdx.x, gridDim.x, uint32_t(xgroup));
     const uint32_t si = tile_solve ? tile_solve[L] : 0u;
     const uint32_t lt = tile_solve ? tile_local[L] : L;
@@ -426,11 +486,41 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_kernel(const SolveDesc *__r
             else { off[d][j] = 0; gmask |= 1u << (4 * d + j); }
         }
     }
-    const Coef<T, DYN, N> cf = make_coef<T, DYN, N>(s, ii);
 
     const T *W, *Vn;
     T *out;
     stage_buffers<T>(s, stage, k, W, Vn, out);
+    const T dt = T(s.dt_sched[k]);
+    const int64_t s0 = s.s0;
+    const int n0 = s.n0;
+    const bool per0 = s.periodic & 1u;
+    const int i0b = int(cid) * s.chunk;
+    const int i0e = min(i0b + s.chunk, n0);
+
+    // per-lane constants of the Hamiltonian
+    Coef<T, DYN == 4 ? 0 : DYN, N> cf;
+    if constexpr (DYN != 4 && PASS == 0) cf = make_coef<T, DYN, N>(s, ii);
+    double pe_y = 0.0, pe_c = 0.0, pe_s = 0.0;
+    double bmin[3] = {0.0, 0.0, 0.0}, bmax[3] = {0.0, 0.0, 0.0};
+    T h[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) h[d] = T(s.inv2dx[d]);
+    if constexpr (DYN == 4) {
+        pe_y = tab_x(s, 1, ii[1]);
+        pe_c = tab_cos(s, 2, ii[2]);
+        pe_s = tab_sin(s, 2, ii[2]);
+        if constexpr (PASS == 0) {
+            if (!s.global_alpha) {
+                for (int d = 0; d < 3; ++d) {
+                    bmin[d] = box_val(s.box[d]);
+                    bmax[d] = box_val(s.box[3 + d]);
+                }
+            }
+        }
+    }
+    const T pe_cx = T(-s.p[0] + s.p[1] * pe_c), pe_sy = T(s.p[1] * pe_s);
+    const T pe_yT = T(pe_y), pe_A = T(s.p[2]), pe_B = T(s.p[3]);
+
     const T *Z = s.tvn ? Vn : (const T *)s.tref;
     const T *G = (const T *)s.oref;
     double wa, wb;
@@ -440,13 +530,6 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_kernel(const SolveDesc *__r
     const bool clamp = last && s.tclamp;
     const bool obst = last && s.obst;
     const bool tmax = s.tmax, omax = s.omax;
-    const T dt = T(s.dt_sched[k]);
-
-    const int64_t s0 = s.s0;
-    const int n0 = s.n0;
-    const bool per0 = s.periodic & 1u;
-    const int i0b = int(cid) * s.chunk;
-    const int i0e = min(i0b + s.chunk, n0);
 
     // axis-0 node j (-2 <= j <= n0 + 1) of this lane: wrapped, or a ghost
     auto ax0 = [&](int j) -> T {
@@ -456,22 +539,25 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_kernel(const SolveDesc *__r
         const T vb = W[int64_t(b) * s0 + qq], vin = W[int64_t(in) * s0 + qq];
         return (j == -1 || j == n0) ? ghost(vb, vin) : ghost2(vb, vin);
     };
-    T r0 = ax0(i0b - 2), r1 = ax0(i0b - 1), r2 = ax0(i0b), r3 = ax0(i0b + 1), r4;
+    T r0 = ORDER == 2 ? ax0(i0b - 2) : T(0), r1 = ax0(i0b - 1), r2 = ax0(i0b), r3 = ax0(i0b + 1), r4 = T(0);
+    double mn[N], mx[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) { mn[d] = INFINITY; mx[d] = -INFINITY; }
     int bad = 0;
     for (int i0 = i0b; i0 < i0e; ++i0) {
-        r4 = ax0(i0 + 2);
+        if constexpr (ORDER == 2) r4 = ax0(i0 + 2);
         const T wc = r2;
         const T *plane = W + int64_t(i0) * s0 + qq;
-        Acc<T> acc{T(0), T(0)};
-        {
-            T dl, dr;
-            eno2_diffs(r0, r1, wc, r3, r4, dl, dr);
-            acc_axis<T, DYN, N>(cf, 0, dl, dr, acc);
-        }
+        T dl[N], dr[N];
+        if constexpr (ORDER == 2) eno2_diffs(r0, r1, wc, r3, r4, dl[0], dr[0]);
+        else { dl[0] = wc - r1; dr[0] = r3 - wc; }
 #pragma unroll
         for (int d = 1; d < N; ++d) {
-            T l2 = plane[off[d][0]], l1 = plane[off[d][1]];
-            T p1 = plane[off[d][2]], p2 = plane[off[d][3]];
+            T l2 = T(0), l1 = plane[off[d][1]], p1 = plane[off[d][2]], p2 = T(0);
+            if constexpr (ORDER == 2) {
+                l2 = plane[off[d][0]];
+                p2 = plane[off[d][3]];
+            }
             const uint32_t gm = (gmask >> (4 * d)) & 15u;
             if (gm) {
                 // near a non-periodic edge: the edge node is the point or its
@@ -481,11 +567,53 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_kernel(const SolveDesc *__r
                 if (gm & 4u) { p1 = ghost(wc, l1); p2 = ghost2(wc, l1); }
                 else if (gm & 8u) p2 = ghost(p1, wc);
             }
-            T dl, dr;
-            eno2_diffs(l2, l1, wc, p1, p2, dl, dr);
-            acc_axis<T, DYN, N>(cf, d, dl, dr, acc);
+            if constexpr (ORDER == 2) eno2_diffs(l2, l1, wc, p1, p2, dl[d], dr[d]);
+            else { dl[d] = wc - l1; dr[d] = p1 - wc; }
         }
-        const T Lh = acc_finish<T, DYN, N>(cf, acc);
+        if constexpr (ORDER == 2) r0 = r1;
+        r1 = r2;
+        r2 = r3;
+        r3 = ORDER == 2 ? r4 : ax0(i0 + 2);
+
+        if constexpr (PASS == 1) {
+            // costate box of this stage: pbar_d = (p+ + p-) / 2
+            if (active) {
+#pragma unroll
+                for (int d = 0; d < N; ++d) {
+                    const double pb = double((dl[d] + dr[d]) * h[d]);
+                    mn[d] = fmin(mn[d], pb);
+                    mx[d] = fmax(mx[d], pb);
+                }
+            }
+            continue;
+        }
+        T Lh;
+        if constexpr (DYN == 4) {
+            const double xd = tab_x(s, 0, i0);
+            const T x = T(xd);
+            const T pbx = (dl[0] + dr[0]) * h[0], pby = (dl[1] + dr[1]) * h[1], pbt = (dl[2] + dr[2]) * h[2];
+            const T sa = pbx * pe_yT - pby * x - pbt;
+            const T a = s.u_mode ? (sa >= T(0) ? pe_A : -pe_A) : (sa >= T(0) ? -pe_A : pe_A);
+            const T b = s.d_mode ? (pbt >= T(0) ? pe_B : -pe_B) : (pbt >= T(0) ? -pe_B : pe_B);
+            const T f0 = pe_cx + a * pe_yT, f1 = pe_sy - a * x, f2 = b - a;
+            T H = pbx * f0;
+            H = fma_t(pby, f1, H);
+            H = fma_t(pbt, f2, H);
+            double al[3];
+            if (s.global_alpha) {
+                for (int d = 0; d < 3; ++d) al[d] = s.amax[d];
+            } else {
+                pe3d_alpha_box(s, xd, pe_y, pe_c, pe_s, bmin, bmax, al);
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) H = fma_t(T(al[d]), (dr[d] - dl[d]) * h[d], H);
+            Lh = H;
+        } else {
+            Acc<T> acc{T(0), T(0)};
+#pragma unroll
+            for (int d = 0; d < N; ++d) acc_axis<T, DYN, N>(cf, d, dl[d], dr[d], acc);
+            Lh = acc_finish<T, DYN, N>(cf, acc);
+        }
         const int64_t o = int64_t(i0) * s0 + qq;
         T v = fma_t(dt, Lh, wc);
         if (wa != 0.0) v = fma_t(ra, Vn[o], rb * v);
@@ -499,12 +627,35 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_kernel(const SolveDesc *__r
         }
         bad |= active && !isfinite(v);
         if (active) out[o] = v;
-        r0 = r1;
-        r1 = r2;
-        r2 = r3;
-        r3 = r4;
     }
-    if (bad) atomicOr(s.flags, 1);
+    if constexpr (PASS == 1) {
+        // wave reduction, then one atomic per wave and bound
+#pragma unroll
+        for (int d = 0; d < N; ++d) {
+            double a = mn[d], b = mx[d];
+            for (int o2 = 32; o2 >= 1; o2 >>= 1) {
+                a = fmin(a, __shfl_xor(a, o2, 64));
+                b = fmax(b, __shfl_xor(b, o2, 64));
+            }
+            if ((threadIdx.x & 63) == 0) {
+                atomicMin((unsigned long long *)&s.box[d], (unsigned long long)box_key(a));
+                atomicMax((unsigned long long *)&s.box[N + d], (unsigned long long)box_key(b));
+            }
+        }
+    } else {
+        if (bad) atomicOr(s.flags, 1);
+    }
+}
+
+// Empty the costate box of the listed solves (before a box pass).
+__global__ void box_reset_kernel(const SolveDesc *__restrict__ descs, int nsolves) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsolves) return;
+    const SolveDesc &s = descs[i];
+    for (int d = 0; d < 3; ++d) {
+        s.box[d] = box_key(INFINITY);
+        s.box[3 + d] = box_key(-INFINITY);
+    }
 }
 
 // VEC consecutive points of the last axis per thread (16-byte loads and
@@ -1102,9 +1253,26 @@ template <typename T, int DYN, int N, int VEC>
 static hipError_t launch_stage_t(int kind, const SolveDesc *d, const uint32_t *ts, const uint32_t *tl,
                                  uint32_t nblocks, int stage, int from_desc, int64_t step, int xg,
                                  hipStream_t st) {
-    if (kind & 16) {
-        // second-order ENO (one point per lane; method flags at run time)
-        hipLaunchKernelGGL((stage_eno2_kernel<T, DYN, N>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl,
+    if constexpr (DYN == 4) {
+        // pursuit-evasion: point per lane, first order or ENO2 (bit 4), the
+        // costate-box pass (bit 5) or the update
+        if (kind & 32) {
+            if (kind & 16)
+                hipLaunchKernelGGL((stage_point_kernel<T, DYN, N, 2, 1>), dim3(nblocks), dim3(kBlock), 0, st, d,
+                                   ts, tl, stage, from_desc, step, xg);
+            else
+                hipLaunchKernelGGL((stage_point_kernel<T, DYN, N, 1, 1>), dim3(nblocks), dim3(kBlock), 0, st, d,
+                                   ts, tl, stage, from_desc, step, xg);
+        } else if (kind & 16) {
+            hipLaunchKernelGGL((stage_point_kernel<T, DYN, N, 2, 0>), dim3(nblocks), dim3(kBlock), 0, st, d, ts,
+                               tl, stage, from_desc, step, xg);
+        } else {
+            hipLaunchKernelGGL((stage_point_kernel<T, DYN, N, 1, 0>), dim3(nblocks), dim3(kBlock), 0, st, d, ts,
+                               tl, stage, from_desc, step, xg);
+        }
+    } else if (kind & 16) {
+        // second-order ENO (point per lane; method flags at run time)
+        hipLaunchKernelGGL((stage_point_kernel<T, DYN, N, 2, 0>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl,
                            stage, from_desc, step, xg);
     } else if constexpr (N == 1) {
         hipLaunchKernelGGL((stage_kernel<T, DYN, N>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl,
@@ -1148,7 +1316,7 @@ template <typename T, int DYN, int N>
 static hipError_t launch_stage_v(int vec, int kind, const SolveDesc *d, const uint32_t *ts,
                                  const uint32_t *tl, uint32_t nb, int stage, int fd, int64_t step,
                                  int xg, hipStream_t st) {
-    if constexpr (N == 1 || DYN == 0) {
+    if constexpr (N == 1 || DYN == 0 || DYN == 4) {
         return launch_stage_t<T, DYN, N, 1>(kind, d, ts, tl, nb, stage, fd, step, xg, st);
     } else {
         if constexpr (sizeof(T) == 4) {
@@ -1167,6 +1335,7 @@ static hipError_t launch_stage_p(int dyn, int ndim, int vec, int kind, const Sol
     case 1: return launch_stage_v<T, 1, 3>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
     case 2: return launch_stage_v<T, 2, 4>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
     case 3: return launch_stage_v<T, 3, 6>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
+    case 4: return launch_stage_v<T, 4, 3>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
     case 0:
         switch (ndim) {
         case 1: return launch_stage_v<T, 0, 1>(vec, kind, d, ts, tl, nb, stage, fd, step, xg, st);
@@ -1204,6 +1373,7 @@ hipError_t launch_alpha(int dyn, int ndim, const SolveDesc *d, int nsolves, int 
     case 1: return launch_alpha_t<1, 3>(d, nsolves, blocks_per_solve, st);
     case 2: return launch_alpha_t<2, 4>(d, nsolves, blocks_per_solve, st);
     case 3: return launch_alpha_t<3, 6>(d, nsolves, blocks_per_solve, st);
+    case 4: return launch_alpha_t<4, 3>(d, nsolves, blocks_per_solve, st);
     case 0:
         switch (ndim) {
         case 1: return launch_alpha_t<0, 1>(d, nsolves, blocks_per_solve, st);
@@ -1252,6 +1422,11 @@ hipError_t launch_set_slice(int precision, SolveDesc *d, int iv, hipStream_t st)
         hipLaunchKernelGGL(set_slice_kernel<float>, dim3(1), dim3(64), 0, st, d, iv);
     else
         hipLaunchKernelGGL(set_slice_kernel<double>, dim3(1), dim3(64), 0, st, d, iv);
+    return hipGetLastError();
+}
+
+hipError_t launch_box_reset(const SolveDesc *d, int nsolves, hipStream_t st) {
+    hipLaunchKernelGGL(box_reset_kernel, dim3((nsolves + 255) / 256), dim3(256), 0, st, d, nsolves);
     return hipGetLastError();
 }
 

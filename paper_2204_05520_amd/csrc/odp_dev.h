@@ -80,6 +80,8 @@ struct SolveDesc {
     int64_t *nsteps;         // device: step count of the schedule
     int64_t *step;           // device: next step to take (server ticks)
     int32_t *flags;          // bit 0: non-finite value produced
+    uint64_t *box;           // costate box of the current stage (pursuit-evasion):
+                             // order-preserving keys of D_min[3], then D_max[3]
     // ---- computation method: after every full step (the last stage) V is
     // compared with a reference point by point and replaced by the smaller
     // (or larger) of the two; then, optionally, again with an obstacle array

@@ -12,7 +12,7 @@ namespace odp {
 
 namespace {
 
-constexpr size_t kStateBytes = 256;  // alpha^max[6], nsteps, step, flags
+constexpr size_t kStateBytes = 256;  // alpha^max[6], nsteps, step, flags; costate box at 128
 
 int64_t step_capacity(const odp_grid *g, const odp_dynamics *dyn, const std::vector<double> &tau,
                       double cfl, double max_dt) {
@@ -59,7 +59,7 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         it.ppad = it.qpad * it.g->n[0];
         it.vec = choose_vec(it.g, prec, it.dyn.id, it.pitch);
         it.lds = uses_lds(it.g->ndim, it.pitch, it.vec);
-        if (opts.space_order == 2) {  // second-order ENO: one point per lane
+        if (opts.space_order == 2 || it.dyn.id == ODP_DYN_PE3D) {  // point-per-lane kernel
             it.vec = 1;
             it.lds = 0;
         }
@@ -196,6 +196,7 @@ void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &
         s.nsteps = (int64_t *)(state + kMaxDim * 8);
         s.step = (int64_t *)(state + kMaxDim * 8 + 8);
         s.flags = (int32_t *)(state + kMaxDim * 8 + 16);
+        s.box = (uint64_t *)(state + 128);
         const size_t tab_off = it.aux_off + kStateBytes;
         const size_t tau_off = tab_off + align256(size_t(it.tab_entries) * 8);
         s.tabd = (const double *)(base + tab_off);
@@ -333,7 +334,16 @@ int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t
         const uint32_t *ts = tsd ? tsd + gr.tile_base : nullptr;
         const uint32_t *tl = tld ? tld + gr.tile_base : nullptr;
         for (int j = 0; j < gr.rk; ++j) {
-            if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, stage_kind(gr.rk, j, mk, gr.lds, p.opts.space_order == 2), descs,
+            const int kind = stage_kind(gr.rk, j, mk, gr.lds, p.opts.space_order == 2);
+            if (gr.dyn == ODP_DYN_PE3D && !p.opts.dissipation) {
+                // Algorithm 1's costate box of this stage's input, then the update
+                if ((rc = check_hip(launch_box_reset(descs, int(p.items.size()), st), "box reset")) ||
+                    (rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, kind | 32, descs, ts, tl, nb, j, 0,
+                                                 k, p.xcd_group, st),
+                                    "box")))
+                    return rc;
+            }
+            if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, kind, descs,
                                              ts, tl, nb, j, 0, k, p.xcd_group, st),
                                 "stage")))
                 return rc;
@@ -406,7 +416,8 @@ int plan_stats(const Plan &p, unsigned char *base, double kernel_ms, odp_solve_s
         sx.dt_max = *std::max_element(dts, dts + it.nsteps);
         sx.t_final = it.tau.back();
         sx.kernel_ms = kernel_ms;
-        sx.alg_bytes = alg_bytes_per_step(o.precision, it.rk_order, method_arrays(o), it.g->npts) * double(it.nsteps);
+        sx.alg_bytes = alg_bytes_per_step(o.precision, it.rk_order,
+                                           method_arrays(o) + box_reads(it.dyn.id, o, it.rk_order), it.g->npts) * double(it.nsteps);
         sx.alg_gbps = kernel_ms > 0 ? sx.alg_bytes / (kernel_ms * 1e6) : 0.0;
         sx.roofline_frac = sx.alg_gbps / 8000.0;
         std::memcpy(sx.alpha_max, state, sizeof(sx.alpha_max));

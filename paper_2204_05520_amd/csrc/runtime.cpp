@@ -33,13 +33,14 @@ static int dyn_ndim(int id) {
     case ODP_DYN_DUBINS3D: return 3;
     case ODP_DYN_DYNCAR4D: return 4;
     case ODP_DYN_TWODUBINS6D: return 6;
+    case ODP_DYN_PE3D: return 3;
     default: return 0;
     }
 }
 
 int validate_dyn(const odp_grid *g, const odp_dynamics *dyn) {
     if (!dyn) return set_error(ODP_EINVAL, "dynamics is NULL");
-    if (dyn->id < 0 || dyn->id > 3) return set_error(ODP_EINVAL, "unknown dynamics id");
+    if (dyn->id < 0 || dyn->id > 4) return set_error(ODP_EINVAL, "unknown dynamics id");
     if (dyn->id != ODP_DYN_SINGLE_INTEGRATOR && dyn_ndim(dyn->id) != g->ndim)
         return set_error(ODP_EINVAL, "dynamics dimension does not match the grid");
     if ((dyn->u_mode != 0 && dyn->u_mode != 1) || (dyn->d_mode != 0 && dyn->d_mode != 1))
@@ -62,6 +63,10 @@ int validate_dyn(const odp_grid *g, const odp_dynamics *dyn) {
         if (dyn->p[1] < 0 || dyn->p[3] < 0) return set_error(ODP_EINVAL, "input bounds must be >= 0");
         if (!g->periodic[2] || !g->periodic[5])
             return set_error(ODP_EINVAL, "the heading axes must be periodic");
+        break;
+    case ODP_DYN_PE3D:
+        if (dyn->p[2] < 0 || dyn->p[3] < 0) return set_error(ODP_EINVAL, "input bounds must be >= 0");
+        if (!g->periodic[2]) return set_error(ODP_EINVAL, "the heading axis must be periodic");
         break;
     }
     return ODP_OK;
@@ -130,6 +135,14 @@ void alpha_bound(const odp_grid *g, const odp_dynamics *dyn, double *ab) {
         ab[3] = ab[4] = std::fabs(p[2]);
         ab[5] = p[3];
         break;
+    case ODP_DYN_PE3D: {
+        const double xm = std::max(std::fabs(g->lo[0]), std::fabs(g->hi[0]));
+        const double ym = std::max(std::fabs(g->lo[1]), std::fabs(g->hi[1]));
+        ab[0] = std::fabs(p[0]) + std::fabs(p[1]) + p[2] * ym;
+        ab[1] = std::fabs(p[1]) + p[2] * xm;
+        ab[2] = p[2] + p[3];
+        break;
+    }
     }
 }
 

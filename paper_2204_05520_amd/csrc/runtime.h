@@ -29,6 +29,8 @@ hipError_t launch_alpha(int dyn, int ndim, const SolveDesc *d, int nsolves, int 
 hipError_t launch_init(const SolveDesc *d, int nsolves, hipStream_t st);
 hipError_t launch_sched(const SolveDesc *d, int nsolves, int64_t *nsteps_all, hipStream_t st);
 hipError_t launch_advance(const SolveDesc *d, const int32_t *list, int n, hipStream_t st);
+// Empty the costate boxes of descs[0..n) (pursuit-evasion, before each box pass).
+hipError_t launch_box_reset(const SolveDesc *d, int nsolves, hipStream_t st);
 // Time-varying sets of a single solve: references of descs[0] to slice iv.
 hipError_t launch_set_slice(int precision, SolveDesc *d, int iv, hipStream_t st);
 // Padded members (SolveDesc::Adst_dense set): A to the caller's dense array.
@@ -62,6 +64,11 @@ double alg_bytes_per_step(int precision, int rk_order, int narr, int64_t npts);
 // for ODP_MIN/MAX_V0 and ODP_MIN/MAX_TARGET, plus the obstacle array.  The
 // value-over-time methods compare with V^n, which the step reads anyway.
 int method_arrays(const odp_solve_opts &o);
+// Stencil-input reads per step of the costate-box passes (pursuit-evasion
+// with per-point dissipation: one per Runge-Kutta stage).
+inline int box_reads(int dyn, const odp_solve_opts &o, int rk_order) {
+    return dyn == ODP_DYN_PE3D && !o.dissipation ? rk_order : 0;
+}
 // Kind bits of the last stage of a step for these options: bit 1 one
 // comparison (a target method, or an obstacle method alone), bit 3 a
 // second one (target and obstacle methods together).
@@ -69,7 +76,8 @@ int method_kind(const odp_solve_opts &o);
 // Stage kind for launch_stage: bit 0 reads V^n, bits 1 and 3 the comparisons
 // of the computation method (method_kind, last stage only), bit 2 the LDS
 // plane exchange (every listed solve must have SolveDesc::lds set), bit 4
-// second-order ENO differences (the point-per-lane kernel).
+// second-order ENO differences (the point-per-lane kernel), bit 5 (added by
+// the caller) the costate-box pass of the pursuit-evasion model.
 inline int stage_kind(int rk_order, int stage, int mkind, int lds = 0, int eno2 = 0) {
     return (stage > 0 ? 1 : 0) | (stage == rk_order - 1 ? mkind : 0) | (lds ? 4 : 0) | (eno2 ? 16 : 0);
 }

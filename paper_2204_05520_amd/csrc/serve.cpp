@@ -676,6 +676,8 @@ int odp_serve_submit(odp_server *srv, const odp_solve_desc *d, uint64_t *ticket)
     if (!d->grid) return set_error(ODP_EINVAL, "grid is NULL");
     int rc;
     if ((rc = validate_dyn(d->grid, &d->dyn)) || (rc = validate_tau(d->tau, d->ntau))) return rc;
+    if (d->dyn.id == ODP_DYN_PE3D)
+        return set_error(ODP_EUNSUPPORTED, "the pursuit-evasion model (costate box) is not served");
     if (!d->V0_dev) return set_error(ODP_EINVAL, "V0 (host) is NULL");
     if (d->rk_order < 0 || d->rk_order > 3) return set_error(ODP_EINVAL, "rk_order must be 0..3");
     auto r = std::make_shared<Req>();

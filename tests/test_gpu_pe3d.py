@@ -1,0 +1,114 @@
+"""GPU parity of the relative pursuit-evasion model (the paper's main
+example) with the costate box of Algorithm 1: a grid-wide reduction of the
+stage input's costate before every stage update, the dissipation taken over
+the input pairs the box realises.  Through the C ABI against the float64
+oracle; bars as elsewhere (float64 1e-9 S, float32 1e-4 S), the same step
+count; non-cubic grids with ragged tails.
+"""
+import numpy as np
+import pytest
+
+from paper_2204_05520_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {64: 1e-9, 32: 1e-4}
+
+
+@pytest.fixture(scope="module")
+def odp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2204_05520_amd as odp
+    odp.lib()
+    return odp
+
+
+def _dev(x, prec):
+    import torch
+    return torch.tensor(x, dtype=torch.float64 if prec == 64 else torch.float32, device="cuda:0")
+
+
+def _check(odp, oracle_mod, spec, space_order=1, dissipation=0, precs=(64, 32)):
+    import torch
+    V0 = W.make_v0(spec)
+    ref = oracle_mod.solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=spec.rk_order, cfl=spec.cfl,
+                           brt=spec.mode == W.BRT, space_order=space_order,
+                           global_alpha=bool(dissipation))
+    S = spec.grid.domain_scale()
+    for prec in precs:
+        print(f"[gpu] pe3d {spec.name} order={space_order} diss={dissipation} fp{prec}", flush=True)
+        res = odp.solve(spec, _dev(V0, prec), precision=prec, space_order=space_order,
+                        dissipation=dissipation)
+        torch.cuda.synchronize()
+        err = float(np.abs(res.V.double().cpu().numpy() - ref.V).max())
+        print(f"    steps gpu={res.stats['steps']} oracle={ref.steps} max|err|/S={err / S:.3e}", flush=True)
+        assert res.stats["steps"] == ref.steps
+        assert res.stats["dt_max"] == ref.dt_max
+        assert err <= TOL[prec] * S, (prec, err / S)
+    return ref
+
+
+@pytest.mark.parametrize("n,rk,order", [([23, 21, 16], 1, 1), ([31, 27, 24], 2, 1),
+                                        ([19, 23, 18], 3, 1), ([23, 21, 16], 2, 2),
+                                        ([40, 40, 36], 1, 1)])
+def test_pe3d_parity(odp, oracle_mod, n, rk, order):
+    spec = W.config_pe3d(n=n, T=0.6, rk_order=rk)
+    ref = _check(odp, oracle_mod, spec, space_order=order)
+    assert np.abs(ref.V - W.make_v0(spec)).max() > 0.1
+
+
+def test_pe3d_global_alpha(odp, oracle_mod):
+    _check(odp, oracle_mod, W.config_pe3d(n=[23, 21, 16], T=0.6), dissipation=1)
+
+
+@pytest.mark.parametrize("rk", [1, 2])
+def test_pe3d_narrow_box(odp, oracle_mod, rk):
+    """V0 = x + 0.3 |y - 0.5|: the costate box stays narrow for the first
+    steps, so its dissipation is below the all-inputs bound (the oracle's
+    results with and without the box differ by 0.07 after 8 steps, far above
+    the bars): the GPU machine reduction and box alpha are what is compared."""
+    import torch
+    g = W.GridSpec([33, 17, 12], [-4.0, -4.0, -np.pi], [4.0, 4.0, np.pi], [0, 0, 1])
+    d = W.DynSpec(W.DYN_PE3D, [1.0, 1.0, 1.0, 1.0], W.MAXIMISE, W.MINIMISE)
+    X, Y, _ = np.meshgrid(g.axis(0), g.axis(1), g.axis(2), indexing="ij")
+    V0 = X + 0.3 * np.abs(Y - 0.5)
+    _, dt = oracle_mod.cfl_dt(g, d, 0.8)
+    spec = W.SolveSpec(g, d, [0.0, 8 * dt * (1 - 1e-12)], rk_order=rk, cfl=0.8, mode=W.BRS,
+                       name=f"pe3d_narrow_box_rk{rk}")
+    ref = oracle_mod.solve(g, d, V0, spec.tau, rk_order=rk, cfl=0.8, brt=False)
+    for prec in (64, 32):
+        res = odp.solve(spec, _dev(V0, prec), precision=prec)
+        torch.cuda.synchronize()
+        err = float(np.abs(res.V.double().cpu().numpy() - ref.V).max())
+        print(f"    narrow box rk{rk} fp{prec}: steps {res.stats['steps']} max|err| {err:.3e}", flush=True)
+        assert res.stats["steps"] == ref.steps == 8
+        assert err <= TOL[prec] * 8.0, (prec, err)
+
+
+def test_pe3d_launch_shapes_and_batch_bitwise(odp):
+    import torch
+    spec = W.config_pe3d(n=[23, 21, 16], T=0.4)
+    V0 = _dev(W.make_v0(spec), 32)
+    outs = [odp.solve(spec, V0, precision=32, tile_chunk=c).V.cpu() for c in (1, 5, 23)]
+    assert all(torch.equal(o, outs[0]) for o in outs[1:])
+    specs = [W.config_pe3d(n=[23, 21, 16], T=0.4), W.config_pe3d(n=[17, 19, 14], T=0.7),
+             W.config_dubins3d(n=(21, 19, 16), T=0.5)]
+    V0s = [_dev(W.make_v0(s), 32) for s in specs]
+    bouts, _ = odp.batch(specs, V0s, precision=32)
+    for s, v0, o in zip(specs, V0s, bouts):
+        one = odp.solve(s, v0, precision=32).V
+        torch.cuda.synchronize()
+        assert torch.equal(o, one), s.name
+
+
+def test_pe3d_not_served(odp):
+    spec = W.config_pe3d(n=[23, 21, 16], T=0.4)
+    srv = odp.Server(1 << 28, 2, precision=32)
+    try:
+        with pytest.raises(odp.OdpError) as ei:
+            srv.submit(spec, W.make_v0(spec))
+        assert ei.value.code == odp.ODP_EUNSUPPORTED
+    finally:
+        srv.close()
