@@ -497,6 +497,9 @@ __global__ __launch_bounds__(kBlock) void stage_point_kernel(const SolveDesc *__
     const int i0b = int(cid) * s.chunk;
     const int i0e = min(i0b + s.chunk, n0);
 
+    // costate box buffer of this stage: two, alternating with the global
+    // stage index
+    const int box_buf = int((k * s.rk_order + stage) & 1);
     // per-lane constants of the Hamiltonian
     Coef<T, DYN == 4 ? 0 : DYN, N> cf;
     if constexpr (DYN != 4 && PASS == 0) cf = make_coef<T, DYN, N>(s, ii);
@@ -511,9 +514,25 @@ __global__ __launch_bounds__(kBlock) void stage_point_kernel(const SolveDesc *__
         pe_s = tab_sin(s, 2, ii[2]);
         if constexpr (PASS == 0) {
             if (!s.global_alpha) {
+                // fold the partial boxes: lane l reads slot l, then a wave
+                // butterfly leaves the box in every lane
+                const uint64_t *bx = s.box + 6 * kBoxSlots * box_buf + 6 * (threadIdx.x & 63);
+#pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    bmin[d] = box_val(s.box[d]);
-                    bmax[d] = box_val(s.box[3 + d]);
+                    double a = box_val(bx[d]), b = box_val(bx[3 + d]);
+                    for (int o2 = 32; o2 >= 1; o2 >>= 1) {
+                        a = fmin(a, __shfl_xor(a, o2, 64));
+                        b = fmax(b, __shfl_xor(b, o2, 64));
+                    }
+                    bmin[d] = a;
+                    bmax[d] = b;
+                }
+                // empty the other buffer for the next stage's box pass (the
+                // passes of this stage read or wrote only this one)
+                if (lt == 0) {
+                    uint64_t *nx = s.box + 6 * kBoxSlots * (box_buf ^ 1);
+                    for (int e = threadIdx.x; e < 6 * kBoxSlots; e += kBlock)
+                        nx[e] = box_key(e % 6 < 3 ? INFINITY : -INFINITY);
                 }
             }
         }
@@ -629,7 +648,11 @@ __global__ __launch_bounds__(kBlock) void stage_point_kernel(const SolveDesc *__
         if (active) out[o] = v;
     }
     if constexpr (PASS == 1) {
-        // wave reduction, then one atomic per wave and bound
+        // wave reduction, then across the block's waves in LDS, then one
+        // atomic per block and bound (the box has 2N addresses for the whole
+        // grid: per-wave atomics would queue on them)
+        __shared__ double red[kBlock / 64][2 * N];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
         for (int d = 0; d < N; ++d) {
             double a = mn[d], b = mx[d];
@@ -637,24 +660,22 @@ __global__ __launch_bounds__(kBlock) void stage_point_kernel(const SolveDesc *__
                 a = fmin(a, __shfl_xor(a, o2, 64));
                 b = fmax(b, __shfl_xor(b, o2, 64));
             }
-            if ((threadIdx.x & 63) == 0) {
-                atomicMin((unsigned long long *)&s.box[d], (unsigned long long)box_key(a));
-                atomicMax((unsigned long long *)&s.box[N + d], (unsigned long long)box_key(b));
+            if (lane == 0) {
+                red[wave][d] = a;
+                red[wave][N + d] = b;
             }
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * N) {
+            const int e = threadIdx.x;
+            double v = red[0][e];
+            for (int w = 1; w < kBlock / 64; ++w) v = e < N ? fmin(v, red[w][e]) : fmax(v, red[w][e]);
+            uint64_t *bx = s.box + 6 * kBoxSlots * box_buf + 6 * (blockIdx.x % kBoxSlots);
+            if (e < N) atomicMin((unsigned long long *)&bx[e], (unsigned long long)box_key(v));
+            else atomicMax((unsigned long long *)&bx[e], (unsigned long long)box_key(v));
         }
     } else {
         if (bad) atomicOr(s.flags, 1);
-    }
-}
-
-// Empty the costate box of the listed solves (before a box pass).
-__global__ void box_reset_kernel(const SolveDesc *__restrict__ descs, int nsolves) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nsolves) return;
-    const SolveDesc &s = descs[i];
-    for (int d = 0; d < 3; ++d) {
-        s.box[d] = box_key(INFINITY);
-        s.box[3 + d] = box_key(-INFINITY);
     }
 }
 
@@ -1077,6 +1098,8 @@ __global__ void init_kernel(const SolveDesc *__restrict__ descs, int nsolves) {
     for (int d = 0; d < kMaxDim; ++d) s.amax[d] = 0.0;
     *s.flags = 0;
     *s.step = 0;
+    if (s.box)  // costate box buffer of the first stage
+        for (int e = 0; e < 6 * kBoxSlots; ++e) s.box[e] = box_key(e % 6 < 3 ? INFINITY : -INFINITY);
     *s.nsteps = 0;
 }
 
@@ -1422,11 +1445,6 @@ hipError_t launch_set_slice(int precision, SolveDesc *d, int iv, hipStream_t st)
         hipLaunchKernelGGL(set_slice_kernel<float>, dim3(1), dim3(64), 0, st, d, iv);
     else
         hipLaunchKernelGGL(set_slice_kernel<double>, dim3(1), dim3(64), 0, st, d, iv);
-    return hipGetLastError();
-}
-
-hipError_t launch_box_reset(const SolveDesc *d, int nsolves, hipStream_t st) {
-    hipLaunchKernelGGL(box_reset_kernel, dim3((nsolves + 255) / 256), dim3(256), 0, st, d, nsolves);
     return hipGetLastError();
 }
 

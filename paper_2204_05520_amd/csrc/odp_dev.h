@@ -14,6 +14,8 @@ namespace odp {
 constexpr int kMaxDim = 6;
 constexpr int kBlock = 256;          // threads per stage block (4 wave64s)
 constexpr int kNumXcd = 8;           // MI355X: 8 XCDs, blocks dealt round robin
+constexpr int kBoxSlots = 64;        // costate box: partial boxes per buffer (blocks
+                                     // spread their atomics over them)
 
 // n / d for n < 2^31 as (mulhi(n, m) + n) >> s (round-up magic number).
 struct FastDiv {
@@ -80,8 +82,10 @@ struct SolveDesc {
     int64_t *nsteps;         // device: step count of the schedule
     int64_t *step;           // device: next step to take (server ticks)
     int32_t *flags;          // bit 0: non-finite value produced
-    uint64_t *box;           // costate box of the current stage (pursuit-evasion):
-                             // order-preserving keys of D_min[3], then D_max[3]
+    uint64_t *box;           // costate box (pursuit-evasion only, else null): two
+                             // buffers, used by alternate stages, of kBoxSlots
+                             // partial boxes of 6 order-preserving keys each
+                             // (D_min[3], then D_max[3])
     // ---- computation method: after every full step (the last stage) V is
     // compared with a reference point by point and replaced by the smaller
     // (or larger) of the two; then, optionally, again with an obstacle array

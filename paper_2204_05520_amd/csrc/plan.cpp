@@ -12,7 +12,7 @@ namespace odp {
 
 namespace {
 
-constexpr size_t kStateBytes = 256;  // alpha^max[6], nsteps, step, flags; costate box at 128
+constexpr size_t kStateBytes = 256;  // alpha^max[6], nsteps, step, flags
 
 int64_t step_capacity(const odp_grid *g, const odp_dynamics *dyn, const std::vector<double> &tau,
                       double cfl, double max_dt) {
@@ -128,6 +128,10 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         off += align256(size_t(it.max_steps) * 8);
         it.land_off = off;
         off += align256(size_t(it.max_steps) * 4);
+        if (it.dyn.id == ODP_DYN_PE3D) {
+            it.box_off = off;
+            off += align256(size_t(2 * kBoxSlots * 6) * 8);
+        }
     }
     p.arr_begin = off;
     for (auto &it : p.items) {
@@ -196,7 +200,7 @@ void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &
         s.nsteps = (int64_t *)(state + kMaxDim * 8);
         s.step = (int64_t *)(state + kMaxDim * 8 + 8);
         s.flags = (int32_t *)(state + kMaxDim * 8 + 16);
-        s.box = (uint64_t *)(state + 128);
+        s.box = it.dyn.id == ODP_DYN_PE3D ? (uint64_t *)(base + it.box_off) : nullptr;
         const size_t tab_off = it.aux_off + kStateBytes;
         const size_t tau_off = tab_off + align256(size_t(it.tab_entries) * 8);
         s.tabd = (const double *)(base + tab_off);
@@ -337,8 +341,7 @@ int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t
             const int kind = stage_kind(gr.rk, j, mk, gr.lds, p.opts.space_order == 2);
             if (gr.dyn == ODP_DYN_PE3D && !p.opts.dissipation) {
                 // Algorithm 1's costate box of this stage's input, then the update
-                if ((rc = check_hip(launch_box_reset(descs, int(p.items.size()), st), "box reset")) ||
-                    (rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, kind | 32, descs, ts, tl, nb, j, 0,
+                if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, kind | 32, descs, ts, tl, nb, j, 0,
                                                  k, p.xcd_group, st),
                                     "box")))
                     return rc;

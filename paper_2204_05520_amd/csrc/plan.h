@@ -39,7 +39,7 @@ struct PlanItem {
     uint32_t tiles = 0;
     int64_t max_steps = 0;
     int tab_entries = 0;
-    size_t aux_off = 0, sched_off = 0, land_off = 0, B_off = 0, C_off = 0;
+    size_t aux_off = 0, sched_off = 0, land_off = 0, box_off = 0, B_off = 0, C_off = 0;
     int64_t nsteps = 0;
 };
 

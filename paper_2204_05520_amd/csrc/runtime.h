@@ -29,8 +29,6 @@ hipError_t launch_alpha(int dyn, int ndim, const SolveDesc *d, int nsolves, int 
 hipError_t launch_init(const SolveDesc *d, int nsolves, hipStream_t st);
 hipError_t launch_sched(const SolveDesc *d, int nsolves, int64_t *nsteps_all, hipStream_t st);
 hipError_t launch_advance(const SolveDesc *d, const int32_t *list, int n, hipStream_t st);
-// Empty the costate boxes of descs[0..n) (pursuit-evasion, before each box pass).
-hipError_t launch_box_reset(const SolveDesc *d, int nsolves, hipStream_t st);
 // Time-varying sets of a single solve: references of descs[0] to slice iv.
 hipError_t launch_set_slice(int precision, SolveDesc *d, int iv, hipStream_t st);
 // Padded members (SolveDesc::Adst_dense set): A to the caller's dense array.
