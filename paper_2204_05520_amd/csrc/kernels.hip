@@ -767,6 +767,202 @@ __device__ __forceinline__ void stp_nt(ODP_GLOBAL T *p, const Pack<T, VEC> &r) {
     }
 }
 
+// Second-order ENO stage with VEC consecutive last-axis points per thread
+// (rows without padding, n_last a multiple of VEC >= 2): the centre, the
+// axis-0 ring (five planes) and the middle axes' neighbours at distance 1 and
+// 2 are one 16-byte pack each for the whole group; along the last axis the
+// group's own values and two scalars on each side give every element its
+// five-node stencil.  Each point's arithmetic is the point-per-lane kernel's
+// (same differences, same ghost substitutions, axes accumulated in the same
+// order), so the two forms give the same bits.
+template <typename T, int DYN, int N, int VEC>
+__global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc *__restrict__ descs,
+                                                                const uint32_t *__restrict__ tile_solve,
+                                                                const uint32_t *__restrict__ tile_local,
+                                                                int stage, int step_from_desc,
+                                                                int64_t fixed_step, int xgroup) {
+    static_assert(N >= 2 && VEC >= 2, "vector form: ndim >= 2, two or more points per thread");
+    using P = Pack<T, VEC>;
+    const uint32_t L = xcd_logical(blockIdx.x, gridDim.x, uint32_t(xgroup));
+    const uint32_t si = tile_solve ? tile_solve[L] : 0u;
+    const uint32_t lt = tile_solve ? tile_local[L] : L;
+    const SolveDesc &s = descs[si];
+
+    const int64_t nsteps = *s.nsteps;
+    const int64_t k = step_from_desc ? *s.step : fixed_step;
+    if (k >= nsteps || stage >= s.rk_order) return;
+
+    const uint32_t cid = lt / s.nqb;
+    const uint32_t qb = lt - cid * s.nqb;
+    const uint32_t Qg = s.Q / VEC;
+    const uint32_t gi = qb * kBlock + threadIdx.x;
+    const bool active = gi < Qg;
+    const uint32_t q = (active ? gi : Qg - 1) * VEC;
+
+    int ii[N];
+    ii[0] = 0;
+    uint32_t rem = q;
+#pragma unroll
+    for (int d = N - 1; d >= 1; --d) {
+        const uint32_t t = fdiv(rem, s.div[d]);
+        ii[d] = int(rem - t * s.div[d].d);
+        rem = t;
+    }
+    // middle axes: offsets of the packs at -2, -1, +1, +2 (periodic wrap
+    // applied); beyond a non-periodic edge: gmask bit 4d + j, offset 0
+    int32_t off[N][4];
+    uint32_t gmask = 0;
+#pragma unroll
+    for (int d = 1; d < N - 1; ++d) {
+        const int32_t st = s.stride[d], nd = s.n[d];
+        const bool per = (s.periodic >> d) & 1u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int sh = j < 2 ? j - 2 : j - 1;
+            const int kk = ii[d] + sh;
+            if (kk >= 0 && kk < nd) off[d][j] = sh * st;
+            else if (per) off[d][j] = ((kk + nd) % nd - ii[d]) * st;
+            else { off[d][j] = 0; gmask |= 1u << (4 * d + j); }
+        }
+    }
+    // last axis: the two nodes before and after the group (il and n_last
+    // are multiples of VEC >= 2, so only a group at a row end reaches past it)
+    const int nl = s.n[N - 1], il = ii[N - 1];
+    const bool perl = (s.periodic >> (N - 1)) & 1u;
+    int32_t xo[4] = {-2, -1, VEC, VEC + 1};
+    bool gxl = false, gxr = false;
+    if (il == 0) {
+        if (perl) { xo[0] = nl - 2; xo[1] = nl - 1; }
+        else { xo[0] = xo[1] = 0; gxl = true; }
+    }
+    if (il + VEC == nl) {
+        if (perl) { xo[2] = -il; xo[3] = 1 - il; }
+        else { xo[2] = xo[3] = 0; gxr = true; }
+    }
+
+    Coef<T, DYN, N> cf[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        int jj[N];
+#pragma unroll
+        for (int d = 0; d < N; ++d) jj[d] = ii[d];
+        jj[N - 1] = il + j;
+        cf[j] = make_coef<T, DYN, N>(s, jj);
+    }
+
+    const T *Wg, *Vng;
+    T *outg;
+    stage_buffers<T>(s, stage, k, Wg, Vng, outg);
+    const ODP_GLOBAL T *W = (const ODP_GLOBAL T *)Wg;
+    const ODP_GLOBAL T *Vn = (const ODP_GLOBAL T *)Vng;
+    ODP_GLOBAL T *out = (ODP_GLOBAL T *)outg;
+    const ODP_GLOBAL T *Z = (const ODP_GLOBAL T *)(s.tvn ? (const void *)Vng : s.tref);
+    const ODP_GLOBAL T *G = (const ODP_GLOBAL T *)s.oref;
+    double wa, wb;
+    rk_weights(s.rk_order, stage, wa, wb);
+    const T ra = T(wa), rb = T(wb);
+    const bool last = stage == s.rk_order - 1;
+    const bool clamp = last && s.tclamp;
+    const bool obst = last && s.obst;
+    const bool tmax = s.tmax, omax = s.omax;
+    const T dt = T(s.dt_sched[k]);
+
+    const int64_t s0 = s.s0;
+    const int n0 = s.n0;
+    const bool per0 = s.periodic & 1u;
+    const int i0b = int(cid) * s.chunk;
+    const int i0e = min(i0b + s.chunk, n0);
+
+    // axis-0 plane j (-2 <= j <= n0 + 1) of this group: wrapped, or ghosts
+    auto ax0 = [&](int j) -> P {
+        if (j >= 0 && j < n0) return ldp<T, VEC>(W + int64_t(j) * s0 + q);
+        if (per0) return ldp<T, VEC>(W + int64_t(j < 0 ? j + n0 : j - n0) * s0 + q);
+        const int b = j < 0 ? 0 : n0 - 1, in = j < 0 ? 1 : n0 - 2;
+        const P vb = ldp<T, VEC>(W + int64_t(b) * s0 + q), vin = ldp<T, VEC>(W + int64_t(in) * s0 + q);
+        P g;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            g.v[e] = (j == -1 || j == n0) ? ghost(vb.v[e], vin.v[e]) : ghost2(vb.v[e], vin.v[e]);
+        return g;
+    };
+    P r0 = ax0(i0b - 2), r1 = ax0(i0b - 1), r2 = ax0(i0b), r3 = ax0(i0b + 1), r4;
+    T nanacc = T(0);
+    for (int i0 = i0b; i0 < i0e; ++i0) {
+        r4 = ax0(i0 + 2);
+        const P wc = r2;
+        const ODP_GLOBAL T *plane = W + int64_t(i0) * s0 + q;
+        Acc<T> acc[VEC];
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            acc[j] = Acc<T>{T(0), T(0)};
+            T dl, dr;
+            eno2_diffs(r0.v[j], r1.v[j], wc.v[j], r3.v[j], r4.v[j], dl, dr);
+            acc_axis<T, DYN, N>(cf[j], 0, dl, dr, acc[j]);
+        }
+#pragma unroll
+        for (int d = 1; d < N - 1; ++d) {
+            P l2 = ldp<T, VEC>(plane + off[d][0]), l1 = ldp<T, VEC>(plane + off[d][1]);
+            P p1 = ldp<T, VEC>(plane + off[d][2]), p2 = ldp<T, VEC>(plane + off[d][3]);
+            const uint32_t gm = (gmask >> (4 * d)) & 15u;
+            if (gm) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    if (gm & 2u) { l1.v[e] = ghost(wc.v[e], p1.v[e]); l2.v[e] = ghost2(wc.v[e], p1.v[e]); }
+                    else if (gm & 1u) l2.v[e] = ghost(l1.v[e], wc.v[e]);
+                    if (gm & 4u) { p1.v[e] = ghost(wc.v[e], l1.v[e]); p2.v[e] = ghost2(wc.v[e], l1.v[e]); }
+                    else if (gm & 8u) p2.v[e] = ghost(p1.v[e], wc.v[e]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                T dl, dr;
+                eno2_diffs(l2.v[j], l1.v[j], wc.v[j], p1.v[j], p2.v[j], dl, dr);
+                acc_axis<T, DYN, N>(cf[j], d, dl, dr, acc[j]);
+            }
+        }
+        // last axis: e[0..VEC+3] = nodes il-2 .. il+VEC+1
+        T e[VEC + 4];
+        e[0] = plane[xo[0]];
+        e[1] = plane[xo[1]];
+        e[VEC + 2] = plane[xo[2]];
+        e[VEC + 3] = plane[xo[3]];
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) e[j + 2] = wc.v[j];
+        if (gxl) { e[1] = ghost(wc.v[0], wc.v[1]); e[0] = ghost2(wc.v[0], wc.v[1]); }
+        if (gxr) { e[VEC + 2] = ghost(wc.v[VEC - 1], wc.v[VEC - 2]); e[VEC + 3] = ghost2(wc.v[VEC - 1], wc.v[VEC - 2]); }
+        const int64_t o = int64_t(i0) * s0 + q;
+        P vn;
+        if (wa != 0.0) vn = ldp_nt<T, VEC>(Vn + o);
+        P zr, gr;
+        if (clamp) zr = ldp_nt<T, VEC>(Z + o);
+        if (obst) gr = ldp_nt<T, VEC>(G + o);
+        P res;
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            T dl, dr;
+            eno2_diffs(e[j], e[j + 1], e[j + 2], e[j + 3], e[j + 4], dl, dr);
+            acc_axis<T, DYN, N>(cf[j], N - 1, dl, dr, acc[j]);
+            const T Lh = acc_finish<T, DYN, N>(cf[j], acc[j]);
+            T v = fma_t(dt, Lh, wc.v[j]);
+            if (wa != 0.0) v = fma_t(ra, vn.v[j], rb * v);
+            if (clamp) {
+                if (tmax ? zr.v[j] > v : zr.v[j] < v) v = zr.v[j];
+            }
+            if (obst) {
+                if (omax ? gr.v[j] > v : gr.v[j] < v) v = gr.v[j];
+            }
+            nanacc = fma_t(v, T(0), nanacc);
+            res.v[j] = v;
+        }
+        if (active) stp_nt<T, VEC>(out + o, res);
+        r0 = r1;
+        r1 = r2;
+        r2 = r3;
+        r3 = r4;
+    }
+    if (nanacc != nanacc && active) atomicOr(s.flags, 1);
+}
+
 // The 4D float32 last stage (V^n, clamp and LDS exchange) is held to 128
 // VGPRs (occupancy 4; two values spill): measured faster than occupancy 3.
 template <typename T, int DYN, int N, int VEC, int KIND>
@@ -1294,9 +1490,14 @@ static hipError_t launch_stage_t(int kind, const SolveDesc *d, const uint32_t *t
                                tl, stage, from_desc, step, xg);
         }
     } else if (kind & 16) {
-        // second-order ENO (point per lane; method flags at run time)
-        hipLaunchKernelGGL((stage_point_kernel<T, DYN, N, 2, 0>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl,
-                           stage, from_desc, step, xg);
+        // second-order ENO (method flags at run time): VEC points per thread
+        // where rows allow it, else point per lane
+        if constexpr (VEC >= 2 && N >= 2 && DYN != 0)
+            hipLaunchKernelGGL((stage_eno2_vec_kernel<T, DYN, N, VEC>), dim3(nblocks), dim3(kBlock), 0, st, d, ts,
+                               tl, stage, from_desc, step, xg);
+        else
+            hipLaunchKernelGGL((stage_point_kernel<T, DYN, N, 2, 0>), dim3(nblocks), dim3(kBlock), 0, st, d, ts,
+                               tl, stage, from_desc, step, xg);
     } else if constexpr (N == 1) {
         hipLaunchKernelGGL((stage_kernel<T, DYN, N>), dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl,
                            stage, from_desc, step, xg);

@@ -59,9 +59,11 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         it.ppad = it.qpad * it.g->n[0];
         it.vec = choose_vec(it.g, prec, it.dyn.id, it.pitch);
         it.lds = uses_lds(it.g->ndim, it.pitch, it.vec);
-        if (opts.space_order == 2 || it.dyn.id == ODP_DYN_PE3D) {  // point-per-lane kernel
-            it.vec = 1;
+        if (it.dyn.id == ODP_DYN_PE3D || (opts.space_order == 2 && it.pitch != nl)) {
+            it.vec = 1;  // point-per-lane kernel (pursuit-evasion; ENO2 on padded rows)
             it.lds = 0;
+        } else if (opts.space_order == 2) {
+            it.lds = 0;  // ENO2: VEC points per thread, no LDS exchange
         }
         total += it.ppad;
     }

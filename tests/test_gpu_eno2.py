@@ -145,12 +145,14 @@ def test_eno2_launch_shapes_bitwise(odp):
 
 def test_eno2_server_equals_alone(odp):
     """Served second-order requests (rows padded to the vector width on the
-    server's side) equal the same requests solved alone."""
+    server's side: the point-per-lane kernel) equal the same requests solved
+    alone (rows of 14 and 18 points: the two-point vector kernel), bit for
+    bit."""
     import time
     import torch
     srv = odp.Server(1 << 30, 4, precision=32, rk_order=2, space_order=2)
     try:
-        specs = [W.config_dubins3d(n=(21, 19, 15), T=0.5), W.config_dubins3d(n=(17, 23, 13), T=0.7)]
+        specs = [W.config_dubins3d(n=(21, 19, 14), T=0.5), W.config_dubins3d(n=(17, 23, 18), T=0.7)]
         tickets = [srv.submit(s, W.make_v0(s), rk_order=2) for s in specs]
         for s, t in zip(specs, tickets):
             out = np.empty(tuple(s.grid.n), np.float32)
