@@ -67,6 +67,10 @@ def _load():
         lib.oracle_hamiltonian.restype = ctypes.c_int
         lib.oracle_hamiltonian.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            _dp, ctypes.c_long, _dp, _dp, _dp]
+        lib.oracle_ttr_solve.restype = ctypes.c_int
+        lib.oracle_ttr_solve.argtypes = [
+            ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp,
+            ctypes.c_double, ctypes.c_double, ctypes.c_long, _dp, _lp, _dp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         _lib = lib
@@ -264,3 +268,32 @@ def hamiltonian(dyn, ndim, z, p):
     if rc != 0:
         raise ValueError("oracle_hamiltonian rejected its arguments")
     return H
+
+
+@dataclass
+class TTRResult:
+    phi: np.ndarray
+    iters: int
+    change: float
+
+
+def ttr_solve(grid, dyn, target, eps=1e-9, max_iters=100000, big=1e4) -> TTRResult:
+    """Time-to-reach by Lax-Friedrichs sweeping; target: l(z) on the grid
+    (the target set is l <= 0).  dyn's u_mode / d_mode say which player
+    minimises the time (u_mode 0) and which maximises it (d_mode 1)."""
+    lib = _load()
+    n, lo, hi, per = _grid_args(grid)
+    tg = _arr(target, np.float64).reshape(-1)
+    P = int(np.prod(n))
+    if tg.size != P:
+        raise ValueError("target size does not match the grid")
+    phi = np.empty(P, dtype=np.float64)
+    it = ctypes.c_long(0)
+    ch = ctypes.c_double(0)
+    p = _params(dyn)
+    rc = lib.oracle_ttr_solve(grid.ndim, _ptr(n, _lp), _ptr(lo, _dp), _ptr(hi, _dp), _ptr(per, _ip),
+                              dyn.id, dyn.u_mode, dyn.d_mode, _ptr(p, _dp), _ptr(tg, _dp), big, eps,
+                              max_iters, _ptr(phi, _dp), ctypes.byref(it), ctypes.byref(ch))
+    if rc != 0:
+        raise ValueError("oracle_ttr_solve rejected its arguments")
+    return TTRResult(phi.reshape(tuple(int(x) for x in n)), int(it.value), ch.value)

@@ -762,6 +762,111 @@ int oracle_step_at(int ndim, const long *n, const double *lo, const double *hi,
     return 0;
 }
 
+/* ------------------------------------------ time-to-reach (static HJ) */
+
+/* Time-to-reach by Lax-Friedrichs sweeping (the Time-independent HJ PDE
+ * subsection and its Algorithm 2, after the cited sweeping method).  The TTR
+ * phi solves  min_u max_d grad(phi) . f(z, u, d) = -1  outside the target,
+ * phi = 0 on it.  Solving the Lax-Friedrichs numerical Hamiltonian of that
+ * equation for phi_i gives the explicit point update
+ *   phi_i <- min(phi_i, [1 + H + sum_d sigma_d (phi_{i+e_d} + phi_{i-e_d}) / (2 dx_d)]
+ *                        / sum_d sigma_d / dx_d)
+ * with H = pbar . f(z, u*, d*) at the centred costate pbar_d =
+ * (phi_{i+e_d} - phi_{i-e_d}) / (2 dx_d) (u* minimising, d* maximising: the
+ * caller passes those modes) and sigma_d = alpha_d(z), the largest |f_d|.
+ * Readings: phi starts at 0 on the target (l(z) <= 0) and at `big`
+ * elsewhere; target nodes stay 0; each iteration is one Gauss-Seidel sweep
+ * over the nodes in row-major order, alternately forward and backward,
+ * updating nodes off every non-periodic edge; then every node on a
+ * non-periodic edge of axis d (axes in order) takes
+ *   phi <- min(max(2 phi_a - phi_b, phi_b), phi)
+ * with a, b the next two nodes inward along d; the iteration stops when the
+ * largest change of an iteration is below eps (or after max_iters).  A node
+ * with sum_d sigma_d = 0 keeps its value. */
+int oracle_ttr_solve(int ndim, const long *n, const double *lo, const double *hi,
+                     const int *periodic, int dyn_id, int u_mode, int d_mode,
+                     const double *params, const double *target, double big, double eps,
+                     long max_iters, double *phi, long *iters_out, double *change_out)
+{
+    og_grid g;
+    og_dyn dy;
+    if (og_setup(&g, &dy, ndim, n, lo, hi, periodic, dyn_id, u_mode, d_mode, params)) return -1;
+    if (og_box_dynamics(&dy) || !(eps > 0.0) || max_iters < 1) return -1;
+    const long P = g.npts;
+    const int N = g.ndim;
+    for (long i = 0; i < P; ++i) phi[i] = target[i] <= 0.0 ? 0.0 : big;
+    double *old = (double *)malloc(sizeof(double) * (size_t)P);
+    if (!old) return -1;
+    long it = 0;
+    double change = INFINITY;
+    while (it < max_iters) {
+        memcpy(old, phi, sizeof(double) * (size_t)P);
+        const int backward = (int)(it & 1);
+        for (long k = 0; k < P; ++k) {
+            const long i = backward ? P - 1 - k : k;
+            if (target[i] <= 0.0) continue;
+            long ii[OG_MAXD] = {0};
+            og_unravel(&g, i, ii);
+            int edge = 0;
+            for (int d = 0; d < N; ++d)
+                if (!g.periodic[d] && (ii[d] == 0 || ii[d] == g.n[d] - 1)) edge = 1;
+            if (edge) continue;
+            double z[OG_MAXD] = {0}, pbar[OG_MAXD], nsum[OG_MAXD];
+            og_state(&g, ii, z);
+            og_field F = {og_get_array, phi, NULL, 0};
+            for (int d = 0; d < N; ++d) {
+                const double r = og_neighbor(&g, &F, i, ii, d, +1);
+                const double l = og_neighbor(&g, &F, i, ii, d, -1);
+                pbar[d] = (r - l) / (2.0 * g.dx[d]);
+                nsum[d] = r + l;
+            }
+            double u[OG_MAXD] = {0}, dd[OG_MAXD] = {0}, f[OG_MAXD], sig[OG_MAXD];
+            og_opt_inputs(&dy, N, z, pbar, u, dd);
+            og_dynamics(&dy, N, z, u, dd, f);
+            og_alpha(&dy, N, z, sig);
+            double H = 0.0, num = 1.0, den = 0.0;
+            for (int d = 0; d < N; ++d) H += pbar[d] * f[d];
+            num += H;
+            for (int d = 0; d < N; ++d) {
+                num += sig[d] * nsum[d] / (2.0 * g.dx[d]);
+                den += sig[d] / g.dx[d];
+            }
+            if (den > 0.0) {
+                const double cand = num / den;
+                if (cand < phi[i]) phi[i] = cand;
+            }
+        }
+        /* edges of the non-periodic axes, axis by axis */
+        for (int d = 0; d < N; ++d) {
+            if (g.periodic[d]) continue;
+            for (long i = 0; i < P; ++i) {
+                if (target[i] <= 0.0) continue;
+                long ii[OG_MAXD] = {0};
+                og_unravel(&g, i, ii);
+                const long s = g.stride[d];
+                long a, b;
+                if (ii[d] == 0) { a = i + s; b = i + 2 * s; }
+                else if (ii[d] == g.n[d] - 1) { a = i - s; b = i - 2 * s; }
+                else continue;
+                double e = 2.0 * phi[a] - phi[b];
+                if (phi[b] > e) e = phi[b];
+                if (e < phi[i]) phi[i] = e;
+            }
+        }
+        change = 0.0;
+        for (long i = 0; i < P; ++i) {
+            const double c = fabs(phi[i] - old[i]);
+            if (c > change) change = c;
+        }
+        ++it;
+        if (change < eps) break;
+    }
+    free(old);
+    if (iters_out) *iters_out = it;
+    if (change_out) *change_out = change;
+    return 0;
+}
+
 /* alpha over a costate box and over all inputs at m states z (row-major,
  * m x ndim): test access to the dissipation coefficients. */
 int oracle_alpha_box(int ndim, int dyn_id, int u_mode, int d_mode, const double *params, long m,

@@ -71,6 +71,9 @@ MUTANTS = [
      "f[0] = -dy->p[1] + dy->p[0] * cos(z[2]) + u[0] * z[1];"),
     ("costate_box_not_used", "static int og_box_dynamics(const og_dyn *dy) { return dy->id == OG_PE3D; }",
      "static int og_box_dynamics(const og_dyn *dy) { return dy->id < 0; }"),
+    ("ttr_right_side_dropped", "double H = 0.0, num = 1.0, den = 0.0;", "double H = 0.0, num = 0.0, den = 0.0;"),
+    ("ttr_hamiltonian_sign", "num += H;", "num -= H;"),
+    ("ttr_sigma_not_used_in_sum", "num += sig[d] * nsum[d] / (2.0 * g.dx[d]);", "num += nsum[d] / (2.0 * g.dx[d]);"),
     ("last_step_not_clipped", "dt = tau[k] - t;", "dt = dt + 0.0;"),
     ("control_bound_for_disturbance", "dd[0] = og_bang(pbar[5], dy->p[3], dy->d_mode);",
      "dd[0] = og_bang(pbar[5], dy->p[1], dy->d_mode);"),
@@ -106,6 +109,9 @@ FAST_PINS = [
     pins.test_pin11_pe3d_without_turning_is_drift,
     pins.test_pin11_pe3d_one_step_with_known_box,
     pins.test_pin11_pe3d_mirror_symmetry,
+    pins.test_pin12_ttr_ball_closed_form_first_order,
+    pins.test_pin12_ttr_speed_scaling,
+    pins.test_pin12_ttr_dubins_straight_ahead,
     lambda o: [pins.test_pin9_restart_reference(o, m, f) for m, f in
                (("minVWithVInit", np.minimum), ("maxVWithVInit", np.maximum), ("minVWithV0", None))],
 ]

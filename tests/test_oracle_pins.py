@@ -639,6 +639,75 @@ def test_pin11_pe3d_mirror_symmetry(oracle_mod):
     assert np.abs(V - W.make_v0(spec)).max() > 0.1
 
 
+# ------------------------------------------------------------------ pin 12
+# Time-to-reach by Lax-Friedrichs sweeping (Algorithm 2).
+
+def _ball_ttr(nn, u_max=1.0, r=1.0):
+    g = W.GridSpec([nn, nn], [-4.0, -4.0], [4.0, 4.0], [0, 0])
+    d = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [u_max, 0.0, 0.0], W.MINIMISE, W.MAXIMISE)
+    return g, d, W.cylinder_v0(g, r)
+
+
+def test_pin12_ttr_ball_closed_form_first_order(oracle_mod):
+    """|u| <= u_max in 2D, disc target of radius 1: the time to reach is
+    max(|z| - 1, 0) / u_max.  The sweeping solution converges to it at first
+    order (max and mean error)."""
+    errs = []
+    for nn in (41, 81, 161):
+        g, d, l = _ball_ttr(nn)
+        r = oracle_mod.ttr_solve(g, d, l, eps=1e-10)
+        assert r.change < 1e-10
+        exact = np.maximum(l, 0.0)
+        errs.append((np.abs(r.phi - exact).max(), np.abs(r.phi - exact).mean()))
+        assert np.all(r.phi[l <= 0] == 0.0)
+    for k in (0, 1):
+        rates = [math.log2(errs[i][k] / errs[i + 1][k]) for i in range(2)]
+        for rt in rates:
+            assert 0.7 <= rt <= 1.3, (k, rates, errs)
+    assert errs[-1][0] < 0.08
+
+
+def test_pin12_ttr_speed_scaling(oracle_mod):
+    """Doubling the speed bound halves the time to reach: every term of the
+    update scales by a power of two, so the converged fields agree to the
+    stopping tolerance."""
+    g, d1, l = _ball_ttr(61, 1.0)
+    _, d2, _ = _ball_ttr(61, 2.0)
+    a = oracle_mod.ttr_solve(g, d1, l, eps=1e-11).phi
+    b = oracle_mod.ttr_solve(g, d2, l, eps=1e-11).phi
+    assert np.abs(b - 0.5 * a).max() < 1e-8
+
+
+def test_pin12_ttr_monotone_in_target(oracle_mod):
+    """A larger target is reached no later, node by node."""
+    g, d, l1 = _ball_ttr(61, 1.0, r=1.0)
+    l2 = W.cylinder_v0(g, 1.5)
+    a = oracle_mod.ttr_solve(g, d, l1, eps=1e-10).phi
+    b = oracle_mod.ttr_solve(g, d, l2, eps=1e-10).phi
+    assert np.all(b <= a + 1e-9)
+    assert np.abs(a - b).max() > 0.3
+
+
+def test_pin12_ttr_dubins_straight_ahead(oracle_mod):
+    """Dubins car (v = 1, |w| <= 1, time-minimising turn), disc target of
+    radius 1: from a state on the x axis heading straight at the target the
+    time to reach is (|x| - 1) / v; the sweeping solution sits within a
+    first-order band of it, and no state is reached faster than its
+    straight-line distance allows."""
+    g = W.GridSpec([41, 41, 32], [-4.0, -4.0, -np.pi], [4.0, 4.0, np.pi], [0, 0, 1])
+    d = W.DynSpec(W.DYN_DUBINS3D, [1.0, 1.0], W.MINIMISE, W.MAXIMISE)
+    l = W.cylinder_v0(g, 1.0)
+    r = oracle_mod.ttr_solve(g, d, l, eps=1e-9)
+    x = g.axis(0)
+    # heading pi (index 0: -pi) from x > 1 on y = 0 drives straight at the target
+    j0 = 20
+    sel = (x > 1.2) & (x < 3.6)
+    got = r.phi[sel, j0, 0]
+    exact = x[sel] - 1.0
+    assert np.abs(got - exact).max() < 0.2, np.abs(got - exact).max()
+    assert np.all(r.phi >= np.maximum(l, 0.0) - 1e-9)
+
+
 # ------------------------------------------------------------------ golden
 
 def test_golden_cfl_steps(oracle_mod):
