@@ -10,8 +10,9 @@ Default workload: the 4D dynamic car, 80^4 nodes on [-5,5]^2 x [0,4] x
 [-pi,pi), |a| <= 1, |w| <= 1, disc target r = 0.5, TVD-RK3, CFL 0.8,
 horizon 3 s, tube (BRT).  Other workloads (--workload): dubins3d (60x60x36,
 float64 form), game6d (36^6, RK2), pe3d (the 3D relative pursuit-evasion
-game, 100^3, horizon 1.5, first order, costate box per stage), batch (512
-Dubins solves), serve.
+game, 100^3, horizon 1.5, first order, costate box per stage), ttr3d (time
+to reach by Lax-Friedrichs sweeping, Dubins 100^3), batch (512 Dubins
+solves), serve.
 --space-order 2 runs a single-solve workload with second-order ENO
 differences and, unless --rk says otherwise, TVD-RK2 (the paper's
 second-order pairing).
@@ -180,6 +181,64 @@ def bench_single(args, W, odp):
     return line
 
 
+def bench_ttr(args, W, odp):
+    """Time to reach by Lax-Friedrichs sweeping (Jacobi form) for the Dubins
+    car (v = 1, |w| <= 1, the turn minimising the time), 100^3 on
+    [-4,4]^2 x [-pi,pi), disc target of radius 1, eps 1e-5 (the paper's TTR
+    example), float32 and float64; one step = one solve to convergence."""
+    import numpy as np
+    import torch
+    n = args.n or 100
+    g = W.GridSpec([n, n, n], [-4.0, -4.0, -W.PI], [4.0, 4.0, W.PI], [0, 0, 1])
+    d = W.DynSpec(W.DYN_DUBINS3D, [1.0, 1.0], W.MINIMISE, W.MAXIMISE)
+    l = W.cylinder_v0(g, 1.0)
+    st = torch.cuda.Stream()
+    res = {}
+    for prec in (32, 64):
+        dt = torch.float32 if prec == 32 else torch.float64
+        tg = torch.tensor(l, dtype=dt, device="cuda:0")
+        with torch.cuda.stream(st):
+            for _ in range(max(args.warmup, 1)):
+                _, s_ = odp.ttr_solve(g, d, tg, precision=prec, eps=1e-5, stream=st)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, s_ = odp.ttr_solve(g, d, tg, precision=prec, eps=1e-5, stream=st)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / args.steps
+        res[prec] = {"ms_per_solve": wall * 1e3, "iters": s_["iters"], "kernel_ms": s_["kernel_ms"],
+                     "pt_updates_per_s": g.npts * s_["iters"] / wall,
+                     "achieved_gbps": s_["alg_bytes"] / (s_["kernel_ms"] * 1e6),
+                     "us_per_iter": s_["kernel_ms"] * 1e3 / s_["iters"]}
+        print(f"# ttr fp{prec}: {res[prec]}", file=sys.stderr, flush=True)
+    r = res[32]
+    line = {
+        "metric": METRIC, "value": r["pt_updates_per_s"], "unit": "grid-point updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_solve"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ttr_dubins3d_{n}x{n}x{n}", "eps": 1e-5, "iterations": r["iters"]},
+        "roofline": {"bound": "hbm", "achieved": r["achieved_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": r["achieved_gbps"] / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "ttr_kernel fp32 (one Jacobi sweep per launch)",
+                     "avg_launch_us": r["us_per_iter"]},
+        "fp64_value": res[64]["pt_updates_per_s"], "fp64_ms_per_step": res[64]["ms_per_solve"],
+        "fp64_iterations": res[64]["iters"],
+    }
+    if not args.no_cpu:
+        import oracle
+        oracle.build(force=False)
+        gs = W.GridSpec([40, 40, 40], [-4.0, -4.0, -W.PI], [4.0, 4.0, W.PI], [0, 0, 1])
+        t0 = time.perf_counter()
+        o = oracle.ttr_solve(gs, d, W.cylinder_v0(gs, 1.0), eps=1e-5)
+        wall = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": gs.npts * o.iters / wall, "unit": "grid-point updates/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"Gauss-Seidel sweeps of the same problem at 40^3 to eps 1e-5: "
+                                          f"{o.iters} sweeps, {wall:.1f} s (the sweep is serial)"}
+    return line
+
+
 def bench_batch(args, W, odp):
     """512 Dubins solves of uneven grids in one odp_hj_batch call (float32),
     beside the same solves run one by one in float64 through odp_hj_solve."""
@@ -314,7 +373,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dyncar4d",
-                    choices=["dyncar4d", "dubins3d", "game6d", "pe3d", "batch", "serve"])
+                    choices=["dyncar4d", "dubins3d", "game6d", "pe3d", "ttr3d", "batch", "serve"])
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--tile-chunk", type=int, default=-1,
                     help="planes per block; -1 (default): the library's autotuner, which times "
@@ -350,6 +409,8 @@ def main():
         line = bench_single(args, W, odp)
     elif args.workload == "batch":
         line = bench_batch(args, W, odp)
+    elif args.workload == "ttr3d":
+        line = bench_ttr(args, W, odp)
     else:
         line = bench_serve(args, W, odp)
     print(json.dumps(line), flush=True)

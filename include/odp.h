@@ -257,6 +257,54 @@ int odp_hj_batch(int nsolves, const odp_solve_desc *descs, const odp_solve_opts 
                  void *workspace_dev, size_t workspace_bytes,
                  odp_solve_stats *stats_per_solve);
 
+/* --------------------------------------------------------- time to reach */
+
+/* Time to reach the target set {z : l(z) <= 0} (the Time-independent HJ PDE
+ * subsection, Algorithm 2: Lax-Friedrichs sweeping), as the fixed point of
+ * the explicit Lax-Friedrichs point update of  min_u max_d grad(phi) . f = -1,
+ * phi = 0 on the target:
+ *   phi_i <- min(phi_i, [1 + H + sum_d sigma_d (phi_{i+e_d} + phi_{i-e_d}) / (2 dx_d)]
+ *                        / sum_d sigma_d / dx_d),
+ * H = pbar . f(z, u*, d*) at the centred costate, sigma_d = max |f_d|; nodes
+ * on a non-periodic edge take min(phi, max(2 phi_a - phi_b, phi_b)) (a, b the
+ * next two nodes inward).  The paper sweeps Gauss-Seidel on the CPU; here
+ * each iteration updates every node from the previous iterate (Jacobi),
+ * which converges to the same fixed point.  The control minimises the time:
+ * pass dyn->u_mode = 0 (and d_mode = 1 for a disturbance that maximises it).
+ * The pursuit-evasion model is not available (ODP_EUNSUPPORTED). */
+typedef struct {
+    int32_t precision;   /* 32 or 64: element type of target and phi */
+    int32_t check_every; /* iterations between convergence checks (0: 32) */
+    double eps;          /* stop once an iteration changes no node by eps or more */
+    int64_t max_iters;   /* >= 1 */
+    double big;          /* start value off the target (0: 1e4, the paper's) */
+    void *stream;        /* hipStream_t (NULL: null stream) */
+} odp_ttr_opts;
+
+typedef struct {
+    int64_t iters;        /* iterations run (a multiple of check_every, or max_iters) */
+    double last_change;   /* largest change of the last iteration */
+    double kernel_ms;     /* device time of the iterations */
+    double alg_bytes;     /* 3 arrays per node and iteration */
+    double alg_gbps;
+    double roofline_frac; /* alg_gbps / 8000 */
+    int32_t converged;    /* 1 if an iteration's largest change fell below eps */
+    int32_t pad_;
+} odp_ttr_stats;
+
+/* Device workspace bytes for odp_ttr_solve (0 for invalid arguments). */
+size_t odp_ttr_workspace_bytes(const odp_grid *grid, const odp_ttr_opts *opts);
+
+/* target_dev: l(z) on the grid (device, read only); phi_out_dev: receives
+ * the time to reach (device, may not alias target).  workspace_dev: NULL
+ * (library allocates stream-ordered) or odp_ttr_workspace_bytes bytes,
+ * 256-byte aligned.  Blocks once per check_every iterations to test
+ * convergence; returns ODP_OK also when max_iters ran out (stats->converged
+ * says which). */
+int odp_ttr_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *target_dev,
+                  const odp_ttr_opts *opts, void *workspace_dev, size_t workspace_bytes,
+                  void *phi_out_dev, odp_ttr_stats *stats);
+
 /* ----------------------------------------------------------------- serve */
 
 /* In-process continuous-batching server.  A scheduler thread admits queued

@@ -70,7 +70,7 @@ def _load():
         lib.oracle_ttr_solve.restype = ctypes.c_int
         lib.oracle_ttr_solve.argtypes = [
             ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp,
-            ctypes.c_double, ctypes.c_double, ctypes.c_long, _dp, _lp, _dp]
+            ctypes.c_double, ctypes.c_double, ctypes.c_long, ctypes.c_int, _dp, _lp, _dp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         _lib = lib
@@ -277,10 +277,12 @@ class TTRResult:
     change: float
 
 
-def ttr_solve(grid, dyn, target, eps=1e-9, max_iters=100000, big=1e4) -> TTRResult:
+def ttr_solve(grid, dyn, target, eps=1e-9, max_iters=100000, big=1e4, jacobi=False) -> TTRResult:
     """Time-to-reach by Lax-Friedrichs sweeping; target: l(z) on the grid
     (the target set is l <= 0).  dyn's u_mode / d_mode say which player
-    minimises the time (u_mode 0) and which maximises it (d_mode 1)."""
+    minimises the time (u_mode 0) and which maximises it (d_mode 1).
+    jacobi: every node of an iteration from the previous iterate (the
+    parallel form) instead of the Gauss-Seidel sweep."""
     lib = _load()
     n, lo, hi, per = _grid_args(grid)
     tg = _arr(target, np.float64).reshape(-1)
@@ -293,7 +295,8 @@ def ttr_solve(grid, dyn, target, eps=1e-9, max_iters=100000, big=1e4) -> TTRResu
     p = _params(dyn)
     rc = lib.oracle_ttr_solve(grid.ndim, _ptr(n, _lp), _ptr(lo, _dp), _ptr(hi, _dp), _ptr(per, _ip),
                               dyn.id, dyn.u_mode, dyn.d_mode, _ptr(p, _dp), _ptr(tg, _dp), big, eps,
-                              max_iters, _ptr(phi, _dp), ctypes.byref(it), ctypes.byref(ch))
+                              max_iters, 1 if jacobi else 0, _ptr(phi, _dp), ctypes.byref(it),
+                              ctypes.byref(ch))
     if rc != 0:
         raise ValueError("oracle_ttr_solve rejected its arguments")
     return TTRResult(phi.reshape(tuple(int(x) for x in n)), int(it.value), ch.value)

@@ -782,11 +782,17 @@ int oracle_step_at(int ndim, const long *n, const double *lo, const double *hi,
  *   phi <- min(max(2 phi_a - phi_b, phi_b), phi)
  * with a, b the next two nodes inward along d; the iteration stops when the
  * largest change of an iteration is below eps (or after max_iters).  A node
- * with sum_d sigma_d = 0 keeps its value. */
+ * with sum_d sigma_d = 0 keeps its value.
+ * jacobi != 0: the parallel form instead of the sweep: every node of an
+ * iteration reads the previous iterate only, and a node on the edges of
+ * several axes takes the smallest of their extrapolations.  (The edge rule
+ * keeps the smallest extrapolation an iteration ever produced, and the
+ * extrapolation is not monotone in phi_b, so near non-periodic edges the
+ * limit depends on the order of the updates.) */
 int oracle_ttr_solve(int ndim, const long *n, const double *lo, const double *hi,
                      const int *periodic, int dyn_id, int u_mode, int d_mode,
                      const double *params, const double *target, double big, double eps,
-                     long max_iters, double *phi, long *iters_out, double *change_out)
+                     long max_iters, int jacobi, double *phi, long *iters_out, double *change_out)
 {
     og_grid g;
     og_dyn dy;
@@ -813,7 +819,7 @@ int oracle_ttr_solve(int ndim, const long *n, const double *lo, const double *hi
             if (edge) continue;
             double z[OG_MAXD] = {0}, pbar[OG_MAXD], nsum[OG_MAXD];
             og_state(&g, ii, z);
-            og_field F = {og_get_array, phi, NULL, 0};
+            og_field F = {og_get_array, jacobi ? old : phi, NULL, 0};
             for (int d = 0; d < N; ++d) {
                 const double r = og_neighbor(&g, &F, i, ii, d, +1);
                 const double l = og_neighbor(&g, &F, i, ii, d, -1);
@@ -836,7 +842,9 @@ int oracle_ttr_solve(int ndim, const long *n, const double *lo, const double *hi
                 if (cand < phi[i]) phi[i] = cand;
             }
         }
-        /* edges of the non-periodic axes, axis by axis */
+        /* edges of the non-periodic axes, axis by axis (Jacobi: from the
+         * previous iterate, so the axes' extrapolations just combine by min) */
+        const double *src = jacobi ? old : phi;
         for (int d = 0; d < N; ++d) {
             if (g.periodic[d]) continue;
             for (long i = 0; i < P; ++i) {
@@ -848,8 +856,8 @@ int oracle_ttr_solve(int ndim, const long *n, const double *lo, const double *hi
                 if (ii[d] == 0) { a = i + s; b = i + 2 * s; }
                 else if (ii[d] == g.n[d] - 1) { a = i - s; b = i - 2 * s; }
                 else continue;
-                double e = 2.0 * phi[a] - phi[b];
-                if (phi[b] > e) e = phi[b];
+                double e = 2.0 * src[a] - src[b];
+                if (src[b] > e) e = src[b];
                 if (e < phi[i]) phi[i] = e;
             }
         }

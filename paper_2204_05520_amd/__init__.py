@@ -47,7 +47,7 @@ SYMBOLS = [
     "odp_strerror", "odp_last_error", "odp_grid_create", "odp_grid_destroy", "odp_grid_points",
     "odp_hj_workspace_bytes", "odp_hj_solve", "odp_hj_batch_workspace_bytes", "odp_hj_batch",
     "odp_server_create", "odp_serve_submit", "odp_serve_poll", "odp_serve_cancel",
-    "odp_server_counts", "odp_server_destroy",
+    "odp_server_counts", "odp_server_destroy", "odp_ttr_workspace_bytes", "odp_ttr_solve",
 ]
 
 
@@ -82,6 +82,20 @@ class odp_solve_stats(ctypes.Structure):
     def as_dict(self):
         return {k: (list(getattr(self, k)) if k == "alpha_max" else getattr(self, k))
                 for k, _ in self._fields_ if k != "pad_"}
+
+
+class odp_ttr_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("check_every", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("max_iters", ctypes.c_int64), ("big", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+class odp_ttr_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("last_change", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double), ("alg_gbps", ctypes.c_double),
+                ("roofline_frac", ctypes.c_double), ("converged", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
 
 
 class odp_solve_desc(ctypes.Structure):
@@ -128,6 +142,11 @@ def lib():
             L.odp_hj_batch.argtypes = [i32, ctypes.POINTER(odp_solve_desc),
                                        ctypes.POINTER(odp_solve_opts), vp, ctypes.c_size_t,
                                        ctypes.POINTER(odp_solve_stats)]
+        L.odp_ttr_workspace_bytes.restype = ctypes.c_size_t
+        L.odp_ttr_workspace_bytes.argtypes = [vp, ctypes.POINTER(odp_ttr_opts)]
+        L.odp_ttr_solve.restype = i32
+        L.odp_ttr_solve.argtypes = [vp, ctypes.POINTER(odp_dynamics), vp, ctypes.POINTER(odp_ttr_opts), vp,
+                                    ctypes.c_size_t, vp, ctypes.POINTER(odp_ttr_stats)]
         if hasattr(L, "odp_server_create"):
             L.odp_server_create.restype = i32
             L.odp_server_create.argtypes = [ctypes.c_size_t, i32, ctypes.POINTER(odp_solve_opts),
@@ -300,6 +319,36 @@ def check_device_tensor(x, precision, npts, name):
         raise TypeError(f"{name} must be a device tensor")
     if x.dtype != _torch_dtype(precision) or not x.is_contiguous() or x.numel() != npts:
         raise ValueError(f"{name} must be contiguous {_torch_dtype(precision)} with {npts} elements")
+
+
+def make_ttr_opts(precision=32, eps=1e-6, max_iters=100000, big=1e4, check_every=32,
+                  stream=None) -> odp_ttr_opts:
+    o = odp_ttr_opts()
+    o.precision = precision
+    o.check_every = check_every
+    o.eps = eps
+    o.max_iters = max_iters
+    o.big = big
+    o.stream = stream
+    return o
+
+
+def ttr_solve(grid_spec, dyn, target, precision=32, eps=1e-6, max_iters=100000, big=1e4,
+              check_every=32, stream=None, workspace=None):
+    """Time to reach {l <= 0} (odp_ttr_solve); target: device tensor l(z).
+    Returns (phi tensor, stats dict)."""
+    import torch
+    grid = Grid.from_spec(grid_spec)
+    check_device_tensor(target, precision, grid.npts, "target")
+    o = make_ttr_opts(precision, eps, max_iters, big, check_every, _stream_handle(stream))
+    d = make_dynamics(dyn)
+    out = torch.empty_like(target)
+    st = odp_ttr_stats()
+    ws = None if workspace is None else ctypes.c_void_p(workspace.data_ptr())
+    wsb = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(lib().odp_ttr_solve(grid.handle, ctypes.byref(d), ctypes.c_void_p(target.data_ptr()),
+                               ctypes.byref(o), ws, wsb, ctypes.c_void_p(out.data_ptr()), ctypes.byref(st)))
+    return out, st.as_dict()
 
 
 def solve(spec, V0, precision=32, V_init=None, tau=None, stream=None, save_all=False,

@@ -1286,6 +1286,138 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
     if (nanacc != nanacc && active) atomicOr(s.flags, 1);
 }
 
+// ------------------------------------------------ time-to-reach (static)
+
+// One Jacobi iteration of Lax-Friedrichs sweeping for the time to reach
+// (the Time-independent HJ PDE subsection's Algorithm 2, with the parallel
+// update in place of the serial sweep): from `src` to `dst`, node per lane,
+// plane i0 = blockIdx.y.  Off every non-periodic edge a node takes
+//   min(src_i, [1 + H + sum_d sigma_d (src_{i+e_d} + src_{i-e_d}) / (2 dx_d)]
+//              / sum_d sigma_d / dx_d)
+// with H = pbar . f(z, u*, d*) at the centred costate and sigma_d the
+// largest |f_d|; on a non-periodic edge of axis d it takes
+// min(src_i, max(2 src_a - src_b, src_b)) (a, b the next two nodes inward;
+// the smallest over its edge axes); target nodes (l <= 0) stay 0.  The
+// largest |dst - src| of each block goes to one of kBoxSlots change slots
+// (non-negative doubles order as their bits; the host takes the largest).
+// Arithmetic in float64, stored as T.
+template <typename T, int DYN, int N>
+__global__ __launch_bounds__(kBlock) void ttr_kernel(const SolveDesc *__restrict__ sd, const T *__restrict__ src,
+                                                     T *__restrict__ dst, const T *__restrict__ target,
+                                                     unsigned long long *__restrict__ change) {
+    const SolveDesc &s = *sd;
+    const uint32_t q = blockIdx.x * kBlock + threadIdx.x;
+    const int i0 = int(blockIdx.y);
+    double ch = 0.0;
+    if (q < s.Q) {
+        int ii[N];
+        ii[0] = i0;
+        uint32_t rem = q;
+#pragma unroll
+        for (int d = N - 1; d >= 1; --d) {
+            const uint32_t t = fdiv(rem, s.div[d]);
+            ii[d] = int(rem - t * s.div[d].d);
+            rem = t;
+        }
+        const int64_t o = int64_t(i0) * s.s0 + q;
+        const double old = double(src[o]);
+        double nv = old;
+        if (double(target[o]) <= 0.0) {
+            nv = 0.0;
+        } else {
+            bool edge = false;
+            double eb = old;
+#pragma unroll
+            for (int d = 0; d < N; ++d) {
+                if ((s.periodic >> d) & 1u) continue;
+                const int64_t st = d == 0 ? s.s0 : int64_t(s.stride[d]);
+                const int nd = s.n[d];
+                if (ii[d] == 0 || ii[d] == nd - 1) {
+                    edge = true;
+                    const int64_t sg = ii[d] == 0 ? st : -st;
+                    const double a = double(src[o + sg]), b = double(src[o + 2 * sg]);
+                    double e = 2.0 * a - b;
+                    if (b > e) e = b;
+                    if (e < eb) eb = e;
+                }
+            }
+            if (edge) {
+                nv = eb;
+            } else {
+                double pb[N], ns[N];
+#pragma unroll
+                for (int d = 0; d < N; ++d) {
+                    const int64_t st = d == 0 ? s.s0 : int64_t(s.stride[d]);
+                    const int nd = s.n[d];
+                    const int64_t offr = ii[d] < nd - 1 ? st : -int64_t(nd - 1) * st;  // periodic wrap
+                    const int64_t offl = ii[d] > 0 ? -st : int64_t(nd - 1) * st;
+                    const double r = double(src[o + offr]), l = double(src[o + offl]);
+                    pb[d] = (r - l) / (2.0 * s.dx[d]);
+                    ns[d] = r + l;
+                }
+                double f[N], sig[N];
+                axis_terms<DYN, N>(s, ii, f);
+                alpha_point<DYN, N>(s, ii, sig);
+                double H = 0.0;
+                if constexpr (DYN == 0) {
+                    double n2 = 0.0;
+                    for (int d = 0; d < N; ++d) n2 += pb[d] * pb[d];
+                    const double nrm = sqrt(n2);
+                    const double sg = s.u_mode ? 1.0 : -1.0;
+                    for (int d = 0; d < N; ++d) {
+                        const double u = nrm > 0.0 ? sg * s.p[0] * pb[d] / nrm : 0.0;
+                        H += pb[d] * (f[d] + u);
+                    }
+                } else {
+                    for (int d = 0; d < N; ++d) {
+                        double fd = f[d];
+                        if (axis_kind(DYN, d) == 1) {
+                            const int mx = (DYN == 3 && d == 5) ? s.d_mode : s.u_mode;
+                            fd = mx ? (pb[d] >= 0.0 ? f[d] : -f[d]) : (pb[d] >= 0.0 ? -f[d] : f[d]);
+                        }
+                        H += pb[d] * fd;
+                    }
+                }
+                double num = 1.0 + H, den = 0.0;
+                for (int d = 0; d < N; ++d) {
+                    num += sig[d] * ns[d] / (2.0 * s.dx[d]);
+                    den += sig[d] / s.dx[d];
+                }
+                if (den > 0.0) {
+                    const double cand = num / den;
+                    if (cand < nv) nv = cand;
+                }
+            }
+        }
+        const T out = T(nv);
+        dst[o] = out;
+        ch = fabs(double(out) - old);
+    }
+    // block maximum of the change, one atomic per block
+    __shared__ double red[kBlock / 64];
+    for (int off = 32; off >= 1; off >>= 1) ch = fmax(ch, __shfl_xor(ch, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ch;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < kBlock / 64; ++w) m = fmax(m, red[w]);
+        atomicMax(change + (blockIdx.x + blockIdx.y * gridDim.x) % kBoxSlots,
+                  (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// Start value of the time to reach: 0 on the target (l <= 0), big elsewhere.
+template <typename T>
+__global__ void ttr_init_kernel(const T *__restrict__ target, T *__restrict__ phi, int64_t npts, double big) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < npts) phi[i] = double(target[i]) <= 0.0 ? T(0) : T(big);
+}
+
+__global__ void ttr_zero_kernel(unsigned long long *__restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
 // Zero alpha^max, the flags and the step counter of every listed solve.
 __global__ void init_kernel(const SolveDesc *__restrict__ descs, int nsolves) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1646,6 +1778,57 @@ hipError_t launch_set_slice(int precision, SolveDesc *d, int iv, hipStream_t st)
         hipLaunchKernelGGL(set_slice_kernel<float>, dim3(1), dim3(64), 0, st, d, iv);
     else
         hipLaunchKernelGGL(set_slice_kernel<double>, dim3(1), dim3(64), 0, st, d, iv);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_ttr_t(int dyn, int ndim, const SolveDesc *d, uint32_t qblocks, int n0,
+                               const void *src, void *dst, const void *target, unsigned long long *change,
+                               hipStream_t st) {
+    const dim3 grid(qblocks, uint32_t(n0));
+    const T *sp = (const T *)src, *tp = (const T *)target;
+    T *dp = (T *)dst;
+#define ODP_TTR(DY, NN) hipLaunchKernelGGL((ttr_kernel<T, DY, NN>), grid, dim3(kBlock), 0, st, d, sp, dp, tp, change)
+    switch (dyn) {
+    case 1: ODP_TTR(1, 3); break;
+    case 2: ODP_TTR(2, 4); break;
+    case 3: ODP_TTR(3, 6); break;
+    case 0:
+        switch (ndim) {
+        case 1: ODP_TTR(0, 1); break;
+        case 2: ODP_TTR(0, 2); break;
+        case 3: ODP_TTR(0, 3); break;
+        case 4: ODP_TTR(0, 4); break;
+        case 5: ODP_TTR(0, 5); break;
+        case 6: ODP_TTR(0, 6); break;
+        default: return hipErrorInvalidValue;
+        }
+        break;
+    default: return hipErrorInvalidValue;
+    }
+#undef ODP_TTR
+    return hipGetLastError();
+}
+
+hipError_t launch_ttr(int precision, int dyn, int ndim, const SolveDesc *d, uint32_t qblocks, int n0,
+                      const void *src, void *dst, const void *target, unsigned long long *change,
+                      hipStream_t st) {
+    if (precision == 32) return launch_ttr_t<float>(dyn, ndim, d, qblocks, n0, src, dst, target, change, st);
+    return launch_ttr_t<double>(dyn, ndim, d, qblocks, n0, src, dst, target, change, st);
+}
+
+hipError_t launch_ttr_init(int precision, const void *target, void *phi, int64_t npts, double big,
+                           hipStream_t st) {
+    const dim3 grid(uint32_t((npts + 255) / 256));
+    if (precision == 32)
+        hipLaunchKernelGGL(ttr_init_kernel<float>, grid, dim3(256), 0, st, (const float *)target, (float *)phi, npts, big);
+    else
+        hipLaunchKernelGGL(ttr_init_kernel<double>, grid, dim3(256), 0, st, (const double *)target, (double *)phi, npts, big);
+    return hipGetLastError();
+}
+
+hipError_t launch_ttr_zero(unsigned long long *p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(ttr_zero_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

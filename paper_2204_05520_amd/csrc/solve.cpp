@@ -5,6 +5,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -240,6 +241,150 @@ int odp_hj_batch(int nsolves, const odp_solve_desc *descs, const odp_solve_opts 
         rc = plan_stats(p, base, ms, sorted.data());
         for (size_t i = 0; i < perm.size(); ++i) stats_per_solve[perm[i]] = sorted[i];
         if (rc) return rc;
+    }
+    return ODP_OK;
+}
+
+size_t odp_ttr_workspace_bytes(const odp_grid *grid, const odp_ttr_opts *opts) {
+    if (!grid || !opts || (opts->precision != 32 && opts->precision != 64)) return 0;
+    size_t tab = 0;
+    for (int d = 0; d < grid->ndim; ++d) tab += 3 * size_t(grid->n[d]);
+    const size_t eb = opts->precision == 32 ? 4 : 8;
+    const int K = opts->check_every > 0 ? opts->check_every : 32;
+    return align256(sizeof(SolveDesc)) + align256(tab * 8) + align256(size_t(K) * kBoxSlots * 8) +
+           align256(size_t(grid->npts) * eb);
+}
+
+int odp_ttr_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *target_dev,
+                  const odp_ttr_opts *opts, void *workspace_dev, size_t workspace_bytes,
+                  void *phi_out_dev, odp_ttr_stats *stats) {
+    int rc;
+    if (!grid) return set_error(ODP_EINVAL, "grid is NULL");
+    if (!opts) return set_error(ODP_EINVAL, "opts is NULL");
+    if ((rc = validate_dyn(grid, dyn))) return rc;
+    if (dyn->id == ODP_DYN_PE3D)
+        return set_error(ODP_EUNSUPPORTED, "time to reach: the pursuit-evasion model is not available");
+    if (opts->precision != 32 && opts->precision != 64) return set_error(ODP_EINVAL, "precision must be 32 or 64");
+    if (!(opts->eps > 0.0) || !std::isfinite(opts->eps)) return set_error(ODP_EINVAL, "eps must be > 0");
+    if (opts->max_iters < 1) return set_error(ODP_EINVAL, "max_iters must be >= 1");
+    if (opts->check_every < 0) return set_error(ODP_EINVAL, "check_every must be >= 0");
+    if (!(opts->big >= 0.0) || !std::isfinite(opts->big)) return set_error(ODP_EINVAL, "big must be >= 0");
+    if (!target_dev || !phi_out_dev || target_dev == phi_out_dev)
+        return set_error(ODP_EINVAL, "target and phi_out are required and may not alias");
+    if (grid->n[0] > 65535) return set_error(ODP_EUNSUPPORTED, "axis 0 longer than 65535 nodes");
+    hipStream_t st = (hipStream_t)opts->stream;
+    const int prec = opts->precision;
+    const size_t eb = prec == 32 ? 4 : 8;
+    const int K = opts->check_every > 0 ? opts->check_every : 32;
+    const double big = opts->big > 0.0 ? opts->big : 1e4;
+    const int N = grid->ndim;
+    const int64_t n0 = grid->n[0];
+    const int64_t Q = grid->npts / n0;
+
+    // descriptor: grid, tables and dynamics (what the kernel reads)
+    SolveDesc s;
+    std::memset(&s, 0, sizeof(s));
+    s.ndim = N;
+    s.n0 = int32_t(n0);
+    s.Q = uint32_t(Q);
+    s.s0 = Q;
+    s.npts = grid->npts;
+    s.pitch = int32_t(grid->n[N - 1]);
+    int64_t stv = 1;
+    for (int d = N - 1; d >= 0; --d) {
+        s.n[d] = int32_t(grid->n[d]);
+        s.stride[d] = d > 0 ? int32_t(stv) : 0;
+        s.div[d] = make_fastdiv(uint32_t(grid->n[d]));
+        s.dx[d] = grid->dx[d];
+        s.inv2dx[d] = 1.0 / (2.0 * grid->dx[d]);
+        if (grid->periodic[d]) s.periodic |= 1u << d;
+        stv *= grid->n[d];
+    }
+    s.dyn = dyn->id;
+    s.u_mode = dyn->u_mode;
+    s.d_mode = dyn->d_mode;
+    for (int k = 0; k < 16; ++k) s.p[k] = dyn->p[k];
+    std::vector<double> tab;
+    for (int d = 0; d < N; ++d) {
+        const int nd = int(grid->n[d]);
+        s.tab[d].off = int32_t(tab.size());
+        s.tab[d].n = nd;
+        for (int k = 0; k < nd; ++k) tab.push_back(grid->lo[d] + double(k) * grid->dx[d]);
+        for (int k = 0; k < nd; ++k) tab.push_back(std::cos(grid->lo[d] + double(k) * grid->dx[d]));
+        for (int k = 0; k < nd; ++k) tab.push_back(std::sin(grid->lo[d] + double(k) * grid->dx[d]));
+    }
+
+    const size_t need = odp_ttr_workspace_bytes(grid, opts);
+    DeviceBuffer ws;
+    if ((rc = alloc_workspace(ws, workspace_dev, workspace_bytes, need, st))) return rc;
+    unsigned char *base = (unsigned char *)ws.ptr;
+    const size_t tab_off = align256(sizeof(SolveDesc));
+    const size_t ch_off = tab_off + align256(tab.size() * 8);
+    const size_t buf_off = ch_off + align256(size_t(K) * kBoxSlots * 8);
+    s.tabd = (const double *)(base + tab_off);
+    SolveDesc *d_desc = (SolveDesc *)base;
+    unsigned long long *d_ch = (unsigned long long *)(base + ch_off);
+    void *bufB = base + buf_off;
+    // the host images stay alive until the stream has copied them
+    std::vector<unsigned long long> hch(size_t(K) * kBoxSlots, 0ull);
+    if ((rc = check_hip(hipMemcpyAsync(d_desc, &s, sizeof(s), hipMemcpyHostToDevice, st), "ttr desc")) ||
+        (rc = check_hip(hipMemcpyAsync(base + tab_off, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, st),
+                        "ttr tables")) ||
+        (rc = check_hip(launch_ttr_init(prec, target_dev, phi_out_dev, grid->npts, big, st), "ttr init")))
+        return rc;
+    Timer tm;
+    if ((rc = check_hip(hipEventCreate(&tm.e0), "event")) || (rc = check_hip(hipEventCreate(&tm.e1), "event")))
+        return rc;
+    (void)hipEventRecord(tm.e0, st);
+    const uint32_t qblocks = uint32_t((Q + kBlock - 1) / kBlock);
+    int64_t it = 0;
+    double last = INFINITY;
+    bool converged = false;
+    void *cur = phi_out_dev, *nxt = bufB;
+    while (it < opts->max_iters && !converged) {
+        const int nb = int(std::min<int64_t>(K, opts->max_iters - it));
+        if ((rc = check_hip(launch_ttr_zero(d_ch, nb * kBoxSlots, st), "ttr zero"))) return rc;
+        for (int j = 0; j < nb; ++j) {
+            if ((rc = check_hip(launch_ttr(prec, dyn->id, N, d_desc, qblocks, int(n0), cur, nxt, target_dev,
+                                           d_ch + size_t(j) * kBoxSlots, st),
+                                "ttr sweep")))
+                return rc;
+            std::swap(cur, nxt);
+        }
+        if ((rc = check_hip(hipMemcpyAsync(hch.data(), d_ch, size_t(nb) * kBoxSlots * 8, hipMemcpyDeviceToHost, st),
+                            "ttr change")) ||
+            (rc = check_hip(hipStreamSynchronize(st), "sync")))
+            return rc;
+        for (int j = 0; j < nb; ++j) {
+            double c = 0.0;
+            for (int k = 0; k < kBoxSlots; ++k) {
+                double v;
+                std::memcpy(&v, &hch[size_t(j) * kBoxSlots + size_t(k)], 8);
+                c = std::max(c, v);
+            }
+            last = c;
+            if (c < opts->eps) converged = true;
+        }
+        it += nb;
+    }
+    if (cur != phi_out_dev &&
+        (rc = check_hip(hipMemcpyAsync(phi_out_dev, cur, size_t(grid->npts) * eb, hipMemcpyDeviceToDevice, st),
+                        "ttr result")))
+        return rc;
+    (void)hipEventRecord(tm.e1, st);
+    if ((rc = check_hip(hipEventSynchronize(tm.e1), "sync"))) return rc;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, tm.e0, tm.e1);
+        stats->iters = it;
+        stats->last_change = last;
+        stats->converged = converged ? 1 : 0;
+        stats->kernel_ms = ms;
+        // each iteration reads the previous iterate and the target, writes the next
+        stats->alg_bytes = 3.0 * double(eb) * double(grid->npts) * double(it);
+        stats->alg_gbps = ms > 0 ? stats->alg_bytes / (double(ms) * 1e6) : 0.0;
+        stats->roofline_frac = stats->alg_gbps / 8000.0;
     }
     return ODP_OK;
 }

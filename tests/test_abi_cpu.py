@@ -215,7 +215,8 @@ def test_struct_layout_matches_header(lib, tmp_path):
     """The ctypes mirrors have the C structs' sizes and field offsets (checked
     by compiling the header with gcc)."""
     structs = {"odp_solve_opts": odp.odp_solve_opts, "odp_solve_stats": odp.odp_solve_stats,
-               "odp_dynamics": odp.odp_dynamics, "odp_solve_desc": odp.odp_solve_desc}
+               "odp_dynamics": odp.odp_dynamics, "odp_solve_desc": odp.odp_solve_desc,
+               "odp_ttr_opts": odp.odp_ttr_opts, "odp_ttr_stats": odp.odp_ttr_stats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "odp.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
@@ -262,3 +263,34 @@ def test_batch_and_server_reject_method_arrays(lib):
         srv = ctypes.c_void_p()
         rc = odp.lib().odp_server_create(1 << 30, 4, ctypes.byref(opts), ctypes.byref(srv))
         assert rc == odp.ODP_EUNSUPPORTED and not srv.value
+
+
+@pytest.mark.parametrize("kw,code,msg", [
+    ({"precision": 16}, -1, "precision"),
+    ({"eps": 0.0}, -1, "eps"),
+    ({"max_iters": 0}, -1, "max_iters"),
+    ({"check_every": -1}, -1, "check_every"),
+    ({"big": -1.0}, -1, "big"),
+    ({"alias": True}, -1, "alias"),
+    ({"pe3d": True}, -4, "pursuit-evasion"),
+])
+def test_ttr_rejects_before_gpu(lib, kw, code, msg):
+    spec = W.config_dubins3d(n=(10, 10, 8))
+    if kw.pop("pe3d", False):
+        spec = W.config_pe3d(n=[10, 10, 8])
+    grid = odp.Grid.from_spec(spec.grid)
+    d = odp.make_dynamics(spec.dyn)
+    alias = kw.pop("alias", False)
+    o = odp.make_ttr_opts(**kw)
+    rc = odp.lib().odp_ttr_solve(grid.handle, ctypes.byref(d), ctypes.c_void_p(0x1000), ctypes.byref(o),
+                                 None, 0, ctypes.c_void_p(0x1000 if alias else 0x2000), None)
+    assert rc == code and msg in odp.odp_last_error()
+
+
+def test_ttr_workspace_bytes(lib):
+    spec = W.config_dubins3d(n=(100, 100, 100))
+    grid = odp.Grid.from_spec(spec.grid)
+    b32 = odp.lib().odp_ttr_workspace_bytes(grid.handle, ctypes.byref(odp.make_ttr_opts(32)))
+    b64 = odp.lib().odp_ttr_workspace_bytes(grid.handle, ctypes.byref(odp.make_ttr_opts(64)))
+    assert 4 * 10**6 <= b32 < 4 * 10**6 + (1 << 20)
+    assert 8 * 10**6 <= b64 < 8 * 10**6 + (1 << 20)

@@ -1,0 +1,77 @@
+"""GPU parity of the time to reach (Lax-Friedrichs sweeping, Algorithm 2):
+the GPU iterates every node from the previous iterate (Jacobi), so it is
+compared with the oracle's Jacobi mode, both run to a tight stopping
+tolerance, node by node.  (The paper's Gauss-Seidel sweep reaches another
+limit near non-periodic edges: the printed edge rule keeps the smallest
+extrapolation an iteration produced; the oracle's pins cover both orders.)
+
+Bars: float64 within 1e-7 S of the oracle (S the largest non-periodic
+extent), float32 within 1e-4 S (float32 rounding of an iterate that is
+still moving by less than its eps when the GPU stops).
+"""
+import numpy as np
+import pytest
+
+from paper_2204_05520_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BAR = {64: 1e-7, 32: 1e-4}
+EPS = {64: 1e-11, 32: 2e-6}
+
+
+@pytest.fixture(scope="module")
+def odp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2204_05520_amd as odp
+    odp.lib()
+    return odp
+
+
+def _dev(x, prec):
+    import torch
+    return torch.tensor(x, dtype=torch.float64 if prec == 64 else torch.float32, device="cuda:0")
+
+
+def _cases():
+    g2 = W.GridSpec([61, 57], [-4.0, -4.0], [4.0, 4.0], [0, 0])
+    d2 = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [1.0, 0.2, -0.1], W.MINIMISE, W.MAXIMISE)
+    g3 = W.GridSpec([41, 37, 32], [-4.0, -4.0, -np.pi], [4.0, 4.0, np.pi], [0, 0, 1])
+    d3 = W.DynSpec(W.DYN_DUBINS3D, [1.0, 1.0], W.MINIMISE, W.MAXIMISE)
+    g4 = W.GridSpec([15, 13, 9, 16], [-5.0, -5.0, 0.0, -np.pi], [5.0, 5.0, 4.0, np.pi], [0, 0, 0, 1])
+    d4 = W.DynSpec(W.DYN_DYNCAR4D, [1.0, 1.0], W.MINIMISE, W.MAXIMISE)
+    return [("ball2d_61x57_drift", g2, d2, 1.0), ("dubins3d_41x37x32", g3, d3, 1.0),
+            ("dyncar4d_15x13x9x16", g4, d4, 1.0)]
+
+
+@pytest.mark.parametrize("name,g,d,r", _cases(), ids=[c[0] for c in _cases()])
+def test_ttr_parity(odp, oracle_mod, name, g, d, r):
+    import torch
+    l = W.cylinder_v0(g, r)
+    ref = oracle_mod.ttr_solve(g, d, l, eps=1e-12, jacobi=True)
+    assert ref.change < 1e-12
+    S = g.domain_scale()
+    reached = ref.phi < 1e3
+    assert reached.mean() > 0.5
+    for prec in (64, 32):
+        phi, st = odp.ttr_solve(g, d, _dev(l, prec), precision=prec, eps=EPS[prec])
+        torch.cuda.synchronize()
+        got = phi.double().cpu().numpy()
+        err = float(np.abs(got - ref.phi).max())
+        print(f"[gpu] ttr {name} fp{prec}: gpu iters {st['iters']} (oracle sweeps {ref.iters}) "
+              f"converged {st['converged']} max|err|/S {err / S:.3e}", flush=True)
+        assert st["converged"] == 1
+        assert np.array_equal(got == 0.0, ref.phi == 0.0)
+        assert err <= BAR[prec] * S, (prec, err / S)
+
+
+def test_ttr_not_converged_reported(odp):
+    import torch
+    g = W.GridSpec([61, 57], [-4.0, -4.0], [4.0, 4.0], [0, 0])
+    d = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [1.0, 0.0, 0.0], W.MINIMISE, W.MAXIMISE)
+    phi, st = odp.ttr_solve(g, d, _dev(W.cylinder_v0(g, 1.0), 32), precision=32, eps=1e-9,
+                            max_iters=10, check_every=4)
+    torch.cuda.synchronize()
+    assert st["iters"] == 10 and st["converged"] == 0

@@ -688,6 +688,20 @@ def test_pin12_ttr_monotone_in_target(oracle_mod):
     assert np.abs(a - b).max() > 0.3
 
 
+def test_pin12_ttr_iteration_orders(oracle_mod):
+    """The Gauss-Seidel sweep and the parallel (Jacobi) iteration reach the
+    same fixed point where the non-periodic edges are outflow edges with
+    values growing outward (the 2D disc target); the parallel form takes
+    more iterations and satisfies the same closed-form band."""
+    g, d, l = _ball_ttr(61)
+    a = oracle_mod.ttr_solve(g, d, l, eps=1e-12)
+    b = oracle_mod.ttr_solve(g, d, l, eps=1e-12, jacobi=True)
+    assert b.iters > a.iters
+    assert np.abs(a.phi - b.phi).max() < 1e-9
+    exact = np.maximum(l, 0.0)
+    assert np.abs(b.phi - exact).max() < 0.25
+
+
 def test_pin12_ttr_dubins_straight_ahead(oracle_mod):
     """Dubins car (v = 1, |w| <= 1, time-minimising turn), disc target of
     radius 1: from a state on the x axis heading straight at the target the
