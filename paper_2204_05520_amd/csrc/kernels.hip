@@ -1352,12 +1352,16 @@ __global__ __launch_bounds__(kBlock) void ttr_kernel(const SolveDesc *__restrict
                     const int64_t offr = ii[d] < nd - 1 ? st : -int64_t(nd - 1) * st;  // periodic wrap
                     const int64_t offl = ii[d] > 0 ? -st : int64_t(nd - 1) * st;
                     const double r = double(src[o + offr]), l = double(src[o + offl]);
-                    pb[d] = (r - l) / (2.0 * s.dx[d]);
+                    pb[d] = (r - l) * s.inv2dx[d];
                     ns[d] = r + l;
                 }
                 double f[N], sig[N];
                 axis_terms<DYN, N>(s, ii, f);
-                alpha_point<DYN, N>(s, ii, sig);
+                if constexpr (DYN == 0) {
+                    for (int d = 0; d < N; ++d) sig[d] = fabs(f[d]) + s.p[0];
+                } else {
+                    for (int d = 0; d < N; ++d) sig[d] = fabs(f[d]);  // input axes: the bound
+                }
                 double H = 0.0;
                 if constexpr (DYN == 0) {
                     double n2 = 0.0;
@@ -1378,10 +1382,11 @@ __global__ __launch_bounds__(kBlock) void ttr_kernel(const SolveDesc *__restrict
                         H += pb[d] * fd;
                     }
                 }
+                // reciprocal spacings instead of divisions (one division per node)
                 double num = 1.0 + H, den = 0.0;
                 for (int d = 0; d < N; ++d) {
-                    num += sig[d] * ns[d] / (2.0 * s.dx[d]);
-                    den += sig[d] / s.dx[d];
+                    num += sig[d] * ns[d] * s.inv2dx[d];
+                    den += sig[d] * (2.0 * s.inv2dx[d]);
                 }
                 if (den > 0.0) {
                     const double cand = num / den;
