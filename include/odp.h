@@ -92,8 +92,7 @@ int64_t odp_grid_points(const odp_grid *grid);
  *      p[0] = v_a, p[1] = v_b, p[2] = a_max, p[3] = b_max.  Its dissipation
  *      is taken over the costate box of each Runge-Kutta stage (Algorithm
  *      1's D_min / D_max: a grid-wide reduction before every stage update);
- *      the step size uses the all-inputs bound.  Not available to the
- *      server (ODP_EUNSUPPORTED).
+ *      the step size uses the all-inputs bound.
  * u_mode / d_mode: 1 = that player maximises the Hamiltonian, 0 = minimises
  * (for a box input: maximiser picks +bound when its switching function is
  * >= 0, minimiser picks -bound). */

@@ -363,7 +363,9 @@ void poll_retirements(odp_server *s) {
         sx.dt_min = *std::min_element(dts, dts + r->nsteps);
         sx.dt_max = *std::max_element(dts, dts + r->nsteps);
         sx.t_final = r->tau.back();
-        sx.alg_bytes = alg_bytes_per_step(s->opts.precision, r->rk_order, method_arrays(s->opts), r->grid.npts) *
+        sx.alg_bytes = alg_bytes_per_step(s->opts.precision, r->rk_order,
+                                          method_arrays(s->opts) + box_reads(r->dyn.id, s->opts, r->rk_order),
+                                          r->grid.npts) *
                        double(r->nsteps);
         std::memcpy(sx.alpha_max, b, sizeof(sx.alpha_max));
         int32_t flags;
@@ -442,7 +444,16 @@ int enqueue_tick(odp_server *s, const std::vector<Group> &groups, hipEvent_t *do
     for (int m = 0; m < kStepsPerTick; ++m) {
         for (const Group &g : groups) {
             for (int j = 0; j < g.rk; ++j) {
-                if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, stage_kind(g.rk, j, mk, g.lds, o.space_order == 2),
+                const int kind = stage_kind(g.rk, j, mk, g.lds, o.space_order == 2);
+                // pursuit-evasion: the costate box of each solve's stage input
+                // first (each solve's own step counter picks its box buffer)
+                if (g.dyn == ODP_DYN_PE3D && !o.dissipation &&
+                    (rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, kind | 32, s->d_slots,
+                                                 s->d_tiles + g.tile_base, s->d_tiles + s->tile_cap + g.tile_base,
+                                                 g.tiles, j, 1, 0, o.xcd_group, s->st),
+                                    "box")))
+                    return rc;
+                if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, kind,
                                                  s->d_slots, s->d_tiles + g.tile_base,
                                                  s->d_tiles + s->tile_cap + g.tile_base, g.tiles, j, 1, 0,
                                                  o.xcd_group, s->st),
@@ -676,8 +687,6 @@ int odp_serve_submit(odp_server *srv, const odp_solve_desc *d, uint64_t *ticket)
     if (!d->grid) return set_error(ODP_EINVAL, "grid is NULL");
     int rc;
     if ((rc = validate_dyn(d->grid, &d->dyn)) || (rc = validate_tau(d->tau, d->ntau))) return rc;
-    if (d->dyn.id == ODP_DYN_PE3D)
-        return set_error(ODP_EUNSUPPORTED, "the pursuit-evasion model (costate box) is not served");
     if (!d->V0_dev) return set_error(ODP_EINVAL, "V0 (host) is NULL");
     if (d->rk_order < 0 || d->rk_order > 3) return set_error(ODP_EINVAL, "rk_order must be 0..3");
     auto r = std::make_shared<Req>();

@@ -103,12 +103,30 @@ def test_pe3d_launch_shapes_and_batch_bitwise(odp):
         assert torch.equal(o, one), s.name
 
 
-def test_pe3d_not_served(odp):
-    spec = W.config_pe3d(n=[23, 21, 16], T=0.4)
-    srv = odp.Server(1 << 28, 2, precision=32)
+def test_pe3d_served_equals_alone(odp):
+    """Served pursuit-evasion requests (each tick runs the box pass of every
+    active solve before its update, each solve's own step counter choosing
+    its box buffer) equal the same solves alone, bit for bit, also mixed with
+    Dubins requests and with staggered horizons."""
+    import time
+    import torch
+    srv = odp.Server(1 << 30, 4, precision=32, rk_order=1)
     try:
-        with pytest.raises(odp.OdpError) as ei:
-            srv.submit(spec, W.make_v0(spec))
-        assert ei.value.code == odp.ODP_EUNSUPPORTED
+        specs = [W.config_pe3d(n=[23, 21, 16], T=0.4), W.config_dubins3d(n=(21, 19, 16), T=0.5),
+                 W.config_pe3d(n=[17, 19, 14], T=0.7)]
+        tickets = [srv.submit(s, W.make_v0(s)) for s in specs]
+        for s, t in zip(specs, tickets):
+            out = np.empty(tuple(s.grid.n), np.float32)
+            t0 = time.time()
+            while True:
+                rc, _ = srv.poll(t, out)
+                if rc != odp.ODP_PENDING:
+                    break
+                assert time.time() - t0 < 60
+                time.sleep(0.002)
+            assert rc == odp.ODP_OK
+            one = odp.solve(s, _dev(W.make_v0(s), 32), precision=32).V
+            torch.cuda.synchronize()
+            assert np.array_equal(out, one.cpu().numpy()), s.name
     finally:
         srv.close()
