@@ -775,7 +775,13 @@ __device__ __forceinline__ void stp_nt(ODP_GLOBAL T *p, const Pack<T, VEC> &r) {
 // five-node stencil.  Each point's arithmetic is the point-per-lane kernel's
 // (same differences, same ghost substitutions, axes accumulated in the same
 // order), so the two forms give the same bits.
-template <typename T, int DYN, int N, int VEC>
+// LDSX (ndim >= 3, 4 rows of the last axis within a block's range): each
+// plane's values of the block's range, with two rows of halo on each side,
+// go to a double-buffered LDS tile (one barrier per plane), from which the
+// neighbours along axis N-2 (distance 1 and 2) and along the last axis are
+// read; rows of axis N-2 wrapped across a periodic edge are loaded from
+// memory (a wave-uniform branch).
+template <typename T, int DYN, int N, int VEC, bool LDSX>
 __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc *__restrict__ descs,
                                                                 const uint32_t *__restrict__ tile_solve,
                                                                 const uint32_t *__restrict__ tile_local,
@@ -873,6 +879,37 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
     const int i0b = int(cid) * s.chunk;
     const int i0e = min(i0b + s.chunk, n0);
 
+    // LDS plane tile (LDSX): [2H halo | B block range | 2H halo], H the row
+    // length; halo rows are loaded by 4H / VEC threads (rows outside the
+    // hyperplane are clamped: such values are replaced by ghosts or wrapped
+    // loads before use)
+    constexpr int B = kBlock * VEC;
+    constexpr int kTileX = LDSX ? 2 * B : 1;  // B + 4 H with 4 H <= B
+    __shared__ __attribute__((aligned(16))) T xtile[2][kTileX];
+    const int H = nl;
+    const uint32_t q0 = qb * uint32_t(B);
+    const int me = int(q - q0) + 2 * H;
+    const int nh = 2 * H / VEC;
+    const int th = int(threadIdx.x);
+    const bool hl = LDSX && th < 2 * nh;
+    int hsrc = th < nh ? int(q0) - 2 * H + th * VEC : int(q0) + B + (th - nh) * VEC;
+    hsrc = min(max(hsrc, 0), int(s.Q) - VEC);
+    const int hdst = th < nh ? th * VEC : 2 * H + B + (th - nh) * VEC;
+    // axis N-2 rows at -2, -1, +1, +2 that wrap across a periodic edge
+    uint32_t wrapm = 0;
+    if constexpr (LDSX) {
+        if ((s.periodic >> (N - 2)) & 1u) {
+            const int nd = s.n[N - 2];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int sh = j < 2 ? j - 2 : j - 1;
+                const int kk = ii[N - 2] + sh;
+                if (kk < 0 || kk >= nd) wrapm |= 1u << j;
+            }
+        }
+    }
+    const bool anywrap = __builtin_amdgcn_ballot_w64(wrapm != 0) != 0;
+
     // axis-0 plane j (-2 <= j <= n0 + 1) of this group: wrapped, or ghosts
     auto ax0 = [&](int j) -> P {
         if (j >= 0 && j < n0) return ldp<T, VEC>(W + int64_t(j) * s0 + q);
@@ -891,6 +928,12 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
         r4 = ax0(i0 + 2);
         const P wc = r2;
         const ODP_GLOBAL T *plane = W + int64_t(i0) * s0 + q;
+        T *tl = xtile[i0 & 1];
+        if constexpr (LDSX) {
+            stp_lds<T, VEC>(tl + me, wc);
+            if (hl) stp_lds<T, VEC>(tl + hdst, ldp<T, VEC>(W + int64_t(i0) * s0 + hsrc));
+            __syncthreads();
+        }
         Acc<T> acc[VEC];
 #pragma unroll
         for (int j = 0; j < VEC; ++j) {
@@ -901,8 +944,24 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
         }
 #pragma unroll
         for (int d = 1; d < N - 1; ++d) {
-            P l2 = ldp<T, VEC>(plane + off[d][0]), l1 = ldp<T, VEC>(plane + off[d][1]);
-            P p1 = ldp<T, VEC>(plane + off[d][2]), p2 = ldp<T, VEC>(plane + off[d][3]);
+            P l2, l1, p1, p2;
+            if (LDSX && d == N - 2) {
+                l2 = ldp_lds<T, VEC>(tl + me - 2 * H);
+                l1 = ldp_lds<T, VEC>(tl + me - H);
+                p1 = ldp_lds<T, VEC>(tl + me + H);
+                p2 = ldp_lds<T, VEC>(tl + me + 2 * H);
+                if (anywrap) {
+                    if (wrapm & 1u) l2 = ldp<T, VEC>(plane + off[d][0]);
+                    if (wrapm & 2u) l1 = ldp<T, VEC>(plane + off[d][1]);
+                    if (wrapm & 4u) p1 = ldp<T, VEC>(plane + off[d][2]);
+                    if (wrapm & 8u) p2 = ldp<T, VEC>(plane + off[d][3]);
+                }
+            } else {
+                l2 = ldp<T, VEC>(plane + off[d][0]);
+                l1 = ldp<T, VEC>(plane + off[d][1]);
+                p1 = ldp<T, VEC>(plane + off[d][2]);
+                p2 = ldp<T, VEC>(plane + off[d][3]);
+            }
             const uint32_t gm = (gmask >> (4 * d)) & 15u;
             if (gm) {
 #pragma unroll
@@ -922,10 +981,17 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
         }
         // last axis: e[0..VEC+3] = nodes il-2 .. il+VEC+1
         T e[VEC + 4];
-        e[0] = plane[xo[0]];
-        e[1] = plane[xo[1]];
-        e[VEC + 2] = plane[xo[2]];
-        e[VEC + 3] = plane[xo[3]];
+        if constexpr (LDSX) {
+            e[0] = tl[me + xo[0]];
+            e[1] = tl[me + xo[1]];
+            e[VEC + 2] = tl[me + xo[2]];
+            e[VEC + 3] = tl[me + xo[3]];
+        } else {
+            e[0] = plane[xo[0]];
+            e[1] = plane[xo[1]];
+            e[VEC + 2] = plane[xo[2]];
+            e[VEC + 3] = plane[xo[3]];
+        }
 #pragma unroll
         for (int j = 0; j < VEC; ++j) e[j + 2] = wc.v[j];
         if (gxl) { e[1] = ghost(wc.v[0], wc.v[1]); e[0] = ghost2(wc.v[0], wc.v[1]); }
@@ -1629,9 +1695,16 @@ static hipError_t launch_stage_t(int kind, const SolveDesc *d, const uint32_t *t
     } else if (kind & 16) {
         // second-order ENO (method flags at run time): VEC points per thread
         // where rows allow it, else point per lane
-        if constexpr (VEC >= 2 && N >= 2 && DYN != 0)
-            hipLaunchKernelGGL((stage_eno2_vec_kernel<T, DYN, N, VEC>), dim3(nblocks), dim3(kBlock), 0, st, d, ts,
-                               tl, stage, from_desc, step, xg);
+        if constexpr (VEC >= 2 && N >= 3 && DYN != 0) {
+            if (kind & 4)
+                hipLaunchKernelGGL((stage_eno2_vec_kernel<T, DYN, N, VEC, true>), dim3(nblocks), dim3(kBlock), 0,
+                                   st, d, ts, tl, stage, from_desc, step, xg);
+            else
+                hipLaunchKernelGGL((stage_eno2_vec_kernel<T, DYN, N, VEC, false>), dim3(nblocks), dim3(kBlock), 0,
+                                   st, d, ts, tl, stage, from_desc, step, xg);
+        } else if constexpr (VEC >= 2 && N >= 2 && DYN != 0)
+            hipLaunchKernelGGL((stage_eno2_vec_kernel<T, DYN, N, VEC, false>), dim3(nblocks), dim3(kBlock), 0, st,
+                               d, ts, tl, stage, from_desc, step, xg);
         else
             hipLaunchKernelGGL((stage_point_kernel<T, DYN, N, 2, 0>), dim3(nblocks), dim3(kBlock), 0, st, d, ts,
                                tl, stage, from_desc, step, xg);

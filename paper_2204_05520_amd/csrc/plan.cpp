@@ -63,7 +63,11 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
             it.vec = 1;  // point-per-lane kernel (pursuit-evasion; ENO2 on padded rows)
             it.lds = 0;
         } else if (opts.space_order == 2) {
-            it.lds = 0;  // ENO2: VEC points per thread, no LDS exchange
+            // ENO2: VEC points per thread; the LDS exchange needs two rows
+            // of halo on each side within a block's range, and pays in 3D
+            // and 4D (measured: 4D 80^4 float32 -5%; 6D 36^6 +5%)
+            it.lds = it.g->ndim >= 3 && it.g->ndim <= 4 && it.vec >= 2 &&
+                     4 * int64_t(it.pitch) <= int64_t(kBlock) * it.vec;
         }
         total += it.ppad;
     }
