@@ -923,17 +923,44 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
         return g;
     };
     P r0 = ax0(i0b - 2), r1 = ax0(i0b - 1), r2 = ax0(i0b), r3 = ax0(i0b + 1), r4;
+    // The next plane's middle-axis neighbours, halo rows and V^n are loaded
+    // while this plane is computed (the barrier waits for LDS only), and are
+    // copied into place after the compute, when they have landed.
+    constexpr int NMG = LDSX ? N - 3 : N - 2;  // middle axes loaded from memory
+    constexpr int NMA = NMG > 0 ? NMG : 1;
+    // with two or more such axes the second set of packs would cost an
+    // occupancy level: those load in their own plane's step
+    constexpr bool kPref = NMG <= 1;
+    P cu[NMA][4], nx[NMA][4];
+    auto load_mid = [&](int i, P (&o)[NMA][4]) {
+        const ODP_GLOBAL T *pl = W + int64_t(i) * s0 + q;
+#pragma unroll
+        for (int d = 1; d <= NMG; ++d)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o[d - 1][j] = ldp<T, VEC>(pl + off[d][j]);
+    };
+    if constexpr (NMG > 0 && kPref) load_mid(i0b, cu);
+    P hq, vn, vnx;
+    if (LDSX && hl) hq = ldp<T, VEC>(W + int64_t(i0b) * s0 + hsrc);
+    if (kPref && wa != 0.0) vn = ldp_nt<T, VEC>(Vn + int64_t(i0b) * s0 + q);
     T nanacc = T(0);
     for (int i0 = i0b; i0 < i0e; ++i0) {
         r4 = ax0(i0 + 2);
         const P wc = r2;
         const ODP_GLOBAL T *plane = W + int64_t(i0) * s0 + q;
+        const int in = min(i0 + 1, i0e - 1);
         T *tl = xtile[i0 & 1];
         if constexpr (LDSX) {
             stp_lds<T, VEC>(tl + me, wc);
-            if (hl) stp_lds<T, VEC>(tl + hdst, ldp<T, VEC>(W + int64_t(i0) * s0 + hsrc));
-            __syncthreads();
+            if (hl) {
+                stp_lds<T, VEC>(tl + hdst, hq);
+                hq = ldp<T, VEC>(W + int64_t(in) * s0 + hsrc);
+            }
         }
+        if constexpr (NMG > 0 && kPref) load_mid(in, nx);
+        if constexpr (NMG > 0 && !kPref) load_mid(i0, cu);
+        if (kPref && wa != 0.0) vnx = ldp_nt<T, VEC>(Vn + int64_t(in) * s0 + q);
+        if constexpr (LDSX) __syncthreads();
         Acc<T> acc[VEC];
 #pragma unroll
         for (int j = 0; j < VEC; ++j) {
@@ -957,10 +984,10 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
                     if (wrapm & 8u) p2 = ldp<T, VEC>(plane + off[d][3]);
                 }
             } else {
-                l2 = ldp<T, VEC>(plane + off[d][0]);
-                l1 = ldp<T, VEC>(plane + off[d][1]);
-                p1 = ldp<T, VEC>(plane + off[d][2]);
-                p2 = ldp<T, VEC>(plane + off[d][3]);
+                l2 = cu[d - 1][0];
+                l1 = cu[d - 1][1];
+                p1 = cu[d - 1][2];
+                p2 = cu[d - 1][3];
             }
             const uint32_t gm = (gmask >> (4 * d)) & 15u;
             if (gm) {
@@ -997,8 +1024,7 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
         if (gxl) { e[1] = ghost(wc.v[0], wc.v[1]); e[0] = ghost2(wc.v[0], wc.v[1]); }
         if (gxr) { e[VEC + 2] = ghost(wc.v[VEC - 1], wc.v[VEC - 2]); e[VEC + 3] = ghost2(wc.v[VEC - 1], wc.v[VEC - 2]); }
         const int64_t o = int64_t(i0) * s0 + q;
-        P vn;
-        if (wa != 0.0) vn = ldp_nt<T, VEC>(Vn + o);
+        if (!kPref && wa != 0.0) vn = ldp_nt<T, VEC>(Vn + o);
         P zr, gr;
         if (clamp) zr = ldp_nt<T, VEC>(Z + o);
         if (obst) gr = ldp_nt<T, VEC>(G + o);
@@ -1025,6 +1051,13 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
         r1 = r2;
         r2 = r3;
         r3 = r4;
+        if constexpr (NMG > 0 && kPref) {
+#pragma unroll
+            for (int d = 0; d < NMG; ++d)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) cu[d][j] = nx[d][j];
+        }
+        if (kPref && wa != 0.0) vn = vnx;
     }
     if (nanacc != nanacc && active) atomicOr(s.flags, 1);
 }
