@@ -383,6 +383,61 @@ def solve(spec, V0, precision=32, V_init=None, tau=None, stream=None, save_all=F
     return SolveResult(out, st.as_dict(), vall)
 
 
+# ------------------------------------------- the paper's solver interface
+
+def HJSolver(dyn, grid, targets, tau, comp_methods=None, save_all=False, precision=32,
+             rk_order=1, cfl=0.8, space_order=1, device="cuda:0"):
+    """The paper's HJSolver call (Solving HJ PDEs section): dyn and grid are
+    workloads.DynSpec / GridSpec; targets is the initial value l(z) (host
+    array on the grid), or [l, g] with g the obstacle for a reach-avoid
+    problem (l then also serves as the target of the target-set methods); tau
+    the output times; comp_methods {"TargetSetMode": ..., "ObstacleSetMode":
+    ...} with the method names of the paper's table (default: none, the
+    backward reachable set).  Returns V at tau[-1] as a host float64 array,
+    or V at every tau (first axis) when save_all.  Runs odp_hj_solve on the
+    device."""
+    import numpy as np
+    import torch
+    from . import workloads as _W
+    cm = dict(comp_methods or {})
+    tmode = cm.get("TargetSetMode", "None")
+    omode = cm.get("ObstacleSetMode", "None")
+    if isinstance(targets, (list, tuple)):
+        l, g = targets[0], (targets[1] if len(targets) > 1 else None)
+    else:
+        l, g = targets, None
+    l = np.asarray(l, dtype=np.float64)
+    dt = torch.float32 if precision == 32 else torch.float64
+    dev = torch.device(device)
+    V0 = torch.tensor(l, dtype=dt, device=dev)
+    uses_target = tmode in ("minVWithVTarget", "maxVWithVTarget")
+    uses_obst = omode != "None"
+    if uses_obst and g is None:
+        raise ValueError("the obstacle method needs targets = [l, g]")
+    spec = _W.SolveSpec(grid, dyn, list(tau), rk_order=rk_order, cfl=cfl, mode=method_code(tmode))
+    res = solve(spec, V0, precision=precision, save_all=save_all, mode=tmode, obstacle_mode=omode,
+                target=V0 if uses_target else None,
+                obstacle=torch.tensor(np.asarray(g, dtype=np.float64), dtype=dt, device=dev) if uses_obst else None,
+                space_order=space_order)
+    torch.cuda.synchronize()
+    out = res.V_all if save_all else res.V
+    return out.double().cpu().numpy()
+
+
+def TTRSolver(dyn, grid, target, epsilon=1e-5, precision=32, max_iters=100000, device="cuda:0"):
+    """The paper's TTRSolver call: the time to reach {l <= 0} (l: host array
+    on the grid) by Lax-Friedrichs sweeping, to convergence epsilon.  dyn's
+    control must minimise the time (u_mode 0).  Returns (phi as a host
+    float64 array, stats).  Runs odp_ttr_solve on the device."""
+    import numpy as np
+    import torch
+    dt = torch.float32 if precision == 32 else torch.float64
+    tg = torch.tensor(np.asarray(target, dtype=np.float64), dtype=dt, device=torch.device(device))
+    phi, st = ttr_solve(grid, dyn, tg, precision=precision, eps=epsilon, max_iters=max_iters)
+    torch.cuda.synchronize()
+    return phi.double().cpu().numpy(), st
+
+
 class BatchPlan:
     """Prebuilt odp_hj_batch arguments (grid handles, descriptors, tau arrays)
     for repeated calls on the same solves."""

@@ -202,3 +202,30 @@ def test_time_varying_sets_graph_equals_eager(odp):
         outs.append(r.V.clone())
         torch.cuda.synchronize()
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
+def test_paper_interface_hjsolver_ttrsolver(odp, oracle_mod):
+    """The paper's HJSolver / TTRSolver calls map onto the entry points:
+    reach-avoid with [goal, obstacle] and compMethods, save_all, and the time
+    to reach, against the oracle."""
+    spec = W.config_dubins3d(n=(37, 29, 22), T=0.8)
+    g, d = spec.grid, spec.dyn
+    goal, obstacle = W.reach_avoid_sets(spec)
+    tau = [0.0, 0.4, 0.8]
+    V = odp.HJSolver(d, g, [goal, obstacle], tau,
+                     {"TargetSetMode": "minVWithVTarget", "ObstacleSetMode": "maxVWithObstacle"},
+                     save_all=True, precision=64)
+    ref = oracle_mod.solve(g, d, goal, tau, rk_order=1, cfl=0.8, tmode="minVWithVTarget",
+                           omode="maxVWithObstacle", target=goal, obstacle=obstacle, save_all=True)
+    assert V.shape == (3,) + tuple(g.n)
+    assert np.abs(V - ref.V_all).max() < 1e-9 * g.domain_scale()
+    brs = odp.HJSolver(d, g, W.make_v0(spec), tau, precision=64)
+    ref = oracle_mod.solve(g, d, W.make_v0(spec), tau, rk_order=1, cfl=0.8, brt=False)
+    assert np.abs(brs - ref.V).max() < 1e-9 * g.domain_scale()
+    g2 = W.GridSpec([61, 57], [-4.0, -4.0], [4.0, 4.0], [0, 0])
+    d2 = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [1.0, 0.0, 0.0], W.MINIMISE, W.MAXIMISE)
+    l2 = W.cylinder_v0(g2, 1.0)
+    phi, st = odp.TTRSolver(d2, g2, l2, epsilon=1e-11, precision=64)
+    ref = oracle_mod.ttr_solve(g2, d2, l2, eps=1e-12, jacobi=True)
+    assert st["converged"] == 1
+    assert np.abs(phi - ref.phi).max() < 1e-7 * g2.domain_scale()
