@@ -54,16 +54,75 @@ enum { R_QUEUED = 0, R_RUNNING = 1, R_DONE = 2 };
 
 using Clock = std::chrono::steady_clock;
 
+// Pinned host buffers recycled by size class.  A pinned allocation is a
+// driver call that costs far more than the small solves a server runs, and a
+// pinned free waits for the whole device; the pool makes both rare: blocks of
+// up to kSlabBlock bytes are carved from kSlab-byte slabs, larger ones are
+// allocated one by one, and every block returns to its class's free list
+// when its request is released.  Classes step by a quarter of a power of two
+// (at most 25% over the request), and the pool keeps what it allocated until
+// the server is destroyed, i.e. the peak of the buffers held at once.
+class HostPool {
+public:
+    static constexpr size_t kMin = 256;
+    static constexpr size_t kSlab = size_t(4) << 20;
+    static constexpr size_t kSlabBlock = size_t(64) << 10;
+
+    static size_t class_size(size_t bytes) {
+        if (bytes <= kMin) return kMin;
+        size_t base = kMin;
+        while (base * 2 < bytes) base *= 2;  // base < bytes <= 2 base
+        const size_t step = base / 4;
+        return base + (bytes - base + step - 1) / step * step;
+    }
+
+    // A block of at least `bytes` bytes, or nullptr if pinned memory runs out.
+    unsigned char *get(size_t bytes) {
+        const size_t c = class_size(bytes);
+        std::lock_guard<std::mutex> lk(mu_);
+        std::vector<unsigned char *> &fl = free_[c];
+        if (fl.empty()) {
+            const size_t len = c <= kSlabBlock ? kSlab : c;
+            unsigned char *p = nullptr;
+            if (hipHostMalloc((void **)&p, len, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            slabs_.push_back(p);
+            for (size_t o = 0; o + c <= len; o += c) fl.push_back(p + o);
+        }
+        unsigned char *p = fl.back();
+        fl.pop_back();
+        return p;
+    }
+
+    void put(unsigned char *p, size_t bytes) {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu_);
+        free_[class_size(bytes)].push_back(p);
+    }
+
+    ~HostPool() {
+        for (unsigned char *p : slabs_) (void)hipHostFree(p);
+    }
+
+private:
+    std::mutex mu_;
+    std::map<size_t, std::vector<unsigned char *>> free_;
+    std::vector<unsigned char *> slabs_;
+};
+
 struct Req {
     uint64_t ticket = 0;
     odp_grid grid{};
     odp_dynamics dyn{};
     std::vector<double> tau;
     int rk_order = 1;
-    // Host copy of V0 in pinned memory (so that the upload is an
-    // asynchronous DMA); the same buffer later receives V(tau_last).
+    // Host copy of V0 in pinned memory from the server's pool (so that the
+    // upload is an asynchronous DMA); the same buffer later receives
+    // V(tau_last).
     unsigned char *host = nullptr;
-    bool host_pinned = false;
+    std::shared_ptr<HostPool> pool;  // owner of `host`; null: plain new[]
     size_t bytes = 0;                         // one grid array (dense, host)
     size_t row = 0, row_pitch = 0, rows = 0;  // last-axis rows: bytes, device pitch, count
     size_t footprint = 0;                     // device bytes while running
@@ -80,7 +139,7 @@ struct Req {
     int64_t nsteps = 0, step = 0;
     hipEvent_t ev = nullptr;  // admission, then retirement, done
     ~Req() {
-        if (host_pinned) (void)hipHostFree(host);
+        if (pool) pool->put(host, bytes);
         else delete[] host;
         if (ev) (void)hipEventDestroy(ev);
     }
@@ -114,6 +173,7 @@ struct odp_server {
     int tab_next = 0;
     std::vector<Staging> up;      // per slot: descriptor image sent up
     std::vector<Staging> back;    // per slot: state and schedule read back
+    std::shared_ptr<HostPool> pool = std::make_shared<HostPool>();  // request host buffers
 
     std::mutex mu;
     std::condition_variable cv;
@@ -688,6 +748,10 @@ int odp_serve_submit(odp_server *srv, const odp_solve_desc *d, uint64_t *ticket)
     int rc;
     if ((rc = validate_dyn(d->grid, &d->dyn)) || (rc = validate_tau(d->tau, d->ntau))) return rc;
     if (!d->V0_dev) return set_error(ODP_EINVAL, "V0 (host) is NULL");
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->queue.size() >= kMaxQueue) return set_error(ODP_EAGAIN, "queue full");
+    }
     if (d->rk_order < 0 || d->rk_order > 3) return set_error(ODP_EINVAL, "rk_order must be 0..3");
     auto r = std::make_shared<Req>();
     r->grid = *d->grid;
@@ -698,10 +762,9 @@ int odp_serve_submit(odp_server *srv, const odp_solve_desc *d, uint64_t *ticket)
     r->footprint = request_layout(*r, srv->opts);
     if (r->footprint > srv->budget)
         return set_error(ODP_ENOMEM, "request needs " + std::to_string(r->footprint) + " device bytes, over the budget");
-    if (hipHostMalloc((void **)&r->host, r->bytes, hipHostMallocDefault) == hipSuccess) {
-        r->host_pinned = true;
+    if ((r->host = srv->pool->get(r->bytes))) {
+        r->pool = srv->pool;
     } else {
-        (void)hipGetLastError();
         r->host = new (std::nothrow) unsigned char[r->bytes];
         if (!r->host) return set_error(ODP_ENOMEM, "server: host buffer allocation failed");
     }

@@ -111,3 +111,73 @@ def test_serve_budget_and_cancel(odp):
         time.sleep(0.002)
     assert rc == 0
     srv.close()
+
+
+def _finish(odp, srv, t, out, timeout=60):
+    """Poll until the request ends; returns its status code."""
+    deadline = time.time() + timeout
+    while time.time() < deadline:
+        try:
+            rc, _ = srv.poll(t, out)
+        except odp.OdpError as e:
+            return e.code
+        if rc != odp.ODP_PENDING:
+            return rc
+        time.sleep(0.002)
+    pytest.fail("request never finished")
+
+
+def test_serve_nonfinite_request(odp):
+    """A request whose value turns non-finite (a NaN in its V0) finishes with
+    ODP_ENONFINITE; the requests running beside it in the same ticks finish
+    normally and equal their solves alone."""
+    specs = mixed_requests(3, 21)
+    V0s = [W.make_v0(s).astype(np.float32) for s in specs]
+    bad = V0s[1].copy()
+    bad.reshape(-1)[bad.size // 2] = np.nan
+    srv = odp.Server(budget_bytes=1 << 30, max_slots=4, precision=32)
+    try:
+        ins = [V0s[0], bad, V0s[2]]
+        tickets = [srv.submit(s, v, rk_order=s.rk_order) for s, v in zip(specs, ins)]
+        for k, (s, v, t) in enumerate(zip(specs, V0s, tickets)):
+            out = np.empty_like(v)
+            code = _finish(odp, srv, t, out)
+            if k == 1:
+                assert code == odp.ODP_ENONFINITE
+            else:
+                assert code == odp.ODP_OK
+                assert np.array_equal(out, alone(odp, s, v)), s.name
+    finally:
+        srv.close()
+
+
+def test_serve_queue_full(odp):
+    """Submissions beyond the queue's capacity get ODP_EAGAIN.  A long solve
+    holds the server's single slot, so the tiny requests behind it stay
+    queued; destroying the server cancels what is still running or queued."""
+    long_spec = W.config_dyncar4d(n=40, T=5000.0)
+    V_long = W.make_v0(long_spec).astype(np.float32)
+    g = W.GridSpec([3, 3, 4], [-1.0, -1.0, -np.pi], [1.0, 1.0, np.pi], [0, 0, 1])
+    d = W.DynSpec(W.DYN_DUBINS3D, [1.0, 1.0], W.MAXIMISE, W.MINIMISE)
+    spec = W.SolveSpec(g, d, [0.0, 0.5], rk_order=1, radius=0.5, name="tiny")
+    V0 = W.make_v0(spec).astype(np.float32)
+    srv = odp.Server(budget_bytes=1 << 30, max_slots=1, precision=32)
+    try:
+        t_long = srv.submit(long_spec, V_long, rk_order=long_spec.rk_order)
+        code = None
+        t0 = time.perf_counter()
+        for _ in range(70000):
+            try:
+                srv.submit(spec, V0)
+            except odp.OdpError as e:
+                code = e.code
+                break
+        print(f"{1 << 16} submits in {time.perf_counter() - t0:.2f} s", flush=True)
+        assert code == odp.ODP_EAGAIN
+        q, r, _ = srv.counts()
+        assert q == 1 << 16 and r == 1
+        out = np.empty_like(V_long)
+        rc, _ = srv.poll(t_long, out)
+        assert rc == odp.ODP_PENDING
+    finally:
+        srv.close()
