@@ -1389,8 +1389,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
 
 // One Jacobi iteration of Lax-Friedrichs sweeping for the time to reach
 // (the Time-independent HJ PDE subsection's Algorithm 2, with the parallel
-// update in place of the serial sweep): from `src` to `dst`, node per lane,
-// plane i0 = blockIdx.y.  Off every non-periodic edge a node takes
+// update in place of the serial sweep): from `src` to `dst`.  Off every
+// non-periodic edge a node takes
 //   min(src_i, [1 + H + sum_d sigma_d (src_{i+e_d} + src_{i-e_d}) / (2 dx_d)]
 //              / sum_d sigma_d / dx_d)
 // with H = pbar . f(z, u*, d*) at the centred costate and sigma_d the
@@ -1400,17 +1400,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
 // largest |dst - src| of each block goes to one of kBoxSlots change slots
 // (non-negative doubles order as their bits; the host takes the largest).
 // Arithmetic in float64, stored as T.
+//
+// Each lane owns one point q of the hyperplane of axes 1..N-1 and marches
+// `chunk` nodes along axis 0 (blockIdx.y selects the run).  No model here
+// has dynamics that depend on axis 0, so f, sigma, the denominator and the
+// in-plane edge tests are worked out once per lane; every node's own
+// arithmetic is the same as with one node per lane.
 template <typename T, int DYN, int N>
 __global__ __launch_bounds__(kBlock) void ttr_kernel(const SolveDesc *__restrict__ sd, const T *__restrict__ src,
                                                      T *__restrict__ dst, const T *__restrict__ target,
-                                                     unsigned long long *__restrict__ change) {
+                                                     unsigned long long *__restrict__ change, int chunk) {
     const SolveDesc &s = *sd;
     const uint32_t q = blockIdx.x * kBlock + threadIdx.x;
-    const int i0 = int(blockIdx.y);
+    const int i0b = int(blockIdx.y) * chunk;
+    const int i0e = min(i0b + chunk, s.n0);
     double ch = 0.0;
     if (q < s.Q) {
         int ii[N];
-        ii[0] = i0;
+        ii[0] = i0b;
         uint32_t rem = q;
 #pragma unroll
         for (int d = N - 1; d >= 1; --d) {
@@ -1418,29 +1425,43 @@ __global__ __launch_bounds__(kBlock) void ttr_kernel(const SolveDesc *__restrict
             ii[d] = int(rem - t * s.div[d].d);
             rem = t;
         }
-        const int64_t o = int64_t(i0) * s.s0 + q;
-        const double old = double(src[o]);
-        double nv = old;
-        if (double(target[o]) <= 0.0) {
-            nv = 0.0;
+        double f[N], sig[N];
+        axis_terms<DYN, N>(s, ii, f);
+        if constexpr (DYN == 0) {
+            for (int d = 0; d < N; ++d) sig[d] = fabs(f[d]) + s.p[0];
         } else {
-            bool edge = false;
-            double eb = old;
+            for (int d = 0; d < N; ++d) sig[d] = fabs(f[d]);  // input axes: the bound
+        }
+        double den = 0.0;
+        for (int d = 0; d < N; ++d) den += sig[d] * (2.0 * s.inv2dx[d]);
+        // in-plane edges: the same for the whole run
+        bool edge_in = false;
 #pragma unroll
-            for (int d = 0; d < N; ++d) {
-                if ((s.periodic >> d) & 1u) continue;
-                const int64_t st = d == 0 ? s.s0 : int64_t(s.stride[d]);
-                const int nd = s.n[d];
-                if (ii[d] == 0 || ii[d] == nd - 1) {
-                    edge = true;
-                    const int64_t sg = ii[d] == 0 ? st : -st;
-                    const double a = double(src[o + sg]), b = double(src[o + 2 * sg]);
-                    double e = 2.0 * a - b;
-                    if (b > e) e = b;
-                    if (e < eb) eb = e;
+        for (int d = 1; d < N; ++d)
+            if (!((s.periodic >> d) & 1u) && (ii[d] == 0 || ii[d] == s.n[d] - 1)) edge_in = true;
+        const bool per0 = (s.periodic & 1u) != 0;
+        for (int i0 = i0b; i0 < i0e; ++i0) {
+            ii[0] = i0;
+            const int64_t o = int64_t(i0) * s.s0 + q;
+            const double old = double(src[o]);
+            double nv = old;
+            if (double(target[o]) <= 0.0) {
+                nv = 0.0;
+            } else if (edge_in || (!per0 && (i0 == 0 || i0 == s.n0 - 1))) {
+                double eb = old;
+#pragma unroll
+                for (int d = 0; d < N; ++d) {
+                    if ((s.periodic >> d) & 1u) continue;
+                    const int64_t st = d == 0 ? s.s0 : int64_t(s.stride[d]);
+                    const int nd = s.n[d];
+                    if (ii[d] == 0 || ii[d] == nd - 1) {
+                        const int64_t sg = ii[d] == 0 ? st : -st;
+                        const double a = double(src[o + sg]), b = double(src[o + 2 * sg]);
+                        double e = 2.0 * a - b;
+                        if (b > e) e = b;
+                        if (e < eb) eb = e;
+                    }
                 }
-            }
-            if (edge) {
                 nv = eb;
             } else {
                 double pb[N], ns[N];
@@ -1453,13 +1474,6 @@ __global__ __launch_bounds__(kBlock) void ttr_kernel(const SolveDesc *__restrict
                     const double r = double(src[o + offr]), l = double(src[o + offl]);
                     pb[d] = (r - l) * s.inv2dx[d];
                     ns[d] = r + l;
-                }
-                double f[N], sig[N];
-                axis_terms<DYN, N>(s, ii, f);
-                if constexpr (DYN == 0) {
-                    for (int d = 0; d < N; ++d) sig[d] = fabs(f[d]) + s.p[0];
-                } else {
-                    for (int d = 0; d < N; ++d) sig[d] = fabs(f[d]);  // input axes: the bound
                 }
                 double H = 0.0;
                 if constexpr (DYN == 0) {
@@ -1482,20 +1496,17 @@ __global__ __launch_bounds__(kBlock) void ttr_kernel(const SolveDesc *__restrict
                     }
                 }
                 // reciprocal spacings instead of divisions (one division per node)
-                double num = 1.0 + H, den = 0.0;
-                for (int d = 0; d < N; ++d) {
-                    num += sig[d] * ns[d] * s.inv2dx[d];
-                    den += sig[d] * (2.0 * s.inv2dx[d]);
-                }
+                double num = 1.0 + H;
+                for (int d = 0; d < N; ++d) num += sig[d] * ns[d] * s.inv2dx[d];
                 if (den > 0.0) {
                     const double cand = num / den;
                     if (cand < nv) nv = cand;
                 }
             }
+            const T out = T(nv);
+            dst[o] = out;
+            ch = fmax(ch, fabs(double(out) - old));
         }
-        const T out = T(nv);
-        dst[o] = out;
-        ch = fabs(double(out) - old);
     }
     // block maximum of the change, one atomic per block
     __shared__ double red[kBlock / 64];
@@ -1893,13 +1904,15 @@ hipError_t launch_set_slice(int precision, SolveDesc *d, int iv, hipStream_t st)
 }
 
 template <typename T>
-static hipError_t launch_ttr_t(int dyn, int ndim, const SolveDesc *d, uint32_t qblocks, int n0,
+static hipError_t launch_ttr_t(int dyn, int ndim, const SolveDesc *d, uint32_t qblocks, int n0, int chunk,
                                const void *src, void *dst, const void *target, unsigned long long *change,
                                hipStream_t st) {
-    const dim3 grid(qblocks, uint32_t(n0));
+    if (chunk < 1 || chunk > n0) return hipErrorInvalidValue;
+    const dim3 grid(qblocks, uint32_t((n0 + chunk - 1) / chunk));
     const T *sp = (const T *)src, *tp = (const T *)target;
     T *dp = (T *)dst;
-#define ODP_TTR(DY, NN) hipLaunchKernelGGL((ttr_kernel<T, DY, NN>), grid, dim3(kBlock), 0, st, d, sp, dp, tp, change)
+#define ODP_TTR(DY, NN) \
+    hipLaunchKernelGGL((ttr_kernel<T, DY, NN>), grid, dim3(kBlock), 0, st, d, sp, dp, tp, change, chunk)
     switch (dyn) {
     case 1: ODP_TTR(1, 3); break;
     case 2: ODP_TTR(2, 4); break;
@@ -1921,11 +1934,11 @@ static hipError_t launch_ttr_t(int dyn, int ndim, const SolveDesc *d, uint32_t q
     return hipGetLastError();
 }
 
-hipError_t launch_ttr(int precision, int dyn, int ndim, const SolveDesc *d, uint32_t qblocks, int n0,
+hipError_t launch_ttr(int precision, int dyn, int ndim, const SolveDesc *d, uint32_t qblocks, int n0, int chunk,
                       const void *src, void *dst, const void *target, unsigned long long *change,
                       hipStream_t st) {
-    if (precision == 32) return launch_ttr_t<float>(dyn, ndim, d, qblocks, n0, src, dst, target, change, st);
-    return launch_ttr_t<double>(dyn, ndim, d, qblocks, n0, src, dst, target, change, st);
+    if (precision == 32) return launch_ttr_t<float>(dyn, ndim, d, qblocks, n0, chunk, src, dst, target, change, st);
+    return launch_ttr_t<double>(dyn, ndim, d, qblocks, n0, chunk, src, dst, target, change, st);
 }
 
 hipError_t launch_ttr_init(int precision, const void *target, void *phi, int64_t npts, double big,

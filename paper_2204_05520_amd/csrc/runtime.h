@@ -29,9 +29,10 @@ hipError_t launch_alpha(int dyn, int ndim, const SolveDesc *d, int nsolves, int 
 hipError_t launch_init(const SolveDesc *d, int nsolves, hipStream_t st);
 hipError_t launch_sched(const SolveDesc *d, int nsolves, int64_t *nsteps_all, hipStream_t st);
 hipError_t launch_advance(const SolveDesc *d, const int32_t *list, int n, hipStream_t st);
-// Time to reach: one Jacobi sweep (node per lane, grid qblocks x n0),
-// the start value, and zeroing of the change slots.
-hipError_t launch_ttr(int precision, int dyn, int ndim, const SolveDesc *d, uint32_t qblocks, int n0,
+// Time to reach: one Jacobi sweep (a lane per hyperplane point marching
+// `chunk` axis-0 nodes, grid qblocks x ceil(n0 / chunk)), the start value,
+// and zeroing of the change slots.
+hipError_t launch_ttr(int precision, int dyn, int ndim, const SolveDesc *d, uint32_t qblocks, int n0, int chunk,
                       const void *src, void *dst, const void *target, unsigned long long *change,
                       hipStream_t st);
 hipError_t launch_ttr_init(int precision, const void *target, void *phi, int64_t npts, double big,

@@ -337,6 +337,10 @@ int odp_ttr_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *tar
         return rc;
     (void)hipEventRecord(tm.e0, st);
     const uint32_t qblocks = uint32_t((Q + kBlock - 1) / kBlock);
+    // axis-0 run per lane: about kTtrBlocks blocks in all (every CU a few),
+    // so each lane amortises its per-column terms over several nodes
+    constexpr int64_t kTtrBlocks = 1024;
+    const int chunk = int(std::min<int64_t>(n0, std::max<int64_t>(1, (n0 * qblocks + kTtrBlocks - 1) / kTtrBlocks)));
     int64_t it = 0;
     double last = INFINITY;
     bool converged = false;
@@ -345,7 +349,7 @@ int odp_ttr_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *tar
         const int nb = int(std::min<int64_t>(K, opts->max_iters - it));
         if ((rc = check_hip(launch_ttr_zero(d_ch, nb * kBoxSlots, st), "ttr zero"))) return rc;
         for (int j = 0; j < nb; ++j) {
-            if ((rc = check_hip(launch_ttr(prec, dyn->id, N, d_desc, qblocks, int(n0), cur, nxt, target_dev,
+            if ((rc = check_hip(launch_ttr(prec, dyn->id, N, d_desc, qblocks, int(n0), chunk, cur, nxt, target_dev,
                                            d_ch + size_t(j) * kBoxSlots, st),
                                 "ttr sweep")))
                 return rc;

@@ -75,3 +75,54 @@ def test_ttr_not_converged_reported(odp):
                             max_iters=10, check_every=4)
     torch.cuda.synchronize()
     assert st["iters"] == 10 and st["converged"] == 0
+
+
+def _run_len(g):
+    """Axis-0 nodes per lane of the sweep launch (the host's choice: about
+    1024 blocks of 256 lanes in all)."""
+    n0 = g.n[0]
+    qblocks = -(-int(np.prod(g.n[1:])) // 256)
+    return min(n0, max(1, -(-n0 * qblocks // 1024)))
+
+
+def _run_cases():
+    gb = W.GridSpec([40, 24, 24, 24], [-4.0] * 4, [4.0] * 4, [0, 0, 0, 0])
+    db = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [1.0, 0.2, -0.1, 0.05, 0.0], W.MINIMISE, W.MAXIMISE)
+    g3 = W.GridSpec([53, 80, 64], [-4.0, -4.0, -np.pi], [4.0, 4.0, np.pi], [0, 0, 1])
+    d3 = W.DynSpec(W.DYN_DUBINS3D, [1.0, 1.0], W.MINIMISE, W.MAXIMISE)
+    g4 = W.GridSpec([19, 20, 20, 36], [-5.0, -5.0, 0.0, -np.pi], [5.0, 5.0, 4.0, np.pi], [0, 0, 0, 1])
+    d4 = W.DynSpec(W.DYN_DYNCAR4D, [1.0, 1.0], W.MINIMISE, W.MAXIMISE)
+    g6 = W.GridSpec([7, 10, 10, 10, 10, 12], [-4.0, -4.0, -np.pi, -4.0, -4.0, -np.pi],
+                    [4.0, 4.0, np.pi, 4.0, 4.0, np.pi], [0, 0, 1, 0, 0, 1])
+    d6 = W.DynSpec(W.DYN_TWODUBINS6D, [1.0, 1.0, 1.0, 1.0], W.MINIMISE, W.MAXIMISE)
+    return [("ball4d_40x24x24x24", gb, db, 48), ("dubins3d_53x80x64", g3, d3, 48),
+            ("dyncar4d_19x20x20x36", g4, d4, 48), ("game6d_7x10x10x10x10x12", g6, d6, 12)]
+
+
+@pytest.mark.parametrize("name,g,d,iters", _run_cases(), ids=[c[0] for c in _run_cases()])
+def test_ttr_axis0_runs_fixed_iterations(odp, oracle_mod, name, g, d, iters):
+    """Shapes whose sweep launch gives every lane a run of several axis-0
+    nodes with a shorter last run (n0 not a multiple of the run length):
+    after the same fixed number of Jacobi iterations, node by node against
+    the oracle (float64 within 1e-12 of max(S, |phi|), float32 within 1e-5;
+    the nodes not yet reached still hold about the start value 1e4, which
+    float32 may round a node just below it to)."""
+    import torch
+    run = _run_len(g)
+    assert run > 1 and g.n[0] % run != 0, (name, run)
+    l = W.cylinder_v0(g, 1.0)
+    ref = oracle_mod.ttr_solve(g, d, l, eps=1e-300, max_iters=iters, jacobi=True)
+    assert ref.iters == iters
+    S = g.domain_scale()
+    scale = np.maximum(S, np.abs(ref.phi))
+    for prec, bar in ((64, 1e-12), (32, 1e-5)):
+        phi, st = odp.ttr_solve(g, d, _dev(l, prec), precision=prec, eps=1e-300, max_iters=iters,
+                                check_every=iters // 2)
+        torch.cuda.synchronize()
+        got = phi.double().cpu().numpy()
+        rel = float((np.abs(got - ref.phi) / scale).max())
+        print(f"[gpu] ttr runs {name} fp{prec}: axis-0 run {run}, {iters} iterations, "
+              f"max|err|/max(S,|phi|) {rel:.3e}", flush=True)
+        assert st["iters"] == iters and st["converged"] == 0
+        assert np.array_equal(got == 0.0, ref.phi == 0.0)
+        assert rel <= bar, (prec, rel)
