@@ -1374,12 +1374,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
     using K1 = std::integral_constant<int, 1>;
     using K2 = std::integral_constant<int, 2>;
     using K3 = std::integral_constant<int, 3>;
-    // whole 4-plane cycles; planes past the chunk end are computed from
-    // clamped loads and neither stored nor checked
+    // 4-plane cycles.  Up to four dimensions the march stops at the chunk
+    // end (the condition is the same for the whole block, so every barrier
+    // is reached by all of its waves; loads already issued for the planes
+    // beyond are clamped and never used): small grids take chunks shorter
+    // than a cycle.  From five dimensions on chunks are whole cycles, and
+    // planes past a shorter last chunk are computed from clamped loads and
+    // neither stored nor checked (the exits cost the 6D kernel 2%).
     for (int i = i0b; i < i0e; i += 4) {
         step(K0{}, i);
+        if constexpr (N <= 4)
+            if (i + 1 >= i0e) break;
         step(K1{}, i + 1);
+        if constexpr (N <= 4)
+            if (i + 2 >= i0e) break;
         step(K2{}, i + 2);
+        if constexpr (N <= 4)
+            if (i + 3 >= i0e) break;
         step(K3{}, i + 3);
     }
     if (nanacc != nanacc && active) atomicOr(s.flags, 1);

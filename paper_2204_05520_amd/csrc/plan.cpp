@@ -30,13 +30,16 @@ int64_t step_capacity(const odp_grid *g, const odp_dynamics *dyn, const std::vec
 
 // Planes per block for a requested c: chunks of (nearly) equal length; for
 // the default choice also a multiple of 4, the marching kernel's register
-// cycle (planes past the end of a shorter chunk are computed and dropped).
+// cycle, except for chunks under 4 planes in up to four dimensions (there
+// the march ends at the chunk end).
 int balanced_chunk(const odp_grid *g, int c, bool cycle4) {
     const int n0 = int(g->n[0]);
     c = std::max(1, std::min(c, n0));
     const int nchunks = (n0 + c - 1) / c;
     int b = (n0 + nchunks - 1) / nchunks;
-    if (cycle4 && g->ndim >= 2) b = std::min((b + 3) / 4 * 4, (n0 + 3) / 4 * 4);
+    // up to four dimensions runs of fewer than 4 planes stay as they are
+    // (small grids: more blocks, and the march ends at the chunk end)
+    if (cycle4 && g->ndim >= 2 && (b >= 4 || g->ndim >= 5)) b = std::min((b + 3) / 4 * 4, (n0 + 3) / 4 * 4);
     return b;
 }
 

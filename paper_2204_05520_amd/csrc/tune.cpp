@@ -98,36 +98,56 @@ int tune_tile_chunk(const std::vector<PlanItem> &items, const odp_solve_opts &op
     if ((rc = check_hip(hipEventCreate(&ev.a), "event")) || (rc = check_hip(hipEventCreate(&ev.b), "event")))
         return rc;
     constexpr int kReps = 3;
-    float best_ms = 0.f;
-    int best = 0;
-    std::vector<int> seen;  // chunk of the first item, to skip candidates that round alike
+    // distinct candidates (a single solve skips those that round alike)
+    std::vector<int> cs;
+    std::vector<int> seen;
     for (int c : candidates(items)) {
-        Plan p;
-        plan_build(p, items, opts, c, true);
         if (items.size() == 1) {
+            Plan p;
+            plan_build(p, items, opts, c, true);
             if (std::find(seen.begin(), seen.end(), p.items[0].chunk) != seen.end()) continue;
             seen.push_back(p.items[0].chunk);
         }
-        if ((rc = plan_prologue(p, base, st)) || (rc = plan_launch_step(p, base, st, 0)) ||
-            (rc = check_hip(hipEventRecord(ev.a, st), "record")))
-            return rc;
-        if (items.size() == 1) {
-            for (int r = 0; r < kReps; ++r)
-                if ((rc = plan_launch_step(p, base, st, 0))) return rc;
-        } else {
-            for (int64_t k = 0; k < p.max_nsteps; ++k)
-                if ((rc = plan_launch_step(p, base, st, k))) return rc;
-        }
-        float ms = 0.f;
-        if ((rc = check_hip(hipEventRecord(ev.b, st), "record")) ||
-            (rc = check_hip(hipEventSynchronize(ev.b), "sync")) ||
-            (rc = check_hip(hipEventElapsedTime(&ms, ev.a, ev.b), "elapsed")))
-            return rc;
-        if (best_ms == 0.f || ms < best_ms) {
-            best_ms = ms;
-            best = c;
-        }
+        cs.push_back(c);
     }
+    // one pass over the candidates; when a pass takes under 5 ms (small
+    // grids, launches of a few microseconds) four more passes, each
+    // candidate keeping its fastest time, so that timer noise does not
+    // decide the choice
+    std::vector<float> best_of(cs.size(), 0.f);
+    int passes = 1;
+    for (int pass = 0; pass < passes; ++pass) {
+        float total = 0.f;
+        for (size_t i = 0; i < cs.size(); ++i) {
+            Plan p;
+            plan_build(p, items, opts, cs[i], true);
+            if ((rc = plan_prologue(p, base, st)) || (rc = plan_launch_step(p, base, st, 0)) ||
+                (rc = check_hip(hipEventRecord(ev.a, st), "record")))
+                return rc;
+            if (items.size() == 1) {
+                for (int r = 0; r < kReps; ++r)
+                    if ((rc = plan_launch_step(p, base, st, 0))) return rc;
+            } else {
+                for (int64_t k = 0; k < p.max_nsteps; ++k)
+                    if ((rc = plan_launch_step(p, base, st, k))) return rc;
+            }
+            float ms = 0.f;
+            if ((rc = check_hip(hipEventRecord(ev.b, st), "record")) ||
+                (rc = check_hip(hipEventSynchronize(ev.b), "sync")) ||
+                (rc = check_hip(hipEventElapsedTime(&ms, ev.a, ev.b), "elapsed")))
+                return rc;
+            total += ms;
+            if (pass == 0 || ms < best_of[i]) best_of[i] = ms;
+        }
+        if (pass == 0 && total < 5.f) passes = 5;
+    }
+    float best_ms = 0.f;
+    int best = 0;
+    for (size_t i = 0; i < cs.size(); ++i)
+        if (i == 0 || best_of[i] < best_ms) {
+            best_ms = best_of[i];
+            best = cs[i];
+        }
     std::lock_guard<std::mutex> lk(g_mu);
     g_cache[key] = best;
     *chunk = best;
