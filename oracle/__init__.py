@@ -71,6 +71,10 @@ def _load():
         lib.oracle_ttr_solve.argtypes = [
             ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp,
             ctypes.c_double, ctypes.c_double, ctypes.c_long, ctypes.c_int, _dp, _lp, _dp]
+        lib.oracle_box_alpha_max.restype = ctypes.c_int
+        lib.oracle_box_alpha_max.argtypes = [
+            ctypes.c_int, _lp, _dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp,
+            ctypes.c_int, _dp, _dp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         _lib = lib
@@ -209,6 +213,25 @@ def cfl_dt(grid, dyn, cfl=0.8):
     if rc != 0:
         raise ValueError("oracle_cfl_dt rejected its arguments")
     return amax[: grid.ndim].copy(), dt.value
+
+
+def box_alpha_max(grid, dyn, V: np.ndarray, space_order=1):
+    """Algorithm 1's alpha^max for field V: (box, alpha_max), box = (D_min,
+    D_max) of the costate over the grid, alpha_max the largest alpha over that
+    box at any node."""
+    lib = _load()
+    n, lo, hi, per = _grid_args(grid)
+    V = _arr(V, np.float64).reshape(-1)
+    box = np.zeros(12, dtype=np.float64)
+    amax = np.zeros(6, dtype=np.float64)
+    p = _params(dyn)
+    rc = lib.oracle_box_alpha_max(grid.ndim, _ptr(n, _lp), _ptr(lo, _dp), _ptr(hi, _dp),
+                                  _ptr(per, _ip), dyn.id, dyn.u_mode, dyn.d_mode, _ptr(p, _dp),
+                                  _ptr(V, _dp), int(space_order), _ptr(box, _dp), _ptr(amax, _dp))
+    if rc != 0:
+        raise ValueError("oracle_box_alpha_max rejected its arguments")
+    N = grid.ndim
+    return (box[:N].copy(), box[N:2 * N].copy()), amax[:N].copy()
 
 
 def step_at(grid, dyn, V: np.ndarray, V0: np.ndarray, dt: float, idx, rk_order=1, brt=True,

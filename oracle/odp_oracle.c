@@ -525,6 +525,30 @@ static void og_alpha_max(const og_grid *g, const og_dyn *dy, double *amax)
     }
 }
 
+/* alpha^max_d over the costate box: the largest alpha_i of Algorithm 1's
+ * dissipation loop, each alpha_i taken over the box [box, box + N). */
+static void og_alpha_box_max(const og_grid *g, const og_dyn *dy, const double *box, double *amax)
+{
+    for (int d = 0; d < g->ndim; ++d) amax[d] = 0.0;
+#pragma omp parallel
+    {
+        double part[OG_MAXD] = {0};
+#pragma omp for schedule(static)
+        for (long i = 0; i < g->npts; ++i) {
+            long ii[OG_MAXD];
+            double z[OG_MAXD], a[OG_MAXD];
+            og_unravel(g, i, ii);
+            og_state(g, ii, z);
+            og_alpha_box(dy, g->ndim, z, box, box + g->ndim, a);
+            for (int d = 0; d < g->ndim; ++d)
+                if (a[d] > part[d]) part[d] = a[d];
+        }
+#pragma omp critical
+        for (int d = 0; d < g->ndim; ++d)
+            if (part[d] > amax[d]) amax[d] = part[d];
+    }
+}
+
 static double og_dt_cfl(const og_grid *g, const double *amax, double cfl, double max_dt)
 {
     double s = 0.0;
@@ -622,9 +646,22 @@ int oracle_hj_solve(int ndim, const long *n, const double *lo, const double *hi,
     long steps = 0;
     double dtmin = INFINITY, dtmax = 0.0, dtfirst = 0.0;
     while (k < ntau) {
-        /* alpha^max over the grid (recomputed every step) and the CFL step */
+        /* alpha^max over the grid (recomputed every step) and the CFL step.
+         * Dynamics whose dissipation depends on the costate take it, as in
+         * Algorithm 1, from the alpha_i of the step's Hamiltonian evaluation:
+         * over the costate box of V^n (the first stage's input); the
+         * global-alpha approximation has no box and keeps the all-inputs
+         * bound. */
         double amax[OG_MAXD];
-        og_alpha_max(&g, &dy, amax);
+        double box0[2 * OG_MAXD];
+        const int box_cfl = og_box_dynamics(&dy) && !global_alpha;
+        if (box_cfl) {
+            og_field Vf = {og_get_array, Vn, NULL, 0};
+            og_costate_box(&g, &Vf, space_order, box0);
+            og_alpha_box_max(&g, &dy, box0, amax);
+        } else {
+            og_alpha_max(&g, &dy, amax);
+        }
         double dt = og_dt_cfl(&g, amax, cfl, max_dt);
         double t_next;
         int land = 0;
@@ -649,7 +686,10 @@ int oracle_hj_solve(int ndim, const long *n, const double *lo, const double *hi,
              * dissipation depends on it) */
             double box[2 * OG_MAXD];
             const int use_box = og_box_dynamics(&dy) && !aglob;
-            if (use_box) og_costate_box(&g, &Wf, space_order, box);
+            if (use_box) {
+                if (s == 0) memcpy(box, box0, sizeof(box));  /* the box of V^n, above */
+                else og_costate_box(&g, &Wf, space_order, box);
+            }
 #pragma omp parallel for schedule(static)
             for (long i = 0; i < P; ++i) {
                 double hh = og_hhat(&g, &dy, &Wf, i, aglob, space_order, 0, use_box ? box : NULL);
@@ -892,6 +932,23 @@ int oracle_alpha_box(int ndim, int dyn_id, int u_mode, int d_mode, const double 
         og_alpha_box(&dy, ndim, z + j * ndim, dmin, dmax, alpha_box + j * ndim);
         og_alpha(&dy, ndim, z + j * ndim, alpha_all + j * ndim);
     }
+    return 0;
+}
+
+/* Algorithm 1's alpha^max for field V: the costate box of V, then the
+ * largest box alpha over the grid (box_out: D_min[ndim], D_max[ndim]). */
+int oracle_box_alpha_max(int ndim, const long *n, const double *lo, const double *hi,
+                         const int *periodic, int dyn_id, int u_mode, int d_mode,
+                         const double *params, const double *V, int space_order, double *box_out,
+                         double *alpha_max_out)
+{
+    og_grid g;
+    og_dyn dy;
+    if (og_setup(&g, &dy, ndim, n, lo, hi, periodic, dyn_id, u_mode, d_mode, params)) return -1;
+    if (dyn_id == OG_SI || (space_order != 1 && space_order != 2)) return -1;
+    og_field Vf = {og_get_array, V, NULL, 0};
+    og_costate_box(&g, &Vf, space_order, box_out);
+    og_alpha_box_max(&g, &dy, box_out, alpha_max_out);
     return 0;
 }
 

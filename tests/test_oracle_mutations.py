@@ -69,6 +69,7 @@ MUTANTS = [
     ("pe3d_heading_rate_sign", "f[2] = dd[0] - u[0];", "f[2] = u[0] - dd[0];"),
     ("pe3d_speeds_exchanged", "f[0] = -dy->p[0] + dy->p[1] * cos(z[2]) + u[0] * z[1];",
      "f[0] = -dy->p[1] + dy->p[0] * cos(z[2]) + u[0] * z[1];"),
+    ("pe3d_cfl_from_all_inputs", "og_alpha_box_max(&g, &dy, box0, amax);", "og_alpha_max(&g, &dy, amax);"),
     ("costate_box_not_used", "static int og_box_dynamics(const og_dyn *dy) { return dy->id == OG_PE3D; }",
      "static int og_box_dynamics(const og_dyn *dy) { return dy->id < 0; }"),
     ("ttr_right_side_dropped", "double H = 0.0, num = 1.0, den = 0.0;", "double H = 0.0, num = 0.0, den = 0.0;"),
@@ -108,6 +109,8 @@ FAST_PINS = [
     pins.test_pin11_alpha_box_brute_force,
     pins.test_pin11_pe3d_without_turning_is_drift,
     pins.test_pin11_pe3d_one_step_with_known_box,
+    pins.test_pin11_pe3d_cfl_step_from_the_box,
+    pins.test_pin11_pe3d_capture_box_is_all_inputs,
     pins.test_pin11_pe3d_mirror_symmetry,
     pins.test_pin12_ttr_ball_closed_form_first_order,
     pins.test_pin12_ttr_speed_scaling,

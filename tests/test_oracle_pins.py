@@ -626,6 +626,62 @@ def test_pin11_pe3d_one_step_with_known_box(oracle_mod):
     assert np.any(kink & ~both & (np.abs(np.sin(Ts) - A * Xs) < np.abs(np.sin(Ts)) + A * np.abs(Xs) - 1e-6))
 
 
+def _narrow_box_case():
+    g = W.GridSpec([33, 17, 12], [-4.0, -4.0, -np.pi], [4.0, 4.0, np.pi], [0, 0, 1])
+    d = W.DynSpec(W.DYN_PE3D, [1.0, 1.0, 1.0, 1.0], W.MAXIMISE, W.MINIMISE)
+    X, Y, _ = np.meshgrid(g.axis(0), g.axis(1), g.axis(2), indexing="ij")
+    return g, d, X + 0.3 * np.abs(Y - 0.5)
+
+
+def test_pin11_pe3d_cfl_step_from_the_box(oracle_mod):
+    """Algorithm 1 takes the CFL step from alpha^max, the largest alpha_i of
+    the dissipation loop, each alpha_i over the costate box.  Worked out by
+    hand for V0 = x + 0.3 |y - 0.5| on 33 x 17 x 12 nodes over [-4,4]^2 x
+    [-pi,pi): the box is {1} x [-0.3, 0.3] x {0} (edges included: a ghost
+    keeps the edge node's sign, which leaves pbar_y in [-0.3, 0.3]).  The
+    pursuer's switching function p_th is 0 (b = -B); the evader's, y - x p_y,
+    ranges over [y - 0.3|x|, y + 0.3|x|], so rows with |y| > 0.3|x| realise
+    only a = sign(y) A.  Then alpha_x = max |-1 + cos th + a y| = 4 (|y| = 4,
+    th = 0), where all inputs give |-1 + cos pi| + 4 = 6; alpha_y = |sin th|
+    + |x| = 5 (x = +-4 with both signs realised, th = +-pi/2); alpha_th =
+    |b - a| = 2.  The first step is therefore 0.8 / (4/dx + 5/dy + 2/dth),
+    1.27 times the all-inputs step, and a horizon of 8 all-inputs steps takes
+    7 (the box stays narrow)."""
+    g, d, V0 = _narrow_box_case()
+    (dmin, dmax), amax = oracle_mod.box_alpha_max(g, d, V0)
+    assert np.allclose(dmin, [1.0, -0.3, 0.0], atol=1e-12) and np.allclose(dmax, [1.0, 0.3, 0.0], atol=1e-12)
+    assert np.abs(amax - [4.0, 5.0, 2.0]).max() < 1e-12
+    all_inputs, dt_all = oracle_mod.cfl_dt(g, d, 0.8)
+    assert np.abs(all_inputs - [6.0, 5.0, 2.0]).max() < 1e-12
+    dx, dy, dth = 8.0 / 32, 8.0 / 16, 2 * np.pi / 12
+    dt_box = 0.8 / (4.0 / dx + 5.0 / dy + 2.0 / dth)
+    assert abs(dt_all - 0.8 / (6.0 / dx + 5.0 / dy + 2.0 / dth)) < 1e-15
+    tau = [0.0, 8 * dt_all * (1 - 1e-12)]
+    for rk in (1, 2):
+        res = oracle_mod.solve(g, d, V0, tau, rk_order=rk, cfl=0.8, brt=False)
+        assert abs(res.dt_first - dt_box) < 1e-15 * dt_box, (res.dt_first, dt_box)
+        assert res.steps == 7, res.steps
+    # the global-alpha approximation has no box: the all-inputs step
+    res = oracle_mod.solve(g, d, V0, tau, rk_order=1, cfl=0.8, brt=False, global_alpha=True)
+    assert abs(res.dt_first - dt_all) < 1e-15 * dt_all and res.steps == 8
+
+
+def test_pin11_pe3d_capture_box_is_all_inputs(oracle_mod):
+    """For the capture target (relative distance - 0.5) the costate box
+    spans both signs of both switching functions at every node, so the box
+    alpha equals the all-inputs alpha everywhere and the CFL step is the
+    all-inputs step: pbar_x and pbar_y take both signs (the distance
+    gradient points every way) and so does pbar_th after one step."""
+    spec = W.config_pe3d(n=[23, 21, 16], T=0.5)
+    V0 = W.make_v0(spec)
+    all_inputs, dt_all = oracle_mod.cfl_dt(spec.grid, spec.dyn, spec.cfl)
+    (dmin, dmax), amax = oracle_mod.box_alpha_max(spec.grid, spec.dyn, V0)
+    assert dmin[0] < 0 < dmax[0] and dmin[1] < 0 < dmax[1]
+    assert np.array_equal(amax, all_inputs)
+    res = oracle_mod.solve_spec(spec)
+    assert res.dt_max == dt_all
+
+
 def test_pin11_pe3d_mirror_symmetry(oracle_mod):
     """(x, y, th) -> (x, -y, -th) with (a, b) -> (-a, -b) maps the game to
     itself and the capture target to itself, so the tube is symmetric."""
