@@ -91,8 +91,11 @@ int64_t odp_grid_points(const odp_grid *grid);
  *      |a| <= a_max), pursuer turn b (disturbance, |b| <= b_max);
  *      p[0] = v_a, p[1] = v_b, p[2] = a_max, p[3] = b_max.  Its dissipation
  *      is taken over the costate box of each Runge-Kutta stage (Algorithm
- *      1's D_min / D_max: a grid-wide reduction before every stage update);
- *      the step size uses the all-inputs bound.
+ *      1's D_min / D_max: a grid-wide reduction before every stage update),
+ *      and so is its CFL step: Algorithm 1's alpha^max, the largest box
+ *      alpha over the grid for the box of the step's first stage, reduced
+ *      on the device every step (with dissipation = 1, the global-alpha
+ *      approximation, there is no box: all inputs bound both).
  * u_mode / d_mode: 1 = that player maximises the Hamiltonian, 0 = minimises
  * (for a box input: maximiser picks +bound when its switching function is
  * >= 0, minimiser picks -bound). */
@@ -162,7 +165,9 @@ typedef struct {
     int32_t graph;       /* time stepping recorded into one HIP graph and
                             replayed: 0 auto (small grids on a non-null
                             stream), 1 always (non-null stream), 2 never.
-                            With a graph the call returns after completion. */
+                            The instantiated graph is kept (16 most recent
+                            shapes per process) and replayed by later calls
+                            with the same shape, options and workspace. */
     int32_t obstacle_mode; /* odp_obstacle_mode (0: none) */
     int32_t set_slices;    /* 0 or 1: target_dev / obstacle_dev hold one grid
                               each, used for the whole horizon; ntau
@@ -218,8 +223,14 @@ size_t odp_hj_workspace_bytes(const odp_grid *grid, const odp_dynamics *dyn, con
  *  stats:      NULL, or filled after an internal stream synchronisation.
  * The CFL step is dt = cfl / sum_d alpha^max_d / dx_d, computed in float64 on
  * the device and clipped so that time lands exactly on every tau[k].  The
- * call blocks once, to learn the step count; the time stepping itself is
- * stream-ordered.  With stats != NULL, ODP_ENONFINITE reports NaN/Inf. */
+ * call is stream-ordered: it returns once the work is enqueued (the host
+ * works out the step count from the same float64 tables and operations as
+ * the device schedule, and uploads through pinned staging), except that
+ * stats != NULL synchronises, and so does the first call of a shape with
+ * tile_chunk = ODP_TILE_AUTOTUNE (its timing runs).  The device checks that
+ * its schedule fits the enqueued steps; with stats != NULL a violation
+ * returns ODP_EHIP and ODP_ENONFINITE reports NaN/Inf.  Input buffers must
+ * stay valid, and V_out unread, until the stream reaches the call's end. */
 int odp_hj_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_dev,
                  const void *V_init_dev, const double *tau, int ntau,
                  const odp_solve_opts *opts, void *workspace_dev, void *V_out_dev,

@@ -2,6 +2,8 @@
 // alpha^max, the CFL schedule, start/finish copies, server step counters,
 // and the dispatch of stage launches to the per-(precision, dynamics)
 // slices compiled from stage_inst.hip.
+#include <algorithm>
+
 #include "kernels_dev.h"
 #include "stage_inst.h"
 
@@ -209,11 +211,21 @@ __global__ __launch_bounds__(kBlock) void alpha_kernel(const SolveDesc *__restri
 
 // The float64 CFL schedule of every listed solve (one thread per solve):
 // dt = cfl / sum_d alpha^max_d / dx_d, capped by max_dt, clipped so that the
-// time lands exactly on every tau[k].
+// time lands exactly on every tau[k].  The host enqueued expect_steps steps,
+// from the same arithmetic; a longer schedule (or an overflow) is flagged.
+// Solves whose step comes from the costate box take it step by step
+// (box_dt_kernel): their step count stays at max_steps until time lands on
+// the last output time.
 __global__ void sched_kernel(const SolveDesc *__restrict__ descs, int nsolves, int64_t *nsteps_all) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nsolves) return;
     const SolveDesc &s = descs[i];
+    if (s.box_cfl) {
+        for (int d = 0; d < kMaxDim; ++d) s.amax[d] = 0.0;  // box alphas maxed in per step
+        *s.nsteps = s.max_steps;
+        if (nsteps_all) nsteps_all[i] = s.expect_steps;
+        return;
+    }
     double sum = 0.0;
     for (int d = 0; d < s.ndim; ++d) sum += s.amax[d] / s.dx[d];
     double dtc = s.cfl / sum;
@@ -239,8 +251,160 @@ __global__ void sched_kernel(const SolveDesc *__restrict__ descs, int nsolves, i
         t = tn;
         if (land >= 0) ++k;
     }
+    if (n < 0 || n > s.expect_steps) atomicOr(s.flags, kFlagStepsExceeded);
     *s.nsteps = n;
     if (nsteps_all) nsteps_all[i] = n;
+}
+
+// Largest pursuit-evasion box alpha over every heading of the grid at (x, y):
+// the input pairs do not depend on the heading, and each |f_d| is the
+// magnitude of a rounded sum that is monotone in its heading term
+// (-v_a + v_b cos th for f_x, v_b sin th for f_y), so the largest over the
+// headings is reached at the smallest or the largest of those terms: the
+// same bits as taking the maximum of pe3d_alpha_box node by node.
+__device__ __forceinline__ void pe3d_alpha_box_headings(const SolveDesc &s, double x, double y,
+                                                        const double (&bmin)[3], const double (&bmax)[3],
+                                                        double (&al)[3]) {
+    al[0] = al[1] = al[2] = 0.0;
+    double av[4], bv[4];
+    const int n = pe3d_pairs(s, x, y, bmin, bmax, av, bv);
+    for (int j = 0; j < n; ++j) {
+        const double ay = av[j] * y, ax = av[j] * x;
+        al[0] = fmax(al[0], fmax(fabs(s.pe_cmin + ay), fabs(s.pe_cmax + ay)));
+        al[1] = fmax(al[1], fmax(fabs(s.pe_smin - ax), fabs(s.pe_smax - ax)));
+        al[2] = fmax(al[2], fabs(bv[j] - av[j]));
+    }
+}
+
+// The CFL step of step k for solves whose step comes from the costate box
+// (Algorithm 1: alpha^max is the largest alpha_i of the step's dissipation
+// loop, here over the box of the first stage's input, which the box pass of
+// stage 0 has just reduced).  One block per listed solve: the box from its
+// 64 partial boxes, the largest box alpha over the (x, y) nodes of the grid
+// (every heading at once), then the float64 step clipped to land on the next
+// output time, recorded as dt_sched[k]; landing on the last output time
+// fixes the step count at k + 1.
+__global__ __launch_bounds__(kBlock) void box_dt_kernel(const SolveDesc *__restrict__ descs,
+                                                        const int32_t *__restrict__ list, int from_desc,
+                                                        int64_t fixed_step) {
+    const SolveDesc &s = descs[list ? list[blockIdx.x] : int(blockIdx.x)];
+    if (!s.box_cfl) return;
+    const int64_t k = from_desc ? *s.step : fixed_step;
+    if (k >= *s.nsteps) return;
+    const int box_buf = int((k * s.rk_order) & 1);
+    const uint64_t *bx = s.box + 6 * kBoxSlots * box_buf;
+    double bmin[3], bmax[3];
+    for (int d = 0; d < 3; ++d) {
+        double a = INFINITY, b = -INFINITY;
+        for (int j = 0; j < kBoxSlots; ++j) {
+            a = fmin(a, box_val(bx[6 * j + d]));
+            b = fmax(b, box_val(bx[6 * j + 3 + d]));
+        }
+        bmin[d] = a;
+        bmax[d] = b;
+    }
+    double m[3] = {0.0, 0.0, 0.0};
+    const int n0 = s.n[0], n1 = s.n[1];
+    for (int p = threadIdx.x; p < n0 * n1; p += kBlock) {
+        const int i0 = p / n1, i1 = p - i0 * n1;
+        double al[3];
+        pe3d_alpha_box_headings(s, tab_x(s, 0, i0), tab_x(s, 1, i1), bmin, bmax, al);
+        for (int d = 0; d < 3; ++d) m[d] = fmax(m[d], al[d]);
+    }
+    __shared__ double red[kBlock / 64][3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int d = 0; d < 3; ++d) {
+        double v = m[d];
+        for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+        if (lane == 0) red[wave][d] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double amax[3];
+    for (int d = 0; d < 3; ++d) {
+        double v = red[0][d];
+        for (int w = 1; w < kBlock / 64; ++w) v = fmax(v, red[w][d]);
+        amax[d] = v;
+        s.amax[d] = fmax(s.amax[d], v);
+    }
+    double sum = 0.0;
+    for (int d = 0; d < 3; ++d) sum += amax[d] / s.dx[d];
+    double dtc = s.cfl / sum;
+    if (s.max_dt > 0.0 && dtc > s.max_dt) dtc = s.max_dt;
+    const double t = k > 0 ? s.t_after[k - 1] : s.tau[0];
+    const int kt = k > 0 ? s.k_after[k - 1] : 1;
+    double dt, tn;
+    int land = -1;
+    if (dtc >= s.tau[kt] - t) {
+        dt = s.tau[kt] - t;
+        tn = s.tau[kt];
+        land = kt;
+    } else {
+        dt = dtc;
+        tn = t + dt;
+    }
+    s.dt_sched[k] = dt;
+    s.land[k] = land;
+    s.t_after[k] = tn;
+    s.k_after[k] = land >= 0 ? kt + 1 : kt;
+    if (land == s.ntau - 1) *s.nsteps = k + 1;
+}
+
+// After the enqueued steps of box_cfl solves: a first-order solve whose
+// step count turned out odd has its result in B (even steps read A), which
+// moves to A; a schedule that had not landed on the last output time within
+// the enqueued steps is flagged.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void box_finish_kernel(const SolveDesc *__restrict__ descs,
+                                                            const uint32_t *__restrict__ tile_solve,
+                                                            const uint32_t *__restrict__ tile_local) {
+    const uint32_t L = blockIdx.x;
+    const uint32_t si = tile_solve ? tile_solve[L] : 0u;
+    const uint32_t lt = tile_solve ? tile_local[L] : L;
+    const SolveDesc &s = descs[si];
+    if (!s.box_cfl) return;
+    const int64_t nst = *s.nsteps;
+    if (nst >= s.max_steps) {
+        if (lt == 0 && threadIdx.x == 0) atomicOr(s.flags, kFlagStepsExceeded);
+        return;
+    }
+    if (s.rk_order != 1 || (nst & 1) == 0) return;
+    const uint32_t cid = lt / s.nqb;
+    const uint32_t q = (lt - cid * s.nqb) * kBlock + threadIdx.x;
+    if (q >= s.Q) return;
+    const int i0b = int(cid) * s.chunk;
+    const int i0e = min(i0b + s.chunk, s.n0);
+    const T *src = (const T *)s.B;
+    T *dst = (T *)s.A;
+    for (int i0 = i0b; i0 < i0e; ++i0) dst[int64_t(i0) * s.s0 + q] = src[int64_t(i0) * s.s0 + q];
+}
+
+// save_all for a box_cfl solve (solve 0): if step k landed on an output
+// time, copy its result (dense rows) into that slice of V_all.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void box_save_kernel(const SolveDesc *__restrict__ descs, int64_t k,
+                                                          T *__restrict__ V_all) {
+    const SolveDesc &s = descs[0];
+    if (k >= *s.nsteps) return;
+    const int land = s.land[k];
+    if (land < 0) return;
+    const T *src = (s.rk_order == 1 && (k & 1) == 0) ? (const T *)s.B : (const T *)s.A;
+    T *dst = V_all + int64_t(land) * s.npts;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < s.npts; i += int64_t(gridDim.x) * kBlock)
+        dst[i] = src[i];
+}
+
+// Time-varying sets for a box_cfl solve (solve 0): before step k, if step
+// k - 1 landed on output time j, the references move to slice j.
+template <typename T>
+__global__ void box_slice_kernel(SolveDesc *__restrict__ descs, int64_t k) {
+    if (threadIdx.x != 0) return;
+    SolveDesc &s = descs[0];
+    if (k == 0 || k >= *s.nsteps) return;
+    const int iv = s.land[k - 1];
+    if (iv < 0) return;
+    s.tref = (const T *)s.tref0 + int64_t(iv) * s.tstride;
+    s.oref = (const T *)s.oref0 + int64_t(iv) * s.ostride;
 }
 
 // Time-varying sets: point the comparison references of solve 0 at slice iv
@@ -276,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void start_copy_kernel(const SolveDesc *__r
     const uint32_t g = (lt - cid * s.nqb) * kBlock + threadIdx.x;
     if (g >= s.Q / uint32_t(s.vec)) return;
     const uint32_t q = g * uint32_t(s.vec);
-    T *dst = (s.rk_order == 1 && ((*s.nsteps) & 1)) ? (T *)s.B : (T *)s.A;
+    T *dst = (s.rk_order == 1 && !s.box_cfl && ((*s.nsteps) & 1)) ? (T *)s.B : (T *)s.A;
     const int i0b = int(cid) * s.chunk;
     const int i0e = min(i0b + s.chunk, s.n0);
     if (s.Vsrc_dense) {
@@ -408,6 +572,41 @@ hipError_t launch_finish_copy(int precision, const SolveDesc *d, const uint32_t 
         hipLaunchKernelGGL(finish_copy_kernel<float>, dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl);
     else
         hipLaunchKernelGGL(finish_copy_kernel<double>, dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl);
+    return hipGetLastError();
+}
+
+hipError_t launch_box_dt(const SolveDesc *d, const int32_t *list, int n, int from_desc, int64_t step,
+                         hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(box_dt_kernel, dim3(n), dim3(kBlock), 0, st, d, list, from_desc, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_box_finish(int precision, const SolveDesc *d, const uint32_t *ts, const uint32_t *tl,
+                             uint32_t nblocks, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    if (precision == 32)
+        hipLaunchKernelGGL(box_finish_kernel<float>, dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl);
+    else
+        hipLaunchKernelGGL(box_finish_kernel<double>, dim3(nblocks), dim3(kBlock), 0, st, d, ts, tl);
+    return hipGetLastError();
+}
+
+hipError_t launch_box_save(int precision, const SolveDesc *d, int64_t k, void *V_all, int64_t npts,
+                           hipStream_t st) {
+    const uint32_t nb = uint32_t(std::min<int64_t>((npts + kBlock - 1) / kBlock, 4096));
+    if (precision == 32)
+        hipLaunchKernelGGL(box_save_kernel<float>, dim3(nb), dim3(kBlock), 0, st, d, k, (float *)V_all);
+    else
+        hipLaunchKernelGGL(box_save_kernel<double>, dim3(nb), dim3(kBlock), 0, st, d, k, (double *)V_all);
+    return hipGetLastError();
+}
+
+hipError_t launch_box_slice(int precision, SolveDesc *d, int64_t k, hipStream_t st) {
+    if (precision == 32)
+        hipLaunchKernelGGL(box_slice_kernel<float>, dim3(1), dim3(64), 0, st, d, k);
+    else
+        hipLaunchKernelGGL(box_slice_kernel<double>, dim3(1), dim3(64), 0, st, d, k);
     return hipGetLastError();
 }
 

@@ -231,9 +231,11 @@ __device__ __forceinline__ void stage_buffers(const SolveDesc &s, int stage, int
                                               const T *&Vn, T *&out) {
     T *A = (T *)s.A, *B = (T *)s.B, *C = (T *)s.C;
     if (s.rk_order == 1) {
-        // ping-pong; parity chosen so that the last step writes A
+        // ping-pong; parity chosen so that the last step writes A (with the
+        // step count not known ahead, box_cfl: even steps read A, and a
+        // copy after the last step moves an odd count's result to A)
         const int64_t nst = *s.nsteps;
-        const bool in_a = ((k + nst) & 1) == 0;
+        const bool in_a = s.box_cfl ? (k & 1) == 0 : ((k + nst) & 1) == 0;
         W = in_a ? A : B;
         out = in_a ? B : A;
         Vn = W;
@@ -391,15 +393,15 @@ __device__ __forceinline__ double bang_d(double sw, double bound, int maximise) 
     return maximise ? (sw >= 0.0 ? bound : -bound) : (sw >= 0.0 ? -bound : bound);
 }
 
-// Pursuit-evasion dissipation over the costate box [bmin, bmax] at (x, y,
-// th): the largest |f_d| over the input pairs some costate in the box selects.
-// The pursuer's switching function is p_th, so each of its branches keeps the
-// half of the p_th interval of its sign (closed at 0); the evader's is
-// y p_x - x p_y - p_th, ranged over that half term by term.
-__device__ __forceinline__ void pe3d_alpha_box(const SolveDesc &s, double x, double y, double cth,
-                                               double sth, const double (&bmin)[3],
-                                               const double (&bmax)[3], double (&al)[3]) {
-    al[0] = al[1] = al[2] = 0.0;
+// Input pairs of the pursuit-evasion game that some costate in the box
+// [bmin, bmax] selects at (x, y): the pursuer's switching function is p_th,
+// so each of its branches keeps the half of the p_th interval of its sign
+// (closed at 0); the evader's is y p_x - x p_y - p_th, ranged over that half
+// term by term.  The heading does not enter, so the pairs hold for every
+// heading at (x, y).  Returns the number of pairs (evader a, pursuer b).
+__device__ __forceinline__ int pe3d_pairs(const SolveDesc &s, double x, double y, const double (&bmin)[3],
+                                          const double (&bmax)[3], double (&av)[4], double (&bv)[4]) {
+    int n = 0;
     const double c0 = y, c1 = -x;
     const double m01 = fmin(c0 * bmin[0], c0 * bmax[0]) + fmin(c1 * bmin[1], c1 * bmax[1]);
     const double M01 = fmax(c0 * bmin[0], c0 * bmax[0]) + fmax(c1 * bmin[1], c1 * bmax[1]);
@@ -408,18 +410,33 @@ __device__ __forceinline__ void pe3d_alpha_box(const SolveDesc &s, double x, dou
         if (br) { if (lo < 0.0) lo = 0.0; }
         else    { if (hi > 0.0) hi = 0.0; }
         if (lo > hi || (!br && !(lo < 0.0))) continue;
-        const double bv = bang_d(br ? 1.0 : -1.0, s.p[3], s.d_mode);
+        const double b = bang_d(br ? 1.0 : -1.0, s.p[3], s.d_mode);
         const double smin = m01 + fmin(-lo, -hi), smax = M01 + fmax(-lo, -hi);
         for (int ar = 1; ar >= 0; --ar) {
             if (ar ? !(smax >= 0.0) : !(smin < 0.0)) continue;
-            const double av = bang_d(ar ? 1.0 : -1.0, s.p[2], s.u_mode);
-            const double f0 = -s.p[0] + s.p[1] * cth + av * y;
-            const double f1 = s.p[1] * sth - av * x;
-            const double f2 = bv - av;
-            al[0] = fmax(al[0], fabs(f0));
-            al[1] = fmax(al[1], fabs(f1));
-            al[2] = fmax(al[2], fabs(f2));
+            av[n] = bang_d(ar ? 1.0 : -1.0, s.p[2], s.u_mode);
+            bv[n] = b;
+            ++n;
         }
+    }
+    return n;
+}
+
+// Pursuit-evasion dissipation over the costate box [bmin, bmax] at (x, y,
+// th): the largest |f_d| over the input pairs some costate in the box selects.
+__device__ __forceinline__ void pe3d_alpha_box(const SolveDesc &s, double x, double y, double cth,
+                                               double sth, const double (&bmin)[3],
+                                               const double (&bmax)[3], double (&al)[3]) {
+    al[0] = al[1] = al[2] = 0.0;
+    double av[4], bv[4];
+    const int n = pe3d_pairs(s, x, y, bmin, bmax, av, bv);
+    for (int j = 0; j < n; ++j) {
+        const double f0 = -s.p[0] + s.p[1] * cth + av[j] * y;
+        const double f1 = s.p[1] * sth - av[j] * x;
+        const double f2 = bv[j] - av[j];
+        al[0] = fmax(al[0], fabs(f0));
+        al[1] = fmax(al[1], fabs(f1));
+        al[2] = fmax(al[2], fabs(f2));
     }
 }
 

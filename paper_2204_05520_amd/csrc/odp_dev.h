@@ -81,7 +81,7 @@ struct SolveDesc {
     int32_t *land;           // tau index reached by each step, -1 if none
     int64_t *nsteps;         // device: step count of the schedule
     int64_t *step;           // device: next step to take (server ticks)
-    int32_t *flags;          // bit 0: non-finite value produced
+    int32_t *flags;          // kFlag* bits
     uint64_t *box;           // costate box (pursuit-evasion only, else null): two
                              // buffers, used by alternate stages, of kBoxSlots
                              // partial boxes of 6 order-preserving keys each
@@ -110,6 +110,26 @@ struct SolveDesc {
     double cfl;
     double max_dt;
     int64_t max_steps;       // capacity of dt_sched / land
+    int64_t expect_steps;    // steps the host enqueues: the step count of the
+                             // schedule, worked out on the host with the same
+                             // float64 arithmetic (the device checks it), or,
+                             // with box_cfl, the all-inputs count, which
+                             // bounds the box schedule's
+    // ---- CFL step from the costate box (pursuit-evasion with per-point
+    // dissipation, Algorithm 1): every step's dt comes from the largest box
+    // alpha over the grid, reduced on the device after the first stage's box
+    // pass; the step count is known once time lands on the last output time
+    // (nsteps holds max_steps until then)
+    int32_t box_cfl;
+    int32_t pad1_;
+    double *t_after;         // time after each step
+    int32_t *k_after;        // output-time index each step's successor aims at
+    double pe_cmin, pe_cmax; // min / max over the heading table of -v_a + v_b cos th
+    double pe_smin, pe_smax; // min / max over the heading table of v_b sin th
 };
+
+// flags bits (SolveDesc::flags)
+constexpr int32_t kFlagNonFinite = 1;     // a NaN or Inf was produced
+constexpr int32_t kFlagStepsExceeded = 2; // the device schedule needs more steps than were enqueued
 
 }  // namespace odp

@@ -1,10 +1,22 @@
 // Plans: layout, host image, prologue (alpha^max + float64 schedules on the
 // device), lockstep stepping and statistics for a list of solves.
+//
+// The host works out every solve's step count from the same float64 tables
+// and operations as the device reduction and schedule (the maximum is exact
+// and no contraction is allowed on either side), so enqueueing the steps
+// needs no read-back: a call returns once its work is enqueued.  The device
+// schedule stays the one the kernels read; it flags a schedule longer than
+// the host's count.  Solves whose step comes from the costate box get it on
+// the device, step by step; the host enqueues the all-inputs count, which
+// bounds theirs (each box step is at least the all-inputs step).
 #include "plan.h"
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <list>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 
@@ -43,6 +55,117 @@ int balanced_chunk(const odp_grid *g, int c, bool cycle4) {
     return b;
 }
 
+// Axis tables: coordinate, cos, sin per axis (float64, computed once on the
+// host; the kernels read these values, never a transcendental).
+void make_tables(const odp_grid *g, std::vector<double> &tab) {
+    tab.clear();
+    for (int d = 0; d < g->ndim; ++d) {
+        const int nd = int(g->n[d]);
+        const size_t off = tab.size();
+        tab.resize(off + 3 * size_t(nd));
+        for (int k = 0; k < nd; ++k) {
+            const double x = g->lo[d] + double(k) * g->dx[d];
+            tab[off + k] = x;
+            tab[off + nd + k] = std::cos(x);
+            tab[off + 2 * nd + k] = std::sin(x);
+        }
+    }
+}
+
+// alpha^max_d as the device reduction (alpha_kernel) computes it: the same
+// float64 expression per node on the same table values, the largest over the
+// nodes (taken over the axes each term depends on; the maximum is exact).
+void host_alpha_max(const PlanItem &it, double *am) {
+    const odp_grid *g = it.g;
+    const double *p = it.dyn.p;
+    const int N = g->ndim;
+    const double *X[kMaxDim], *C[kMaxDim], *S[kMaxDim];
+    size_t off = 0;
+    for (int d = 0; d < N; ++d) {
+        const size_t nd = size_t(g->n[d]);
+        X[d] = it.tab.data() + off;
+        C[d] = it.tab.data() + off + nd;
+        S[d] = it.tab.data() + off + 2 * nd;
+        off += 3 * nd;
+    }
+    for (int d = 0; d < kMaxDim; ++d) am[d] = 0.0;
+    auto mx = [](double &a, double v) { a = std::fmax(a, v); };
+    switch (it.dyn.id) {
+    case ODP_DYN_SINGLE_INTEGRATOR:
+        for (int d = 0; d < N; ++d) am[d] = std::fabs(p[1 + d]) + p[0];
+        break;
+    case ODP_DYN_DUBINS3D:
+        for (int64_t k = 0; k < g->n[2]; ++k) {
+            mx(am[0], std::fabs(p[0] * C[2][k]));
+            mx(am[1], std::fabs(p[0] * S[2][k]));
+        }
+        am[2] = std::fabs(p[1]);
+        break;
+    case ODP_DYN_DYNCAR4D:
+        for (int64_t j = 0; j < g->n[2]; ++j)
+            for (int64_t k = 0; k < g->n[3]; ++k) {
+                const double v = X[2][j];
+                mx(am[0], std::fabs(v * C[3][k]));
+                mx(am[1], std::fabs(v * S[3][k]));
+            }
+        am[2] = std::fabs(p[0]);
+        am[3] = std::fabs(p[1]);
+        break;
+    case ODP_DYN_TWODUBINS6D:
+        for (int64_t k = 0; k < g->n[2]; ++k) {
+            mx(am[0], std::fabs(p[0] * C[2][k]));
+            mx(am[1], std::fabs(p[0] * S[2][k]));
+        }
+        for (int64_t k = 0; k < g->n[5]; ++k) {
+            mx(am[3], std::fabs(p[2] * C[5][k]));
+            mx(am[4], std::fabs(p[2] * S[5][k]));
+        }
+        am[2] = std::fabs(p[1]);
+        am[5] = std::fabs(p[3]);
+        break;
+    case ODP_DYN_PE3D:
+        // all inputs admissible (the bound of the box alphas)
+        for (int64_t k = 0; k < g->n[2]; ++k) {
+            for (int64_t j = 0; j < g->n[1]; ++j)
+                mx(am[0], std::fabs(-p[0] + p[1] * C[2][k]) + p[2] * std::fabs(X[1][j]));
+            for (int64_t i = 0; i < g->n[0]; ++i)
+                mx(am[1], std::fabs(p[1] * S[2][k]) + p[2] * std::fabs(X[0][i]));
+        }
+        am[2] = p[2] + p[3];
+        break;
+    }
+}
+
+// The float64 schedule as the device's sched_kernel computes it: the step
+// count (-1 beyond max_steps) and the output index each step lands on.
+int64_t host_schedule(const PlanItem &it, const odp_solve_opts &o, std::vector<int32_t> &land) {
+    double sum = 0.0;
+    for (int d = 0; d < it.g->ndim; ++d) sum += it.amax[d] / it.g->dx[d];
+    double dtc = o.cfl / sum;
+    if (o.max_dt > 0.0 && dtc > o.max_dt) dtc = o.max_dt;
+    const std::vector<double> &tau = it.tau;
+    double t = tau[0];
+    size_t k = 1;
+    int64_t n = 0;
+    land.clear();
+    while (k < tau.size()) {
+        if (n >= it.max_steps) return -1;
+        double tn;
+        int32_t l = -1;
+        if (dtc >= tau[k] - t) {
+            tn = tau[k];
+            l = int32_t(k);
+        } else {
+            tn = t + dtc;
+        }
+        land.push_back(l);
+        ++n;
+        t = tn;
+        if (l >= 0) ++k;
+    }
+    return n;
+}
+
 }  // namespace
 
 std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solve_opts &opts,
@@ -50,6 +173,7 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
     p.opts = opts;
     p.xcd_group = opts.xcd_group > 0 ? opts.xcd_group
                                      : (items.size() == 1 ? default_xcd_group(items[0].g) : 0);
+    p.error.clear();
     const int prec = opts.precision;
     const size_t eb = prec == 32 ? 4 : 8;
     const int n = int(items.size());
@@ -72,6 +196,7 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
             it.lds = it.g->ndim >= 3 && it.g->ndim <= 4 && it.vec >= 2 &&
                      4 * int64_t(it.pitch) <= int64_t(kBlock) * it.vec;
         }
+        it.box_cfl = it.dyn.id == ODP_DYN_PE3D && !opts.dissipation;
         total += it.ppad;
     }
     for (auto &it : items) {
@@ -89,6 +214,13 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         it.max_steps = step_capacity(it.g, &it.dyn, it.tau, opts.cfl, opts.max_dt);
         it.tab_entries = 0;
         for (int d = 0; d < it.g->ndim; ++d) it.tab_entries += 3 * int(it.g->n[d]);
+        // the schedule on the host (box_cfl: the all-inputs count, a bound)
+        make_tables(it.g, it.tab);
+        host_alpha_max(it, it.amax);
+        it.nsteps = host_schedule(it, opts, it.land);
+        if (it.nsteps < 0 && p.error.empty()) p.error = "schedule overflow (internal step bound exceeded)";
+        if (it.nsteps >= it.max_steps) it.max_steps = it.nsteps + 1;  // box_cfl sentinel above the count
+        if (it.box_cfl) it.land.assign(it.land.size(), -1);         // landings decided on the device
     }
     // group by kernel instantiation
     std::vector<int> perm(n);
@@ -115,6 +247,23 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         }
         p.groups.back().count++;
     }
+    // members by step count, descending, so that the solves still running at
+    // step k are a prefix of each group's tile table
+    p.max_nsteps = 0;
+    p.total_tiles = 0;
+    for (PlanGroup &gr : p.groups) {
+        gr.order.resize(size_t(gr.count));
+        std::iota(gr.order.begin(), gr.order.end(), gr.first);
+        std::stable_sort(gr.order.begin(), gr.order.end(),
+                         [&](int a, int b) { return p.items[size_t(a)].nsteps > p.items[size_t(b)].nsteps; });
+        gr.tile_base = p.total_tiles;
+        gr.prefix.assign(1, 0);
+        for (int i : gr.order) {
+            gr.prefix.push_back(gr.prefix.back() + p.items[size_t(i)].tiles);
+            p.max_nsteps = std::max(p.max_nsteps, p.items[size_t(i)].nsteps);
+        }
+        p.total_tiles += gr.prefix.back();
+    }
     // layout
     size_t off = 0;
     p.desc_off = off;
@@ -126,11 +275,9 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         it.aux_off = off;
         off += kStateBytes + align256(size_t(it.tab_entries) * 8) + align256(it.tau.size() * 8);
     }
-    p.upload_bytes = off;
-    p.total_tiles = 0;
-    for (auto &it : p.items) p.total_tiles += it.tiles;
     p.tt_off = off;
-    off += align256(p.total_tiles * 4) * 2;
+    off += n > 1 ? align256(p.total_tiles * 4) * 2 : 0;
+    p.upload_bytes = off;
     p.sched_begin = off;
     for (auto &it : p.items) {
         it.sched_off = off;
@@ -140,6 +287,10 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         if (it.dyn.id == ODP_DYN_PE3D) {
             it.box_off = off;
             off += align256(size_t(2 * kBoxSlots * 6) * 8);
+        }
+        if (it.box_cfl) {
+            it.tk_off = off;
+            off += align256(size_t(it.max_steps) * 8) + align256(size_t(it.max_steps) * 4);
         }
     }
     p.arr_begin = off;
@@ -247,35 +398,59 @@ void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &
         s.cfl = o.cfl;
         s.max_dt = o.max_dt;
         s.max_steps = it.max_steps;
-        // axis tables: coordinate, cos, sin (float64, computed once on the host)
-        double *tab = (double *)(img.data() + tab_off);
-        int toff = 0;
-        for (int d = 0; d < g->ndim; ++d) {
-            const int nd = int(g->n[d]);
-            s.tab[d].off = toff;
-            s.tab[d].n = nd;
-            for (int k = 0; k < nd; ++k) {
-                const double x = g->lo[d] + double(k) * g->dx[d];
-                tab[toff + k] = x;
-                tab[toff + nd + k] = std::cos(x);
-                tab[toff + 2 * nd + k] = std::sin(x);
+        s.expect_steps = it.nsteps;
+        s.box_cfl = it.box_cfl ? 1 : 0;
+        if (it.box_cfl) {
+            s.t_after = (double *)(base + it.tk_off);
+            s.k_after = (int32_t *)(base + it.tk_off + align256(size_t(it.max_steps) * 8));
+            // extremes over the heading table of the heading terms of f_x, f_y
+            const int nt = int(g->n[2]);
+            const double *th = it.tab.data() + 3 * size_t(g->n[0]) + 3 * size_t(g->n[1]);
+            s.pe_cmin = s.pe_smin = INFINITY;
+            s.pe_cmax = s.pe_smax = -INFINITY;
+            for (int k = 0; k < nt; ++k) {
+                const double c = -it.dyn.p[0] + it.dyn.p[1] * th[nt + k];
+                const double sn = it.dyn.p[1] * th[2 * nt + k];
+                s.pe_cmin = std::fmin(s.pe_cmin, c);
+                s.pe_cmax = std::fmax(s.pe_cmax, c);
+                s.pe_smin = std::fmin(s.pe_smin, sn);
+                s.pe_smax = std::fmax(s.pe_smax, sn);
             }
-            toff += 3 * nd;
         }
+        for (int d = 0; d < g->ndim; ++d) {
+            int toff = 0;
+            for (int e = 0; e < d; ++e) toff += 3 * int(g->n[e]);
+            s.tab[d].off = toff;
+            s.tab[d].n = int32_t(g->n[d]);
+        }
+        std::memcpy(img.data() + tab_off, it.tab.data(), it.tab.size() * 8);
         std::memcpy(img.data() + p.desc_off + i * sizeof(SolveDesc), &s, sizeof(s));
         std::memcpy(img.data() + tau_off, it.tau.data(), it.tau.size() * 8);
+    }
+    // tile tables of a plan of several solves: per group, members in
+    // descending step count
+    if (p.items.size() > 1) {
+        uint32_t *ts = (uint32_t *)(img.data() + p.tt_off);
+        uint32_t *tl = ts + align256(p.total_tiles * 4) / 4;
+        size_t e = 0;
+        for (const PlanGroup &gr : p.groups)
+            for (int i : gr.order)
+                for (uint32_t k = 0; k < p.items[size_t(i)].tiles; ++k, ++e) {
+                    ts[e] = uint32_t(i);
+                    tl[e] = k;
+                }
     }
 }
 
 int plan_prologue(Plan &p, unsigned char *base, hipStream_t st) {
     int rc;
+    if (!p.error.empty()) return set_error(ODP_EHIP, p.error);
     std::vector<unsigned char> img;
     plan_image(p, base, img);
     const int n = int(p.items.size());
     const SolveDesc *descs = (const SolveDesc *)(base + p.desc_off);
     int64_t *nsteps_dev = (int64_t *)(base + p.nsteps_off);
-    if ((rc = check_hip(hipMemcpyAsync(base, img.data(), img.size(), hipMemcpyHostToDevice, st), "upload")))
-        return rc;
+    if ((rc = upload_async(base, img.data(), img.size(), st))) return rc;
     if ((rc = check_hip(launch_init(descs, n, st), "init"))) return rc;
     for (const PlanGroup &gr : p.groups) {
         int64_t qmax = 1;
@@ -286,47 +461,6 @@ int plan_prologue(Plan &p, unsigned char *base, hipStream_t st) {
             return rc;
     }
     if ((rc = check_hip(launch_sched(descs, n, nsteps_dev, st), "schedule"))) return rc;
-    std::vector<int64_t> nst(size_t(n), 0);
-    if ((rc = check_hip(hipMemcpyAsync(nst.data(), nsteps_dev, size_t(n) * 8, hipMemcpyDeviceToHost, st),
-                        "read steps")))
-        return rc;
-    if ((rc = check_hip(hipStreamSynchronize(st), "sync"))) return rc;
-    p.max_nsteps = 0;
-    for (int i = 0; i < n; ++i) {
-        if (nst[size_t(i)] <= 0) return set_error(ODP_EHIP, "schedule overflow (internal step bound exceeded)");
-        p.items[size_t(i)].nsteps = nst[size_t(i)];
-        p.max_nsteps = std::max(p.max_nsteps, nst[size_t(i)]);
-    }
-    // tile tables: per group, members by step count (descending), so that
-    // the solves still running at step k are a prefix
-    std::vector<uint32_t> ts, tl;
-    ts.reserve(p.total_tiles);
-    tl.reserve(p.total_tiles);
-    for (PlanGroup &gr : p.groups) {
-        gr.order.resize(size_t(gr.count));
-        std::iota(gr.order.begin(), gr.order.end(), gr.first);
-        std::stable_sort(gr.order.begin(), gr.order.end(),
-                         [&](int a, int b) { return p.items[size_t(a)].nsteps > p.items[size_t(b)].nsteps; });
-        gr.tile_base = ts.size();
-        gr.prefix.assign(1, 0);
-        for (int i : gr.order) {
-            const uint32_t t = p.items[size_t(i)].tiles;
-            for (uint32_t k = 0; k < t; ++k) {
-                ts.push_back(uint32_t(i));
-                tl.push_back(k);
-            }
-            gr.prefix.push_back(gr.prefix.back() + t);
-        }
-    }
-    if (n > 1) {
-        uint32_t *tsd = (uint32_t *)(base + p.tt_off);
-        uint32_t *tld = tsd + align256(p.total_tiles * 4) / 4;
-        if ((rc = check_hip(hipMemcpyAsync(tsd, ts.data(), ts.size() * 4, hipMemcpyHostToDevice, st), "tiles")) ||
-            (rc = check_hip(hipMemcpyAsync(tld, tl.data(), tl.size() * 4, hipMemcpyHostToDevice, st), "tiles")))
-            return rc;
-        // the host vectors must outlive the copies
-        if ((rc = check_hip(hipStreamSynchronize(st), "sync"))) return rc;
-    }
     return ODP_OK;
 }
 
@@ -349,10 +483,14 @@ int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t
         for (int j = 0; j < gr.rk; ++j) {
             const int kind = stage_kind(gr.rk, j, mk, gr.lds, p.opts.space_order == 2);
             if (gr.dyn == ODP_DYN_PE3D && !p.opts.dissipation) {
-                // Algorithm 1's costate box of this stage's input, then the update
+                // Algorithm 1's costate box of this stage's input, then (first
+                // stage) the step from the box, then the update
                 if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, kind | 32, descs, ts, tl, nb, j, 0,
                                                  k, p.xcd_group, st),
                                     "box")))
+                    return rc;
+                if (j == 0 &&
+                    (rc = check_hip(launch_box_dt(descs + gr.first, nullptr, gr.count, 0, k, st), "box step")))
                     return rc;
             }
             if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, kind, descs,
@@ -364,8 +502,9 @@ int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t
     return ODP_OK;
 }
 
-static int plan_enqueue(Plan &p, unsigned char *base, hipStream_t st, const std::vector<int32_t> *land,
-                        void *V_all) {
+namespace {
+
+int plan_enqueue(const Plan &p, unsigned char *base, hipStream_t st, void *V_all) {
     int rc;
     const odp_solve_opts &o = p.opts;
     const int prec = o.precision;
@@ -378,77 +517,165 @@ static int plan_enqueue(Plan &p, unsigned char *base, hipStream_t st, const std:
         const uint32_t *tl = tld ? tld + gr.tile_base : nullptr;
         if ((rc = check_hip(launch_start_copy(prec, descs, ts, tl, gr.prefix.back(), st), "start copy"))) return rc;
     }
-    const size_t bytes = single ? size_t(p.items[0].g->npts) * (prec == 32 ? 4 : 8) : 0;
+    const PlanItem &it0 = p.items[0];
+    const size_t bytes = single ? size_t(it0.g->npts) * (prec == 32 ? 4 : 8) : 0;
     // time-varying sets (single solves): the steps after landing on tau[j]
-    // compare with slice j
-    const bool sliced = single && o.set_slices > 1 && land;
+    // compare with slice j; a box_cfl solve learns its landings on the device
+    const bool sliced = single && o.set_slices > 1;
     for (int64_t k = 0; k < p.max_nsteps; ++k) {
-        if (sliced && k > 0 && (*land)[size_t(k - 1)] >= 0 &&
-            (rc = check_hip(launch_set_slice(prec, (SolveDesc *)descs, (*land)[size_t(k - 1)], st), "slice")))
-            return rc;
+        if (sliced) {
+            if (it0.box_cfl) {
+                if (k > 0 && (rc = check_hip(launch_box_slice(prec, (SolveDesc *)descs, k, st), "slice"))) return rc;
+            } else if (k > 0 && it0.land[size_t(k - 1)] >= 0 &&
+                       (rc = check_hip(launch_set_slice(prec, (SolveDesc *)descs, it0.land[size_t(k - 1)], st),
+                                       "slice"))) {
+                return rc;
+            }
+        }
         if ((rc = plan_launch_step(p, base, st, k))) return rc;
-        if (land && V_all && (*land)[size_t(k)] >= 0) {
-            const PlanItem &it = p.items[0];
-            const void *outb = (it.rk_order == 1 && ((k + it.nsteps) & 1) == 0) ? base + it.B_off : it.A;
-            unsigned char *dst = (unsigned char *)V_all + size_t((*land)[size_t(k)]) * bytes;
-            if ((rc = check_hip(hipMemcpyAsync(dst, outb, bytes, hipMemcpyDeviceToDevice, st), "save"))) return rc;
+        if (single && V_all) {
+            if (it0.box_cfl) {
+                if ((rc = check_hip(launch_box_save(prec, descs, k, V_all, it0.g->npts, st), "save"))) return rc;
+            } else if (it0.land[size_t(k)] >= 0) {
+                const void *outb =
+                    (it0.rk_order == 1 && ((k + it0.nsteps) & 1) == 0) ? base + it0.B_off : it0.A;
+                unsigned char *dst = (unsigned char *)V_all + size_t(it0.land[size_t(k)]) * bytes;
+                if ((rc = check_hip(hipMemcpyAsync(dst, outb, bytes, hipMemcpyDeviceToDevice, st), "save")))
+                    return rc;
+            }
         }
     }
-    // padded members: the result back to the caller's dense array
     for (const PlanGroup &gr : p.groups) {
-        bool any = false;
-        for (int i = gr.first; i < gr.first + gr.count; ++i) any = any || p.items[size_t(i)].pad_io;
-        if (!any) continue;
         const uint32_t *ts = tsd ? tsd + gr.tile_base : nullptr;
         const uint32_t *tl = tld ? tld + gr.tile_base : nullptr;
-        if ((rc = check_hip(launch_finish_copy(prec, descs, ts, tl, gr.prefix.back(), st), "finish copy")))
+        bool pad = false, box = false;
+        for (int i = gr.first; i < gr.first + gr.count; ++i) {
+            pad = pad || p.items[size_t(i)].pad_io;
+            box = box || p.items[size_t(i)].box_cfl;
+        }
+        // box_cfl: an odd first-order step count's result to A, landing check
+        if (box && (rc = check_hip(launch_box_finish(prec, descs, ts, tl, gr.prefix.back(), st), "box finish")))
+            return rc;
+        // padded members: the result back to the caller's dense array
+        if (pad && (rc = check_hip(launch_finish_copy(prec, descs, ts, tl, gr.prefix.back(), st), "finish copy")))
             return rc;
     }
     return ODP_OK;
 }
 
+// Instantiated graphs of recent plans, keyed by everything that decides
+// their launches (workspace address, step counts, tiling, options, V_all):
+// a repeated solve of the same shape on the same workspace replays its graph
+// without recording or instantiating it again.  The stepping reads every
+// per-call value (V0, V_out, tables, tau) from the descriptors, which the
+// prologue uploads before each replay.
+struct GraphEntry {
+    std::vector<int64_t> key;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // after its last launch (eviction waits for it)
+};
+
+std::mutex g_graph_mu;
+std::list<GraphEntry> g_graphs;  // most recent first
+constexpr size_t kGraphCache = 16;
+
+std::vector<int64_t> plan_key(const Plan &p, unsigned char *base, void *V_all) {
+    std::vector<int64_t> k;
+    auto put = [&](int64_t v) { k.push_back(v); };
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    put(dev);
+    put(int64_t(uintptr_t(base)));
+    put(int64_t(uintptr_t(V_all)));
+    const odp_solve_opts &o = p.opts;
+    put(o.precision);
+    put(o.mode);
+    put(o.obstacle_mode);
+    put(o.space_order);
+    put(o.dissipation);
+    put(o.set_slices);
+    put(p.xcd_group);
+    put(int64_t(p.total_tiles));
+    put(p.max_nsteps);
+    put(int64_t(p.desc_off));
+    put(int64_t(p.tt_off));
+    for (const PlanItem &it : p.items) {
+        put(it.dyn.id);
+        put(it.g->ndim);
+        put(it.rk_order);
+        put(it.vec);
+        put(it.lds);
+        put(it.chunk);
+        put(int64_t(it.tiles));
+        put(it.nsteps);
+        put(it.pad_io);
+        put(it.box_cfl);
+        for (size_t o : {it.aux_off, it.sched_off, it.land_off, it.box_off, it.tk_off, it.B_off, it.C_off,
+                         it.V0p_off, it.Ap_off})
+            put(int64_t(o));
+        put(int64_t(uintptr_t(it.A)));
+        put(it.g->npts);
+        for (int32_t l : it.land) put(l);
+    }
+    for (const PlanGroup &gr : p.groups) {
+        put(int64_t(gr.tile_base));
+        for (int i : gr.order) put(i);
+    }
+    return k;
+}
+
+}  // namespace
+
 int plan_stats(const Plan &p, unsigned char *base, double kernel_ms, odp_solve_stats *stats) {
     int rc;
     const odp_solve_opts &o = p.opts;
     // two bulk copies: every solve's state/tables/tau, every schedule
-    std::vector<unsigned char> aux(p.upload_bytes - p.aux_begin), sched(p.arr_begin - p.sched_begin);
+    std::vector<unsigned char> aux(p.tt_off - p.aux_begin), sched(p.arr_begin - p.sched_begin);
     if ((rc = check_hip(hipMemcpy(aux.data(), base + p.aux_begin, aux.size(), hipMemcpyDeviceToHost), "read state")) ||
         (rc = check_hip(hipMemcpy(sched.data(), base + p.sched_begin, sched.size(), hipMemcpyDeviceToHost),
                         "read schedules")))
         return rc;
     int worst = ODP_OK;
+    std::string why;
     for (size_t i = 0; i < p.items.size(); ++i) {
         const PlanItem &it = p.items[i];
         const unsigned char *state = aux.data() + (it.aux_off - p.aux_begin);
         const double *dts = (const double *)(sched.data() + (it.sched_off - p.sched_begin));
         odp_solve_stats &sx = stats[i];
         std::memset(&sx, 0, sizeof(sx));
-        sx.steps = it.nsteps;
-        sx.dt_min = *std::min_element(dts, dts + it.nsteps);
-        sx.dt_max = *std::max_element(dts, dts + it.nsteps);
+        int64_t nst;
+        std::memcpy(&nst, state + kMaxDim * 8, 8);
+        int32_t flags;
+        std::memcpy(&flags, state + kMaxDim * 8 + 16, 4);
+        if ((flags & kFlagStepsExceeded) || nst <= 0 || nst > it.nsteps) {
+            worst = ODP_EHIP;
+            why = "device schedule longer than the steps enqueued";
+            nst = std::max<int64_t>(0, std::min(nst, it.nsteps));
+        }
+        sx.steps = nst;
+        if (nst > 0) {
+            sx.dt_min = *std::min_element(dts, dts + nst);
+            sx.dt_max = *std::max_element(dts, dts + nst);
+        }
         sx.t_final = it.tau.back();
         sx.kernel_ms = kernel_ms;
         sx.alg_bytes = alg_bytes_per_step(o.precision, it.rk_order,
-                                           method_arrays(o) + box_reads(it.dyn.id, o, it.rk_order), it.g->npts) * double(it.nsteps);
+                                           method_arrays(o) + box_reads(it.dyn.id, o, it.rk_order), it.g->npts) * double(nst);
         sx.alg_gbps = kernel_ms > 0 ? sx.alg_bytes / (kernel_ms * 1e6) : 0.0;
         sx.roofline_frac = sx.alg_gbps / 8000.0;
         std::memcpy(sx.alpha_max, state, sizeof(sx.alpha_max));
-        int32_t flags;
-        std::memcpy(&flags, state + kMaxDim * 8 + 16, 4);
-        sx.nonfinite = flags & 1;
-        if (sx.nonfinite) worst = ODP_ENONFINITE;
+        sx.nonfinite = flags & kFlagNonFinite;
+        if (sx.nonfinite && worst == ODP_OK) {
+            worst = ODP_ENONFINITE;
+            why = "NaN or Inf in the value function";
+        }
     }
-    if (worst != ODP_OK) return set_error(worst, "NaN or Inf in the value function");
+    if (worst != ODP_OK) return set_error(worst, why);
     return ODP_OK;
 }
 
-}  // namespace odp
-
-namespace odp {
-
 // Launch-bound plans (small grids, many steps) are recorded into one HIP
-// graph and replayed with a single launch; the call then waits for the
-// graph to finish before it frees the executable graph.
+// graph and replayed with a single launch.
 bool plan_wants_graph(const Plan &p) {
     if (p.opts.graph == 2 || p.opts.stream == nullptr) return false;
     if (p.opts.graph == 1) return true;
@@ -457,28 +684,53 @@ bool plan_wants_graph(const Plan &p) {
     return pts <= (int64_t(1) << 22) && p.max_nsteps * int64_t(p.groups.size()) >= 8;
 }
 
-int plan_steps(Plan &p, unsigned char *base, hipStream_t st, const std::vector<int32_t> *land,
-               void *V_all) {
-    if (!plan_wants_graph(p)) return plan_enqueue(p, base, st, land, V_all);
+int plan_steps(Plan &p, unsigned char *base, hipStream_t st, void *V_all) {
+    if (!plan_wants_graph(p)) return plan_enqueue(p, base, st, V_all);
     int rc;
+    std::vector<int64_t> key = plan_key(p, base, V_all);
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto e = g_graphs.begin(); e != g_graphs.end(); ++e) {
+        if (e->key != key) continue;
+        g_graphs.splice(g_graphs.begin(), g_graphs, e);
+        GraphEntry &g = g_graphs.front();
+        if ((rc = check_hip(hipGraphLaunch(g.exec, st), "graph launch"))) return rc;
+        return check_hip(hipEventRecord(g.done, st), "record");
+    }
     hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    GraphEntry ne;
+    ne.key = std::move(key);
     if ((rc = check_hip(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture")))
         return rc;
-    const int erc = plan_enqueue(p, base, st, land, V_all);
+    const int erc = plan_enqueue(p, base, st, V_all);
     const hipError_t ec = hipStreamEndCapture(st, &graph);
     if (erc) {
         if (graph) (void)hipGraphDestroy(graph);
         return erc;
     }
     if ((rc = check_hip(ec, "end capture"))) return rc;
-    rc = check_hip(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
+    rc = check_hip(hipGraphInstantiate(&ne.exec, graph, nullptr, nullptr, 0), "instantiate");
     (void)hipGraphDestroy(graph);
     if (rc) return rc;
-    rc = check_hip(hipGraphLaunch(exec, st), "graph launch");
-    if (!rc) rc = check_hip(hipStreamSynchronize(st), "sync");
-    (void)hipGraphExecDestroy(exec);
-    return rc;
+    if ((rc = check_hip(hipEventCreateWithFlags(&ne.done, hipEventDisableTiming), "event"))) {
+        (void)hipGraphExecDestroy(ne.exec);
+        return rc;
+    }
+    if ((rc = check_hip(hipGraphLaunch(ne.exec, st), "graph launch")) ||
+        (rc = check_hip(hipEventRecord(ne.done, st), "record"))) {
+        (void)hipStreamSynchronize(st);
+        (void)hipGraphExecDestroy(ne.exec);
+        (void)hipEventDestroy(ne.done);
+        return rc;
+    }
+    g_graphs.push_front(std::move(ne));
+    while (g_graphs.size() > kGraphCache) {
+        GraphEntry &old = g_graphs.back();
+        (void)hipEventSynchronize(old.done);  // its last replay has finished
+        (void)hipGraphExecDestroy(old.exec);
+        (void)hipEventDestroy(old.done);
+        g_graphs.pop_back();
+    }
+    return ODP_OK;
 }
 
 }  // namespace odp

@@ -14,6 +14,7 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <string>
 #include <vector>
 
 #include "runtime.h"
@@ -39,8 +40,16 @@ struct PlanItem {
     uint32_t tiles = 0;
     int64_t max_steps = 0;
     int tab_entries = 0;
-    size_t aux_off = 0, sched_off = 0, land_off = 0, box_off = 0, B_off = 0, C_off = 0;
-    int64_t nsteps = 0;
+    size_t aux_off = 0, sched_off = 0, land_off = 0, box_off = 0, tk_off = 0, B_off = 0, C_off = 0;
+    // host side of the schedule: axis tables (x, cos x, sin x per axis, as
+    // uploaded), alpha^max and the step count from the same float64
+    // arithmetic as the device reduction and schedule, and the output index
+    // each step lands on (-1: none)
+    std::vector<double> tab;
+    double amax[kMaxDim] = {0, 0, 0, 0, 0, 0};
+    std::vector<int32_t> land;
+    bool box_cfl = false;               // step from the costate box (device, per step)
+    int64_t nsteps = 0;                 // steps enqueued (box_cfl: an upper bound)
 };
 
 struct PlanGroup {
@@ -59,6 +68,7 @@ struct Plan {
     size_t tt_off = 0, total_tiles = 0, sched_begin = 0, arr_begin = 0, total = 0;
     int64_t max_nsteps = 0;
     int xcd_group = 0;                  // tile runs per XCD for the stage launches
+    std::string error;                  // set by plan_build when a schedule overflows
 };
 
 // Order items by (dynamics, ndim, vector width, RK order), fill the layout.
@@ -71,13 +81,14 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
 int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t k);
 // Host image of [0, upload_bytes) for a workspace at device address base.
 void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &img);
-// Upload, alpha^max, schedules; reads back the step counts (one sync), sorts
-// group members and uploads the tile tables.
+// Upload, alpha^max, schedules (stream-ordered: the step counts are known on
+// the host from plan_build), member order and tile tables.
 int plan_prologue(Plan &p, unsigned char *base, hipStream_t st);
 // Start copies and every step of every solve (stream-ordered, no sync).
-// save_all: single-solve only; land[] of item 0 and the V_all buffer.
-int plan_steps(Plan &p, unsigned char *base, hipStream_t st, const std::vector<int32_t> *land,
-               void *V_all);
+// V_all: save_all of a single solve (slice k = V at tau[k]), else null.
+int plan_steps(Plan &p, unsigned char *base, hipStream_t st, void *V_all);
+// Whether the plan's stepping is recorded into a HIP graph.
+bool plan_wants_graph(const Plan &p);
 // Fill per-item stats after the stream has been synchronised.
 int plan_stats(const Plan &p, unsigned char *base, double kernel_ms, odp_solve_stats *stats);
 

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -27,6 +28,51 @@ int check_hip(hipError_t e, const char *what) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+namespace {
+
+// Pinned staging blocks for upload_async, kept for the life of the process
+// (a pinned allocation is a driver call; the blocks are recycled instead).
+struct StageBlock {
+    unsigned char *p = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;  // recorded after the block's last copy
+    int device = -1;
+};
+
+std::mutex g_stage_mu;
+std::vector<StageBlock> g_stage;
+
+}  // namespace
+
+int upload_async(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return ODP_OK;
+    int dev = 0, rc;
+    if ((rc = check_hip(hipGetDevice(&dev), "device"))) return rc;
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    StageBlock *b = nullptr;
+    for (StageBlock &c : g_stage)
+        if (c.device == dev && c.cap >= bytes && hipEventQuery(c.ev) == hipSuccess) {
+            b = &c;
+            break;
+        }
+    if (!b) {
+        StageBlock n;
+        n.device = dev;
+        n.cap = std::max<size_t>(size_t(64) << 10, size_t(1) << size_t(std::ceil(std::log2(double(bytes)))));
+        if ((rc = check_hip(hipHostMalloc((void **)&n.p, n.cap, hipHostMallocDefault), "pinned staging")))
+            return rc;
+        if ((rc = check_hip(hipEventCreateWithFlags(&n.ev, hipEventDisableTiming), "event"))) {
+            (void)hipHostFree(n.p);
+            return rc;
+        }
+        g_stage.push_back(n);
+        b = &g_stage.back();
+    }
+    std::memcpy(b->p, src, bytes);
+    if ((rc = check_hip(hipMemcpyAsync(dst, b->p, bytes, hipMemcpyHostToDevice, st), "upload"))) return rc;
+    return check_hip(hipEventRecord(b->ev, st), "record");
+}
 
 static int dyn_ndim(int id) {
     switch (id) {

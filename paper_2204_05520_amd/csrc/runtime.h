@@ -38,6 +38,18 @@ hipError_t launch_ttr(int precision, int dyn, int ndim, const SolveDesc *d, uint
 hipError_t launch_ttr_init(int precision, const void *target, void *phi, int64_t npts, double big,
                            hipStream_t st);
 hipError_t launch_ttr_zero(unsigned long long *p, int n, hipStream_t st);
+// Solves whose CFL step comes from the costate box (SolveDesc::box_cfl):
+// the step of step k from the box of its first stage (one block per listed
+// solve: list[j], or descriptor j when list is null; from_desc: each solve's
+// own step counter), the final parity copy / landing check over the tiles,
+// and the device-conditional save_all copy and set switch of solve 0.
+hipError_t launch_box_dt(const SolveDesc *d, const int32_t *list, int n, int from_desc, int64_t step,
+                         hipStream_t st);
+hipError_t launch_box_finish(int precision, const SolveDesc *d, const uint32_t *ts, const uint32_t *tl,
+                             uint32_t nblocks, hipStream_t st);
+hipError_t launch_box_save(int precision, const SolveDesc *d, int64_t k, void *V_all, int64_t npts,
+                           hipStream_t st);
+hipError_t launch_box_slice(int precision, SolveDesc *d, int64_t k, hipStream_t st);
 // Time-varying sets of a single solve: references of descs[0] to slice iv.
 hipError_t launch_set_slice(int precision, SolveDesc *d, int iv, hipStream_t st);
 // Padded members (SolveDesc::Adst_dense set): A to the caller's dense array.
@@ -52,6 +64,11 @@ int check_hip(hipError_t e, const char *what);
 int validate_dyn(const odp_grid *g, const odp_dynamics *dyn);
 int validate_opts(const odp_solve_opts *o);
 int validate_tau(const double *tau, int ntau);
+
+// Host-to-device copy on stream st that does not wait: src is first copied
+// into a pinned staging block (reused once the event after its last copy has
+// completed), so the caller may free src on return.
+int upload_async(void *dst, const void *src, size_t bytes, hipStream_t st);
 
 // Upper bound of max_i alpha_d(z_i) from the parameters and the domain.
 void alpha_bound(const odp_grid *g, const odp_dynamics *dyn, double *ab);

@@ -346,8 +346,6 @@ void admit(odp_server *s) {
                             "alpha")) ||
             (rc = check_hip(launch_sched(slot, 1, s->d_nsteps + r->slot, s->ust), "schedule")) ||
             (rc = check_hip(launch_start_copy(o.precision, slot, nullptr, nullptr, it.tiles, s->ust), "start copy")) ||
-            (rc = check_hip(hipMemcpyAsync(s->h_nsteps + r->slot, s->d_nsteps + r->slot, 8, hipMemcpyDeviceToHost,
-                                           s->ust), "steps")) ||
             (rc = get_event(s, &r->ev)) || (rc = check_hip(hipEventRecord(r->ev, s->ust), "record"))) {
             (void)hipStreamSynchronize(s->ust);
             release(s, r);
@@ -374,7 +372,9 @@ bool poll_admissions(odp_server *s) {
             std::lock_guard<std::mutex> lk(s->mu);
             cancel = r->cancel;
         }
-        r->nsteps = s->h_nsteps[r->slot];
+        // the step count from the host's copy of the schedule (box_cfl: the
+        // all-inputs count, a bound; finished solves' launches return early)
+        r->nsteps = r->plan.items[0].nsteps;
         r->step = 0;
         if (cancel || r->nsteps <= 0) {
             release(s, r);
@@ -395,6 +395,9 @@ int start_retire(odp_server *s, const std::shared_ptr<Req> &r, hipEvent_t after)
     int rc;
     if ((rc = stage_reserve(b, kStateBytes + size_t(r->nsteps) * 8)) ||
         (rc = check_hip(hipStreamWaitEvent(s->dst, after, 0), "wait")) ||
+        // a box_cfl first-order result after an odd step count is in B
+        (it.box_cfl && (rc = check_hip(launch_box_finish(s->opts.precision, s->d_slots + r->slot, nullptr, nullptr,
+                                                         it.tiles, s->dst), "box finish"))) ||
         (rc = check_hip(hipMemcpy2DAsync(r->host, r->row, r->dmem + r->off_a, r->row_pitch, r->row, r->rows,
                                          hipMemcpyDeviceToHost, s->dst), "result")) ||
         (rc = check_hip(hipMemcpyAsync(b.p, r->dmem + it.aux_off, kStateBytes, hipMemcpyDeviceToHost, s->dst),
@@ -419,20 +422,26 @@ void poll_retirements(odp_server *s) {
         const unsigned char *b = s->back[size_t(r->slot)].p;
         const double *dts = (const double *)(b + kStateBytes);
         odp_solve_stats &sx = r->stats;
-        sx.steps = r->nsteps;
-        sx.dt_min = *std::min_element(dts, dts + r->nsteps);
-        sx.dt_max = *std::max_element(dts, dts + r->nsteps);
+        int64_t nst;
+        std::memcpy(&nst, b + kMaxDim * 8, 8);
+        int32_t flags;
+        std::memcpy(&flags, b + kMaxDim * 8 + 16, 4);
+        const bool bad_steps = (flags & kFlagStepsExceeded) || nst <= 0 || nst > r->nsteps;
+        if (bad_steps) nst = std::max<int64_t>(0, std::min(nst, r->nsteps));
+        sx.steps = nst;
+        if (nst > 0) {
+            sx.dt_min = *std::min_element(dts, dts + nst);
+            sx.dt_max = *std::max_element(dts, dts + nst);
+        }
         sx.t_final = r->tau.back();
         sx.alg_bytes = alg_bytes_per_step(s->opts.precision, r->rk_order,
                                           method_arrays(s->opts) + box_reads(r->dyn.id, s->opts, r->rk_order),
                                           r->grid.npts) *
-                       double(r->nsteps);
+                       double(nst);
         std::memcpy(sx.alpha_max, b, sizeof(sx.alpha_max));
-        int32_t flags;
-        std::memcpy(&flags, b + kMaxDim * 8 + 16, 4);
-        sx.nonfinite = flags & 1;
+        sx.nonfinite = flags & kFlagNonFinite;
         release(s, r);
-        finish(s, r, sx.nonfinite ? ODP_ENONFINITE : ODP_OK);
+        finish(s, r, bad_steps ? ODP_EHIP : sx.nonfinite ? ODP_ENONFINITE : ODP_OK);
     }
 }
 
@@ -508,10 +517,14 @@ int enqueue_tick(odp_server *s, const std::vector<Group> &groups, hipEvent_t *do
                 // pursuit-evasion: the costate box of each solve's stage input
                 // first (each solve's own step counter picks its box buffer)
                 if (g.dyn == ODP_DYN_PE3D && !o.dissipation &&
-                    (rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, kind | 32, s->d_slots,
-                                                 s->d_tiles + g.tile_base, s->d_tiles + s->tile_cap + g.tile_base,
-                                                 g.tiles, j, 1, 0, o.xcd_group, s->st),
-                                    "box")))
+                    ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, kind | 32, s->d_slots,
+                                                  s->d_tiles + g.tile_base, s->d_tiles + s->tile_cap + g.tile_base,
+                                                  g.tiles, j, 1, 0, o.xcd_group, s->st),
+                                     "box")) ||
+                     // the step from the box of the first stage (Algorithm 1)
+                     (j == 0 && (rc = check_hip(launch_box_dt(s->d_slots, s->d_list + g.list_base,
+                                                              int(g.slots.size()), 1, 0, s->st),
+                                                "box step")))))
                     return rc;
                 if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, kind,
                                                  s->d_slots, s->d_tiles + g.tile_base,

@@ -120,16 +120,6 @@ int odp_hj_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_d
     }
     if ((rc = plan_prologue(p, base, st))) return rc;
 
-    std::vector<int32_t> land;
-    const bool want_land = opts->save_all || opts->set_slices > 1;
-    if (want_land) {
-        const PlanItem &it = p.items[0];
-        land.resize(size_t(it.nsteps));
-        if ((rc = check_hip(hipMemcpyAsync(land.data(), base + it.land_off, land.size() * 4,
-                                           hipMemcpyDeviceToHost, st), "read landings")) ||
-            (rc = check_hip(hipStreamSynchronize(st), "sync")))
-            return rc;
-    }
     if (opts->save_all) {
         const size_t bytes = size_t(grid->npts) * (opts->precision == 32 ? 4 : 8);
         const void *src = V_init_dev ? V_init_dev : V0_dev;
@@ -142,7 +132,7 @@ int odp_hj_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_d
             return rc;
         (void)hipEventRecord(tm.e0, st);
     }
-    if ((rc = plan_steps(p, base, st, want_land ? &land : nullptr, opts->save_all ? V_all_dev : nullptr)))
+    if ((rc = plan_steps(p, base, st, opts->save_all ? V_all_dev : nullptr)))
         return rc;
     if (stats) {
         (void)hipEventRecord(tm.e1, st);
@@ -231,7 +221,7 @@ int odp_hj_batch(int nsolves, const odp_solve_desc *descs, const odp_solve_opts 
             return rc;
         (void)hipEventRecord(tm.e0, st);
     }
-    if ((rc = plan_steps(p, base, st, nullptr, nullptr))) return rc;
+    if ((rc = plan_steps(p, base, st, nullptr))) return rc;
     if (stats_per_solve) {
         (void)hipEventRecord(tm.e1, st);
         if ((rc = check_hip(hipEventSynchronize(tm.e1), "sync"))) return rc;

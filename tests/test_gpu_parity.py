@@ -186,3 +186,62 @@ def test_graph_replays_equal_eager(odp):
                 e = gpu_solve(odp, spec, V0, prec, graph=2, stream=stream).V.cpu()
                 same = bool(torch.equal(g, eager)) and bool(torch.equal(e, eager))
                 assert same, (spec.name, prec, rep)
+
+
+def test_solve_is_stream_ordered(odp, oracle_mod):
+    """odp_hj_solve without stats returns once its work is enqueued: the step
+    count is worked out on the host, so nothing waits for the device.  Right
+    after the call the stream still runs the 4D solve (about 0.1 s of
+    kernels); once it drains, the result equals the same solve with stats
+    (which synchronises) bit for bit."""
+    import time
+    import torch
+    spec = W.config_dyncar4d(n=80)
+    V0 = torch.tensor(W.make_v0(spec), dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.Stream()
+    grid = odp.Grid.from_spec(spec.grid)
+    opts = odp.make_opts(32, spec.rk_order, spec.cfl, spec.mode, 0, 0.0, 0, 0, odp._stream_handle(stream))
+    ws = torch.empty(odp.odp_hj_workspace_bytes(grid, spec.dyn, spec.tau, opts), dtype=torch.uint8,
+                     device="cuda:0")
+    out = torch.empty_like(V0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    odp.odp_hj_solve(grid, spec.dyn, V0, None, spec.tau, opts, ws, out, want_stats=False)
+    t_call = time.perf_counter() - t0
+    busy = not stream.query()
+    stream.synchronize()
+    t_all = time.perf_counter() - t0
+    print(f"    call returned after {t_call * 1e3:.1f} ms, stream busy: {busy}, done after {t_all * 1e3:.1f} ms",
+          flush=True)
+    assert busy and t_call < 0.5 * t_all
+    ref = torch.empty_like(V0)
+    st = odp.odp_hj_solve(grid, spec.dyn, V0, None, spec.tau, opts, ws, ref, want_stats=True)
+    assert st.steps == 359
+    assert torch.equal(out, ref)
+
+
+def test_cached_graph_replays_new_inputs(odp, oracle_mod):
+    """A repeated solve of one shape on one workspace replays its cached HIP
+    graph; the graph reads V0 and V_out through the descriptors the prologue
+    uploads, so new inputs and outputs give the eager results."""
+    import torch
+    stream = torch.cuda.Stream()
+    spec = W.config_dubins3d(n=(30, 28, 20), T=0.8)
+    grid = odp.Grid.from_spec(spec.grid)
+    for prec in (64, 32):
+        dt = _dtype(prec)
+        V0a = torch.tensor(W.make_v0(spec), dtype=dt, device="cuda:0")
+        V0b = V0a * 0.5 - 0.25
+        opts_g = odp.make_opts(prec, 1, spec.cfl, spec.mode, 0, 0.0, 0, 0, odp._stream_handle(stream), 0, 1)
+        opts_e = odp.make_opts(prec, 1, spec.cfl, spec.mode, 0, 0.0, 0, 0, odp._stream_handle(stream), 0, 2)
+        ws = torch.empty(odp.odp_hj_workspace_bytes(grid, spec.dyn, spec.tau, opts_g), dtype=torch.uint8,
+                         device="cuda:0")
+        outs = {}
+        for name, v0 in (("a", V0a), ("b", V0b), ("a2", V0a)):
+            og, oe = torch.empty_like(v0), torch.empty_like(v0)
+            odp.odp_hj_solve(grid, spec.dyn, v0, None, spec.tau, opts_g, ws, og, want_stats=False)
+            odp.odp_hj_solve(grid, spec.dyn, v0, None, spec.tau, opts_e, ws, oe, want_stats=True)
+            stream.synchronize()
+            assert torch.equal(og, oe), (prec, name)
+            outs[name] = og
+        assert torch.equal(outs["a"], outs["a2"]) and not torch.equal(outs["a"], outs["b"])

@@ -45,7 +45,12 @@ def _check(odp, oracle_mod, spec, space_order=1, dissipation=0, precs=(64, 32)):
         err = float(np.abs(res.V.double().cpu().numpy() - ref.V).max())
         print(f"    steps gpu={res.stats['steps']} oracle={ref.steps} max|err|/S={err / S:.3e}", flush=True)
         assert res.stats["steps"] == ref.steps
-        assert res.stats["dt_max"] == ref.dt_max
+        # float64 boxes round like the oracle's; a float32 box may differ in
+        # its last bits, which moves the step only at a pattern threshold
+        if prec == 64:
+            assert res.stats["dt_max"] == ref.dt_max
+        else:
+            assert abs(res.stats["dt_max"] - ref.dt_max) <= 1e-12 * ref.dt_max
         assert err <= TOL[prec] * S, (prec, err / S)
     return ref
 
@@ -66,9 +71,11 @@ def test_pe3d_global_alpha(odp, oracle_mod):
 @pytest.mark.parametrize("rk", [1, 2])
 def test_pe3d_narrow_box(odp, oracle_mod, rk):
     """V0 = x + 0.3 |y - 0.5|: the costate box stays narrow for the first
-    steps, so its dissipation is below the all-inputs bound (the oracle's
-    results with and without the box differ by 0.07 after 8 steps, far above
-    the bars): the GPU machine reduction and box alpha are what is compared."""
+    steps, so its dissipation and Algorithm 1's CFL step (from the largest box
+    alpha, (4, 5, 2) against the all-inputs (6, 5, 2) at the start) differ
+    from the all-inputs ones: a horizon of 8 all-inputs steps takes 7.  The
+    GPU machine reduction, the per-step box alpha^max and the box dissipation are
+    what is compared."""
     import torch
     g = W.GridSpec([33, 17, 12], [-4.0, -4.0, -np.pi], [4.0, 4.0, np.pi], [0, 0, 1])
     d = W.DynSpec(W.DYN_PE3D, [1.0, 1.0, 1.0, 1.0], W.MAXIMISE, W.MINIMISE)
@@ -78,13 +85,66 @@ def test_pe3d_narrow_box(odp, oracle_mod, rk):
     spec = W.SolveSpec(g, d, [0.0, 8 * dt * (1 - 1e-12)], rk_order=rk, cfl=0.8, mode=W.BRS,
                        name=f"pe3d_narrow_box_rk{rk}")
     ref = oracle_mod.solve(g, d, V0, spec.tau, rk_order=rk, cfl=0.8, brt=False)
+    assert ref.steps == 7
     for prec in (64, 32):
         res = odp.solve(spec, _dev(V0, prec), precision=prec)
         torch.cuda.synchronize()
         err = float(np.abs(res.V.double().cpu().numpy() - ref.V).max())
-        print(f"    narrow box rk{rk} fp{prec}: steps {res.stats['steps']} max|err| {err:.3e}", flush=True)
-        assert res.stats["steps"] == ref.steps == 8
+        print(f"    narrow box rk{rk} fp{prec}: steps {res.stats['steps']} dt_max {res.stats['dt_max']:.6e} "
+              f"(oracle {ref.dt_max:.6e}) max|err| {err:.3e}", flush=True)
+        assert res.stats["steps"] == ref.steps
+        assert abs(res.stats["dt_max"] - ref.dt_max) <= 1e-12 * ref.dt_max
         assert err <= TOL[prec] * 8.0, (prec, err)
+
+
+def test_pe3d_narrow_box_save_all_and_odd_steps(odp, oracle_mod):
+    """save_all on a solve whose landings the device decides (the box step),
+    with output times chosen so that the step count is odd and even across
+    intervals (first-order results then end in either ping-pong buffer):
+    every saved slice matches the oracle's."""
+    import torch
+    g = W.GridSpec([33, 17, 12], [-4.0, -4.0, -np.pi], [4.0, 4.0, np.pi], [0, 0, 1])
+    d = W.DynSpec(W.DYN_PE3D, [1.0, 1.0, 1.0, 1.0], W.MAXIMISE, W.MINIMISE)
+    X, Y, _ = np.meshgrid(g.axis(0), g.axis(1), g.axis(2), indexing="ij")
+    V0 = X + 0.3 * np.abs(Y - 0.5)
+    _, dt = oracle_mod.cfl_dt(g, d, 0.8)
+    tau = [0.0, 2.5 * dt, 5.2 * dt, 8.1 * dt]
+    spec = W.SolveSpec(g, d, tau, rk_order=1, cfl=0.8, mode=W.BRS, name="pe3d_narrow_box_save_all")
+    ref = oracle_mod.solve(g, d, V0, tau, rk_order=1, cfl=0.8, brt=False, save_all=True)
+    for prec in (64, 32):
+        res = odp.solve(spec, _dev(V0, prec), precision=prec, save_all=True)
+        torch.cuda.synchronize()
+        assert res.stats["steps"] == ref.steps
+        allv = res.V_all.double().cpu().numpy()
+        for k in range(len(tau)):
+            err = float(np.abs(allv[k] - ref.V_all[k]).max())
+            assert err <= TOL[prec] * 8.0, (prec, k, err)
+        assert np.array_equal(res.V.cpu().numpy(), res.V_all[-1].cpu().numpy())
+
+
+def test_pe3d_capture_100_full_size(odp, oracle_mod):
+    """The benchmark workload itself (100^3, horizon 1.5, first order, tube):
+    the costate box spans both signs of the evader's switching function at
+    every node from the first step on, so Algorithm 1's box alpha^max is the
+    all-inputs bound at every step (all 315 steps take the all-inputs dt, the
+    last one clipped), and the whole grid matches the oracle."""
+    import torch
+    spec = W.config_pe3d(n=100)
+    V0 = W.make_v0(spec)
+    _, dt_all = oracle_mod.cfl_dt(spec.grid, spec.dyn, spec.cfl)
+    print("[gpu] pe3d 100^3 full size: oracle solve (float64, CPU)", flush=True)
+    ref = oracle_mod.solve_spec(spec, V0)
+    assert ref.dt_max == dt_all and ref.steps == 315
+    S = spec.grid.domain_scale()
+    for prec in (64, 32):
+        res = odp.solve(spec, _dev(V0, prec), precision=prec)
+        torch.cuda.synchronize()
+        err = float(np.abs(res.V.double().cpu().numpy() - ref.V).max())
+        print(f"    100^3 fp{prec}: steps {res.stats['steps']} dt_max {res.stats['dt_max']!r} "
+              f"max|err|/S {err / S:.3e}", flush=True)
+        assert res.stats["steps"] == 315
+        assert res.stats["dt_max"] == dt_all
+        assert err <= TOL[prec] * S
 
 
 def test_pe3d_launch_shapes_and_batch_bitwise(odp):
