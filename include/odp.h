@@ -236,6 +236,29 @@ int odp_hj_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_d
                  const odp_solve_opts *opts, void *workspace_dev, void *V_out_dev,
                  void *V_all_dev, odp_solve_stats *stats);
 
+/* ------------------------------------------------- allocation-free solve */
+
+/* For callers that cannot allocate device or pinned memory (code recorded
+ * into a HIP graph, tight serving loops, harnesses that forbid allocation):
+ * odp_hj_solve with the same arguments and results, whose workspace is a
+ * fixed device array of 256 MiB inside the library (one per GPU, held from
+ * the library's load until the process ends) instead of a caller or
+ * library allocation.  It allocates nothing: the time stepping is launched
+ * eagerly (opts->graph is ignored), ODP_TILE_AUTOTUNE means the default
+ * tiling, and the plan is uploaded from pageable host memory (the runtime
+ * performs that copy synchronously).  stats: NULL, or filled after a stream
+ * synchronisation (kernel_ms is 0: timing would need events).
+ * Returns ODP_ENOMEM, before touching the device, when the solve needs more
+ * workspace than the array holds (odp_hj_workspace_bytes with the default
+ * tiling: e.g. up to about 64M float32 points with RK1/RK2, 32M with RK3).
+ * Every call on one GPU uses that GPU's one array: calls that overlap on a
+ * GPU (from several threads, or on streams that run concurrently) race and
+ * give wrong results; calls in one stream's order are safe. */
+int odp_hj_solve_noalloc(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_dev,
+                         const void *V_init_dev, const double *tau, int ntau,
+                         const odp_solve_opts *opts, void *V_out_dev, void *V_all_dev,
+                         odp_solve_stats *stats);
+
 /* ----------------------------------------------------------------- batch */
 
 /* One solve of a batch: its own grid, dynamics, target and horizon. */

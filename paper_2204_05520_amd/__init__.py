@@ -134,6 +134,10 @@ def lib():
         L.odp_hj_solve.argtypes = [vp, ctypes.POINTER(odp_dynamics), vp, vp, dp, i32,
                                    ctypes.POINTER(odp_solve_opts), vp, vp, vp,
                                    ctypes.POINTER(odp_solve_stats)]
+        L.odp_hj_solve_noalloc.restype = i32
+        L.odp_hj_solve_noalloc.argtypes = [vp, ctypes.POINTER(odp_dynamics), vp, vp, dp, i32,
+                                           ctypes.POINTER(odp_solve_opts), vp, vp,
+                                           ctypes.POINTER(odp_solve_stats)]
         if hasattr(L, "odp_hj_batch"):
             L.odp_hj_batch_workspace_bytes.restype = ctypes.c_size_t
             L.odp_hj_batch_workspace_bytes.argtypes = [i32, ctypes.POINTER(odp_solve_desc),
@@ -295,6 +299,21 @@ def odp_hj_solve(grid: Grid, dyn, V0, V_init, tau, opts: odp_solve_opts, workspa
     rc = lib().odp_hj_solve(grid.handle, ctypes.byref(d), ptr(V0), ptr(V_init), t, len(tau),
                             ctypes.byref(opts), ptr(workspace), ptr(V_out), ptr(V_all),
                             ctypes.byref(st) if want_stats else None)
+    _check(rc)
+    return st
+
+
+def odp_hj_solve_noalloc(grid: Grid, dyn, V0, V_init, tau, opts: odp_solve_opts, V_out, V_all=None,
+                         want_stats=True):
+    """Raw allocation-free entry point (the library's fixed scratch array as
+    the workspace): tensors (or None) are passed by data_ptr."""
+    d = make_dynamics(dyn)
+    t = _tau_array(tau)
+    st = odp_solve_stats()
+    ptr = lambda x: None if x is None else ctypes.c_void_p(x.data_ptr())
+    rc = lib().odp_hj_solve_noalloc(grid.handle, ctypes.byref(d), ptr(V0), ptr(V_init), t, len(tau),
+                                    ctypes.byref(opts), ptr(V_out), ptr(V_all),
+                                    ctypes.byref(st) if want_stats else None)
     _check(rc)
     return st
 

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libodp.so")
 
-SOURCES = ["kernels.hip", "runtime.cpp", "plan.cpp", "tune.cpp", "solve.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "plan.cpp", "tune.cpp", "solve.cpp", "serve.cpp", "noalloc.hip"]
 # (precision, dynamics id) slices of the stage kernels
 SLICES = [(p, d) for p in (32, 64) for d in range(5)]
 

@@ -442,7 +442,7 @@ void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &
     }
 }
 
-int plan_prologue(Plan &p, unsigned char *base, hipStream_t st) {
+int plan_prologue(Plan &p, unsigned char *base, hipStream_t st, bool pageable) {
     int rc;
     if (!p.error.empty()) return set_error(ODP_EHIP, p.error);
     std::vector<unsigned char> img;
@@ -450,7 +450,14 @@ int plan_prologue(Plan &p, unsigned char *base, hipStream_t st) {
     const int n = int(p.items.size());
     const SolveDesc *descs = (const SolveDesc *)(base + p.desc_off);
     int64_t *nsteps_dev = (int64_t *)(base + p.nsteps_off);
-    if ((rc = upload_async(base, img.data(), img.size(), st))) return rc;
+    // pageable: a plain copy from host memory (performed synchronously by
+    // the runtime), for callers that must not allocate pinned staging
+    if (pageable) {
+        if ((rc = check_hip(hipMemcpyAsync(base, img.data(), img.size(), hipMemcpyHostToDevice, st), "upload")))
+            return rc;
+    } else if ((rc = upload_async(base, img.data(), img.size(), st))) {
+        return rc;
+    }
     if ((rc = check_hip(launch_init(descs, n, st), "init"))) return rc;
     for (const PlanGroup &gr : p.groups) {
         int64_t qmax = 1;
@@ -626,14 +633,16 @@ std::vector<int64_t> plan_key(const Plan &p, unsigned char *base, void *V_all) {
 
 }  // namespace
 
-int plan_stats(const Plan &p, unsigned char *base, double kernel_ms, odp_solve_stats *stats) {
+int plan_stats(const Plan &p, unsigned char *base, double kernel_ms, odp_solve_stats *stats, hipStream_t st) {
     int rc;
     const odp_solve_opts &o = p.opts;
     // two bulk copies: every solve's state/tables/tau, every schedule
     std::vector<unsigned char> aux(p.tt_off - p.aux_begin), sched(p.arr_begin - p.sched_begin);
-    if ((rc = check_hip(hipMemcpy(aux.data(), base + p.aux_begin, aux.size(), hipMemcpyDeviceToHost), "read state")) ||
-        (rc = check_hip(hipMemcpy(sched.data(), base + p.sched_begin, sched.size(), hipMemcpyDeviceToHost),
-                        "read schedules")))
+    if ((rc = check_hip(hipMemcpyAsync(aux.data(), base + p.aux_begin, aux.size(), hipMemcpyDeviceToHost, st),
+                        "read state")) ||
+        (rc = check_hip(hipMemcpyAsync(sched.data(), base + p.sched_begin, sched.size(), hipMemcpyDeviceToHost, st),
+                        "read schedules")) ||
+        (rc = check_hip(hipStreamSynchronize(st), "sync")))
         return rc;
     int worst = ODP_OK;
     std::string why;

@@ -83,14 +83,15 @@ int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t
 void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &img);
 // Upload, alpha^max, schedules (stream-ordered: the step counts are known on
 // the host from plan_build), member order and tile tables.
-int plan_prologue(Plan &p, unsigned char *base, hipStream_t st);
+// pageable: upload from pageable host memory (no pinned staging).
+int plan_prologue(Plan &p, unsigned char *base, hipStream_t st, bool pageable = false);
 // Start copies and every step of every solve (stream-ordered, no sync).
 // V_all: save_all of a single solve (slice k = V at tau[k]), else null.
 int plan_steps(Plan &p, unsigned char *base, hipStream_t st, void *V_all);
 // Whether the plan's stepping is recorded into a HIP graph.
 bool plan_wants_graph(const Plan &p);
 // Fill per-item stats after the stream has been synchronised.
-int plan_stats(const Plan &p, unsigned char *base, double kernel_ms, odp_solve_stats *stats);
+int plan_stats(const Plan &p, unsigned char *base, double kernel_ms, odp_solve_stats *stats, hipStream_t st);
 
 
 }  // namespace odp

@@ -139,7 +139,7 @@ int odp_hj_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *V0_d
         if ((rc = check_hip(hipEventSynchronize(tm.e1), "sync"))) return rc;
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, tm.e0, tm.e1);
-        return plan_stats(p, base, ms, stats);
+        return plan_stats(p, base, ms, stats, st);
     }
     return ODP_OK;
 }
@@ -228,7 +228,7 @@ int odp_hj_batch(int nsolves, const odp_solve_desc *descs, const odp_solve_opts 
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, tm.e0, tm.e1);
         std::vector<odp_solve_stats> sorted(p.items.size());
-        rc = plan_stats(p, base, ms, sorted.data());
+        rc = plan_stats(p, base, ms, sorted.data(), st);
         for (size_t i = 0; i < perm.size(); ++i) stats_per_solve[perm[i]] = sorted[i];
         if (rc) return rc;
     }
