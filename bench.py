@@ -288,6 +288,11 @@ def bench_batch(args, W, odp):
                      "kernel": "stage_kernel fp32 (batched launches)"},
         "fp64_per_solve_value": pts / wall64, "fp64_per_solve_ms": wall64 * 1e3,
         "batch_over_per_solve": wall64 / wall,
+        # algorithmic bytes over the call's wall time (prologue included) and
+        # over the device time of its stepping
+        "wall_roofline_frac": alg / wall / 1e9 / HBM_PEAK_GBPS,
+        "kernel_roofline_frac": alg / kernel_s / 1e9 / HBM_PEAK_GBPS,
+        "prologue_ms": wall * 1e3 - kernel_s * 1e3,
     }
     return line
 
@@ -307,6 +312,8 @@ def bench_serve(args, W, odp):
     srv = odp.Server(budget_bytes=96 << 30, max_slots=512, precision=32, rk_order=1)
     tickets = [None] * len(reqs)
     lat = [None] * len(reqs)
+    sub_t = [None] * len(reqs)
+    done_t = [None] * len(reqs)
     steps = [0] * len(reqs)
     pts = [0] * len(reqs)
     algb = [0.0] * len(reqs)
@@ -321,6 +328,7 @@ def bench_serve(args, W, odp):
             t = srv.submit(reqs[i].spec, V0s[i], rk_order=reqs[i].spec.rk_order)
             with lock:
                 tickets[i] = t
+                sub_t[i] = time.perf_counter() - t0
 
     threads = [threading.Thread(target=submitter, args=(k, 4)) for k in range(4)]
     for th in threads:
@@ -338,6 +346,7 @@ def bench_serve(args, W, odp):
                 continue
             rc, st = srv.poll(t, outs[i])
             if rc == 0:
+                done_t[i] = time.perf_counter() - t0
                 lat[i] = st["latency_ms"]
                 steps[i] = st["steps"]
                 pts[i] = reqs[i].spec.grid.npts * st["steps"]
@@ -349,22 +358,117 @@ def bench_serve(args, W, odp):
         th.join()
     srv.close()
     meas = np.array(lat[warm:])
+    # client clock: from the request's scheduled (Poisson) arrival to the poll
+    # that saw it done (includes any lag of the submitting threads)
+    client = np.array([(done_t[i] - reqs[i].arrival_s) * 1e3 for i in range(warm, len(reqs))])
+    lag = np.array([(sub_t[i] - reqs[i].arrival_s) * 1e3 for i in range(warm, len(reqs))])
     t_first = reqs[warm].arrival_s
     span = wall - t_first
     line = {
         "metric": METRIC, "value": float(sum(pts[warm:]) / span), "unit": "grid-point updates/s",
-        "n_gpus": 1, "steps": nreq, "warmup": warm, "ms_per_step": float(np.mean(meas)),
+        "n_gpus": 1, "steps": nreq, "warmup": warm, "ms_per_step": float(np.mean(client)),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "serve_poisson200_mixed_dubins3d_dyncar4d", "requests": nreq,
                    "rate_per_s": 200.0},
-        "latency_ms": {"p50": float(np.percentile(meas, 50)), "p90": float(np.percentile(meas, 90)),
-                       "p99": float(np.percentile(meas, 99)), "max": float(meas.max())},
+        "latency_ms": {"p50": float(np.percentile(client, 50)), "p90": float(np.percentile(client, 90)),
+                       "p99": float(np.percentile(client, 99)), "max": float(client.max()),
+                       "clock": "client: scheduled arrival to observed completion"},
+        "server_latency_ms": {"p50": float(np.percentile(meas, 50)), "p90": float(np.percentile(meas, 90)),
+                              "p99": float(np.percentile(meas, 99)), "max": float(meas.max()),
+                              "clock": "server: submit to completion"},
+        "submit_lag_ms": {"p50": float(np.percentile(lag, 50)), "p99": float(np.percentile(lag, 99))},
         "completed_per_s": nreq / span,
         "alg_tbps_over_run": sum(algb[warm:]) / span / 1e12,
         "offered_alg_tbps": sum(algb[warm:]) / (reqs[-1].arrival_s - t_first) / 1e12,
     }
     return line
+
+
+def _max_abs_diff(a, b, chunk=1 << 26):
+    """max |a - b| in float64 over two device arrays, in chunks."""
+    a, b = a.reshape(-1), b.reshape(-1)
+    m = 0.0
+    for i in range(0, a.numel(), chunk):
+        m = max(m, float((a[i:i + chunk].double() - b[i:i + chunk].double()).abs().max()))
+    return m
+
+
+def leg_small3d(args, W, odp):
+    """The 60x60x36 Dubins solve (float64 plain form and float32): a 1 MB
+    grid that stays in the caches, so it is launch-bound; reported per CFL
+    step."""
+    a = argparse.Namespace(**vars(args))
+    a.workload, a.n, a.steps, a.warmup, a.no_cpu, a.space_order, a.rk = "dubins3d", 0, 20, 2, True, 1, 0
+    ln = bench_single(a, W, odp)
+    steps = ln["config"]["cfl_steps_per_solve"]
+    out = {"grid": ln["config"]["grid"], "cfl_steps_per_solve": steps,
+           "fp64_ms_per_solve": ln["fp64_ms_per_step"] if "fp64_ms_per_step" in ln else ln["ms_per_step"],
+           "fp32_ms_per_solve": ln["ms_per_step"] if ln["dtype"] == "f32" else None,
+           "fp32_pt_updates_per_s": ln["value"], "fp64_pt_updates_per_s": ln.get("fp64_value")}
+    out["fp64_us_per_step"] = out["fp64_ms_per_solve"] * 1e3 / steps
+    out["fp32_us_per_step"] = ln["ms_per_step"] * 1e3 / steps
+    out["bound"] = "launch latency (HIP graph of the whole stepping, cached per shape)"
+    return out
+
+
+def leg_game6d(args, W, odp):
+    """The 36^6 game (2.18e9 points, RK2, T = 2, 73 steps): float32 timed and
+    held, then the float64 plain form; the roofline fraction of the float32
+    stage launches, the float32 speed-up and the float32 max-norm error
+    against the float64 solve over the whole horizon."""
+    import torch
+    dev = torch.device("cuda:0")
+    spec = W.config_game6d()
+    stream = torch.cuda.Stream()
+    res = {}
+    outs = {}
+    for prec, dt, steps in ((32, torch.float32, 2), (64, torch.float64, 1)):
+        V0 = W.make_v0_torch(spec, dev, dt)
+        with torch.cuda.stream(stream):
+            wall, st, kms, out = time_solves(odp, spec, V0, prec, steps, 1, stream, -1)
+        nl = st.steps * spec.rk_order
+        avg = (sum(kms) / len(kms)) / 1e3 / nl
+        res[prec] = {"ms_per_solve": wall / steps * 1e3, "pt_updates_per_s": spec.grid.npts * st.steps * steps / wall,
+                     "steps": st.steps, "avg_launch_us": avg * 1e6,
+                     "frac": st.alg_bytes / nl / avg / 1e9 / HBM_PEAK_GBPS}
+        print(f"# game6d fp{prec}: {res[prec]}", file=sys.stderr, flush=True)
+        outs[prec] = out
+        del V0
+        torch.cuda.empty_cache()
+    err = _max_abs_diff(outs[32], outs[64])
+    del outs
+    torch.cuda.empty_cache()
+    S = spec.grid.domain_scale()
+    return {"grid": spec.grid.n, "cfl_steps_per_solve": res[32]["steps"],
+            "fp32_pt_updates_per_s": res[32]["pt_updates_per_s"], "fp32_ms_per_solve": res[32]["ms_per_solve"],
+            "fp32_roofline_frac": res[32]["frac"], "fp32_avg_stage_launch_us": res[32]["avg_launch_us"],
+            "fp64_pt_updates_per_s": res[64]["pt_updates_per_s"], "fp64_ms_per_solve": res[64]["ms_per_solve"],
+            "fp64_roofline_frac": res[64]["frac"],
+            "fp32_over_fp64": res[32]["pt_updates_per_s"] / res[64]["pt_updates_per_s"],
+            "fp32_vs_fp64_max_abs_err": err, "fp32_vs_fp64_err_over_S": err / S}
+
+
+def leg_batch(args, W, odp):
+    a = argparse.Namespace(**vars(args))
+    a.steps, a.warmup = 5, 1
+    ln = bench_batch(a, W, odp)
+    keep = ("value", "ms_per_step", "fp64_per_solve_ms", "batch_over_per_solve")
+    out = {k: ln[k] for k in keep}
+    out["pt_updates_per_s"] = out.pop("value")
+    out["wall_ms_per_batch"] = out.pop("ms_per_step")
+    out.update({k: ln[k] for k in ("wall_roofline_frac", "kernel_roofline_frac", "prologue_ms") if k in ln})
+    return out
+
+
+def leg_serve(args, W, odp):
+    ln = bench_serve(args, W, odp)
+    keep = ("latency_ms", "server_latency_ms", "completed_per_s", "alg_tbps_over_run", "offered_alg_tbps",
+            "phases_ms")
+    out = {k: ln[k] for k in keep if k in ln}
+    out["requests"] = ln["config"]["requests"]
+    out["rate_per_s"] = ln["config"]["rate_per_s"]
+    return out
 
 
 def main():
@@ -387,6 +491,8 @@ def main():
                     help="2: second-order ENO differences (single-solve workloads)")
     ap.add_argument("--rk", type=int, default=0, choices=[0, 1, 2, 3],
                     help="Runge-Kutta order override (0: the workload's; 2 with --space-order 2)")
+    ap.add_argument("--only", action="store_true",
+                    help="the default 4D workload alone (without the other four configurations' keys)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU sharding is a design "
@@ -407,6 +513,18 @@ def main():
         del a, b
     if args.workload in ("dyncar4d", "game6d", "dubins3d", "pe3d"):
         line = bench_single(args, W, odp)
+        if args.workload == "dyncar4d" and not args.only and args.space_order == 1 and not args.n:
+            # the other four configurations, measured in the same run
+            legs = {}
+            for name, fn in (("dubins3d_60x60x36_rk1_brt", leg_small3d), ("game6d_36^6_rk2_brt", leg_game6d),
+                             ("batch512_dubins3d_rk1_brt", leg_batch),
+                             ("serve_poisson200_mixed_dubins3d_dyncar4d", leg_serve)):
+                print(f"# leg {name}", file=sys.stderr, flush=True)
+                t0 = time.perf_counter()
+                legs[name] = fn(args, W, odp)
+                legs[name]["leg_wall_s"] = time.perf_counter() - t0
+                torch.cuda.empty_cache()
+            line["configs"] = legs
     elif args.workload == "batch":
         line = bench_batch(args, W, odp)
     elif args.workload == "ttr3d":

@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "odp_dev.h"):
+    for f in ("kernels_dev.h", "kernels.hip", "stage_inst.hip", "odp_dev.h"):
         with open(os.path.join(ROOT, "paper_2204_05520_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

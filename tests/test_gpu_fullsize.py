@@ -74,10 +74,12 @@ def test_dyncar4d_80_full_size(odp, oracle_mod):
         # sign-keeping ghost is not monotone at non-periodic faces and what it
         # does there spreads inwards over ~180 steps; the oracle shows the
         # same at faces), bounded here, not proven
+        # (observed: 1.05e-5 in float32, 2.2e-8 in float64; bounds about 10x)
         inc = (A[2] - A[1])
-        print(f"    max increase V(3.0) - V(1.5): {float(inc.max()):.2e} (bound 1e-3), "
+        bound = {32: 1.5e-4, 64: 3e-7}[prec]
+        print(f"    max increase V(3.0) - V(1.5): {float(inc.max()):.2e} (bound {bound:.0e}), "
               f"max decrease {float(-inc.min()):.2e}", flush=True)
-        assert float(inc.max()) <= 1e-3
+        assert float(inc.max()) <= bound
         assert bool((A[2] < V0 - 0.05).any())  # the tube grew beyond the target
         outs[prec] = A[2].double().cpu()
         del V0, A, res
@@ -102,3 +104,63 @@ def test_game6d_36_full_size(odp, oracle_mod):
     assert out.stats["steps"] == 73
     assert bool((out.V <= V0).all())
     assert out.stats["nonfinite"] == 0
+
+
+def _max_abs_diff(a, b, chunk=1 << 26):
+    """max |a - b| in float64 over two device arrays, in chunks."""
+    a, b = a.reshape(-1), b.reshape(-1)
+    m = 0.0
+    for i in range(0, a.numel(), chunk):
+        m = max(m, float((a[i:i + chunk].double() - b[i:i + chunk].double()).abs().max()))
+    return m
+
+
+def test_game6d_36_full_horizon_fp32_vs_fp64(odp):
+    """The 36^6 game over the whole horizon (T = 2, 73 RK2 steps) in float32
+    and in the float64 plain form (3 x 17.4 GB): the float32 solve stays
+    within 1e-4 S of the float64 one (whose parity with the oracle is checked
+    on smaller grids: the chain of the 6D row)."""
+    import torch
+    spec = W.config_game6d()
+    dev = torch.device("cuda:0")
+    print("[gpu] 36^6 full horizon fp32", flush=True)
+    V0 = W.make_v0_torch(spec, dev, torch.float32)
+    r32 = odp.solve(spec, V0, precision=32)
+    torch.cuda.synchronize()
+    out32 = r32.V
+    del V0, r32
+    torch.cuda.empty_cache()
+    print("[gpu] 36^6 full horizon fp64", flush=True)
+    V0 = W.make_v0_torch(spec, dev, torch.float64)
+    r64 = odp.solve(spec, V0, precision=64)
+    torch.cuda.synchronize()
+    assert r64.stats["steps"] == 73
+    err = _max_abs_diff(out32, r64.V)
+    S = spec.grid.domain_scale()
+    print(f"    fp32 vs fp64, 36^6, T=2: max|err| = {err:.3e} (/S {err / S:.2e}, limit 1e-4)", flush=True)
+    assert err <= 1e-4 * S
+    del V0, r64, out32
+    torch.cuda.empty_cache()
+
+
+def test_dyncar4d_80_eno2_full_horizon_fp32_vs_fp64(odp):
+    """The second-order solve the benchmark times (ENO2 + TVD-RK2, 80^4,
+    T = 3, 359 steps) in float32 against float64: within 1e-4 S over the
+    whole horizon."""
+    import torch
+    spec = W.config_dyncar4d()
+    spec.rk_order = 2
+    V0_np = W.make_v0(spec)
+    outs = {}
+    for prec, dt in ((32, torch.float32), (64, torch.float64)):
+        print(f"[gpu] 80^4 ENO2 RK2 full horizon fp{prec}", flush=True)
+        V0 = torch.tensor(V0_np, dtype=dt, device="cuda:0")
+        r = odp.solve(spec, V0, precision=prec, space_order=2)
+        torch.cuda.synchronize()
+        assert r.stats["steps"] == 359
+        outs[prec] = r.V
+        del V0, r
+    err = _max_abs_diff(outs[32], outs[64])
+    S = spec.grid.domain_scale()
+    print(f"    fp32 vs fp64, ENO2 80^4, T=3: max|err| = {err:.3e} (/S {err / S:.2e}, limit 1e-4)", flush=True)
+    assert err <= 1e-4 * S
