@@ -70,6 +70,15 @@ MUTANTS = [
     ("pe3d_speeds_exchanged", "f[0] = -dy->p[0] + dy->p[1] * cos(z[2]) + u[0] * z[1];",
      "f[0] = -dy->p[1] + dy->p[0] * cos(z[2]) + u[0] * z[1];"),
     ("pe3d_cfl_from_all_inputs", "og_alpha_box_max(&g, &dy, box0, amax);", "og_alpha_max(&g, &dy, amax);"),
+    ("global_alpha_ignored", "const double *aglob = global_alpha ? amax : NULL;", "const double *aglob = NULL;"),
+    ("global_alpha_axis0_for_all", "for (int d = 0; d < N; ++d) alpha[d] = alpha_glob[d];",
+     "for (int d = 0; d < N; ++d) alpha[d] = alpha_glob[0];"),
+    ("eno_f32_tie_to_second", "    return fabsf(x) <= fabsf(y);", "    return fabsf(x) < fabsf(y);"),
+    ("eno_f32_decides_in_float64", "    return fabsf(x) <= fabsf(y);",
+     "    return fabs((w2 - w1) - (w1 - w0)) <= fabs((w3 - w2) - (w2 - w1));"),
+    ("ttr_jacobi_reads_new_iterate", "og_field F = {og_get_array, jacobi ? old : phi, NULL, 0};",
+     "og_field F = {og_get_array, phi, NULL, 0};"),
+    ("ttr_jacobi_edge_reads_new_iterate", "const double *src = jacobi ? old : phi;", "const double *src = phi;"),
     ("costate_box_not_used", "static int og_box_dynamics(const og_dyn *dy) { return dy->id == OG_PE3D; }",
      "static int og_box_dynamics(const og_dyn *dy) { return dy->id < 0; }"),
     ("ttr_right_side_dropped", "double H = 0.0, num = 1.0, den = 0.0;", "double H = 0.0, num = 0.0, den = 0.0;"),
@@ -115,6 +124,12 @@ FAST_PINS = [
     pins.test_pin12_ttr_ball_closed_form_first_order,
     pins.test_pin12_ttr_speed_scaling,
     pins.test_pin12_ttr_dubins_straight_ahead,
+    pins.test_pin13_global_alpha_heat_step_where_the_drift_vanishes,
+    pins.test_pin13_global_alpha_converges_at_first_order,
+    pins.test_pin13_global_alpha_tube_monotone,
+    pins.test_pin14_eno_f32_choices_agree_with_margins,
+    pins.test_pin14_eno_f32_near_tie_built_by_hand,
+    pins.test_pin15_ttr_jacobi_front_in_1d,
     lambda o: [pins.test_pin9_restart_reference(o, m, f) for m, f in
                (("minVWithVInit", np.minimum), ("maxVWithVInit", np.maximum), ("minVWithV0", None))],
 ]

@@ -973,3 +973,155 @@ def test_pin9_obstacle_bounds(oracle_mod):
     c = oracle_mod.solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=1, brt=True,
                          omode="maxVWithObstacle", obstacle=np.full(V0.shape, 7.0)).V
     assert np.array_equal(a, ref) and np.array_equal(b, ref) and (c == 7.0).all()
+
+
+# ------------------------------------------------------------------ pin 13
+# The global-alpha approximation (Algorithm 1's note that the per-point alpha
+# may be replaced by the largest rate of change over the grid).
+
+def _dubins_no_turn(n_xy, n_th, v=1.0, w=0.3, T=0.4):
+    g = W.GridSpec([n_xy, n_xy, n_th], [-4.0, -4.0, -np.pi], [4.0, 4.0, np.pi], [0, 0, 1])
+    d = W.DynSpec(W.DYN_DUBINS3D, [v, w], W.MAXIMISE, W.MINIMISE)
+    return g, d
+
+
+def test_pin13_global_alpha_heat_step_where_the_drift_vanishes(oracle_mod):
+    """Dubins car with V = x^2 (no y or heading dependence).  On the heading
+    slice th = pi/2 the x-velocity v cos th vanishes (to rounding), so with
+    per-point alpha the x term is zero and V does not move, while the global
+    approximation dissipates with alpha^max_x = v: one step is the discrete
+    heat step V_i + dt (v / 2dx)(V_{i+1} - 2 V_i + V_{i-1}) = x^2 + dt v dx at
+    interior nodes (worked out by hand).  On th = 0 both forms are the
+    upwind step x^2 + dt v (2x + dx) (forward difference, v > 0).  The
+    heading term (alpha_th = w) and y terms see zero differences."""
+    v, w, dt = 1.3, 0.3, 0.01
+    g, d = _dubins_no_turn(41, 4, v=v, w=w)  # headings -pi, -pi/2, 0, pi/2
+    x = g.axis(0)
+    X = np.broadcast_to(x[:, None, None], tuple(g.n))
+    V = np.ascontiguousarray(X * X)
+    dx = x[1] - x[0]
+    amax, _ = oracle_mod.cfl_dt(g, d, 0.8)
+    assert abs(amax[0] - v) < 1e-15 and abs(amax[2] - w) < 1e-15
+    ix = np.arange(1, 40)
+    for k, expect_local, expect_global in (
+            (3, x[ix] ** 2, x[ix] ** 2 + dt * v * dx),                       # th = pi/2
+            (2, x[ix] ** 2 + dt * v * (2 * x[ix] + dx), x[ix] ** 2 + dt * v * (2 * x[ix] + dx))):  # th = 0
+        idx = np.ravel_multi_index((ix, np.full_like(ix, 2), np.full_like(ix, k)), tuple(g.n))
+        loc = oracle_mod.step_at(g, d, V, V, dt, idx, brt=False)
+        glo = oracle_mod.step_at(g, d, V, V, dt, idx, brt=False, alpha_glob=amax)
+        assert np.abs(loc - expect_local).max() < 1e-12, k
+        assert np.abs(glo - expect_global).max() < 1e-12, k
+    # the whole solve takes the same global-alpha dissipation
+    res = oracle_mod.solve(g, d, V, [0.0, dt], rk_order=1, cfl=0.8, brt=False, global_alpha=True)
+    got = res.V[ix, 2, 3]
+    assert np.abs(got - (x[ix] ** 2 + dt * v * dx)).max() < 1e-12
+
+
+def _advected(g, v, T, r=1.0):
+    """Dubins with w = 0 is a constant-velocity advection on every heading
+    slice: V(z, T) = V0(x + v cos th T, y + v sin th T) for V0 = |(x, y)| - r."""
+    X, Y, TH = np.meshgrid(g.axis(0), g.axis(1), g.axis(2), indexing="ij")
+    return np.sqrt((X + v * np.cos(TH) * T) ** 2 + (Y + v * np.sin(TH) * T) ** 2) - r
+
+
+def test_pin13_global_alpha_converges_at_first_order(oracle_mod):
+    """With the turn bound 0 every heading slice is an advection whose exact
+    solution is the advected cone; the global-alpha scheme (more diffusive
+    where |v cos th| < v) still converges to it at first order in the band
+    |V| <= 0.5 (observed order in [0.7, 1.3]) and differs from the
+    per-point form by O(dx)."""
+    errs, hs = [], []
+    for n in (26, 51, 101):
+        g, d = _dubins_no_turn(n, 8, v=1.0, w=0.0)
+        V0 = W.cylinder_v0(g, 1.0)
+        T = 0.5
+        res = oracle_mod.solve(g, d, V0, [0.0, T], rk_order=1, cfl=0.8, brt=False, global_alpha=True)
+        exact = _advected(g, 1.0, T)
+        band = np.abs(exact) <= 0.5
+        errs.append(np.abs(res.V - exact)[band].max())
+        hs.append(8.0 / (n - 1))
+        loc = oracle_mod.solve(g, d, V0, [0.0, T], rk_order=1, cfl=0.8, brt=False)
+        diff = np.abs(res.V - loc.V)[band].max()
+        assert 0.01 * hs[-1] < diff < 2.0 * hs[-1], (n, diff)
+    orders = [math.log(errs[i] / errs[i + 1]) / math.log(hs[i] / hs[i + 1]) for i in range(2)]
+    assert all(0.7 <= o <= 1.3 for o in orders), (errs, orders)
+
+
+def test_pin13_global_alpha_tube_monotone(oracle_mod):
+    """Pin 3 with the global approximation: the scheme stays monotone (alpha
+    only grows), so the tube never grows back inside and V <= V0."""
+    spec = W.config_dubins3d(n=(24, 24, 16), T=0.6)
+    V0 = W.make_v0(spec)
+    res = oracle_mod.solve(spec.grid, spec.dyn, V0, [0.0, 0.3, 0.6], rk_order=1, cfl=0.8, brt=True,
+                           global_alpha=True, save_all=True)
+    A = res.V_all
+    assert np.all(A[1] <= V0 + 1e-12) and np.all(A[2] <= V0 + 1e-12)
+    inner = (slice(1, -1), slice(1, -1), slice(None))
+    assert np.all(A[2][inner] <= A[1][inner] + 1e-12)
+    assert np.abs(A[2] - V0).max() > 0.1
+
+
+# ------------------------------------------------------------------ pin 14
+# ENO2 stencil choices taken in float32 (as a float32 solve takes them).
+
+def test_pin14_eno_f32_choices_agree_with_margins(oracle_mod):
+    """Where the two candidate second differences differ by far more than
+    float32 rounding (V = exp(x/2): consecutive second differences differ by
+    a factor e^{dx/2}), taking the choices in float32 changes nothing: the
+    step is the same, bit for bit, on float32-representable data."""
+    for c in (0.8, -0.6):
+        g, d = _drift_1d(41, c=c)
+        V = np.exp(g.axis(0) / 2).astype(np.float32).astype(np.float64)
+        idx = np.arange(41)
+        a = oracle_mod.step_at(g, d, V, V, 0.01, idx, brt=False, space_order=2, eno_f32=True)
+        b = oracle_mod.step_at(g, d, V, V, 0.01, idx, brt=False, space_order=2, eno_f32=False)
+        assert np.array_equal(a, b), c
+
+
+def test_pin14_eno_f32_near_tie_built_by_hand(oracle_mod):
+    """A stencil (V_{i-2}, V_{i-1}, V_i, V_{i+1}) = (2^-30, 0, 1, 3) on unit
+    spacing: the minus side's candidates are sm = 1 + 2^-30 and s0 = 1.  In
+    float64 |sm| > |s0|, so p- = dm + s0/2 = 1.5; in float32 the difference
+    1 + 2^-30 rounds to 1, a tie, which takes the first candidate: p- = 1 +
+    (1 + 2^-30)/2 (the correction itself in float64).  With drift c = -1
+    (alpha = 1) the step is V_i - dt p-, so the two forms differ by exactly
+    dt 2^-31."""
+    g = W.GridSpec([8], [0.0], [7.0], [0])
+    d = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [0.0, -1.0], W.MAXIMISE, W.MINIMISE)
+    V = np.array([5.0, 4.0, 2.0 ** -30, 0.0, 1.0, 3.0, 6.0, 10.0])
+    dt = 0.25
+    i = 4
+    f64 = oracle_mod.step_at(g, d, V, V, dt, [i], brt=False, space_order=2, eno_f32=False)[0]
+    f32 = oracle_mod.step_at(g, d, V, V, dt, [i], brt=False, space_order=2, eno_f32=True)[0]
+    # plus side (s0 = 1 against sp = 3 - 2 = 1, a tie in both: first) is the
+    # same in both forms; with c = -1 the LF form uses p- only
+    assert f64 == 1.0 - dt * 1.5
+    assert f32 == 1.0 - dt * (1.5 + 2.0 ** -31)
+
+
+# ------------------------------------------------------------------ pin 15
+# The parallel (Jacobi) time-to-reach iteration, derived by hand.
+
+def test_pin15_ttr_jacobi_front_in_1d(oracle_mod):
+    """1D, |u| <= 1 (sigma = 1), target = node 0, unit spacing.  The point
+    update reduces to phi_i <- min(phi_i, 1 + min(phi_{i-1}, phi_{i+1})) (the
+    centred costate's |pbar| term cancels the neighbour mean's difference),
+    so in the parallel form the front advances exactly one node per
+    iteration: after k iterations phi_i = i for i <= k and the start value
+    beyond.  The far edge node takes max(2 phi_a - phi_b, phi_b) from the
+    previous iterate, one iteration after its inner neighbour is reached,
+    giving n - 1.  (A forward Gauss-Seidel sweep finishes the interior in one
+    iteration.)"""
+    n, big = 12, 1e4
+    g = W.GridSpec([n], [0.0], [float(n - 1)], [0])
+    d = W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [1.0, 0.0], W.MINIMISE, W.MAXIMISE)
+    l = np.arange(n, dtype=np.float64) - 0.5  # only node 0 has l <= 0
+    for k in (1, 4, n - 3, n - 2, n - 1):
+        r = oracle_mod.ttr_solve(g, d, l, eps=1e-300, max_iters=k, big=big, jacobi=True)
+        expect = np.where(np.arange(n) <= k, np.arange(n, dtype=np.float64), big)
+        expect[n - 1] = n - 1.0 if k >= n - 1 else big
+        assert np.array_equal(r.phi, expect), (k, r.phi)
+    conv = oracle_mod.ttr_solve(g, d, l, eps=1e-12, jacobi=True, big=big)
+    assert np.array_equal(conv.phi, np.arange(n, dtype=np.float64)) and conv.iters == n
+    gs = oracle_mod.ttr_solve(g, d, l, eps=1e-300, max_iters=1, big=big)
+    assert np.array_equal(gs.phi[:n - 1], np.arange(n - 1, dtype=np.float64))
