@@ -1207,6 +1207,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
     // end logic sits in branches that such waves skip.
     const bool anyg = __builtin_amdgcn_ballot_w64((gl | gr) != 0) != 0;
     const bool rowx = __builtin_amdgcn_ballot_w64(gxl || gxr || jend < VEC - 1) != 0;
+    // which faces any lane of the wave is on: bit d of wgl (wgr) set when
+    // some lane is on the lower (upper) non-periodic face of middle axis d
+    uint32_t wgl = 0, wgr = 0;
+#pragma unroll
+    for (int d = 1; d < N - 1; ++d) {
+        if (__builtin_amdgcn_ballot_w64((gl >> d) & 1u) != 0) wgl |= 1u << d;
+        if (__builtin_amdgcn_ballot_w64((gr >> d) & 1u) != 0) wgr |= 1u << d;
+    }
 
     using P = Pack<T, VEC>;
     const int wlast = i0e, vlast = i0e - 1;
@@ -1325,28 +1333,65 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
 
         Acc<T> acc[VEC];
         P dp;  // W(i+1) - W(i)
-        const bool g0l = !per0 && i == 0, g0r = !per0 && i == n0 - 1;
+        // The edge cases (ghost nodes) are substituted in one uniform branch
+        // per kind and plane, taken only on the edge planes of axis 0 and by
+        // the waves that hold a lane on a non-periodic face: the common path
+        // is straight-line.  The values, and the order of the accumulation,
+        // are the same either way.
+        T dl0[VEC], dr0[VEC];
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            dp.v[j] = wp.v[j] - wc.v[j];
+            dl0[j] = dm.v[j];
+            dr0[j] = dp.v[j];
+        }
+        if (!per0 && (i == 0 || i == n0 - 1)) {
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                if (i == 0) dl0[j] = wc.v[j] - ghost(wc.v[j], wp.v[j]);
+                if (i == n0 - 1) dr0[j] = ghost_d(wc.v[j], dm.v[j]) - wc.v[j];
+            }
+        }
+        T na[NM][VEC], nbv[NM][VEC];  // neighbour values of the middle axes
+#pragma unroll
+        for (int d = 1; d < N - 1; ++d)
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                na[d - 1][j] = cur.l[d - 1].v[j];
+                nbv[d - 1][j] = cur.r[d - 1].v[j];
+            }
+        if (anyg) {
+#pragma unroll
+            for (int d = 1; d < N - 1; ++d) {
+                if (wgl & (1u << d)) {
+                    const bool on = (gl >> d) & 1u;
+#pragma unroll
+                    for (int j = 0; j < VEC; ++j) {
+                        const T gv = ghost(wc.v[j], cur.r[d - 1].v[j]);
+                        na[d - 1][j] = on ? gv : na[d - 1][j];
+                    }
+                }
+                if (wgr & (1u << d)) {
+                    const bool on = (gr >> d) & 1u;
+#pragma unroll
+                    for (int j = 0; j < VEC; ++j) {
+                        const T gv = ghost(wc.v[j], cur.l[d - 1].v[j]);
+                        nbv[d - 1][j] = on ? gv : nbv[d - 1][j];
+                    }
+                }
+            }
+        }
 #pragma unroll
         for (int j = 0; j < VEC; ++j) {
             acc[j].L = T(0);
             acc[j].n2 = T(0);
-            dp.v[j] = wp.v[j] - wc.v[j];
-            T dl = dm.v[j], dr = dp.v[j];
-            if (g0l) dl = wc.v[j] - ghost(wc.v[j], wp.v[j]);
-            if (g0r) dr = ghost_d(wc.v[j], dm.v[j]) - wc.v[j];
-            acc_axis<T, DYN, N>(cf[j], 0, dl, dr, acc[j]);
+            acc_axis<T, DYN, N>(cf[j], 0, dl0[j], dr0[j], acc[j]);
         }
 #pragma unroll
         for (int d = 1; d < N - 1; ++d) {
 #pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                T a = cur.l[d - 1].v[j], b = cur.r[d - 1].v[j];
-                if (anyg) {
-                    if (gl & (1u << d)) a = ghost(wc.v[j], cur.r[d - 1].v[j]);
-                    if (gr & (1u << d)) b = ghost(wc.v[j], cur.l[d - 1].v[j]);
-                }
-                acc_axis<T, DYN, N>(cf[j], d, wc.v[j] - a, b - wc.v[j], acc[j]);
-            }
+            for (int j = 0; j < VEC; ++j)
+                acc_axis<T, DYN, N>(cf[j], d, wc.v[j] - na[d - 1][j], nbv[d - 1][j] - wc.v[j], acc[j]);
         }
         if (!rowx) {
             T dx[VEC + 1];
