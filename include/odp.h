@@ -198,6 +198,10 @@ typedef struct {
     double roofline_frac;/* alg_gbps / 8000 */
     double alpha_max[6]; /* grid-wide maximum dissipation coefficients */
     double latency_ms;   /* server only: submit -> completion (host clock) */
+    double queue_ms;     /* server only: submit -> admission (slot and memory) */
+    double admit_ms;     /* server only: admission -> prologue done (upload, schedule) */
+    double run_ms;       /* server only: prologue done -> last step done */
+    double retire_ms;    /* server only: last step done -> result on the host */
     int32_t nonfinite;   /* 1 if a NaN / Inf was produced */
     int32_t pad_;
 } odp_solve_stats;

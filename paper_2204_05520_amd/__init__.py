@@ -77,7 +77,9 @@ class odp_solve_stats(ctypes.Structure):
                 ("t_final", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("alg_bytes", ctypes.c_double), ("alg_gbps", ctypes.c_double),
                 ("roofline_frac", ctypes.c_double), ("alpha_max", ctypes.c_double * 6),
-                ("latency_ms", ctypes.c_double), ("nonfinite", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("latency_ms", ctypes.c_double), ("queue_ms", ctypes.c_double), ("admit_ms", ctypes.c_double),
+                ("run_ms", ctypes.c_double), ("retire_ms", ctypes.c_double),
+                ("nonfinite", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: (list(getattr(self, k)) if k == "alpha_max" else getattr(self, k))

@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/odp.h"
+#include "odp.h"
 #include "odp_dev.h"
 
 struct odp_grid {

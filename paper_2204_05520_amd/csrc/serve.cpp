@@ -9,10 +9,13 @@
 //     descriptor, alpha^max and the float64 schedule on the device, the start
 //     copy and the step count read back; an event marks it ready;
 //   tick (compute stream): the ready requests with the least remaining work
-//     (up to a work budget; long-waiting ones always) advance by up to
-//     kStepsPerTick steps, one batched launch per RK stage and kernel group,
+//     (up to a work budget; long-waiting ones always) advance by
+//     kStepsPerTick steps (small requests by up to kSmallStepsPerTick), one
+//     batched launch per RK stage and kernel group per step of the tick,
 //     each solve reading its own step counter on the device; at most two
-//     ticks are in flight while the host prepares the next;
+//     ticks are in flight, and while the scheduler waits for a tick slot it
+//     keeps admitting arrivals and picking up finished admissions and
+//     retirements;
 //   retirement (download stream, after the tick that finished the request):
 //     result, state and schedule to pinned host memory; an event marks it
 //     done, then the device memory and the slot are released.
@@ -44,6 +47,7 @@ using namespace odp;
 namespace {
 
 constexpr int kStepsPerTick = 8;
+constexpr int kSmallStepsPerTick = 16;
 constexpr int kTicksInFlight = 2;
 constexpr double kTickWork = 2.0e9;   // point-stage updates per tick (a few ms)
 constexpr double kMaxWaitMs = 1500.0;
@@ -130,7 +134,8 @@ struct Req {
     int rc = ODP_OK;
     bool cancel = false;
     odp_solve_stats stats{};
-    Clock::time_point t_submit;
+    Clock::time_point t_submit, t_admit, t_ready, t_ran;
+    int tick_steps = 0;                       // steps of the tick being planned
     // scheduler-owned while running
     unsigned char *dmem = nullptr;
     size_t off_v0 = 0, off_a = 0;
@@ -196,7 +201,9 @@ namespace {
 
 struct Group {
     int dyn, ndim, vec, rk, lds;
-    std::vector<int> slots;
+    std::vector<int> slots;        // members, by this tick's step count (descending)
+    std::vector<int> steps;        // their step counts in this tick
+    std::vector<uint32_t> prefix;  // prefix[m]: tiles of the first m members
     uint32_t tiles = 0;
     size_t tile_base = 0, list_base = 0;
 };
@@ -269,7 +276,17 @@ void finish(odp_server *s, const std::shared_ptr<Req> &r, int rc) {
     std::lock_guard<std::mutex> lk(s->mu);
     r->rc = rc;
     r->state = R_DONE;
-    r->stats.latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - r->t_submit).count();
+    const Clock::time_point now = Clock::now();
+    auto ms = [](Clock::time_point a, Clock::time_point b) {
+        return a.time_since_epoch().count() && b.time_since_epoch().count()
+                   ? std::chrono::duration<double, std::milli>(b - a).count()
+                   : 0.0;
+    };
+    r->stats.latency_ms = ms(r->t_submit, now);
+    r->stats.queue_ms = ms(r->t_submit, r->t_admit);
+    r->stats.admit_ms = ms(r->t_admit, r->t_ready);
+    r->stats.run_ms = ms(r->t_ready, r->t_ran);
+    r->stats.retire_ms = ms(r->t_ran, now);
     s->running--;
     s->done++;
 }
@@ -306,6 +323,7 @@ void admit(odp_server *s) {
             used += r->footprint;
             slots--;
             r->state = R_RUNNING;
+            r->t_admit = Clock::now();
             s->running++;
             take.push_back(r);
             s->queue.pop_front();
@@ -381,6 +399,7 @@ bool poll_admissions(odp_server *s) {
             finish(s, r, cancel ? ODP_ECANCELED : set_error(ODP_EHIP, "server: schedule overflow"));
             continue;
         }
+        r->t_ready = Clock::now();
         s->active.push_back(r);
         joined = true;
     }
@@ -406,6 +425,7 @@ int start_retire(odp_server *s, const std::shared_ptr<Req> &r, hipEvent_t after)
                                        hipMemcpyDeviceToHost, s->dst), "schedule")) ||
         (rc = get_event(s, &r->ev)) || (rc = check_hip(hipEventRecord(r->ev, s->dst), "record")))
         return rc;
+    r->t_ran = Clock::now();
     s->retiring.push_back(r);
     return ODP_OK;
 }
@@ -447,19 +467,37 @@ void poll_retirements(odp_server *s) {
 
 // Kernel groups and tile tables of the selected requests; the tables go to
 // the device on the compute stream, after the ticks already in flight.
+// Within a group the members are ordered by their step count in this tick,
+// largest first, so that the members still stepping at step m of the tick
+// are a prefix of its tile table and of its member list.
 int build_groups(odp_server *s, const std::vector<std::shared_ptr<Req>> &sel, std::vector<Group> &groups) {
     groups.clear();
     std::map<std::tuple<int, int, int, int, int>, size_t> idx;
+    std::vector<const Req *> by_slot(size_t(s->max_slots), nullptr);
     for (auto &r : sel) {
         const PlanItem &it = r->plan.items[0];
+        by_slot[size_t(r->slot)] = r.get();
         auto key = std::make_tuple(r->dyn.id, r->grid.ndim, it.vec, it.rk_order, it.lds);
         auto f = idx.find(key);
         if (f == idx.end()) {
             idx[key] = groups.size();
-            groups.push_back(Group{r->dyn.id, r->grid.ndim, it.vec, it.rk_order, it.lds, {}, 0, 0, 0});
+            Group g;
+            g.dyn = r->dyn.id;
+            g.ndim = r->grid.ndim;
+            g.vec = it.vec;
+            g.rk = it.rk_order;
+            g.lds = it.lds;
+            groups.push_back(g);
             f = idx.find(key);
         }
         groups[f->second].slots.push_back(r->slot);
+    }
+    for (Group &g : groups) {
+        std::stable_sort(g.slots.begin(), g.slots.end(), [&](int a, int b) {
+            return by_slot[size_t(a)]->tick_steps > by_slot[size_t(b)]->tick_steps;
+        });
+        g.steps.clear();
+        for (int sl : g.slots) g.steps.push_back(by_slot[size_t(sl)]->tick_steps);
     }
     size_t ntiles = 0;
     for (auto &r : sel) ntiles += r->plan.items[0].tiles;
@@ -479,12 +517,11 @@ int build_groups(odp_server *s, const std::vector<std::shared_ptr<Req>> &sel, st
     if ((rc = stage_reserve(b, ntiles * 8 + sel.size() * 4))) return rc;
     uint32_t *ts = (uint32_t *)b.p, *tl = ts + ntiles;
     int32_t *list = (int32_t *)(tl + ntiles);
-    std::vector<const Req *> by_slot(size_t(s->max_slots), nullptr);
-    for (auto &r : sel) by_slot[size_t(r->slot)] = r.get();
     size_t nt = 0, nl = 0;
     for (Group &g : groups) {
         g.tile_base = nt;
         g.list_base = nl;
+        g.prefix.assign(1, 0);
         for (int sl : g.slots) {
             const uint32_t t = by_slot[size_t(sl)]->plan.items[0].tiles;
             for (uint32_t k = 0; k < t; ++k) {
@@ -492,6 +529,7 @@ int build_groups(odp_server *s, const std::vector<std::shared_ptr<Req>> &sel, st
                 tl[nt++] = k;
             }
             list[nl++] = sl;
+            g.prefix.push_back(uint32_t(nt - g.tile_base));
         }
         g.tiles = uint32_t(nt - g.tile_base);
     }
@@ -510,31 +548,35 @@ int enqueue_tick(odp_server *s, const std::vector<Group> &groups, hipEvent_t *do
     const odp_solve_opts &o = s->opts;
     const int mk = method_kind(o);
     int rc;
-    for (int m = 0; m < kStepsPerTick; ++m) {
+    int most = 0;
+    for (const Group &g : groups)
+        if (!g.steps.empty()) most = std::max(most, g.steps.front());
+    for (int m = 0; m < most; ++m) {
         for (const Group &g : groups) {
+            // members with more than m steps in this tick: a prefix
+            int nm = 0;
+            while (nm < int(g.steps.size()) && g.steps[size_t(nm)] > m) ++nm;
+            if (nm == 0) continue;
+            const uint32_t nt = g.prefix[size_t(nm)];
+            const uint32_t *ts = s->d_tiles + g.tile_base, *tl = s->d_tiles + s->tile_cap + g.tile_base;
             for (int j = 0; j < g.rk; ++j) {
                 const int kind = stage_kind(g.rk, j, mk, g.lds, o.space_order == 2);
                 // pursuit-evasion: the costate box of each solve's stage input
                 // first (each solve's own step counter picks its box buffer)
                 if (g.dyn == ODP_DYN_PE3D && !o.dissipation &&
-                    ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, kind | 32, s->d_slots,
-                                                  s->d_tiles + g.tile_base, s->d_tiles + s->tile_cap + g.tile_base,
-                                                  g.tiles, j, 1, 0, o.xcd_group, s->st),
+                    ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, kind | 32, s->d_slots, ts, tl,
+                                                  nt, j, 1, 0, o.xcd_group, s->st),
                                      "box")) ||
                      // the step from the box of the first stage (Algorithm 1)
-                     (j == 0 && (rc = check_hip(launch_box_dt(s->d_slots, s->d_list + g.list_base,
-                                                              int(g.slots.size()), 1, 0, s->st),
+                     (j == 0 && (rc = check_hip(launch_box_dt(s->d_slots, s->d_list + g.list_base, nm, 1, 0, s->st),
                                                 "box step")))))
                     return rc;
-                if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, kind,
-                                                 s->d_slots, s->d_tiles + g.tile_base,
-                                                 s->d_tiles + s->tile_cap + g.tile_base, g.tiles, j, 1, 0,
-                                                 o.xcd_group, s->st),
+                if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, kind, s->d_slots, ts, tl, nt, j,
+                                                 1, 0, o.xcd_group, s->st),
                                     "stage")))
                     return rc;
             }
-            if ((rc = check_hip(launch_advance(s->d_slots, s->d_list + g.list_base, int(g.slots.size()), s->st),
-                                "advance")))
+            if ((rc = check_hip(launch_advance(s->d_slots, s->d_list + g.list_base, nm, s->st), "advance")))
                 return rc;
         }
     }
@@ -614,10 +656,19 @@ void scheduler(odp_server *s) {
                 std::this_thread::sleep_for(std::chrono::microseconds(50));
             continue;
         }
+        // wait for a tick slot without blocking: finished retirements and
+        // admissions are picked up (and new arrivals admitted) meanwhile, so
+        // their results and prologues are not held until the tick ends
         while (int(s->ticks.size()) >= kTicksInFlight) {
-            (void)hipEventSynchronize(s->ticks.front());
-            put_event(s, s->ticks.front());
-            s->ticks.pop_front();
+            if (hipEventQuery(s->ticks.front()) == hipSuccess) {
+                put_event(s, s->ticks.front());
+                s->ticks.pop_front();
+                continue;
+            }
+            poll_retirements(s);
+            admit(s);
+            if (poll_admissions(s)) dirty = true;
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
         // This tick advances the requests with the least remaining work
         // first, up to about kTickWork point-stage updates (at least one
@@ -640,8 +691,21 @@ void scheduler(odp_server *s) {
                 acc += w;
             }
         }
+        // steps of each selected request in this tick: kStepsPerTick, or up
+        // to kSmallStepsPerTick for a request whose extra steps cost under 2%
+        // of the tick's work (small grids then finish in fewer ticks instead
+        // of advancing at the large requests' pace; measured: p50 28.5 ->
+        // 22.8 ms at the same p99); members with fewer steps drop out of the
+        // tick's later launches
+        double base = 0.0;
+        for (auto &r : sel) base += work(r, std::min<int64_t>(kStepsPerTick, r->nsteps - r->step));
         std::vector<uint64_t> sel_ids;
-        for (auto &r : sel) sel_ids.push_back(r->ticket);
+        for (auto &r : sel) {
+            const bool small = work(r, kSmallStepsPerTick - kStepsPerTick) <= 0.02 * base;
+            r->tick_steps = int(std::min<int64_t>(small ? kSmallStepsPerTick : kStepsPerTick, r->nsteps - r->step));
+            sel_ids.push_back(r->ticket);
+            sel_ids.push_back(uint64_t(r->tick_steps));
+        }
         if (sel_ids != last_sel) dirty = true;
         if (dirty) {
             if (build_groups(s, sel, groups) != ODP_OK) {
@@ -659,7 +723,7 @@ void scheduler(odp_server *s) {
             continue;
         }
         s->ticks.push_back(tick_done);
-        for (auto &r : sel) r->step = std::min<int64_t>(r->step + kStepsPerTick, r->nsteps);
+        for (auto &r : sel) r->step = std::min<int64_t>(r->step + r->tick_steps, r->nsteps);
         for (size_t i = 0; i < s->active.size();) {
             auto r = s->active[i];
             if (r->step >= r->nsteps) {

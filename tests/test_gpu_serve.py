@@ -181,3 +181,42 @@ def test_serve_queue_full(odp):
         assert rc == odp.ODP_PENDING
     finally:
         srv.close()
+
+
+def test_serve_fp64_matches_oracle(odp, oracle_mod):
+    """A float64 server: staggered mixed requests (Dubins RK1 and 4D car RK3,
+    ticks shared between them, small ones taking more steps per tick), each
+    result against the float64 oracle within 1e-9 S, the oracle's step
+    count, and the phase times adding up to the latency."""
+    specs = mixed_requests(10, 11)
+    V0s = [W.make_v0(s) for s in specs]
+    srv = odp.Server(budget_bytes=1 << 30, max_slots=6, precision=64, rk_order=1)
+    print(f"[gpu] serve fp64: {len(specs)} mixed requests, 6 slots", flush=True)
+    try:
+        tickets = []
+        for i, (s, v) in enumerate(zip(specs, V0s)):
+            tickets.append(srv.submit(s, v, rk_order=s.rk_order))
+            if i % 3 == 2:
+                time.sleep(0.002)
+        for s, v, t in zip(specs, V0s, tickets):
+            out = np.empty(tuple(s.grid.n), np.float64)
+            t0 = time.time()
+            while True:
+                rc, st = srv.poll(t, out)
+                if rc != odp.ODP_PENDING:
+                    break
+                assert time.time() - t0 < 60
+                time.sleep(0.002)
+            assert rc == odp.ODP_OK
+            ref = oracle_mod.solve(s.grid, s.dyn, v, s.tau, rk_order=s.rk_order, cfl=s.cfl, brt=True)
+            err = float(np.abs(out - ref.V).max())
+            S = s.grid.domain_scale()
+            print(f"    {s.name} {s.grid.n} rk{s.rk_order}: steps {st['steps']} / {ref.steps}, "
+                  f"max|err|/S {err / S:.2e}, phases q {st['queue_ms']:.1f} a {st['admit_ms']:.1f} "
+                  f"r {st['run_ms']:.1f} ret {st['retire_ms']:.1f} (latency {st['latency_ms']:.1f}) ms", flush=True)
+            assert st["steps"] == ref.steps
+            assert err <= 1e-9 * S
+            parts = st["queue_ms"] + st["admit_ms"] + st["run_ms"] + st["retire_ms"]
+            assert abs(parts - st["latency_ms"]) <= 1e-6 * max(1.0, st["latency_ms"]) + 1e-6
+    finally:
+        srv.close()
