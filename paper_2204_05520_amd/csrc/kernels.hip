@@ -252,6 +252,13 @@ __global__ void sched_kernel(const SolveDesc *__restrict__ descs, int nsolves, i
         if (land >= 0) ++k;
     }
     if (n < 0 || n > s.expect_steps) atomicOr(s.flags, kFlagStepsExceeded);
+    double lo = INFINITY, hi = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        lo = fmin(lo, s.dt_sched[j]);
+        hi = fmax(hi, s.dt_sched[j]);
+    }
+    s.dtmm[0] = lo;
+    s.dtmm[1] = hi;
     *s.nsteps = n;
     if (nsteps_all) nsteps_all[i] = n;
 }
@@ -345,6 +352,8 @@ __global__ __launch_bounds__(kBlock) void box_dt_kernel(const SolveDesc *__restr
     }
     s.dt_sched[k] = dt;
     s.land[k] = land;
+    s.dtmm[0] = k > 0 ? fmin(s.dtmm[0], dt) : dt;
+    s.dtmm[1] = k > 0 ? fmax(s.dtmm[1], dt) : dt;
     s.t_after[k] = tn;
     s.k_after[k] = land >= 0 ? kt + 1 : kt;
     if (land == s.ntau - 1) *s.nsteps = k + 1;

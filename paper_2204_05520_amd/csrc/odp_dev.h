@@ -82,6 +82,7 @@ struct SolveDesc {
     int64_t *nsteps;         // device: step count of the schedule
     int64_t *step;           // device: next step to take (server ticks)
     int32_t *flags;          // kFlag* bits
+    double *dtmm;            // smallest and largest step of the schedule
     uint64_t *box;           // costate box (pursuit-evasion only, else null): two
                              // buffers, used by alternate stages, of kBoxSlots
                              // partial boxes of 6 order-preserving keys each

@@ -24,7 +24,9 @@ namespace odp {
 
 namespace {
 
-constexpr size_t kStateBytes = 256;  // alpha^max[6], nsteps, step, flags
+// per-solve state: alpha^max[6] (0), nsteps (48), step (56), flags (64),
+// dt min / max (72, 80)
+constexpr size_t kStateBytes = 128;
 
 int64_t step_capacity(const odp_grid *g, const odp_dynamics *dyn, const std::vector<double> &tau,
                       double cfl, double max_dt) {
@@ -56,19 +58,25 @@ int balanced_chunk(const odp_grid *g, int c, bool cycle4) {
 }
 
 // Axis tables: coordinate, cos, sin per axis (float64, computed once on the
-// host; the kernels read these values, never a transcendental).
-void make_tables(const odp_grid *g, std::vector<double> &tab) {
+// host; the kernels read these values, never a transcendental).  Axes with
+// the same node count, lower bound and spacing share their table (the many
+// solves of a batch repeat a few axis shapes).
+using AxisKey = std::tuple<int64_t, double, double>;
+void make_tables(const odp_grid *g, std::vector<double> &tab, std::map<AxisKey, std::vector<double>> &cache) {
     tab.clear();
     for (int d = 0; d < g->ndim; ++d) {
         const int nd = int(g->n[d]);
-        const size_t off = tab.size();
-        tab.resize(off + 3 * size_t(nd));
-        for (int k = 0; k < nd; ++k) {
-            const double x = g->lo[d] + double(k) * g->dx[d];
-            tab[off + k] = x;
-            tab[off + nd + k] = std::cos(x);
-            tab[off + 2 * nd + k] = std::sin(x);
+        std::vector<double> &t = cache[AxisKey(g->n[d], g->lo[d], g->dx[d])];
+        if (t.empty()) {
+            t.resize(3 * size_t(nd));
+            for (int k = 0; k < nd; ++k) {
+                const double x = g->lo[d] + double(k) * g->dx[d];
+                t[k] = x;
+                t[nd + k] = std::cos(x);
+                t[2 * nd + k] = std::sin(x);
+            }
         }
+        tab.insert(tab.end(), t.begin(), t.end());
     }
 }
 
@@ -199,6 +207,7 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         it.box_cfl = it.dyn.id == ODP_DYN_PE3D && !opts.dissipation;
         total += it.ppad;
     }
+    std::map<AxisKey, std::vector<double>> tables;
     for (auto &it : items) {
         int c = tile_chunk;
         if (c <= 0) {
@@ -215,7 +224,7 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         it.tab_entries = 0;
         for (int d = 0; d < it.g->ndim; ++d) it.tab_entries += 3 * int(it.g->n[d]);
         // the schedule on the host (box_cfl: the all-inputs count, a bound)
-        make_tables(it.g, it.tab);
+        make_tables(it.g, it.tab, tables);
         host_alpha_max(it, it.amax);
         it.nsteps = host_schedule(it, opts, it.land);
         if (it.nsteps < 0 && p.error.empty()) p.error = "schedule overflow (internal step bound exceeded)";
@@ -230,7 +239,8 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
     };
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key(a) < key(b); });
     p.items.clear();
-    for (int i : perm) p.items.push_back(items[i]);
+    p.items.reserve(items.size());
+    for (int i : perm) p.items.push_back(std::move(items[i]));
     p.groups.clear();
     for (int i = 0; i < n; ++i) {
         const PlanItem &it = p.items[i];
@@ -270,10 +280,16 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
     off += align256(size_t(n) * sizeof(SolveDesc));
     p.nsteps_off = off;
     off += align256(size_t(n) * 8);
+    p.state_begin = off;
+    for (auto &it : p.items) {
+        it.state_off = off;
+        off += kStateBytes;
+    }
+    off = align256(off);
     p.aux_begin = off;
     for (auto &it : p.items) {
         it.aux_off = off;
-        off += kStateBytes + align256(size_t(it.tab_entries) * 8) + align256(it.tau.size() * 8);
+        off += align256(size_t(it.tab_entries) * 8) + align256(it.tau.size() * 8);
     }
     p.tt_off = off;
     off += n > 1 ? align256(p.total_tiles * 4) * 2 : 0;
@@ -355,13 +371,14 @@ void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &
         s.Vinit = it.pad_io ? base + it.V0p_off : (it.Vinit ? it.Vinit : it.V0);
         s.Vsrc_dense = it.pad_io ? it.V0 : nullptr;
         s.Adst_dense = it.pad_io ? it.A : nullptr;
-        unsigned char *state = base + it.aux_off;
+        unsigned char *state = base + it.state_off;
         s.amax = (double *)state;
         s.nsteps = (int64_t *)(state + kMaxDim * 8);
         s.step = (int64_t *)(state + kMaxDim * 8 + 8);
         s.flags = (int32_t *)(state + kMaxDim * 8 + 16);
+        s.dtmm = (double *)(state + kMaxDim * 8 + 24);
         s.box = it.dyn.id == ODP_DYN_PE3D ? (uint64_t *)(base + it.box_off) : nullptr;
-        const size_t tab_off = it.aux_off + kStateBytes;
+        const size_t tab_off = it.aux_off;
         const size_t tau_off = tab_off + align256(size_t(it.tab_entries) * 8);
         s.tabd = (const double *)(base + tab_off);
         s.dt_sched = (double *)(base + it.sched_off);
@@ -636,20 +653,17 @@ std::vector<int64_t> plan_key(const Plan &p, unsigned char *base, void *V_all) {
 int plan_stats(const Plan &p, unsigned char *base, double kernel_ms, odp_solve_stats *stats, hipStream_t st) {
     int rc;
     const odp_solve_opts &o = p.opts;
-    // two bulk copies: every solve's state/tables/tau, every schedule
-    std::vector<unsigned char> aux(p.tt_off - p.aux_begin), sched(p.arr_begin - p.sched_begin);
-    if ((rc = check_hip(hipMemcpyAsync(aux.data(), base + p.aux_begin, aux.size(), hipMemcpyDeviceToHost, st),
+    // one copy: every solve's state (alpha^max, step count, flags, dt range)
+    std::vector<unsigned char> aux(p.aux_begin - p.state_begin);
+    if ((rc = check_hip(hipMemcpyAsync(aux.data(), base + p.state_begin, aux.size(), hipMemcpyDeviceToHost, st),
                         "read state")) ||
-        (rc = check_hip(hipMemcpyAsync(sched.data(), base + p.sched_begin, sched.size(), hipMemcpyDeviceToHost, st),
-                        "read schedules")) ||
         (rc = check_hip(hipStreamSynchronize(st), "sync")))
         return rc;
     int worst = ODP_OK;
     std::string why;
     for (size_t i = 0; i < p.items.size(); ++i) {
         const PlanItem &it = p.items[i];
-        const unsigned char *state = aux.data() + (it.aux_off - p.aux_begin);
-        const double *dts = (const double *)(sched.data() + (it.sched_off - p.sched_begin));
+        const unsigned char *state = aux.data() + (it.state_off - p.state_begin);
         odp_solve_stats &sx = stats[i];
         std::memset(&sx, 0, sizeof(sx));
         int64_t nst;
@@ -663,8 +677,8 @@ int plan_stats(const Plan &p, unsigned char *base, double kernel_ms, odp_solve_s
         }
         sx.steps = nst;
         if (nst > 0) {
-            sx.dt_min = *std::min_element(dts, dts + nst);
-            sx.dt_max = *std::max_element(dts, dts + nst);
+            std::memcpy(&sx.dt_min, state + kMaxDim * 8 + 24, 8);
+            std::memcpy(&sx.dt_max, state + kMaxDim * 8 + 32, 8);
         }
         sx.t_final = it.tau.back();
         sx.kernel_ms = kernel_ms;

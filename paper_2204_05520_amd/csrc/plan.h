@@ -40,7 +40,7 @@ struct PlanItem {
     uint32_t tiles = 0;
     int64_t max_steps = 0;
     int tab_entries = 0;
-    size_t aux_off = 0, sched_off = 0, land_off = 0, box_off = 0, tk_off = 0, B_off = 0, C_off = 0;
+    size_t state_off = 0, aux_off = 0, sched_off = 0, land_off = 0, box_off = 0, tk_off = 0, B_off = 0, C_off = 0;
     // host side of the schedule: axis tables (x, cos x, sin x per axis, as
     // uploaded), alpha^max and the step count from the same float64
     // arithmetic as the device reduction and schedule, and the output index
@@ -64,7 +64,7 @@ struct Plan {
     odp_solve_opts opts{};
     std::vector<PlanItem> items;        // descriptor order (grouped)
     std::vector<PlanGroup> groups;
-    size_t desc_off = 0, nsteps_off = 0, aux_begin = 0, upload_bytes = 0;
+    size_t desc_off = 0, nsteps_off = 0, state_begin = 0, aux_begin = 0, upload_bytes = 0;
     size_t tt_off = 0, total_tiles = 0, sched_begin = 0, arr_begin = 0, total = 0;
     int64_t max_nsteps = 0;
     int xcd_group = 0;                  // tile runs per XCD for the stage launches

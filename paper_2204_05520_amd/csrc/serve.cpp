@@ -52,7 +52,7 @@ constexpr int kTicksInFlight = 2;
 constexpr double kTickWork = 2.0e9;   // point-stage updates per tick (a few ms)
 constexpr double kMaxWaitMs = 1500.0;
 constexpr size_t kMaxQueue = 1 << 16;
-constexpr size_t kStateBytes = kMaxDim * 8 + 24;  // alpha^max, time, flags
+constexpr size_t kStateBytes = kMaxDim * 8 + 40;  // alpha^max, step count, step, flags, dt range
 
 enum { R_QUEUED = 0, R_RUNNING = 1, R_DONE = 2 };
 
@@ -412,17 +412,15 @@ int start_retire(odp_server *s, const std::shared_ptr<Req> &r, hipEvent_t after)
     const PlanItem &it = r->plan.items[0];
     Staging &b = s->back[size_t(r->slot)];
     int rc;
-    if ((rc = stage_reserve(b, kStateBytes + size_t(r->nsteps) * 8)) ||
+    if ((rc = stage_reserve(b, kStateBytes)) ||
         (rc = check_hip(hipStreamWaitEvent(s->dst, after, 0), "wait")) ||
         // a box_cfl first-order result after an odd step count is in B
         (it.box_cfl && (rc = check_hip(launch_box_finish(s->opts.precision, s->d_slots + r->slot, nullptr, nullptr,
                                                          it.tiles, s->dst), "box finish"))) ||
         (rc = check_hip(hipMemcpy2DAsync(r->host, r->row, r->dmem + r->off_a, r->row_pitch, r->row, r->rows,
                                          hipMemcpyDeviceToHost, s->dst), "result")) ||
-        (rc = check_hip(hipMemcpyAsync(b.p, r->dmem + it.aux_off, kStateBytes, hipMemcpyDeviceToHost, s->dst),
+        (rc = check_hip(hipMemcpyAsync(b.p, r->dmem + it.state_off, kStateBytes, hipMemcpyDeviceToHost, s->dst),
                         "state")) ||
-        (rc = check_hip(hipMemcpyAsync(b.p + kStateBytes, r->dmem + it.sched_off, size_t(r->nsteps) * 8,
-                                       hipMemcpyDeviceToHost, s->dst), "schedule")) ||
         (rc = get_event(s, &r->ev)) || (rc = check_hip(hipEventRecord(r->ev, s->dst), "record")))
         return rc;
     r->t_ran = Clock::now();
@@ -440,7 +438,6 @@ void poll_retirements(odp_server *s) {
         }
         s->retiring.erase(s->retiring.begin() + long(i));
         const unsigned char *b = s->back[size_t(r->slot)].p;
-        const double *dts = (const double *)(b + kStateBytes);
         odp_solve_stats &sx = r->stats;
         int64_t nst;
         std::memcpy(&nst, b + kMaxDim * 8, 8);
@@ -450,8 +447,8 @@ void poll_retirements(odp_server *s) {
         if (bad_steps) nst = std::max<int64_t>(0, std::min(nst, r->nsteps));
         sx.steps = nst;
         if (nst > 0) {
-            sx.dt_min = *std::min_element(dts, dts + nst);
-            sx.dt_max = *std::max_element(dts, dts + nst);
+            std::memcpy(&sx.dt_min, b + kMaxDim * 8 + 24, 8);
+            std::memcpy(&sx.dt_max, b + kMaxDim * 8 + 32, 8);
         }
         sx.t_final = r->tau.back();
         sx.alg_bytes = alg_bytes_per_step(s->opts.precision, r->rk_order,
