@@ -931,6 +931,13 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
         }
     }
     const bool anywrap = __builtin_amdgcn_ballot_w64(wrapm != 0) != 0;
+    // wave-level edge masks (computed once): bit d of wgm set when some lane
+    // of the wave has a ghost node on middle axis d; the last axis' edges
+    uint32_t wgm = 0;
+#pragma unroll
+    for (int d = 1; d < N - 1; ++d)
+        if (__builtin_amdgcn_ballot_w64(((gmask >> (4 * d)) & 15u) != 0) != 0) wgm |= 1u << d;
+    const bool wgxl = __builtin_amdgcn_ballot_w64(gxl) != 0, wgxr = __builtin_amdgcn_ballot_w64(gxr) != 0;
 
     // axis-0 plane j (-2 <= j <= n0 + 1) of this group: wrapped, or ghosts
     auto ax0 = [&](int j) -> P {
@@ -1011,14 +1018,20 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
                 p1 = cu[d - 1][2];
                 p2 = cu[d - 1][3];
             }
-            const uint32_t gm = (gmask >> (4 * d)) & 15u;
-            if (gm) {
+            // ghosts: one uniform branch, taken by the waves that hold a lane
+            // next to a non-periodic face of axis d
+            if (wgm & (1u << d)) {
+                const uint32_t gm = (gmask >> (4 * d)) & 15u;
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
-                    if (gm & 2u) { l1.v[e] = ghost(wc.v[e], p1.v[e]); l2.v[e] = ghost2(wc.v[e], p1.v[e]); }
-                    else if (gm & 1u) l2.v[e] = ghost(l1.v[e], wc.v[e]);
-                    if (gm & 4u) { p1.v[e] = ghost(wc.v[e], l1.v[e]); p2.v[e] = ghost2(wc.v[e], l1.v[e]); }
-                    else if (gm & 8u) p2.v[e] = ghost(p1.v[e], wc.v[e]);
+                    const T a1 = ghost(wc.v[e], p1.v[e]), a2 = ghost2(wc.v[e], p1.v[e]);
+                    const T a3 = ghost(l1.v[e], wc.v[e]);
+                    const T b1 = ghost(wc.v[e], l1.v[e]), b2 = ghost2(wc.v[e], l1.v[e]);
+                    const T b3 = ghost(p1.v[e], wc.v[e]);
+                    if (gm & 2u) { l1.v[e] = a1; l2.v[e] = a2; }
+                    else if (gm & 1u) l2.v[e] = a3;
+                    if (gm & 4u) { p1.v[e] = b1; p2.v[e] = b2; }
+                    else if (gm & 8u) p2.v[e] = b3;
                 }
             }
 #pragma unroll
@@ -1043,8 +1056,14 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
         }
 #pragma unroll
         for (int j = 0; j < VEC; ++j) e[j + 2] = wc.v[j];
-        if (gxl) { e[1] = ghost(wc.v[0], wc.v[1]); e[0] = ghost2(wc.v[0], wc.v[1]); }
-        if (gxr) { e[VEC + 2] = ghost(wc.v[VEC - 1], wc.v[VEC - 2]); e[VEC + 3] = ghost2(wc.v[VEC - 1], wc.v[VEC - 2]); }
+        if (wgxl) {
+            const T g1 = ghost(wc.v[0], wc.v[1]), g2 = ghost2(wc.v[0], wc.v[1]);
+            if (gxl) { e[1] = g1; e[0] = g2; }
+        }
+        if (wgxr) {
+            const T g1 = ghost(wc.v[VEC - 1], wc.v[VEC - 2]), g2 = ghost2(wc.v[VEC - 1], wc.v[VEC - 2]);
+            if (gxr) { e[VEC + 2] = g1; e[VEC + 3] = g2; }
+        }
         const int64_t o = int64_t(i0) * s0 + q;
         if (!kPref && wa != 0.0) vn = ldp_nt<T, VEC>(Vn + o);
         P zr, gr;
