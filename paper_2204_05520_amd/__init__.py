@@ -48,6 +48,7 @@ SYMBOLS = [
     "odp_hj_workspace_bytes", "odp_hj_solve", "odp_hj_batch_workspace_bytes", "odp_hj_batch",
     "odp_server_create", "odp_serve_submit", "odp_serve_poll", "odp_serve_cancel",
     "odp_server_counts", "odp_server_destroy", "odp_ttr_workspace_bytes", "odp_ttr_solve",
+    "odp_hj_solve_noalloc",
 ]
 
 
