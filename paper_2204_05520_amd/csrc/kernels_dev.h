@@ -1127,10 +1127,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
 
     const uint32_t cid = lt / s.nqb;
     const uint32_t qb = lt - cid * s.nqb;
-    const uint32_t Qg = s.Q / VEC;
-    const uint32_t gi = qb * kBlock + threadIdx.x;
-    const bool active = gi < Qg;
-    const uint32_t q = (active ? gi : Qg - 1) * VEC;
+    const TileGroup tg = tile_group(s, qb, threadIdx.x, VEC);
+    const bool active = tg.active;
+    const uint32_t q = tg.q;
 
     int ii[N];
     ii[0] = 0;
@@ -1252,7 +1251,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
     constexpr int kTile = kLdsK ? 2 * B : 1;  // B + 2 H with H <= B / 2
     __shared__ __attribute__((aligned(16))) T tile[2][kTile];
     const int H = s.pitch;
-    const uint32_t q0 = qb * uint32_t(B);
+    const uint32_t q0 = tg.q0;
     const int me = int(q - q0) + H;
     const int nh = H / VEC;
     const int th = int(threadIdx.x);

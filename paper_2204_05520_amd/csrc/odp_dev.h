@@ -57,10 +57,14 @@ struct SolveDesc {
     // ---- tiling
     int32_t chunk;           // planes of axis 0 per tile
     int32_t vec;             // consecutive last-axis points per thread
-    uint32_t nqb;            // blocks per hyperplane (256 * vec points each)
+    uint32_t nqb;            // tiles per hyperplane (256 groups of vec elements each)
     uint32_t tiles;          // nqb * ceil(n0 / chunk)
     int32_t rk_order;
-    int32_t pad0_;
+    uint32_t brick;          // 0: row-major tiles; k > 0 (six dimensions): tiles aligned
+                             // to the cubes of axes 3..5, dealt in k x k squares of
+                             // axes 1 and 2 (tile_group)
+    uint32_t cube;           // brick > 0: elements per cube of axes 3..5
+    uint32_t cube_tiles;     // brick > 0: tiles per cube, ceil(cube / (256 vec))
     // ---- dynamics
     int32_t dyn;
     int32_t u_mode, d_mode;
@@ -128,6 +132,48 @@ struct SolveDesc {
     double pe_cmin, pe_cmax; // min / max over the heading table of -v_a + v_b cos th
     double pe_smin, pe_smax; // min / max over the heading table of v_b sin th
 };
+
+// Tile qb of a hyperplane, thread t (0..kBlock-1): the element offset q0 of
+// the tile's first group, the offset q of the thread's group of vec
+// consecutive elements, and whether that group exists (a thread past the end
+// takes the last group of its range, for loads only).
+//   brick == 0: tiles of kBlock groups in row-major order.
+//   brick == k: each cube of axes 3..5 (a fixed pair of axis-1 and axis-2
+//   indices) is cut into cube_tiles tiles, the last one ragged; tiles are
+//   numbered square by square of k x k (axis 1, axis 2) pairs, within a
+//   square by tile of the cube, then by pair.  Consecutive tiles, which the
+//   XCD-aware launch keeps on one XCD, are then each other's neighbours
+//   along axes 1 and 2 (and, one tile of the cube further, axis 3), so those
+//   neighbour loads hit that XCD's L2.
+struct TileGroup {
+    uint32_t q0, q;
+    bool active;
+};
+
+__host__ __device__ inline TileGroup tile_group(const SolveDesc &s, uint32_t qb, uint32_t t, uint32_t vec) {
+    TileGroup r;
+    const uint32_t span = uint32_t(kBlock) * vec;
+    if (s.brick) {
+        const uint32_t k = s.brick, kk = k * k;
+        const uint32_t per = kk * s.cube_tiles;
+        const uint32_t sq = qb / per, rem = qb - sq * per;
+        const uint32_t j = rem / kk, pr = rem - j * kk;
+        const uint32_t r1 = pr / k, r2 = pr - r1 * k;
+        const uint32_t nsq2 = uint32_t(s.n[2]) / k;
+        const uint32_t s1 = sq / nsq2, s2 = sq - s1 * nsq2;
+        const uint32_t base = ((s1 * k + r1) * uint32_t(s.n[2]) + s2 * k + r2) * s.cube;
+        const uint32_t loc = j * span + t * vec;
+        r.q0 = base + j * span;
+        r.active = loc < s.cube;
+        r.q = base + (r.active ? loc : s.cube - vec);
+    } else {
+        const uint32_t g = qb * uint32_t(kBlock) + t, Qg = s.Q / vec;
+        r.q0 = qb * span;
+        r.active = g < Qg;
+        r.q = (r.active ? g : Qg - 1) * vec;
+    }
+    return r;
+}
 
 // flags bits (SolveDesc::flags)
 constexpr int32_t kFlagNonFinite = 1;     // a NaN or Inf was produced

@@ -33,6 +33,9 @@ struct PlanItem {
     int64_t qpad = 0, ppad = 0;         // hyperplane / array elements with padding
     int vec = 1, chunk = 1;
     int lds = 0;                        // the stage kernel's LDS plane exchange
+    uint32_t brick = 0;                 // tile_group's brick side (0: row-major tiles)
+    uint32_t cube = 0, cube_tiles = 0;  // brick > 0: the cubes of axes 3..5
+    uint32_t nqb = 0;                   // tiles per hyperplane
     // pad_io: the caller's V0 and A are dense while `pitch` pads the rows;
     // the plan keeps padded copies (V0p, Ap) and copies in and out itself
     bool pad_io = false;

@@ -219,11 +219,6 @@ int default_chunk(const odp_grid *g, int vec, int precision) {
 // round robin keep the 8 XCDs on one shared working set.
 int default_xcd_group(const odp_grid *g) { return g->npts >= (int64_t(1) << 28) ? 64 : 0; }
 
-uint32_t solve_tiles(int64_t n0, int64_t qpad, int chunk, int vec) {
-    const int64_t nqb = (qpad + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec);
-    return uint32_t(nqb * ((n0 + chunk - 1) / chunk));
-}
-
 double alg_bytes_per_step(int precision, int rk_order, int narr, int64_t npts) {
     // each stage reads its stencil input once and writes its output once;
     // stages after the first also read V^n; the computation method reads

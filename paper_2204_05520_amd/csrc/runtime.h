@@ -80,7 +80,6 @@ int default_xcd_group(const odp_grid *g);
 // and 1 that divides the row pitch (1 for ndim 1 and the ball-input test
 // dynamics).
 int choose_vec(const odp_grid *g, int precision, int dyn, int64_t pitch);
-uint32_t solve_tiles(int64_t n0, int64_t qpad, int chunk, int vec);
 // narr: grid-sized arrays the computation method reads per step besides the
 // stencil input and V^n (method_arrays).
 double alg_bytes_per_step(int precision, int rk_order, int narr, int64_t npts);

@@ -32,9 +32,16 @@ static odp_grid *grid(int nd, const int64_t *n, const uint8_t *per, double lo = 
     return g;
 }
 
-// Replay of the tile mapping: tile lt of a solve covers planes
-// [cid * chunk, min(+chunk, n0)) and groups [qb * 256, +256) of VEC
-// consecutive hyperplane elements, cid = lt / nqb, qb = lt % nqb.
+// Replay of the stage kernel's tile mapping: tile lt of a solve covers planes
+// [cid * chunk, min(+chunk, n0)), cid = lt / nqb, and, for each of its
+// kBlock threads, the group of VEC consecutive hyperplane elements that
+// tile_group gives tile qb = lt % nqb (row-major or brick tiles).  Every
+// element must be covered exactly once, every group (also a past-the-end
+// thread's) must lie inside the hyperplane, and a tile's first element must
+// be the start of its threads' range.  The copy kernels' row-major groups
+// must cover the hyperplane too (brick tiles are at least as many).
+static int g_brick_plans = 0;  // plans whose tiles were brick tiles
+
 static void coverage(const Plan &p, const std::vector<unsigned char> &img) {
     for (size_t i = 0; i < p.items.size(); ++i) {
         SolveDesc s;
@@ -44,18 +51,28 @@ static void coverage(const Plan &p, const std::vector<unsigned char> &img) {
         for (uint32_t lt = 0; lt < s.tiles; ++lt) {
             const uint32_t cid = lt / s.nqb, qb = lt - cid * s.nqb;
             const int i0b = int(cid) * s.chunk, i0e = std::min<int>(i0b + s.chunk, int(n0));
+            CHECK(i0b < i0e);
             for (int t = 0; t < kBlock; ++t) {
-                const int64_t g = int64_t(qb) * kBlock + t;
-                if (g >= Q / s.vec) continue;
+                const TileGroup tg = tile_group(s, qb, uint32_t(t), uint32_t(s.vec));
+                CHECK(int64_t(tg.q) + s.vec <= Q);
+                if (t == 0 && tg.active) CHECK(tg.q == tg.q0);
+                if (!tg.active) continue;
+                CHECK(tg.q % uint32_t(s.vec) == 0);
                 for (int j = 0; j < s.vec; ++j)
-                    for (int i0 = i0b; i0 < i0e; ++i0) cnt[size_t(i0 * Q + g * s.vec + j)]++;
+                    for (int i0 = i0b; i0 < i0e; ++i0) cnt[size_t(i0 * Q + tg.q + j)]++;
             }
         }
         bool once = true;
         for (uint8_t c : cnt) once = once && c == 1;
         CHECK(once);
         CHECK(Q % s.vec == 0);
+        CHECK(int64_t(s.nqb) * kBlock * s.vec >= Q);
         CHECK(s.pitch >= s.n[s.ndim - 1] || s.ndim == 1);
+        if (s.brick) {
+            ++g_brick_plans;
+            CHECK(s.ndim == 6 && s.n[1] % int(s.brick) == 0 && s.n[2] % int(s.brick) == 0);
+            CHECK(int64_t(s.cube) * s.n[1] * s.n[2] == Q);
+        }
     }
 }
 
@@ -174,6 +191,30 @@ int main() {
                 plan_case(gs, ds, o, 4);
                 for (odp_grid *g : owned) odp_grid_destroy(g);
             }
+    // six-dimensional grids with cubes of axes 3..5 large enough for brick
+    // tiles, and some that miss a condition (an axis-1 extent that is not a
+    // multiple of 3, second order)
+    for (int prec : {32, 64})
+        for (int order : {1, 2}) {
+            odp_solve_opts o;
+            std::memset(&o, 0, sizeof(o));
+            o.precision = prec;
+            o.rk_order = 2;
+            o.cfl = 0.8;
+            o.mode = ODP_BRT;
+            o.space_order = order;
+            const uint8_t p6[6] = {0, 0, 1, 0, 0, 1};
+            for (int rep = 0; rep < 3; ++rep) {
+                const int64_t n6[6] = {U(3, 6), 3 * U(1, 3) + (rep == 2 ? 1 : 0), 3 * U(1, 2), U(18, 26), U(18, 26),
+                                       4 * U(6, 10)};
+                odp_grid *g6 = grid(6, n6, p6);
+                odp_dynamics d3{};
+                d3.id = ODP_DYN_TWODUBINS6D; d3.u_mode = 1; d3.p[0] = 1; d3.p[1] = 1; d3.p[2] = 1; d3.p[3] = 1;
+                for (int chunk : {0, 5}) plan_case({g6}, {d3}, o, chunk);
+                odp_grid_destroy(g6);
+            }
+        }
+    CHECK(g_brick_plans > 0);
     // time to reach workspace, the server's argument checks (no device here)
     {
         const int64_t n[3] = {20, 20, 16};

@@ -32,7 +32,17 @@ GRIDS = {
     "si2d_61_rk2": lambda: W.single_integrator(2, 61, 0.2, [0.5, -0.3], W.MAXIMISE, 0.4, rk_order=2),
     "dubins3d_37x29x22_rk1": lambda: W.config_dubins3d(n=(37, 29, 22), T=0.8),
     "dyncar4d_13x12x9x16_rk3": lambda: W.config_dyncar4d(n=[13, 12, 9, 16], T=0.3),
+    # six dimensions: the far axes' neighbours and the pointwise operands
+    # (V^n, the target or V0, the obstacle) reach LDS by direct copies
+    "game6d_7x6x6x5x6x8_rk1": lambda: _rk(W.config_game6d(n=[7, 6, 6, 5, 6, 8], T=0.2), 1),
+    "game6d_7x6x6x5x6x8_rk2": lambda: W.config_game6d(n=[7, 6, 6, 5, 6, 8], T=0.2),
+    "game6d_6x7x5x6x5x8_rk3": lambda: _rk(W.config_game6d(n=[6, 7, 5, 6, 5, 8], T=0.2), 3),
 }
+
+
+def _rk(spec, order):
+    spec.rk_order = order
+    return spec
 
 
 @pytest.fixture(scope="module")

@@ -68,7 +68,21 @@ CASES = [
     ("dubins3d_ragged", lambda: W.config_dubins3d(n=(37, 29, 22), T=1.3), (64, 32)),
     ("dyncar4d_22x21x19x24_rk3", lambda: W.config_dyncar4d(n=[22, 21, 19, 24], T=0.6), (64, 32)),
     ("game6d_9x8x8x7x9x8_rk2", lambda: W.config_game6d(n=[9, 8, 8, 7, 9, 8], T=0.5), (64, 32)),
+    # axis N-2 periodic: its rows wrapped across the edge are not in a
+    # block's LDS tile; in 6D they are copied into LDS with the plane's other
+    # memory-loaded neighbours
+    ("game6d_periodic_axis4", lambda: _periodic4(W.config_game6d(n=[8, 7, 6, 5, 9, 12], T=0.4)),
+     (64, 32)),
+    # axes 1 and 2 in 3 x 3 squares, cubes of axes 3..5 of 11200 points:
+    # brick tiles (ragged last tile of every cube)
+    ("game6d_brick_5x6x6x20x20x28", lambda: W.config_game6d(n=[5, 6, 6, 20, 20, 28], T=0.25), (64, 32)),
 ]
+
+
+def _periodic4(spec):
+    spec.grid.periodic[4] = 1
+    spec.name += "_periodic4"
+    return spec
 
 
 @pytest.mark.parametrize("name,mk,precs", CASES, ids=[c[0] for c in CASES])
@@ -103,7 +117,8 @@ def _chunk_specs():
     g6 = W.config_game6d(n=[7, 6, 6, 5, 6, 8], T=0.2)
     return [("dyncar4d_13x17x9x20", W.config_dyncar4d(n=[13, 17, 9, 20], T=0.2)),
             ("dubins3d_15x22x16", W.config_dubins3d(n=(15, 22, 16), T=0.3)),
-            ("game6d_7x6x6x5x6x8", g6)]
+            ("game6d_7x6x6x5x6x8", g6),
+            ("game6d_brick_5x6x6x20x20x28", W.config_game6d(n=[5, 6, 6, 20, 20, 28], T=0.1))]
 
 
 @pytest.mark.parametrize("name,spec", _chunk_specs(), ids=[c[0] for c in _chunk_specs()])
