@@ -1116,6 +1116,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
     constexpr bool kClamp = KIND & 2;
     constexpr bool kLdsK = (KIND & 4) && N >= 3;
     constexpr bool kObst = (KIND & 8) && kClamp;
+    // quad tiles (six dimensions): the four waves of a block are the 2x2
+    // (axis 1, axis 2) pairs of a square at one offset in their cubes
+    constexpr bool kQuad = (KIND & 64) && N == 6 && kLdsK;
     const uint32_t L = xcd_logical(blockIdx.x, gridDim.x, uint32_t(xgroup));
     const uint32_t si = tile_solve ? tile_solve[L] : 0u;
     const uint32_t lt = tile_solve ? tile_local[L] : L;
@@ -1247,18 +1250,42 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
     // wrapped when periodic).  Lanes on the first or last row of axis N-2
     // replace that value by a ghost, or, when the axis is periodic, by a
     // load of the wrapped row.
+    // Quad tiles: each wave exchanges its own range of 64 VEC elements with a
+    // row of halo on each side (loaded by its first 2 H / VEC lanes) in a
+    // region of its own, and reads its neighbours along axis 1 (axis 2) on
+    // the side of its partner wave w ^ 2 (w ^ 1) from the partner's region,
+    // at the same offset; the other side is a memory load.
     constexpr int B = kBlock * VEC;
-    constexpr int kTile = kLdsK ? 2 * B : 1;  // B + 2 H with H <= B / 2
+    // B + 2 H with H <= B / 2; quad: 4 (B / 4 + 2 H) with H <= B / 8
+    constexpr int kTile = kLdsK ? 2 * B : 1;
     __shared__ __attribute__((aligned(16))) T tile[2][kTile];
     const int H = s.pitch;
     const uint32_t q0 = tg.q0;
-    const int me = int(q - q0) + H;
     const int nh = H / VEC;
     const int th = int(threadIdx.x);
-    const bool hl = kLdsK && th < 2 * nh;
-    int hsrc = th < nh ? int(q0) - H + th * VEC : int(q0) + B + (th - nh) * VEC;
+    int me, hsrc, hdst;
+    bool hl;
+    int dq1 = 0, dq2 = 0;       // kQuad: partner offsets in the tile
+    bool up1 = false, up2 = false;  // kQuad: the wave is the upper pair member
+    if constexpr (kQuad) {
+        constexpr int WS = 64 * VEC;
+        const int R = WS + 2 * H;
+        const int w = th >> 6, l = th & 63;
+        me = w * R + int(q - q0) + H;
+        hl = l < 2 * nh;
+        hsrc = l < nh ? int(q0) - H + l * VEC : int(q0) + WS + (l - nh) * VEC;
+        hdst = w * R + (l < nh ? l * VEC : H + WS + (l - nh) * VEC);
+        up1 = (w >> 1) & 1;
+        up2 = w & 1;
+        dq1 = ((w ^ 2) - w) * R;
+        dq2 = ((w ^ 1) - w) * R;
+    } else {
+        me = int(q - q0) + H;
+        hl = kLdsK && th < 2 * nh;
+        hsrc = th < nh ? int(q0) - H + th * VEC : int(q0) + B + (th - nh) * VEC;
+        hdst = th < nh ? th * VEC : H + B + (th - nh) * VEC;
+    }
     hsrc = min(max(hsrc, 0), int(s.Q) - VEC);  // rows outside the hyperplane are never read
-    const int hdst = th < nh ? th * VEC : H + B + (th - nh) * VEC;
     bool lane_wrap = false;
     if constexpr (kLdsK)
         lane_wrap = ((s.periodic >> (N - 2)) & 1u) && (ii[N - 2] == 0 || ii[N - 2] == s.n[N - 2] - 1);
@@ -1288,8 +1315,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
     P vq, zq;        // V^n and the comparison's reference of plane i
     P gq;            // obstacle of plane i (KIND bit 3)
     P hq;            // halo rows of plane i
+    // kQuad: the memory side of axes 1 and 2
+    uint32_t qg1 = 0, qg2 = 0;
+    if constexpr (kQuad) {
+        qg1 = up1 ? qR[1] : qL[1];
+        qg2 = up2 ? qR[2] : qL[2];
+    }
     auto load_nb = [&](int i, Nb &o) {
         const ODP_GLOBAL T *plane = W + int64_t(i) * s0;
+        if constexpr (kQuad) {
+            // axes 1 and 2: the memory side, held in l until the partner's
+            // side is read from LDS
+            o.l[0] = ldp<T, VEC>(plane + qg1);
+            o.l[1] = ldp<T, VEC>(plane + qg2);
+            o.l[2] = ldp<T, VEC>(plane + qL[3]);
+            o.r[2] = ldp<T, VEC>(plane + qR[3]);
+            return;
+        }
 #pragma unroll
         for (int d = 1; d <= NG; ++d) {
             o.l[d - 1] = ldp<T, VEC>(plane + qL[d]);
@@ -1342,6 +1384,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
             cur.r[N - 3] = ldp_lds<T, VEC>(tb + me + H);
             cur.xl = tb[me + oxl];
             cur.xr = tb[me + oxr];
+            if constexpr (kQuad) {
+                const P p1 = ldp_lds<T, VEC>(tb + me + dq1), p2 = ldp_lds<T, VEC>(tb + me + dq2);
+                const P g1 = cur.l[0], g2 = cur.l[1];
+                cur.l[0] = up1 ? p1 : g1;
+                cur.r[0] = up1 ? g1 : p1;
+                cur.l[1] = up2 ? p2 : g2;
+                cur.r[1] = up2 ? g2 : p2;
+            }
             if (anywrap && lane_wrap) {
                 const ODP_GLOBAL T *plane = W + int64_t(min(i, vlast)) * s0;
                 cur.l[N - 3] = ldp<T, VEC>(plane + qL[N - 2]);
@@ -1530,7 +1580,7 @@ static hipError_t launch_stage_t(int kind, const SolveDesc *d, const uint32_t *t
                            d, ts, tl, stage, from_desc, step, xg);                                 \
         break;
         // bit 3 (a second comparison) only comes with bit 1; bit 2 (LDS)
-        // only from three dimensions on
+        // only from three dimensions on; bit 6 (quad tiles) only in six
         switch (kind) {
             ODP_STAGE_CASE(0)
             ODP_STAGE_CASE(1)
@@ -1547,7 +1597,20 @@ static hipError_t launch_stage_t(int kind, const SolveDesc *d, const uint32_t *t
                     ODP_STAGE_CASE(7)
                     ODP_STAGE_CASE(14)
                     ODP_STAGE_CASE(15)
-                default: return hipErrorInvalidValue;
+                default:
+                    if constexpr (N == 6) {
+                        switch (kind) {
+                            ODP_STAGE_CASE(68)
+                            ODP_STAGE_CASE(69)
+                            ODP_STAGE_CASE(70)
+                            ODP_STAGE_CASE(71)
+                            ODP_STAGE_CASE(78)
+                            ODP_STAGE_CASE(79)
+                        default: return hipErrorInvalidValue;
+                        }
+                    } else {
+                        return hipErrorInvalidValue;
+                    }
                 }
             } else {
                 return hipErrorInvalidValue;

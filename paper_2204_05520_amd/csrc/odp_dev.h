@@ -64,7 +64,11 @@ struct SolveDesc {
                              // to the cubes of axes 3..5, dealt in k x k squares of
                              // axes 1 and 2 (tile_group)
     uint32_t cube;           // brick > 0: elements per cube of axes 3..5
-    uint32_t cube_tiles;     // brick > 0: tiles per cube, ceil(cube / (256 vec))
+    uint32_t cube_tiles;     // brick > 0: tiles per cube, ceil(cube / span), span =
+                             // 256 vec, or 64 vec with quad
+    uint32_t quad;           // brick > 0 (even): a tile's four waves take the 2x2
+                             // (axis 1, axis 2) pairs of a square at one cube offset
+    uint32_t pad0_;
     // ---- dynamics
     int32_t dyn;
     int32_t u_mode, d_mode;
@@ -145,6 +149,12 @@ struct SolveDesc {
 //   XCD-aware launch keeps on one XCD, are then each other's neighbours
 //   along axes 1 and 2 (and, one tile of the cube further, axis 3), so those
 //   neighbour loads hit that XCD's L2.
+//   quad (k even): a tile is 4 waves of 64 groups; wave w takes the pair
+//   (2 b1 + (w >> 1), 2 b2 + (w & 1)) of a 2x2 block (b1, b2) of the square,
+//   all four at the same offset in their cubes, so each wave's neighbours
+//   along axes 1 and 2 on one side are another wave's values; tiles are
+//   numbered square by square, then by cube tile, then by 2x2 block.  q0 is
+//   the start of the thread's wave's range.
 struct TileGroup {
     uint32_t q0, q;
     bool active;
@@ -153,7 +163,23 @@ struct TileGroup {
 __host__ __device__ inline TileGroup tile_group(const SolveDesc &s, uint32_t qb, uint32_t t, uint32_t vec) {
     TileGroup r;
     const uint32_t span = uint32_t(kBlock) * vec;
-    if (s.brick) {
+    if (s.quad) {
+        const uint32_t ws = 64u * vec;  // a wave's range
+        const uint32_t hk = s.brick / 2u, nbq = hk * hk;
+        const uint32_t per = nbq * s.cube_tiles;
+        const uint32_t sq = qb / per, rem = qb - sq * per;
+        const uint32_t j = rem / nbq, b = rem - j * nbq;
+        const uint32_t b1 = b / hk, b2 = b - b1 * hk;
+        const uint32_t nsq2 = uint32_t(s.n[2]) / s.brick;
+        const uint32_t s1 = sq / nsq2, s2 = sq - s1 * nsq2;
+        const uint32_t w = t >> 6, l = t & 63u;
+        const uint32_t a1 = s1 * s.brick + 2u * b1 + (w >> 1), a2 = s2 * s.brick + 2u * b2 + (w & 1u);
+        const uint32_t base = (a1 * uint32_t(s.n[2]) + a2) * s.cube;
+        const uint32_t loc = j * ws + l * vec;
+        r.q0 = base + j * ws;
+        r.active = loc < s.cube;
+        r.q = base + (r.active ? loc : s.cube - vec);
+    } else if (s.brick) {
         const uint32_t k = s.brick, kk = k * k;
         const uint32_t per = kk * s.cube_tiles;
         const uint32_t sq = qb / per, rem = qb - sq * per;

@@ -177,25 +177,45 @@ int64_t host_schedule(const PlanItem &it, const odp_solve_opts &o, std::vector<i
 }  // namespace
 
 // Tiles of one hyperplane (tile_group).  Six-dimensional first-order solves
-// whose axes 1 and 2 split into 3 x 3 squares and whose cubes of axes 3..5
-// waste under 5% of a tile's lanes in their ragged last tile take brick
-// tiles: their axis-1..3 neighbour loads then hit the L2 of the XCD that
-// marches them (36^6 float32: 17.0 -> 15.9 ms per step).  Everything else
-// takes row-major tiles.
+// whose cubes of axes 3..5 waste under 5% of the lanes in their ragged last
+// tile take brick tiles when axes 1 and 2 split into squares: their
+// axis-1..3 neighbour loads then hit the L2 of the XCD that marches them
+// (36^6 float32: 17.0 -> 15.9 ms per step).  With the LDS plane exchange, a
+// row pitch of at most 32 vec (each wave loads its own halo rows) and even
+// squares, the quad layout also takes one axis-1 and one axis-2 neighbour
+// per point from another wave's LDS tile (lds = 2).  Everything else takes
+// row-major tiles.
 static void choose_tiling(PlanItem &it, int space_order) {
     const int64_t span = int64_t(kBlock) * it.vec;
     it.brick = 0;
     it.cube = 0;
     it.cube_tiles = 0;
+    it.quad = 0;
     it.nqb = uint32_t((it.qpad + span - 1) / span);
     const odp_grid *g = it.g;
     if (g->ndim != 6 || space_order != 1 || it.dyn.id == ODP_DYN_PE3D) return;
-    constexpr int64_t k = 3;
-    if (g->n[1] % k || g->n[2] % k) return;
     const int64_t cube = it.qpad / (g->n[1] * g->n[2]);
+    auto fits = [&](int64_t k, int64_t sp) {
+        const int64_t ct = (cube + sp - 1) / sp;
+        return g->n[1] % k == 0 && g->n[2] % k == 0 && ct * sp * 20 <= cube * 21;
+    };
+    if (it.lds == 1 && it.pitch <= 32 * int64_t(it.vec)) {
+        const int64_t ws = 64 * int64_t(it.vec);
+        for (int64_t k : {6, 4, 2}) {
+            if (!fits(k, ws)) continue;
+            const int64_t ct = (cube + ws - 1) / ws;
+            it.brick = uint32_t(k);
+            it.quad = 1;
+            it.lds = 2;
+            it.cube = uint32_t(cube);
+            it.cube_tiles = uint32_t(ct);
+            it.nqb = uint32_t((g->n[1] / 2) * (g->n[2] / 2) * ct);
+            return;
+        }
+    }
+    if (!fits(3, span)) return;
     const int64_t ct = (cube + span - 1) / span;
-    if (ct * span * 20 > cube * 21) return;
-    it.brick = uint32_t(k);
+    it.brick = 3;
     it.cube = uint32_t(cube);
     it.cube_tiles = uint32_t(ct);
     it.nqb = uint32_t(g->n[1] * g->n[2] * ct);
@@ -388,6 +408,7 @@ void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &
         s.brick = it.brick;
         s.cube = it.cube;
         s.cube_tiles = it.cube_tiles;
+        s.quad = it.quad;
         s.tiles = it.tiles;
         s.rk_order = it.rk_order;
         s.dyn = it.dyn.id;

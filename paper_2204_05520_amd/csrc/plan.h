@@ -32,9 +32,10 @@ struct PlanItem {
     int pitch = 0;                      // last-axis row pitch in memory (0: dense)
     int64_t qpad = 0, ppad = 0;         // hyperplane / array elements with padding
     int vec = 1, chunk = 1;
-    int lds = 0;                        // the stage kernel's LDS plane exchange
+    int lds = 0;                        // the stage kernel's LDS plane exchange (2: quad tiles)
     uint32_t brick = 0;                 // tile_group's brick side (0: row-major tiles)
     uint32_t cube = 0, cube_tiles = 0;  // brick > 0: the cubes of axes 3..5
+    uint32_t quad = 0;                  // tile_group's quad layout (then lds == 2)
     uint32_t nqb = 0;                   // tiles per hyperplane
     // pad_io: the caller's V0 and A are dense while `pitch` pads the rows;
     // the plan keeps padded copies (V0p, Ap) and copies in and out itself

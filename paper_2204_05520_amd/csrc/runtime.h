@@ -101,8 +101,11 @@ int method_kind(const odp_solve_opts &o);
 // plane exchange (every listed solve must have SolveDesc::lds set), bit 4
 // second-order ENO differences (the point-per-lane kernel), bit 5 (added by
 // the caller) the costate-box pass of the pursuit-evasion model.
+// lds: 0 none, 1 the LDS plane exchange, 2 the exchange with quad tiles
+// (kind bit 6: six dimensions, tile_group's quad layout).
 inline int stage_kind(int rk_order, int stage, int mkind, int lds = 0, int eno2 = 0) {
-    return (stage > 0 ? 1 : 0) | (stage == rk_order - 1 ? mkind : 0) | (lds ? 4 : 0) | (eno2 ? 16 : 0);
+    return (stage > 0 ? 1 : 0) | (stage == rk_order - 1 ? mkind : 0) | (lds ? 4 : 0) | (lds == 2 ? 64 : 0) |
+           (eno2 ? 16 : 0);
 }
 // Whether a solve of this shape uses the LDS plane exchange.
 inline int uses_lds(int ndim, int64_t pitch, int vec) { return ndim >= 3 && pitch <= 128 * int64_t(vec) ? 1 : 0; }

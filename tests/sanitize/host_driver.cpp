@@ -41,6 +41,7 @@ static odp_grid *grid(int nd, const int64_t *n, const uint8_t *per, double lo = 
 // be the start of its threads' range.  The copy kernels' row-major groups
 // must cover the hyperplane too (brick tiles are at least as many).
 static int g_brick_plans = 0;  // plans whose tiles were brick tiles
+static int g_quad_plans = 0;   // of which quad tiles
 
 static void coverage(const Plan &p, const std::vector<unsigned char> &img) {
     for (size_t i = 0; i < p.items.size(); ++i) {
@@ -55,7 +56,8 @@ static void coverage(const Plan &p, const std::vector<unsigned char> &img) {
             for (int t = 0; t < kBlock; ++t) {
                 const TileGroup tg = tile_group(s, qb, uint32_t(t), uint32_t(s.vec));
                 CHECK(int64_t(tg.q) + s.vec <= Q);
-                if (t == 0 && tg.active) CHECK(tg.q == tg.q0);
+                // a tile's (quad: a wave's) first thread starts its range
+                if ((t == 0 || (s.quad && (t & 63) == 0)) && tg.active) CHECK(tg.q == tg.q0);
                 if (!tg.active) continue;
                 CHECK(tg.q % uint32_t(s.vec) == 0);
                 for (int j = 0; j < s.vec; ++j)
@@ -70,8 +72,10 @@ static void coverage(const Plan &p, const std::vector<unsigned char> &img) {
         CHECK(s.pitch >= s.n[s.ndim - 1] || s.ndim == 1);
         if (s.brick) {
             ++g_brick_plans;
+            if (s.quad) ++g_quad_plans;
             CHECK(s.ndim == 6 && s.n[1] % int(s.brick) == 0 && s.n[2] % int(s.brick) == 0);
             CHECK(int64_t(s.cube) * s.n[1] * s.n[2] == Q);
+            CHECK(!s.quad || (s.brick % 2 == 0 && s.lds == 2 && s.pitch <= 32 * s.vec));
         }
     }
 }
@@ -192,8 +196,9 @@ int main() {
                 for (odp_grid *g : owned) odp_grid_destroy(g);
             }
     // six-dimensional grids with cubes of axes 3..5 large enough for brick
-    // tiles, and some that miss a condition (an axis-1 extent that is not a
-    // multiple of 3, second order)
+    // tiles: quad tiles (even squares), 3x3 squares, and one that misses a
+    // condition (an axis-1 extent that is not a multiple of 3); second order
+    // takes row-major tiles
     for (int prec : {32, 64})
         for (int order : {1, 2}) {
             odp_solve_opts o;
@@ -205,8 +210,10 @@ int main() {
             o.space_order = order;
             const uint8_t p6[6] = {0, 0, 1, 0, 0, 1};
             for (int rep = 0; rep < 3; ++rep) {
-                const int64_t n6[6] = {U(3, 6), 3 * U(1, 3) + (rep == 2 ? 1 : 0), 3 * U(1, 2), U(18, 26), U(18, 26),
-                                       4 * U(6, 10)};
+                const int64_t n6q[6] = {U(3, 6), 6, 6, U(18, 26), U(18, 26), 4 * U(6, 8)};
+                const int64_t n6b[6] = {U(3, 6), 9, 3, 24, 24, 36};
+                const int64_t n6r[6] = {U(3, 6), 7, 6, U(18, 26), U(18, 26), 4 * U(6, 10)};
+                const int64_t *n6 = rep == 0 ? n6q : rep == 1 ? n6b : n6r;
                 odp_grid *g6 = grid(6, n6, p6);
                 odp_dynamics d3{};
                 d3.id = ODP_DYN_TWODUBINS6D; d3.u_mode = 1; d3.p[0] = 1; d3.p[1] = 1; d3.p[2] = 1; d3.p[3] = 1;
@@ -214,7 +221,7 @@ int main() {
                 odp_grid_destroy(g6);
             }
         }
-    CHECK(g_brick_plans > 0);
+    CHECK(g_brick_plans > 0 && g_quad_plans > 0 && g_quad_plans < g_brick_plans);
     // time to reach workspace, the server's argument checks (no device here)
     {
         const int64_t n[3] = {20, 20, 16};

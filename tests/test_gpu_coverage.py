@@ -4,7 +4,7 @@ exact in float32 up to 2^24) must leave every output point holding its own
 value: a point that no tile wrote keeps the output buffer's fill (NaN), one
 written from the wrong place holds another index.  Every launch form: single
 solves with several axis-0 chunkings (runs shorter than the 4-plane cycle,
-ragged last runs), both spatial orders, row-major and brick tiles, the
+ragged last runs), both spatial orders, row-major, brick and quad tiles, the
 point-per-lane kernel, batches with padded rows, the server."""
 import time
 
@@ -45,8 +45,11 @@ CASES = [
     ("dyncar4d", [13, 11, 9, 18], W.DynSpec(W.DYN_DYNCAR4D, [1.0, 1.0], W.MAXIMISE, W.MINIMISE)),
     ("si5d", [7, 6, 5, 9, 11], W.DynSpec(W.DYN_SINGLE_INTEGRATOR, [1.0], W.MINIMISE, W.MINIMISE)),
     ("game6d", [7, 6, 5, 6, 7, 10], W.DynSpec(W.DYN_TWODUBINS6D, [1.0, 1.0, 1.0, 1.0], W.MAXIMISE, W.MINIMISE)),
-    # cubes of axes 3..5 of 11200 points: first order takes brick tiles
-    ("game6d_brick", [4, 6, 6, 20, 20, 28],
+    # cubes of axes 3..5 of 11200 and 20736 points: first order takes quad
+    # tiles (6x6 squares of axes 1 and 2) and brick tiles (3x3 squares)
+    ("game6d_quad", [4, 6, 6, 20, 20, 28],
+     W.DynSpec(W.DYN_TWODUBINS6D, [1.0, 1.0, 1.0, 1.0], W.MAXIMISE, W.MINIMISE)),
+    ("game6d_brick3", [3, 9, 3, 24, 24, 36],
      W.DynSpec(W.DYN_TWODUBINS6D, [1.0, 1.0, 1.0, 1.0], W.MAXIMISE, W.MINIMISE)),
     ("pe3d", [21, 19, 14], W.DynSpec(W.DYN_PE3D, [1.0, 1.0, 1.0, 1.0], W.MAXIMISE, W.MINIMISE)),
 ]

@@ -73,9 +73,12 @@ CASES = [
     # memory-loaded neighbours
     ("game6d_periodic_axis4", lambda: _periodic4(W.config_game6d(n=[8, 7, 6, 5, 9, 12], T=0.4)),
      (64, 32)),
-    # axes 1 and 2 in 3 x 3 squares, cubes of axes 3..5 of 11200 points:
-    # brick tiles (ragged last tile of every cube)
+    # axes 1 and 2 in 6 x 6 squares, cubes of axes 3..5 of 11200 points:
+    # quad tiles (a block's waves are 2x2 axis-1/axis-2 neighbours; ragged
+    # last tile of every cube)
     ("game6d_brick_5x6x6x20x20x28", lambda: W.config_game6d(n=[5, 6, 6, 20, 20, 28], T=0.25), (64, 32)),
+    # axes 1 and 2 in 3 x 3 squares only: brick tiles of whole blocks
+    ("game6d_brick3_4x9x3x24x24x36", lambda: W.config_game6d(n=[4, 9, 3, 24, 24, 36], T=0.2), (64, 32)),
 ]
 
 
@@ -118,7 +121,8 @@ def _chunk_specs():
     return [("dyncar4d_13x17x9x20", W.config_dyncar4d(n=[13, 17, 9, 20], T=0.2)),
             ("dubins3d_15x22x16", W.config_dubins3d(n=(15, 22, 16), T=0.3)),
             ("game6d_7x6x6x5x6x8", g6),
-            ("game6d_brick_5x6x6x20x20x28", W.config_game6d(n=[5, 6, 6, 20, 20, 28], T=0.1))]
+            ("game6d_brick_5x6x6x20x20x28", W.config_game6d(n=[5, 6, 6, 20, 20, 28], T=0.1)),
+            ("game6d_brick3_4x9x3x24x24x36", W.config_game6d(n=[4, 9, 3, 24, 24, 36], T=0.1))]
 
 
 @pytest.mark.parametrize("name,spec", _chunk_specs(), ids=[c[0] for c in _chunk_specs()])
