@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void box_dt_kernel(const SolveDesc *__restr
                                                         int64_t fixed_step) {
     const SolveDesc &s = descs[list ? list[blockIdx.x] : int(blockIdx.x)];
     if (!s.box_cfl) return;
-    const int64_t k = from_desc ? *s.step : fixed_step;
+    const int64_t k = (from_desc ? *s.step : 0) + fixed_step;
     if (k >= *s.nsteps) return;
     const int box_buf = int((k * s.rk_order) & 1);
     const uint64_t *bx = s.box + 6 * kBoxSlots * box_buf;
@@ -426,13 +426,15 @@ __global__ void set_slice_kernel(SolveDesc *__restrict__ descs, int iv) {
     s.oref = (const T *)s.oref0 + int64_t(iv) * s.ostride;
 }
 
-// Server ticks: advance the step counter of every listed unfinished solve.
+// End of a server tick: advance the step counter of every listed solve by
+// its steps in the tick (inc[i]), capped at its step count.
 __global__ void advance_kernel(const SolveDesc *__restrict__ descs, const int32_t *__restrict__ list,
-                               int n) {
+                               const int32_t *__restrict__ inc, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const SolveDesc &s = descs[list[i]];
-    if (*s.step < *s.nsteps) *s.step += 1;
+    const int64_t t = *s.step + inc[i];
+    *s.step = t < *s.nsteps ? t : *s.nsteps;
 }
 
 // Copy the start value into the buffer the first step reads, for every
@@ -680,8 +682,8 @@ hipError_t launch_ttr_zero(unsigned long long *p, int n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_advance(const SolveDesc *d, const int32_t *list, int n, hipStream_t st) {
-    hipLaunchKernelGGL(advance_kernel, dim3((n + 255) / 256), dim3(256), 0, st, d, list, n);
+hipError_t launch_advance(const SolveDesc *d, const int32_t *list, const int32_t *inc, int n, hipStream_t st) {
+    hipLaunchKernelGGL(advance_kernel, dim3((n + 255) / 256), dim3(256), 0, st, d, list, inc, n);
     return hipGetLastError();
 }
 

@@ -252,8 +252,10 @@ __device__ __forceinline__ void stage_buffers(const SolveDesc &s, int stage, int
 
 // ------------------------------------------------------------ kernels
 
-// Stage `stage` of step k (k = fixed_step, or the solve's own step counter
-// when step_from_desc != 0) for every listed solve.
+// Stage `stage` of step k for every listed solve: k = fixed_step, plus the
+// solve's own step counter when step_from_desc != 0 (server ticks: the
+// counter holds the step at the start of the tick, fixed_step the offset
+// within it).
 template <typename T, int DYN, int N>
 __global__ __launch_bounds__(kBlock) void stage_kernel(const SolveDesc *__restrict__ descs,
                                                        const uint32_t *__restrict__ tile_solve,
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const SolveDesc *__restri
     const SolveDesc &s = descs[si];
 
     const int64_t nsteps = *s.nsteps;
-    const int64_t k = step_from_desc ? *s.step : fixed_step;
+    const int64_t k = (step_from_desc ? *s.step : 0) + fixed_step;
     if (k >= nsteps || stage >= s.rk_order) return;
 
     const uint32_t cid = lt / s.nqb;
@@ -464,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void stage_point_kernel(const SolveDesc *__
     const SolveDesc &s = descs[si];
 
     const int64_t nsteps = *s.nsteps;
-    const int64_t k = step_from_desc ? *s.step : fixed_step;
+    const int64_t k = (step_from_desc ? *s.step : 0) + fixed_step;
     if (k >= nsteps || stage >= s.rk_order) return;
 
     const uint32_t cid = lt / s.nqb;
@@ -817,7 +819,7 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
     const SolveDesc &s = descs[si];
 
     const int64_t nsteps = *s.nsteps;
-    const int64_t k = step_from_desc ? *s.step : fixed_step;
+    const int64_t k = (step_from_desc ? *s.step : 0) + fixed_step;
     if (k >= nsteps || stage >= s.rk_order) return;
 
     const uint32_t cid = lt / s.nqb;
@@ -1125,7 +1127,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
     const SolveDesc &s = descs[si];
 
     const int64_t nsteps = *s.nsteps;
-    const int64_t k = step_from_desc ? *s.step : fixed_step;
+    const int64_t k = (step_from_desc ? *s.step : 0) + fixed_step;
     if (k >= nsteps || stage >= s.rk_order) return;
 
     const uint32_t cid = lt / s.nqb;

@@ -28,7 +28,7 @@ hipError_t launch_alpha(int dyn, int ndim, const SolveDesc *d, int nsolves, int 
                         hipStream_t st);
 hipError_t launch_init(const SolveDesc *d, int nsolves, hipStream_t st);
 hipError_t launch_sched(const SolveDesc *d, int nsolves, int64_t *nsteps_all, hipStream_t st);
-hipError_t launch_advance(const SolveDesc *d, const int32_t *list, int n, hipStream_t st);
+hipError_t launch_advance(const SolveDesc *d, const int32_t *list, const int32_t *inc, int n, hipStream_t st);
 // Time to reach: one Jacobi sweep (a lane per hyperplane point marching
 // `chunk` axis-0 nodes, grid qblocks x ceil(n0 / chunk)), the start value,
 // and zeroing of the change slots.

@@ -172,7 +172,8 @@ struct odp_server {
     int64_t *d_nsteps = nullptr;
     int64_t *h_nsteps = nullptr;  // pinned, one per slot
     uint32_t *d_tiles = nullptr;  // [cap] solve slot, [cap] local tile
-    int32_t *d_list = nullptr;    // [max_slots] per-group member slots
+    int32_t *d_list = nullptr;    // [2 max_slots] per-group member slots, then each
+                                  // member's steps in the tick (same order)
     size_t tile_cap = 0;
     Staging tab[2];               // tile tables on their way to the device
     int tab_next = 0;
@@ -511,9 +512,10 @@ int build_groups(odp_server *s, const std::vector<std::shared_ptr<Req>> &sel, st
     }
     Staging &b = s->tab[s->tab_next];
     s->tab_next ^= 1;
-    if ((rc = stage_reserve(b, ntiles * 8 + sel.size() * 4))) return rc;
+    if ((rc = stage_reserve(b, ntiles * 8 + sel.size() * 8))) return rc;
     uint32_t *ts = (uint32_t *)b.p, *tl = ts + ntiles;
     int32_t *list = (int32_t *)(tl + ntiles);
+    int32_t *inc = list + sel.size();
     size_t nt = 0, nl = 0;
     for (Group &g : groups) {
         g.tile_base = nt;
@@ -525,6 +527,7 @@ int build_groups(odp_server *s, const std::vector<std::shared_ptr<Req>> &sel, st
                 ts[nt] = uint32_t(sl);
                 tl[nt++] = k;
             }
+            inc[nl] = by_slot[size_t(sl)]->tick_steps;
             list[nl++] = sl;
             g.prefix.push_back(uint32_t(nt - g.tile_base));
         }
@@ -535,6 +538,8 @@ int build_groups(odp_server *s, const std::vector<std::shared_ptr<Req>> &sel, st
         (rc = check_hip(hipMemcpyAsync(s->d_tiles + s->tile_cap, tl, ntiles * 4, hipMemcpyHostToDevice, s->st),
                         "tiles")) ||
         (rc = check_hip(hipMemcpyAsync(s->d_list, list, nl * 4, hipMemcpyHostToDevice, s->st), "list")) ||
+        (rc = check_hip(hipMemcpyAsync(s->d_list + s->max_slots, inc, nl * 4, hipMemcpyHostToDevice, s->st),
+                        "tick steps")) ||
         (rc = check_hip(hipEventRecord(b.ev, s->st), "record")))
         return rc;
     b.pending = true;
@@ -560,22 +565,29 @@ int enqueue_tick(odp_server *s, const std::vector<Group> &groups, hipEvent_t *do
                 const int kind = stage_kind(g.rk, j, mk, g.lds, o.space_order == 2);
                 // pursuit-evasion: the costate box of each solve's stage input
                 // first (each solve's own step counter picks its box buffer)
+                // (step m of the tick: the solve's counter holds the tick's first step)
                 if (g.dyn == ODP_DYN_PE3D && !o.dissipation &&
                     ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, kind | 32, s->d_slots, ts, tl,
-                                                  nt, j, 1, 0, o.xcd_group, s->st),
+                                                  nt, j, 1, m, o.xcd_group, s->st),
                                      "box")) ||
                      // the step from the box of the first stage (Algorithm 1)
-                     (j == 0 && (rc = check_hip(launch_box_dt(s->d_slots, s->d_list + g.list_base, nm, 1, 0, s->st),
+                     (j == 0 && (rc = check_hip(launch_box_dt(s->d_slots, s->d_list + g.list_base, nm, 1, m, s->st),
                                                 "box step")))))
                     return rc;
                 if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, kind, s->d_slots, ts, tl, nt, j,
-                                                 1, 0, o.xcd_group, s->st),
+                                                 1, m, o.xcd_group, s->st),
                                     "stage")))
                     return rc;
             }
-            if ((rc = check_hip(launch_advance(s->d_slots, s->d_list + g.list_base, nm, s->st), "advance")))
-                return rc;
         }
+    }
+    // one advance per group: every member by its steps in the tick
+    for (const Group &g : groups) {
+        if (g.steps.empty()) continue;
+        if ((rc = check_hip(launch_advance(s->d_slots, s->d_list + g.list_base, s->d_list + s->max_slots + g.list_base,
+                                           int(g.steps.size()), s->st),
+                            "advance")))
+            return rc;
     }
     if ((rc = get_event(s, done))) return rc;
     if ((rc = check_hip(hipEventRecord(*done, s->st), "record"))) put_event(s, *done);
@@ -802,7 +814,7 @@ int odp_server_create(size_t hbm_budget_bytes, int max_slots, const odp_solve_op
         (rc = check_hip(hipStreamCreateWithFlags(&s->dst, hipStreamNonBlocking), "stream")) ||
         (rc = check_hip(hipMalloc(&s->d_slots, sizeof(SolveDesc) * size_t(max_slots)), "slots")) ||
         (rc = check_hip(hipMalloc(&s->d_nsteps, 8 * size_t(max_slots)), "slots")) ||
-        (rc = check_hip(hipMalloc(&s->d_list, 4 * size_t(max_slots)), "slots")) ||
+        (rc = check_hip(hipMalloc(&s->d_list, 8 * size_t(max_slots)), "slots")) ||
         (rc = check_hip(hipHostMalloc((void **)&s->h_nsteps, 8 * size_t(max_slots), hipHostMallocDefault), "pinned")) ||
         (rc = check_hip(hipEventCreateWithFlags(&s->tab[0].ev, hipEventDisableTiming), "event")) ||
         (rc = check_hip(hipEventCreateWithFlags(&s->tab[1].ev, hipEventDisableTiming), "event"))) {
