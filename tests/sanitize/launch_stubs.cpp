@@ -9,7 +9,7 @@ hipError_t launch_stage(int, int, int, int, int, const SolveDesc *, const uint32
 hipError_t launch_alpha(int, int, const SolveDesc *, int, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_init(const SolveDesc *, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_sched(const SolveDesc *, int, int64_t *, hipStream_t) { return hipErrorInvalidValue; }
-hipError_t launch_advance(const SolveDesc *, const int32_t *, int, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_advance(const SolveDesc *, const int32_t *, const int32_t *, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_ttr(int, int, int, const SolveDesc *, uint32_t, int, int, const void *, void *, const void *,
                       unsigned long long *, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_ttr_init(int, const void *, void *, int64_t, double, hipStream_t) { return hipErrorInvalidValue; }
