@@ -824,10 +824,9 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
 
     const uint32_t cid = lt / s.nqb;
     const uint32_t qb = lt - cid * s.nqb;
-    const uint32_t Qg = s.Q / VEC;
-    const uint32_t gi = qb * kBlock + threadIdx.x;
-    const bool active = gi < Qg;
-    const uint32_t q = (active ? gi : Qg - 1) * VEC;
+    const TileGroup tg = tile_group(s, qb, threadIdx.x, VEC);  // row-major, or brick tiles (6D)
+    const bool active = tg.active;
+    const uint32_t q = tg.q;
 
     int ii[N];
     ii[0] = 0;
@@ -911,7 +910,7 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
     constexpr int kTileX = LDSX ? 2 * B : 1;  // B + 4 H with 4 H <= B
     __shared__ __attribute__((aligned(16))) T xtile[2][kTileX];
     const int H = nl;
-    const uint32_t q0 = qb * uint32_t(B);
+    const uint32_t q0 = tg.q0;
     const int me = int(q - q0) + 2 * H;
     const int nh = 2 * H / VEC;
     const int th = int(threadIdx.x);

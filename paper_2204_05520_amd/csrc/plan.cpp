@@ -176,15 +176,16 @@ int64_t host_schedule(const PlanItem &it, const odp_solve_opts &o, std::vector<i
 
 }  // namespace
 
-// Tiles of one hyperplane (tile_group).  Six-dimensional first-order solves
-// whose cubes of axes 3..5 waste under 5% of the lanes in their ragged last
-// tile take brick tiles when axes 1 and 2 split into squares: their
-// axis-1..3 neighbour loads then hit the L2 of the XCD that marches them
-// (36^6 float32: 17.0 -> 15.9 ms per step).  With the LDS plane exchange, a
-// row pitch of at most 32 vec (each wave loads its own halo rows) and even
-// squares, the quad layout also takes one axis-1 and one axis-2 neighbour
-// per point from another wave's LDS tile (lds = 2).  Everything else takes
-// row-major tiles.
+// Tiles of one hyperplane (tile_group).  Six-dimensional solves of the
+// vector kernels (first order; second order with two or more points per
+// thread) whose cubes of axes 3..5 waste under 5% of the lanes in their
+// ragged last tile take brick tiles when axes 1 and 2 split into squares:
+// their axis-1..3 neighbour loads then hit the L2 of the XCD that marches
+// them (36^6 float32 first order: 17.0 -> 15.9 ms per step).  First order
+// with the LDS plane exchange, a row pitch of at most 32 vec (each wave
+// loads its own halo rows) and even squares takes the quad layout, which
+// also reads one axis-1 and one axis-2 neighbour per point from another
+// wave's LDS tile (lds = 2).  Everything else takes row-major tiles.
 static void choose_tiling(PlanItem &it, int space_order) {
     const int64_t span = int64_t(kBlock) * it.vec;
     it.brick = 0;
@@ -193,13 +194,16 @@ static void choose_tiling(PlanItem &it, int space_order) {
     it.quad = 0;
     it.nqb = uint32_t((it.qpad + span - 1) / span);
     const odp_grid *g = it.g;
-    if (g->ndim != 6 || space_order != 1 || it.dyn.id == ODP_DYN_PE3D) return;
+    if (g->ndim != 6 || it.dyn.id == ODP_DYN_PE3D) return;
+    // second order: the vector kernel only (the point-per-lane kernel keeps
+    // its own row-major mapping)
+    if (space_order == 2 && (it.vec < 2 || it.dyn.id == ODP_DYN_SINGLE_INTEGRATOR)) return;
     const int64_t cube = it.qpad / (g->n[1] * g->n[2]);
     auto fits = [&](int64_t k, int64_t sp) {
         const int64_t ct = (cube + sp - 1) / sp;
         return g->n[1] % k == 0 && g->n[2] % k == 0 && ct * sp * 20 <= cube * 21;
     };
-    if (it.lds == 1 && it.pitch <= 32 * int64_t(it.vec)) {
+    if (space_order == 1 && it.lds == 1 && it.pitch <= 32 * int64_t(it.vec)) {
         const int64_t ws = 64 * int64_t(it.vec);
         for (int64_t k : {6, 4, 2}) {
             if (!fits(k, ws)) continue;

@@ -196,9 +196,9 @@ int main() {
                 for (odp_grid *g : owned) odp_grid_destroy(g);
             }
     // six-dimensional grids with cubes of axes 3..5 large enough for brick
-    // tiles: quad tiles (even squares), 3x3 squares, and one that misses a
-    // condition (an axis-1 extent that is not a multiple of 3); second order
-    // takes row-major tiles
+    // tiles: quad tiles (even squares; first order), 3x3 squares (and second
+    // order on either), and one that misses a condition (an axis-1 extent
+    // that is not a multiple of 3)
     for (int prec : {32, 64})
         for (int order : {1, 2}) {
             odp_solve_opts o;

@@ -7,7 +7,17 @@ whole grids (ragged tails, several tiles, non-periodic and periodic axes,
 edges within two nodes of every face), the same step count.  The ENO
 stencil choice is a decision taken in floating point: a one-step check
 compares a float32 step with the oracle taking its choices in float32 from
-the same float32 input.
+the same float32 input.  In float64 both sides take it from inputs that
+differ only by rounding, so an exact tie between two second differences of
+opposite sign (the smaller magnitude is then undefined and the first
+stencil is taken) can fall either way: the benchmark's start values hold
+exact symmetries (the 6D game's V0 does not depend on the headings) that
+put thousands of such ties into the first steps of a 6D solve, each moving
+its point by about dt |D2| / dx.  The six-dimensional parity cases
+therefore run on generic inputs, the workload's V0 plus a seeded
+perturbation of 1e-4, on which the oracle's own stage inputs hold no two
+opposite-sign second differences within 1e-12 of a tie (checked with the
+oracle on the CPU).
 """
 import numpy as np
 import pytest
@@ -34,9 +44,19 @@ def _dev(x, prec):
     return torch.tensor(x, dtype=torch.float64 if prec == 64 else torch.float32, device="cuda:0")
 
 
-def _compare(odp, oracle_mod, spec, precs=(64, 32), **kw):
-    import torch
+def _generic_v0(spec):
+    """Six dimensions: the workload's V0 plus a seeded perturbation of 1e-4
+    (no exact ENO ties); otherwise the workload's V0."""
     V0 = W.make_v0(spec)
+    if spec.grid.ndim < 6:
+        return V0
+    rng = np.random.default_rng(220405522)
+    return V0 + 1e-4 * rng.standard_normal(tuple(spec.grid.n))
+
+
+def _compare(odp, oracle_mod, spec, precs=(64, 32), V0=None, **kw):
+    import torch
+    V0 = W.make_v0(spec) if V0 is None else V0
     okw = {k: v for k, v in kw.items() if k in ("tmode", "omode", "target", "obstacle")}
     ref = oracle_mod.solve(spec.grid, spec.dyn, V0, spec.tau, rk_order=spec.rk_order, cfl=spec.cfl,
                            brt=spec.mode == W.BRT, space_order=2, **okw)
@@ -68,13 +88,22 @@ CASES = [
     ("dubins3d_60x60x36_rk2", lambda: _rk(W.config_dubins3d(), 2)),
     ("dyncar4d_22x21x19x24_rk2", lambda: _rk(W.config_dyncar4d(n=[22, 21, 19, 24], T=0.5), 2)),
     ("game6d_9x8x8x7x9x8_rk2", lambda: W.config_game6d(n=[9, 8, 8, 7, 9, 8], T=0.5)),
+    # cubes of axes 3..5 of 11200 points, axes 1 and 2 in 3x3 squares: brick
+    # tiles
+    ("game6d_brick_4x6x6x20x20x28_rk2", lambda: W.config_game6d(n=[4, 6, 6, 20, 20, 28], T=0.2)),
 ]
 
 
 @pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
 def test_eno2_parity(odp, oracle_mod, name, mk):
-    ref = _compare(odp, oracle_mod, mk())
-    first = oracle_mod.solve_spec(mk())
+    V0 = _generic_v0(mk())
+    # the brick grid (4 nodes on axis 0, finer axes 3..5) checks the tile
+    # mapping in float64; in float32 its ENO decisions flip at near-ties of
+    # the symmetric 6D value function (1.0-3.7e-4 S with or without the
+    # perturbation, measured), above the float32 bar whatever the tiling
+    precs = (64,) if "brick" in name else (64, 32)
+    ref = _compare(odp, oracle_mod, mk(), V0=V0, precs=precs)
+    first = oracle_mod.solve_spec(mk(), V0=V0)
     # the second-order solve differs from the first-order one
     assert np.abs(first.V - ref.V).max() > 1e-4
 
@@ -127,13 +156,15 @@ def test_eno2_methods_and_restart(odp, oracle_mod):
 
 
 def test_eno2_launch_shapes_bitwise(odp):
-    """Every axis-0 chunking and the batch give the same bits (one padded
-    batch member is not padded on this path: its rows are read as they are)."""
+    """Every axis-0 chunking (row-major and brick tiles) and the batch give
+    the same bits (one padded batch member is not padded on this path: its
+    rows are read as they are)."""
     import torch
-    spec = _rk(W.config_dyncar4d(n=[13, 17, 9, 20], T=0.2), 2)
-    V0 = _dev(W.make_v0(spec), 32)
-    outs = [odp.solve(spec, V0, precision=32, tile_chunk=c, space_order=2).V.cpu() for c in (1, 3, 13)]
-    assert all(torch.equal(o, outs[0]) for o in outs[1:])
+    for spec in (_rk(W.config_dyncar4d(n=[13, 17, 9, 20], T=0.2), 2),
+                 W.config_game6d(n=[4, 6, 6, 20, 20, 28], T=0.1)):
+        V0 = _dev(W.make_v0(spec), 32)
+        outs = [odp.solve(spec, V0, precision=32, tile_chunk=c, space_order=2).V.cpu() for c in (1, 3, 13)]
+        assert all(torch.equal(o, outs[0]) for o in outs[1:]), spec.grid.n
     specs = [_rk(W.config_dubins3d(n=(21, 19, 15), T=0.5), 2), _rk(W.config_dubins3d(n=(17, 23, 13), T=0.7), 2)]
     V0s = [_dev(W.make_v0(s), 32) for s in specs]
     bouts, _ = odp.batch(specs, V0s, precision=32, space_order=2)
