@@ -165,8 +165,10 @@ __global__ void init_kernel(const SolveDesc *__restrict__ descs, int nsolves) {
     for (int d = 0; d < kMaxDim; ++d) s.amax[d] = 0.0;
     *s.flags = 0;
     *s.step = 0;
-    if (s.box)  // costate box buffer of the first stage
+    if (s.box) {  // costate box buffer of the first stage, the box CFL step's words
         for (int e = 0; e < 6 * kBoxSlots; ++e) s.box[e] = box_key(e % 6 < 3 ? INFINITY : -INFINITY);
+        for (int e = 0; e < kBoxStepWords; ++e) s.box[12 * kBoxSlots + e] = 0;
+    }
     *s.nsteps = 0;
 }
 
@@ -286,54 +288,74 @@ __device__ __forceinline__ void pe3d_alpha_box_headings(const SolveDesc &s, doub
 // The CFL step of step k for solves whose step comes from the costate box
 // (Algorithm 1: alpha^max is the largest alpha_i of the step's dissipation
 // loop, here over the box of the first stage's input, which the box pass of
-// stage 0 has just reduced).  One block per listed solve: the box from its
-// 64 partial boxes, the largest box alpha over the (x, y) nodes of the grid
-// (every heading at once), then the float64 step clipped to land on the next
-// output time, recorded as dt_sched[k]; landing on the last output time
-// fixes the step count at k + 1.
+// stage 0 has just reduced).  A row of gridDim.x blocks per listed solve
+// (blockIdx.y): each takes the box from its 64 partial boxes (a lane each)
+// and the largest box alpha over its share of the grid's (x, y) nodes (every heading at
+// once), maxes it into the solve's step words with one atomic per axis, and
+// counts itself in; the block that arrives last takes the float64 step,
+// clipped to land on the next output time, records it as dt_sched[k], and
+// clears the words for the next step.  Landing on the last output time fixes
+// the step count at k + 1.  Every block of a row takes the same early exits
+// (the step count only drops to k + 1 during the launch).
 __global__ __launch_bounds__(kBlock) void box_dt_kernel(const SolveDesc *__restrict__ descs,
                                                         const int32_t *__restrict__ list, int from_desc,
                                                         int64_t fixed_step) {
-    const SolveDesc &s = descs[list ? list[blockIdx.x] : int(blockIdx.x)];
+    const SolveDesc &s = descs[list ? list[blockIdx.y] : int(blockIdx.y)];
     if (!s.box_cfl) return;
     const int64_t k = (from_desc ? *s.step : 0) + fixed_step;
     if (k >= *s.nsteps) return;
     const int box_buf = int((k * s.rk_order) & 1);
     const uint64_t *bx = s.box + 6 * kBoxSlots * box_buf;
+    unsigned long long *words = (unsigned long long *)(s.box + 12 * kBoxSlots);
+    // the box: lane j of every wave takes partial box j, then a butterfly
+    static_assert(kBoxSlots == 64, "one partial box per lane");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double bmin[3], bmax[3];
     for (int d = 0; d < 3; ++d) {
-        double a = INFINITY, b = -INFINITY;
-        for (int j = 0; j < kBoxSlots; ++j) {
-            a = fmin(a, box_val(bx[6 * j + d]));
-            b = fmax(b, box_val(bx[6 * j + 3 + d]));
+        double a = box_val(bx[6 * lane + d]), b = box_val(bx[6 * lane + 3 + d]);
+        for (int off = 32; off >= 1; off >>= 1) {
+            a = fmin(a, __shfl_xor(a, off, 64));
+            b = fmax(b, __shfl_xor(b, off, 64));
         }
         bmin[d] = a;
         bmax[d] = b;
     }
     double m[3] = {0.0, 0.0, 0.0};
     const int n0 = s.n[0], n1 = s.n[1];
-    for (int p = threadIdx.x; p < n0 * n1; p += kBlock) {
+    for (int p = int(blockIdx.x) * kBlock + int(threadIdx.x); p < n0 * n1; p += int(gridDim.x) * kBlock) {
         const int i0 = p / n1, i1 = p - i0 * n1;
         double al[3];
         pe3d_alpha_box_headings(s, tab_x(s, 0, i0), tab_x(s, 1, i1), bmin, bmax, al);
         for (int d = 0; d < 3; ++d) m[d] = fmax(m[d], al[d]);
     }
     __shared__ double red[kBlock / 64][3];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ bool last;
     for (int d = 0; d < 3; ++d) {
         double v = m[d];
         for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
         if (lane == 0) red[wave][d] = v;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x == 0) {
+        for (int d = 0; d < 3; ++d) {
+            double v = red[0][d];
+            for (int w = 1; w < kBlock / 64; ++w) v = fmax(v, red[w][d]);
+            // alpha >= 0: its bits order as the values
+            atomicMax(&words[d], (unsigned long long)__double_as_longlong(v));
+        }
+        __threadfence();
+        last = atomicAdd(&words[3], 1ull) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();
     double amax[3];
     for (int d = 0; d < 3; ++d) {
-        double v = red[0][d];
-        for (int w = 1; w < kBlock / 64; ++w) v = fmax(v, red[w][d]);
-        amax[d] = v;
-        s.amax[d] = fmax(s.amax[d], v);
+        amax[d] = __longlong_as_double(
+            (long long)__hip_atomic_load(&words[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        s.amax[d] = fmax(s.amax[d], amax[d]);
     }
+    for (int e = 0; e < kBoxStepWords; ++e) words[e] = 0;
     double sum = 0.0;
     for (int d = 0; d < 3; ++d) sum += amax[d] / s.dx[d];
     double dtc = s.cfl / sum;
@@ -586,10 +608,11 @@ hipError_t launch_finish_copy(int precision, const SolveDesc *d, const uint32_t 
     return hipGetLastError();
 }
 
-hipError_t launch_box_dt(const SolveDesc *d, const int32_t *list, int n, int from_desc, int64_t step,
+hipError_t launch_box_dt(const SolveDesc *d, const int32_t *list, int n, int parts, int from_desc, int64_t step,
                          hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(box_dt_kernel, dim3(n), dim3(kBlock), 0, st, d, list, from_desc, step);
+    hipLaunchKernelGGL(box_dt_kernel, dim3(parts > 0 ? parts : 1, n), dim3(kBlock), 0, st, d, list, from_desc,
+                       step);
     return hipGetLastError();
 }
 

@@ -16,6 +16,9 @@ constexpr int kBlock = 256;          // threads per stage block (4 wave64s)
 constexpr int kNumXcd = 8;           // MI355X: 8 XCDs, blocks dealt round robin
 constexpr int kBoxSlots = 64;        // costate box: partial boxes per buffer (blocks
                                      // spread their atomics over them)
+// after the two box buffers: the box CFL step's largest box alpha per axis
+// (order-preserving keys of non-negative doubles) and its block counter
+constexpr int kBoxStepWords = 4;
 
 // n / d for n < 2^31 as (mulhi(n, m) + n) >> s (round-up magic number).
 struct FastDiv {
@@ -94,7 +97,8 @@ struct SolveDesc {
     uint64_t *box;           // costate box (pursuit-evasion only, else null): two
                              // buffers, used by alternate stages, of kBoxSlots
                              // partial boxes of 6 order-preserving keys each
-                             // (D_min[3], then D_max[3])
+                             // (D_min[3], then D_max[3]), then kBoxStepWords
+                             // words for the box CFL step
     // ---- computation method: after every full step (the last stage) V is
     // compared with a reference point by point and replaced by the smaller
     // (or larger) of the two; then, optionally, again with an obstacle array

@@ -308,6 +308,7 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
             p.groups.push_back(gr);
         }
         p.groups.back().count++;
+        p.groups.back().box_parts = std::max(p.groups.back().box_parts, box_parts(it.g));
     }
     // members by step count, descending, so that the solves still running at
     // step k are a prefix of each group's tile table
@@ -354,7 +355,7 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         off += align256(size_t(it.max_steps) * 4);
         if (it.dyn.id == ODP_DYN_PE3D) {
             it.box_off = off;
-            off += align256(size_t(2 * kBoxSlots * 6) * 8);
+            off += align256(size_t(2 * kBoxSlots * 6 + kBoxStepWords) * 8);
         }
         if (it.box_cfl) {
             it.tk_off = off;
@@ -570,7 +571,7 @@ int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t
                                     "box")))
                     return rc;
                 if (j == 0 &&
-                    (rc = check_hip(launch_box_dt(descs + gr.first, nullptr, gr.count, 0, k, st), "box step")))
+                    (rc = check_hip(launch_box_dt(descs + gr.first, nullptr, gr.count, gr.box_parts, 0, k, st), "box step")))
                     return rc;
             }
             if ((rc = check_hip(launch_stage(prec, gr.dyn, gr.ndim, gr.vec, kind, descs,

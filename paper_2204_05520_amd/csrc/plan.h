@@ -58,6 +58,7 @@ struct PlanItem {
 
 struct PlanGroup {
     int dyn = 0, ndim = 0, vec = 1, rk = 1, lds = 0;
+    int box_parts = 1;                  // blocks per member of the box CFL step
     int first = 0, count = 0;           // descriptor range
     std::vector<int> order;             // members sorted by step count, descending
     std::vector<uint32_t> prefix;       // prefix[m] = tiles of order[0..m)

@@ -43,8 +43,16 @@ hipError_t launch_ttr_zero(unsigned long long *p, int n, hipStream_t st);
 // solve: list[j], or descriptor j when list is null; from_desc: each solve's
 // own step counter), the final parity copy / landing check over the tiles,
 // and the device-conditional save_all copy and set switch of solve 0.
-hipError_t launch_box_dt(const SolveDesc *d, const int32_t *list, int n, int from_desc, int64_t step,
+// box CFL step: `parts` blocks per listed solve share its (x, y) nodes
+// (box_parts), the last to finish takes the step
+hipError_t launch_box_dt(const SolveDesc *d, const int32_t *list, int n, int parts, int from_desc, int64_t step,
                          hipStream_t st);
+// Blocks per solve for the box CFL step: one node of (axis 0, axis 1) per thread, at most 1024 blocks.
+inline int box_parts(const odp_grid *g) {
+    const int64_t nodes = g->n[0] * g->n[1];
+    const int64_t b = (nodes + kBlock - 1) / kBlock;
+    return int(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
 hipError_t launch_box_finish(int precision, const SolveDesc *d, const uint32_t *ts, const uint32_t *tl,
                              uint32_t nblocks, hipStream_t st);
 hipError_t launch_box_save(int precision, const SolveDesc *d, int64_t k, void *V_all, int64_t npts,

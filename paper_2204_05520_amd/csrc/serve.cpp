@@ -207,6 +207,7 @@ struct Group {
     std::vector<uint32_t> prefix;  // prefix[m]: tiles of the first m members
     uint32_t tiles = 0;
     size_t tile_base = 0, list_base = 0;
+    int box_parts = 1;             // blocks per member of the box CFL step (pursuit-evasion)
 };
 
 int get_event(odp_server *s, hipEvent_t *ev) {
@@ -495,7 +496,11 @@ int build_groups(odp_server *s, const std::vector<std::shared_ptr<Req>> &sel, st
             return by_slot[size_t(a)]->tick_steps > by_slot[size_t(b)]->tick_steps;
         });
         g.steps.clear();
-        for (int sl : g.slots) g.steps.push_back(by_slot[size_t(sl)]->tick_steps);
+        g.box_parts = 1;
+        for (int sl : g.slots) {
+            g.steps.push_back(by_slot[size_t(sl)]->tick_steps);
+            g.box_parts = std::max(g.box_parts, box_parts(&by_slot[size_t(sl)]->grid));
+        }
     }
     size_t ntiles = 0;
     for (auto &r : sel) ntiles += r->plan.items[0].tiles;
@@ -571,7 +576,7 @@ int enqueue_tick(odp_server *s, const std::vector<Group> &groups, hipEvent_t *do
                                                   nt, j, 1, m, o.xcd_group, s->st),
                                      "box")) ||
                      // the step from the box of the first stage (Algorithm 1)
-                     (j == 0 && (rc = check_hip(launch_box_dt(s->d_slots, s->d_list + g.list_base, nm, 1, m, s->st),
+                     (j == 0 && (rc = check_hip(launch_box_dt(s->d_slots, s->d_list + g.list_base, nm, g.box_parts, 1, m, s->st),
                                                 "box step")))))
                     return rc;
                 if ((rc = check_hip(launch_stage(o.precision, g.dyn, g.ndim, g.vec, kind, s->d_slots, ts, tl, nt, j,

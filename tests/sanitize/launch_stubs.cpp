@@ -14,7 +14,7 @@ hipError_t launch_ttr(int, int, int, const SolveDesc *, uint32_t, int, int, cons
                       unsigned long long *, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_ttr_init(int, const void *, void *, int64_t, double, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_ttr_zero(unsigned long long *, int, hipStream_t) { return hipErrorInvalidValue; }
-hipError_t launch_box_dt(const SolveDesc *, const int32_t *, int, int, int64_t, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_box_dt(const SolveDesc *, const int32_t *, int, int, int, int64_t, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_box_finish(int, const SolveDesc *, const uint32_t *, const uint32_t *, uint32_t, hipStream_t) {
     return hipErrorInvalidValue;
 }
