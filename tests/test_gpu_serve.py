@@ -78,6 +78,49 @@ def test_serve_equals_alone(odp):
         assert stats[i]["latency_ms"] > 0
 
 
+def test_serve_two_lanes_equal_alone(odp):
+    """Requests submitted together share their first ticks: the 4D group
+    (six members) splits into two halves launched on the server's two tick
+    streams beside the 3D group; every result still equals its solve alone,
+    bit for bit."""
+    rng = np.random.default_rng(17)
+    specs = []
+    for i in range(6):
+        n = [int(x) for x in rng.integers(10, 18, size=4)]
+        g = W.GridSpec(n, [-5.0, -5.0, 0.0, -np.pi], [5.0, 5.0, 4.0, np.pi], [0, 0, 0, 1])
+        d = W.DynSpec(W.DYN_DYNCAR4D, [float(rng.uniform(0.5, 1.5)), float(rng.uniform(0.5, 2.0))],
+                      W.MAXIMISE, W.MINIMISE)
+        specs.append(W.SolveSpec(g, d, [0.0, float(rng.uniform(0.3, 0.6))], rk_order=3,
+                                 radius=float(rng.uniform(0.3, 1.2)), name=f"car{i}"))
+    for i in range(4):
+        n = [int(x) for x in rng.integers(16, 30, size=3)]
+        g = W.GridSpec(n, [-4.0, -4.0, -np.pi], [4.0, 4.0, np.pi], [0, 0, 1])
+        d = W.DynSpec(W.DYN_DUBINS3D, [float(rng.uniform(0.5, 1.5)), float(rng.uniform(0.5, 2.0))],
+                      W.MAXIMISE, W.MINIMISE)
+        specs.append(W.SolveSpec(g, d, [0.0, float(rng.uniform(0.3, 0.6))], rk_order=1,
+                                 radius=float(rng.uniform(0.3, 1.2)), name=f"dub{i}"))
+    V0s = [W.make_v0(s).astype(np.float32) for s in specs]
+    srv = odp.Server(budget_bytes=1 << 30, max_slots=len(specs), precision=32, rk_order=1)
+    print(f"[gpu] serve {len(specs)} requests submitted together (two tick lanes)", flush=True)
+    try:
+        tickets = [srv.submit(s, v, rk_order=s.rk_order) for s, v in zip(specs, V0s)]
+        outs = [np.empty_like(v) for v in V0s]
+        for i, t in enumerate(tickets):
+            t0 = time.time()
+            while True:
+                rc, _ = srv.poll(t, outs[i])
+                if rc != odp.ODP_PENDING:
+                    break
+                assert time.time() - t0 < 60
+                time.sleep(0.001)
+            assert rc == odp.ODP_OK
+    finally:
+        srv.close()
+    for i, s in enumerate(specs):
+        ref = alone(odp, s, V0s[i])
+        assert np.array_equal(ref, outs[i]), (s.name, float(np.abs(ref - outs[i]).max()))
+
+
 def test_serve_budget_and_cancel(odp):
     spec = mixed_requests(1, 9)[0]
     V0 = W.make_v0(spec).astype(np.float32)
