@@ -385,6 +385,8 @@ def bench_serve(args, W, odp):
                               "clock": "server: submit to completion"},
         "submit_lag_ms": {"p50": float(np.percentile(lag, 50)), "p99": float(np.percentile(lag, 99))},
         "completed_per_s": nreq / span,
+        # the measured requests' own arrival rate (first to last arrival)
+        "offered_per_s": nreq / (reqs[-1].arrival_s - t_first),
         # time from the last arrival to the last completion: the run ends with
         # this drain, which completed_per_s includes; a backlog would make it
         # grow past the latency tail
@@ -473,7 +475,8 @@ def leg_batch(args, W, odp):
 
 def leg_serve(args, W, odp):
     ln = bench_serve(args, W, odp)
-    keep = ("latency_ms", "server_latency_ms", "completed_per_s", "drain_after_last_arrival_ms", "alg_tbps_over_run",
+    keep = ("latency_ms", "server_latency_ms", "completed_per_s", "offered_per_s", "drain_after_last_arrival_ms",
+            "alg_tbps_over_run",
             "offered_alg_tbps",
             "phases_ms")
     out = {k: ln[k] for k in keep if k in ln}
