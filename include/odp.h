@@ -346,10 +346,13 @@ int odp_ttr_solve(const odp_grid *grid, const odp_dynamics *dyn, const void *tar
 
 /* In-process continuous-batching server.  A scheduler thread admits queued
  * requests while their device footprint fits hbm_budget_bytes and a slot is
- * free, keeps their value functions resident, and advances every active
- * solve by a few steps per tick in one batched launch, so requests that
- * arrive while others run join at the next tick.  Results are the same as
- * odp_hj_solve with the server's options, bit for bit. */
+ * free, keeps their value functions resident, and advances the active
+ * solves (in arrival order, up to a work budget per tick) by a few steps
+ * per tick in batched launches, one per RK stage and kernel group, on two
+ * compute streams; requests that arrive while others run join at a later
+ * tick.  The server owns four streams (two compute, upload, download).
+ * Results are the same as odp_hj_solve with the server's options, bit for
+ * bit. */
 typedef struct odp_server odp_server;
 
 int odp_server_create(size_t hbm_budget_bytes, int max_slots, const odp_solve_opts *opts,
