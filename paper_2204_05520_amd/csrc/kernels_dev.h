@@ -806,7 +806,7 @@ __device__ __forceinline__ void stp_nt(ODP_GLOBAL T *p, const Pack<T, VEC> &r) {
 // read; rows of axis N-2 wrapped across a periodic edge are loaded from
 // memory (a wave-uniform branch).
 template <typename T, int DYN, int N, int VEC, bool LDSX>
-__global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc *__restrict__ descs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(N == 4 && sizeof(T) == 8 ? 3 : 1))) void stage_eno2_vec_kernel(const SolveDesc *__restrict__ descs,
                                                                 const uint32_t *__restrict__ tile_solve,
                                                                 const uint32_t *__restrict__ tile_local,
                                                                 int stage, int step_from_desc,
@@ -952,7 +952,12 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
             g.v[e] = (j == -1 || j == n0) ? ghost(vb.v[e], vin.v[e]) : ghost2(vb.v[e], vin.v[e]);
         return g;
     };
-    P r0 = ax0(i0b - 2), r1 = ax0(i0b - 1), r2 = ax0(i0b), r3 = ax0(i0b + 1), r4;
+    // float64: the farthest axis-0 neighbour is loaded a plane ahead (4D
+    // float64 230.5 -> 224.1 ms per solve, held at occupancy 3 with a few
+    // values spilled; float32 with the same: 109.2 -> 116.2 ms, not used)
+    constexpr bool kAx0Ahead = sizeof(T) == 8;
+    P r0 = ax0(i0b - 2), r1 = ax0(i0b - 1), r2 = ax0(i0b), r3 = ax0(i0b + 1), r4, r5;
+    if constexpr (kAx0Ahead) r4 = ax0(i0b + 2);
     // The next plane's middle-axis neighbours, halo rows and V^n are loaded
     // while this plane is computed (the barrier waits for LDS only), and are
     // copied into place after the compute, when they have landed.
@@ -975,7 +980,11 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
     if (kPref && wa != 0.0) vn = ldp_nt<T, VEC>(Vn + int64_t(i0b) * s0 + q);
     T nanacc = T(0);
     for (int i0 = i0b; i0 < i0e; ++i0) {
-        r4 = ax0(i0 + 2);
+        if constexpr (kAx0Ahead) {
+            if (i0 + 1 < i0e) r5 = ax0(i0 + 3);
+        } else {
+            r4 = ax0(i0 + 2);
+        }
         const P wc = r2;
         const ODP_GLOBAL T *plane = W + int64_t(i0) * s0 + q;
         const int in = min(i0 + 1, i0e - 1);
@@ -1093,6 +1102,7 @@ __global__ __launch_bounds__(kBlock) void stage_eno2_vec_kernel(const SolveDesc 
         r1 = r2;
         r2 = r3;
         r3 = r4;
+        if constexpr (kAx0Ahead) r4 = r5;
         if constexpr (NMG > 0 && kPref) {
 #pragma unroll
             for (int d = 0; d < NMG; ++d)
