@@ -42,21 +42,6 @@ int64_t step_capacity(const odp_grid *g, const odp_dynamics *dyn, const std::vec
     return int64_t(std::min(est, 1e9)) + 2 * int64_t(tau.size()) + 8;
 }
 
-// Planes per block for a requested c: chunks of (nearly) equal length; for
-// the default choice also a multiple of 4, the marching kernel's register
-// cycle, except for chunks under 4 planes in up to four dimensions (there
-// the march ends at the chunk end).
-int balanced_chunk(const odp_grid *g, int c, bool cycle4) {
-    const int n0 = int(g->n[0]);
-    c = std::max(1, std::min(c, n0));
-    const int nchunks = (n0 + c - 1) / c;
-    int b = (n0 + nchunks - 1) / nchunks;
-    // up to four dimensions runs of fewer than 4 planes stay as they are
-    // (small grids: more blocks, and the march ends at the chunk end)
-    if (cycle4 && g->ndim >= 2 && (b >= 4 || g->ndim >= 5)) b = std::min((b + 3) / 4 * 4, (n0 + 3) / 4 * 4);
-    return b;
-}
-
 // Axis tables: coordinate, cos, sin per axis (float64, computed once on the
 // host; the kernels read these values, never a transcendental).  Axes with
 // the same node count, lower bound and spacing share their table (the many
@@ -176,6 +161,22 @@ int64_t host_schedule(const PlanItem &it, const odp_solve_opts &o, std::vector<i
 
 }  // namespace
 
+// Planes per block for a requested c: chunks of (nearly) equal length; for
+// the default choice also a multiple of 4, the marching kernel's register
+// cycle, except for chunks under 4 planes in up to four dimensions (there
+// the march ends at the chunk end).
+static int balanced_chunk(const odp_grid *g, int c, bool cycle4) {
+    const int n0 = int(g->n[0]);
+    c = std::max(1, std::min(c, n0));
+    const int nchunks = (n0 + c - 1) / c;
+    int b = (n0 + nchunks - 1) / nchunks;
+    // up to four dimensions runs of fewer than 4 planes stay as they are
+    // (small grids: more blocks, and the march ends at the chunk end)
+    if (cycle4 && g->ndim >= 2 && (b >= 4 || g->ndim >= 5)) b = std::min((b + 3) / 4 * 4, (n0 + 3) / 4 * 4);
+    return b;
+}
+
+
 // Tiles of one hyperplane (tile_group).  Six-dimensional solves of the
 // vector kernels (first order; second order with two or more points per
 // thread) whose cubes of axes 3..5 waste under 5% of the lanes in their
@@ -264,13 +265,15 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
             if (items.size() == 1) {
                 // brick tiles: every block marches the whole axis (on the
                 // 36^6 float32 grid 36 planes beat 8 and 12 by 7-12%)
-                c = it.brick ? int(it.g->n[0]) : default_chunk(it.g, it.vec, prec);
+                c = it.brick ? int(it.g->n[0]) : default_chunk(it.g, it.vec, prec, opts.space_order);
             } else {
                 // many solves share every launch: about 8192 blocks in all
                 c = int(std::max<int64_t>(1, total / (int64_t(kBlock) * it.vec * 8192)));
             }
         }
-        it.chunk = balanced_chunk(it.g, c, tile_chunk <= 0 || round4);
+        const bool exact = tile_chunk <= 0 && items.size() == 1 && !it.brick &&
+                           default_chunk_exact(it.g, it.vec, prec, opts.space_order);
+        it.chunk = balanced_chunk(it.g, c, (tile_chunk <= 0 && !exact) || round4);
         it.tiles = uint32_t(int64_t(it.nqb) * ((it.g->n[0] + it.chunk - 1) / it.chunk));
         it.max_steps = step_capacity(it.g, &it.dyn, it.tau, opts.cfl, opts.max_dt);
         it.tab_entries = 0;

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -199,19 +200,54 @@ int choose_vec(const odp_grid *g, int precision, int dyn, int64_t pitch) {
     return 1;
 }
 
-// Planes of axis 0 marched per block: about 2048 tiles per solve (two to
-// three rounds of resident blocks at the stage kernel's occupancy, measured
-// on the 4D 80^4 grid in both precisions), at most a third of the axis from
+// Planes of axis 0 marched per block.  First order in four dimensions: the
+// fewest chunks (of balanced lengths) whose tiles fill 65-100% of one round
+// of resident blocks of the stage kernels (1024 in float32 at 4 waves per
+// SIMD, 768 in float64 at 3): a tile reads the two planes beyond its chunk
+// and pays a start-up, so long chunks win as long as the GPU is full, and a
+// second, partial round costs more than it saves (measured on 4D grids of
+// 40-80 nodes per axis in both precisions: the choice matched or beat the
+// autotuner, where about 2048 tiles per solve lost up to 20%; the ENO2
+// kernel, whose waves wait longer on memory, lost 20% with it at 80^4).
+// ENO2, grids with more whole-axis tiles than one round and other
+// dimensions: about 2048 tiles per solve, at most a third of the axis from
 // five dimensions on (measured on the 6D 36^6 grid: 12 planes beat 4, 8, 20
-// and 36); the plan rounds it to whole 4-plane cycles.
-int default_chunk(const odp_grid *g, int vec, int precision) {
-    (void)precision;
+// and 36); the plan rounds these to whole 4-plane cycles.
+namespace {
+int64_t resident_blocks(int precision) { return precision == 32 ? 1024 : 768; }
+}  // namespace
+
+int default_chunk(const odp_grid *g, int vec, int precision, int space_order) {
     const int64_t n0 = g->n[0];
     const int64_t Q = g->npts / n0;
     const int64_t nqb = (Q + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec);
+    if (g->ndim == 4 && space_order == 1) {
+        const int64_t round = resident_blocks(precision), fill = round * 13 / 20;
+        int64_t most = 0, at = 0;
+        for (int64_t nch = 1; nch <= n0; ++nch) {
+            const int64_t b = (n0 + nch - 1) / nch;
+            const int64_t tiles = nqb * ((n0 + b - 1) / b);
+            if (tiles > round) break;  // tiles only grow with nch
+            if (tiles >= fill) return int(b);
+            if (tiles > most) {
+                most = tiles;
+                at = b;
+            }
+        }
+        if (at > 0) return int(at);  // small grids: one round as full as it gets
+    }
     int64_t c = (n0 * nqb + 2047) / 2048;
     if (g->ndim >= 5) c = std::min<int64_t>(c, (n0 + 2) / 3);
     return int(std::max<int64_t>(1, std::min<int64_t>(c, n0)));
+}
+
+// True when default_chunk's choice for this grid is taken as it is (not
+// rounded to whole 4-plane cycles): the one-round choice in four dimensions.
+bool default_chunk_exact(const odp_grid *g, int vec, int precision, int space_order) {
+    if (g->ndim != 4 || space_order != 1) return false;
+    const int64_t n0 = g->n[0];
+    const int64_t nqb = (g->npts / n0 + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec);
+    return nqb <= resident_blocks(precision);
 }
 
 // Tile runs per XCD: one contiguous run, except for grids whose arrays are

@@ -82,7 +82,8 @@ int upload_async(void *dst, const void *src, size_t bytes, hipStream_t st);
 void alpha_bound(const odp_grid *g, const odp_dynamics *dyn, double *ab);
 size_t align256(size_t x);
 
-int default_chunk(const odp_grid *g, int vec, int precision);
+int default_chunk(const odp_grid *g, int vec, int precision, int space_order = 1);
+bool default_chunk_exact(const odp_grid *g, int vec, int precision, int space_order = 1);
 int default_xcd_group(const odp_grid *g);
 // Points per thread along the last axis: the largest of 4 (float32 only), 2
 // and 1 that divides the row pitch (1 for ndim 1 and the ball-input test

@@ -257,17 +257,14 @@ size_t request_layout(Req &r, const odp_solve_opts &o) {
     const int64_t nl = r.grid.n[r.grid.ndim - 1];
     const int64_t w = o.precision == 32 ? 4 : 2;
     it.pitch = int((nl + w - 1) / w * w);
-    // many requests share every launch: march at least 16 planes per block
-    // (each tile reads two planes beyond its chunk, and a short chunk makes
-    // them a large share: at 8 planes the 4D stage launches fetched 1.13-1.25x
-    // their stencil input; measured at 200 requests/s, p99 with at least 8 /
-    // 12 / 16 / 20 / 24 planes: 118-124 / 118 / 107-109 / 111 / 117 ms, half
-    // the axis 172 ms, the whole axis (too few tiles) 868 ms)
+    // many requests share every launch: blocks march 16 planes (each tile
+    // reads two planes beyond its chunk, and a short chunk makes them a
+    // large share: at 8 planes the 4D stage launches fetched 1.13-1.25x their
+    // stencil input; measured at 200 requests/s, p99 with 8 / 12 / 16 / 20 /
+    // 24 planes: 118-124 / 118 / 107-109 / 111 / 117 ms, half the axis 172
+    // ms, the whole axis (too few tiles) 868 ms)
     int chunk = o.tile_chunk;
-    if (chunk <= 0) {
-        int vec = choose_vec(&r.grid, o.precision, r.dyn.id, it.pitch);
-        chunk = std::max(default_chunk(&r.grid, vec, o.precision), int(std::min<int64_t>(16, r.grid.n[0])));
-    }
+    if (chunk <= 0) chunk = int(std::min<int64_t>(16, r.grid.n[0]));
     std::vector<PlanItem> items{it};
     plan_build(r.plan, std::move(items), o, chunk);
     const PlanItem &pi = r.plan.items[0];
