@@ -273,7 +273,8 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         }
         const bool exact = tile_chunk <= 0 && items.size() == 1 && !it.brick &&
                            default_chunk_exact(it.g, it.vec, prec, opts.space_order);
-        it.chunk = balanced_chunk(it.g, c, (tile_chunk <= 0 && !exact) || round4);
+        // (the default is the tuner's candidate 0: taken as it is, too)
+        it.chunk = balanced_chunk(it.g, c, tile_chunk <= 0 ? !exact : round4);
         it.tiles = uint32_t(int64_t(it.nqb) * ((it.g->n[0] + it.chunk - 1) / it.chunk));
         it.max_steps = step_capacity(it.g, &it.dyn, it.tau, opts.cfl, opts.max_dt);
         it.tab_entries = 0;
