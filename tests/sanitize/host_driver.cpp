@@ -4,7 +4,9 @@
 // order and spatial order, their host images, and a tile-coverage count:
 // replaying the stage kernels' block -> (solve, planes, points) mapping from
 // each plan's descriptors, every (plane, hyperplane element) of every solve
-// must be covered by exactly one tile.  Prints "ok" on success.
+// must be covered by exactly one tile; and the default chunk of single
+// first-order 4D solves (one round of resident blocks).  Prints "ok" on
+// success.
 #include <cstdio>
 #include <cstring>
 #include <random>
@@ -112,6 +114,49 @@ static void plan_case(const std::vector<const odp_grid *> &gs, const std::vector
         CHECK(it.box_cfl || int64_t(it.land.size()) == it.nsteps);
     }
     coverage(p, img);
+}
+
+// The default chunk of a single first-order 4D solve: whole tiles of one
+// round of resident blocks (1024 float32, 768 float64) when the whole-axis
+// tiles fit one round, filled to at least 65% unless even one-plane chunks
+// cannot fill it, and the fewest chunks that do.
+static void default_chunk_case(const int64_t *n, int prec) {
+    const uint8_t per[4] = {0, 0, 0, 1};
+    odp_grid *g = grid(4, n, per);
+    odp_dynamics d{};
+    d.id = ODP_DYN_DYNCAR4D; d.u_mode = 1; d.p[0] = 1.0; d.p[1] = 1.0;
+    odp_solve_opts o{};
+    o.precision = prec;
+    o.rk_order = 3;
+    o.cfl = 0.8;
+    o.mode = ODP_BRT;
+    o.space_order = 1;
+    PlanItem it;
+    it.g = g;
+    it.dyn = d;
+    it.V0 = (const void *)uintptr_t(4096);
+    it.A = (void *)uintptr_t(8192);
+    it.tau = {0.0, 0.3};
+    Plan p;
+    plan_build(p, {it}, o, 0);
+    CHECK(p.error.empty());
+    const PlanItem &q = p.items[0];
+    const int64_t n0 = n[0], round = prec == 32 ? 1024 : 768;
+    const int64_t chunks = (n0 + q.chunk - 1) / q.chunk;
+    CHECK(q.chunk >= 1 && q.chunk <= n0);
+    CHECK(int64_t(q.tiles) == int64_t(q.nqb) * chunks);
+    if (int64_t(q.nqb) <= round) {
+        const int64_t fill = round * 13 / 20, tiles = q.tiles;
+        CHECK(tiles <= round);
+        for (int64_t b = 1; b <= n0; ++b) {
+            const int64_t t = int64_t(q.nqb) * ((n0 + b - 1) / b);
+            // filled: no chunk length giving fewer chunks fills 65% too;
+            // not filled: no chunk length that fits one round has more tiles
+            if (tiles >= fill && (n0 + b - 1) / b < chunks) CHECK(t < fill);
+            if (tiles < fill && t <= round) CHECK(t <= tiles);
+        }
+    }
+    odp_grid_destroy(g);
 }
 
 int main() {
@@ -222,6 +267,19 @@ int main() {
             }
         }
     CHECK(g_brick_plans > 0 && g_quad_plans > 0 && g_quad_plans < g_brick_plans);
+    // default chunks of single first-order 4D solves, cubic and ragged
+    for (int prec : {32, 64}) {
+        for (int64_t c = 20; c <= 100; c += 4) {
+            const int64_t n[4] = {c, c, c, c};
+            default_chunk_case(n, prec);
+        }
+        std::mt19937 rng(7);
+        for (int rep = 0; rep < 40; ++rep) {
+            auto V = [&](int a, int b) { return int64_t(std::uniform_int_distribution<int>(a, b)(rng)); };
+            const int64_t n[4] = {V(20, 100), V(20, 100), V(20, 100), 4 * V(5, 25)};
+            default_chunk_case(n, prec);
+        }
+    }
     // time to reach workspace, the server's argument checks (no device here)
     {
         const int64_t n[3] = {20, 20, 16};
