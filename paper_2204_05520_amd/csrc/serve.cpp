@@ -752,7 +752,8 @@ void scheduler(odp_server *s) {
         // kTickWork point-stage updates (at least one request; requests that
         // do not fit are passed over, so later small ones still join; any
         // request waiting longer than kMaxWaitMs joins anyway).  Measured at
-        // 200 requests/s (p50 / p99 ms, two lanes): least remaining work
+        // 200 requests/s (p50 / p99 ms, two lanes, 8-plane chunks; 16-plane
+        // chunks then took 0.75e9 to 14.1 / 109): least remaining work
         // first with a budget of 2e9, 17.5 / 140; arrival order with 2e9,
         // 17.7 / 145; with 1e9, 16.5 / 124; with 0.75e9, 14.4 / 119; with
         // 0.5e9, 12.1 / 148 (the launches get too small); least remaining
