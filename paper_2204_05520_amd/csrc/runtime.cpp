@@ -202,8 +202,8 @@ int choose_vec(const odp_grid *g, int precision, int dyn, int64_t pitch) {
 
 // Planes of axis 0 marched per block.  First order in four dimensions: the
 // fewest chunks (of balanced lengths) whose tiles fill 65-100% of one round
-// of resident blocks of the stage kernels (1024 in float32 at 4 waves per
-// SIMD, 768 in float64 at 3): a tile reads the two planes beyond its chunk
+// of resident blocks of the stage kernels (1024: 4 waves per SIMD in both
+// precisions): a tile reads the two planes beyond its chunk
 // and pays a start-up, so long chunks win as long as the GPU is full, and a
 // second, partial round costs more than it saves (measured on 4D grids of
 // 40-80 nodes per axis in both precisions: the choice matched or beat the
@@ -214,7 +214,9 @@ int choose_vec(const odp_grid *g, int precision, int dyn, int64_t pitch) {
 // five dimensions on (measured on the 6D 36^6 grid: 12 planes beat 4, 8, 20
 // and 36); the plan rounds these to whole 4-plane cycles.
 namespace {
-int64_t resident_blocks(int precision) { return precision == 32 ? 1024 : 768; }
+// blocks of the 4D first-order stage kernels resident at once (256 CUs, 4
+// blocks of 4 waves each)
+constexpr int64_t kResident4D = 1024;
 }  // namespace
 
 int default_chunk(const odp_grid *g, int vec, int precision, int space_order) {
@@ -222,7 +224,7 @@ int default_chunk(const odp_grid *g, int vec, int precision, int space_order) {
     const int64_t Q = g->npts / n0;
     const int64_t nqb = (Q + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec);
     if (g->ndim == 4 && space_order == 1) {
-        const int64_t round = resident_blocks(precision), fill = round * 13 / 20;
+        const int64_t round = kResident4D, fill = round * 13 / 20;
         int64_t most = 0, at = 0;
         for (int64_t nch = 1; nch <= n0; ++nch) {
             const int64_t b = (n0 + nch - 1) / nch;
@@ -247,7 +249,7 @@ bool default_chunk_exact(const odp_grid *g, int vec, int precision, int space_or
     if (g->ndim != 4 || space_order != 1) return false;
     const int64_t n0 = g->n[0];
     const int64_t nqb = (g->npts / n0 + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec);
-    return nqb <= resident_blocks(precision);
+    return nqb <= kResident4D;
 }
 
 // Tile runs per XCD: one contiguous run, except for grids whose arrays are

@@ -117,7 +117,7 @@ static void plan_case(const std::vector<const odp_grid *> &gs, const std::vector
 }
 
 // The default chunk of a single first-order 4D solve: whole tiles of one
-// round of resident blocks (1024 float32, 768 float64) when the whole-axis
+// round of resident blocks (1024) when the whole-axis
 // tiles fit one round, filled to at least 65% unless even one-plane chunks
 // cannot fill it, and the fewest chunks that do.
 static void default_chunk_case(const int64_t *n, int prec) {
@@ -141,7 +141,7 @@ static void default_chunk_case(const int64_t *n, int prec) {
     plan_build(p, {it}, o, 0);
     CHECK(p.error.empty());
     const PlanItem &q = p.items[0];
-    const int64_t n0 = n[0], round = prec == 32 ? 1024 : 768;
+    const int64_t n0 = n[0], round = 1024;
     const int64_t chunks = (n0 + q.chunk - 1) / q.chunk;
     CHECK(q.chunk >= 1 && q.chunk <= n0);
     CHECK(int64_t(q.tiles) == int64_t(q.nqb) * chunks);
