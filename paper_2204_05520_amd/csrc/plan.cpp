@@ -176,7 +176,6 @@ static int balanced_chunk(const odp_grid *g, int c, bool cycle4) {
     return b;
 }
 
-
 // Tiles of one hyperplane (tile_group).  Six-dimensional solves of the
 // vector kernels (first order; second order with two or more points per
 // thread) whose cubes of axes 3..5 waste under 5% of the lanes in their

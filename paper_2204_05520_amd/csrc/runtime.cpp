@@ -220,6 +220,7 @@ constexpr int64_t kResident4D = 1024;
 }  // namespace
 
 int default_chunk(const odp_grid *g, int vec, int precision, int space_order) {
+    (void)precision;  // the same in both precisions (vec carries the width)
     const int64_t n0 = g->n[0];
     const int64_t Q = g->npts / n0;
     const int64_t nqb = (Q + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec);
@@ -246,6 +247,7 @@ int default_chunk(const odp_grid *g, int vec, int precision, int space_order) {
 // True when default_chunk's choice for this grid is taken as it is (not
 // rounded to whole 4-plane cycles): the one-round choice in four dimensions.
 bool default_chunk_exact(const odp_grid *g, int vec, int precision, int space_order) {
+    (void)precision;
     if (g->ndim != 4 || space_order != 1) return false;
     const int64_t n0 = g->n[0];
     const int64_t nqb = (g->npts / n0 + int64_t(kBlock) * vec - 1) / (int64_t(kBlock) * vec);
