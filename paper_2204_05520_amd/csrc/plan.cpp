@@ -313,6 +313,53 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
         p.groups.back().count++;
         p.groups.back().box_parts = std::max(p.groups.back().box_parts, box_parts(it.g));
     }
+    // Batches: every group of several solves splits in two halves of about
+    // equal work (contiguous descriptor ranges), and the groups go to two
+    // lanes (the caller's stream and a second one, forked and joined around
+    // the stepping), the larger first onto the lighter lane: one lane's
+    // launch ramps and tails overlap the other's body.
+    if (n > 1) {
+        auto work = [&](int i) {
+            const PlanItem &it = p.items[size_t(i)];
+            return double(it.tiles) * double(it.nsteps) * double(it.rk_order);
+        };
+        std::vector<PlanGroup> split;
+        for (const PlanGroup &gr : p.groups) {
+            if (gr.count < 2) {
+                split.push_back(gr);
+                continue;
+            }
+            double tot = 0.0, acc = 0.0;
+            for (int i = gr.first; i < gr.first + gr.count; ++i) tot += work(i);
+            int k = 0;
+            while (k < gr.count - 1 && (k == 0 || acc + 0.5 * work(gr.first + k) <= 0.5 * tot)) acc += work(gr.first + k++);
+            PlanGroup a = gr, b = gr;
+            a.count = k;
+            b.first = gr.first + k;
+            b.count = gr.count - k;
+            for (PlanGroup *h : {&a, &b}) {
+                h->box_parts = 1;
+                for (int i = h->first; i < h->first + h->count; ++i)
+                    h->box_parts = std::max(h->box_parts, box_parts(p.items[size_t(i)].g));
+            }
+            split.push_back(a);
+            split.push_back(b);
+        }
+        p.groups = std::move(split);
+        std::vector<double> gw(p.groups.size(), 0.0);
+        std::vector<size_t> go(p.groups.size());
+        for (size_t g = 0; g < p.groups.size(); ++g) {
+            go[g] = g;
+            for (int i = p.groups[g].first; i < p.groups[g].first + p.groups[g].count; ++i) gw[g] += work(i);
+        }
+        std::stable_sort(go.begin(), go.end(), [&](size_t a, size_t b) { return gw[a] > gw[b]; });
+        double lw[2] = {0.0, 0.0};
+        for (size_t g : go) {
+            const int l = lw[1] < lw[0] ? 1 : 0;
+            p.groups[g].lane = l;
+            lw[l] += gw[g];
+        }
+    }
     // members by step count, descending, so that the solves still running at
     // step k are a prefix of each group's tile table
     p.max_nsteps = 0;
@@ -548,7 +595,7 @@ int plan_prologue(Plan &p, unsigned char *base, hipStream_t st, bool pageable) {
     return ODP_OK;
 }
 
-int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t k) {
+int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st0, int64_t k, hipStream_t st2) {
     int rc;
     const int prec = p.opts.precision;
     const int mk = method_kind(p.opts);
@@ -557,6 +604,7 @@ int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t
     const uint32_t *tsd = single ? nullptr : (const uint32_t *)(base + p.tt_off);
     const uint32_t *tld = single ? nullptr : tsd + align256(p.total_tiles * 4) / 4;
     for (const PlanGroup &gr : p.groups) {
+        hipStream_t st = gr.lane && st2 ? st2 : st0;
         // members with more than k steps form a prefix of gr.order
         size_t m = 0;
         while (m < gr.order.size() && p.items[size_t(gr.order[m])].nsteps > k) ++m;
@@ -588,6 +636,28 @@ int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t
 
 namespace {
 
+struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// The second lane of batches: one stream per host thread and device (so
+// that graph captures on different threads never share it), created on
+// first use at the default priority and kept until the process ends.
+hipStream_t lane_stream() {
+    thread_local std::vector<hipStream_t> per_device;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+    if (per_device.size() <= size_t(dev)) per_device.resize(size_t(dev) + 1, nullptr);
+    if (!per_device[size_t(dev)] &&
+        hipStreamCreateWithFlags(&per_device[size_t(dev)], hipStreamNonBlocking) != hipSuccess)
+        per_device[size_t(dev)] = nullptr;
+    return per_device[size_t(dev)];
+}
+
 int plan_enqueue(const Plan &p, unsigned char *base, hipStream_t st, void *V_all) {
     int rc;
     const odp_solve_opts &o = p.opts;
@@ -603,6 +673,17 @@ int plan_enqueue(const Plan &p, unsigned char *base, hipStream_t st, void *V_all
     }
     const PlanItem &it0 = p.items[0];
     const size_t bytes = single ? size_t(it0.g->npts) * (prec == 32 ? 4 : 8) : 0;
+    // batches with a lane-1 group: the second lane starts after the start
+    // copies and rejoins the caller's stream before the finish copies
+    hipStream_t st2 = nullptr;
+    Events lane_ev;
+    for (const PlanGroup &gr : p.groups)
+        if (gr.lane) st2 = lane_stream();
+    if (st2 && ((rc = check_hip(hipEventCreateWithFlags(&lane_ev.a, hipEventDisableTiming), "event")) ||
+                (rc = check_hip(hipEventCreateWithFlags(&lane_ev.b, hipEventDisableTiming), "event")) ||
+                (rc = check_hip(hipEventRecord(lane_ev.a, st), "record")) ||
+                (rc = check_hip(hipStreamWaitEvent(st2, lane_ev.a, 0), "wait"))))
+        return rc;
     // time-varying sets (single solves): the steps after landing on tau[j]
     // compare with slice j; a box_cfl solve learns its landings on the device
     const bool sliced = single && o.set_slices > 1;
@@ -616,7 +697,7 @@ int plan_enqueue(const Plan &p, unsigned char *base, hipStream_t st, void *V_all
                 return rc;
             }
         }
-        if ((rc = plan_launch_step(p, base, st, k))) return rc;
+        if ((rc = plan_launch_step(p, base, st, k, st2))) return rc;
         if (single && V_all) {
             if (it0.box_cfl) {
                 if ((rc = check_hip(launch_box_save(prec, descs, k, V_all, it0.g->npts, st), "save"))) return rc;
@@ -629,6 +710,9 @@ int plan_enqueue(const Plan &p, unsigned char *base, hipStream_t st, void *V_all
             }
         }
     }
+    if (st2 && ((rc = check_hip(hipEventRecord(lane_ev.b, st2), "record")) ||
+                (rc = check_hip(hipStreamWaitEvent(st, lane_ev.b, 0), "wait"))))
+        return rc;
     for (const PlanGroup &gr : p.groups) {
         const uint32_t *ts = tsd ? tsd + gr.tile_base : nullptr;
         const uint32_t *tl = tld ? tld + gr.tile_base : nullptr;

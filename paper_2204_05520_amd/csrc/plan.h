@@ -63,6 +63,7 @@ struct PlanGroup {
     std::vector<int> order;             // members sorted by step count, descending
     std::vector<uint32_t> prefix;       // prefix[m] = tiles of order[0..m)
     size_t tile_base = 0;               // first entry in the tile tables
+    int lane = 0;                       // batches: 0 on the caller's stream, 1 on a second one
 };
 
 struct Plan {
@@ -83,7 +84,8 @@ std::vector<int> plan_build(Plan &p, std::vector<PlanItem> items, const odp_solv
                             int tile_chunk, bool round4 = false);
 // The stage launches of step k for every group (the members that have a
 // step k, as in the solve itself).
-int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t k);
+// Lane-1 groups go to st2 when it is given (else everything to st).
+int plan_launch_step(const Plan &p, unsigned char *base, hipStream_t st, int64_t k, hipStream_t st2 = nullptr);
 // Host image of [0, upload_bytes) for a workspace at device address base.
 void plan_image(const Plan &p, unsigned char *base, std::vector<unsigned char> &img);
 // Upload, alpha^max, schedules (stream-ordered: the step counts are known on
